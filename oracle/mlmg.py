@@ -1,0 +1,471 @@
+"""Cell-centred variable-coefficient operator and its geometric multigrid solve.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The operator is the one of the paper's "Linear Solvers" section,
+``alpha*a*phi - beta*div(b grad phi) = f`` (the paper's scalars and
+coefficients renamed: alpha, beta scalars; ``a`` per cell; ``b`` per face).
+Its standard 7-point cell-centred discretisation on a level with mesh size h:
+
+    (A phi)_i = alpha a_i phi_i
+                - beta sum_d [ b_{d,i+e_d} (phi_{i+e_d} - phi_i)
+                              - b_{d,i}     (phi_i - phi_{i-e_d}) ] / h_d^2
+
+Face array ``b[d][box]`` holds, at index i, the face on the low side of cell i
+along d (indices lo_d .. hi_d+1).  Readings taken where the paper is silent:
+
+* domain = unit cube, h_d = 1 / n_d;
+* periodic directions go through ghost cells filled by the exchange;
+* a homogeneous Dirichlet wall (phi = 0 on the face) uses the linear ghost
+  value phi_ghost = -phi_i folded into the stencil: that face adds 2 c_f to the
+  diagonal and has no neighbour term (symmetric, so CG and the adjoint work);
+* smoother = red/black Gauss-Seidel, colour = (i+j+k) mod 2 in global level
+  indices, red (0) first, ghost exchange before every half-sweep;
+* restriction = average of the 8 children, interpolation = piecewise constant
+  (the averaging and interpolation of "Operations between levels");
+* coefficients coarsened by averaging (a: 8 cells, b: the 4 fine faces on a
+  coarse face) and the operator re-discretised at h_c = 2h;
+* bottom = unpreconditioned CG from a zero guess, stopped on the 2-norm;
+* outer stop test on the max norm relative to max|f|.
+"""
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .boxes import box_shape, coarsen_box, fill_boundary
+
+NG = 1  # ghost width of cell data used by the solver
+
+
+@dataclass
+class Level:
+    boxes: list
+    domain: tuple
+    periodic: tuple
+    h: tuple
+    alpha: float
+    beta: float
+    a: list            # per box, valid shape; None means a == 1
+    b: list            # b[d][box], face arrays (valid shape + e_d)
+    dtype: type = np.float64
+    _stencil: list = field(default=None, repr=False)
+
+
+def make_level(boxes, domain, periodic, alpha, beta, a=None, b=None, prob_len=(1.0, 1.0, 1.0),
+               dtype=np.float64):
+    """Build level-0 of a solve.  ``a`` and ``b`` are per-box lists (None = 1)."""
+    n = box_shape(domain)
+    h = tuple(prob_len[d] / n[d] for d in range(3))
+    if b is None:
+        b = []
+        for d in range(3):
+            e = [0, 0, 0]
+            e[d] = 1
+            b.append([np.ones(tuple(box_shape(bx)[a_] + e[a_] for a_ in range(3)), dtype=dtype)
+                      for bx in boxes])
+    if a is not None:
+        a = [np.asarray(x, dtype=dtype) for x in a]
+    b = [[np.asarray(x, dtype=dtype) for x in b[d]] for d in range(3)]
+    return Level(list(boxes), domain, tuple(bool(p) for p in periodic), h, float(alpha),
+                 float(beta), a, b, dtype)
+
+
+def new_cell_data(level, ng=NG, dtype=None):
+    dt = level.dtype if dtype is None else dtype
+    return [np.zeros(tuple(e + 2 * ng for e in box_shape(bx)), dtype=dt) for bx in level.boxes]
+
+
+def valid(arr, ng=NG):
+    return arr[ng:-ng, ng:-ng, ng:-ng] if ng > 0 else arr
+
+
+def coarsen_level(lev):
+    """Next multigrid level: boxes coarsened by 2, coefficients averaged.
+
+    a_c = mean of the 8 child cells; b_c on a coarse d-face = mean of the 4 fine
+    d-faces that make it up.  Coarsening is done in float64.
+    """
+    boxes = [coarsen_box(bx) for bx in lev.boxes]
+    a = None
+    if lev.a is not None:
+        a = []
+        for af in lev.a:
+            af = af.astype(np.float64)
+            z0 = ((af[0::2, 0::2, 0::2] + af[1::2, 0::2, 0::2])
+                  + (af[0::2, 1::2, 0::2] + af[1::2, 1::2, 0::2]))
+            z1 = ((af[0::2, 0::2, 1::2] + af[1::2, 0::2, 1::2])
+                  + (af[0::2, 1::2, 1::2] + af[1::2, 1::2, 1::2]))
+            s = z0 + z1
+            a.append(s * 0.125)
+    b = []
+    for d in range(3):
+        t1, t2 = [x for x in range(3) if x != d]
+        bl = []
+        for bf in lev.b[d]:
+            bf = bf.astype(np.float64)
+            sl = [slice(None)] * 3
+            sl[d] = slice(0, None, 2)       # fine faces 0, 2, ..., n_d lie on coarse faces
+            sub = bf[tuple(sl)]
+            parts = []
+            for o1 in (0, 1):
+                for o2 in (0, 1):
+                    s2 = [slice(None)] * 3
+                    s2[t1] = slice(o1, None, 2)
+                    s2[t2] = slice(o2, None, 2)
+                    parts.append(sub[tuple(s2)])
+            bl.append(((parts[0] + parts[1]) + (parts[2] + parts[3])) * 0.25)
+        b.append(bl)
+    h = tuple(2.0 * x for x in lev.h)
+    out = Level(boxes, coarsen_box(lev.domain), lev.periodic, h, lev.alpha, lev.beta, a, b,
+                np.float64)
+    return out
+
+
+def cast_level(lev, dtype):
+    """Same level with its coefficients rounded to ``dtype``."""
+    a = None if lev.a is None else [x.astype(dtype) for x in lev.a]
+    b = [[x.astype(dtype) for x in lev.b[d]] for d in range(3)]
+    return Level(lev.boxes, lev.domain, lev.periodic, lev.h, lev.alpha, lev.beta, a, b, dtype)
+
+
+def stencil(lev):
+    """Per box: (diag, [(c, dirichlet_mask) for faces xlo, xhi, ylo, yhi, zlo, zhi]).
+
+    c_f = beta * b_f / h_d^2.  A face on a Dirichlet wall has weight 2 in the
+    diagonal and no neighbour term; every other face has weight 1.  The diagonal
+    is summed in the fixed face order xlo, xhi, ylo, yhi, zlo, zhi.
+    """
+    if lev._stencil is not None:
+        return lev._stencil
+    dt = lev.dtype
+    out = []
+    for ib, bx in enumerate(lev.boxes):
+        shp = box_shape(bx)
+        lo, hi = bx
+        if lev.a is None:
+            diag = np.full(shp, lev.alpha, dtype=dt)
+        else:
+            diag = (dt(lev.alpha) * lev.a[ib]).astype(dt)
+        faces = []
+        for d in range(3):
+            inv_h2 = dt(1.0 / (lev.h[d] * lev.h[d]))
+            bf = lev.b[d][ib]
+            sl_lo = [slice(None)] * 3
+            sl_hi = [slice(None)] * 3
+            sl_lo[d] = slice(0, shp[d])
+            sl_hi[d] = slice(1, shp[d] + 1)
+            for side, sl in (("lo", sl_lo), ("hi", sl_hi)):
+                c = (dt(lev.beta) * bf[tuple(sl)]) * inv_h2
+                mask = np.zeros(shp, dtype=bool)
+                if not lev.periodic[d]:
+                    edge = [slice(None)] * 3
+                    if side == "lo" and lo[d] == lev.domain[0][d]:
+                        edge[d] = slice(0, 1)
+                        mask[tuple(edge)] = True
+                    if side == "hi" and hi[d] == lev.domain[1][d]:
+                        edge[d] = slice(shp[d] - 1, shp[d])
+                        mask[tuple(edge)] = True
+                faces.append((c.astype(dt), mask))
+        for (c, m) in faces:
+            diag = diag + np.where(m, dt(2) * c, c)
+        out.append((diag.astype(dt), faces))
+    lev._stencil = out
+    return out
+
+
+def _neighbours(P, ng=NG):
+    """Views of the six neighbours of every valid cell: xlo, xhi, ylo, yhi, zlo, zhi."""
+    n0, n1, n2 = (P.shape[0] - 2 * ng, P.shape[1] - 2 * ng, P.shape[2] - 2 * ng)
+    g = ng
+    return [
+        P[g - 1:g - 1 + n0, g:g + n1, g:g + n2], P[g + 1:g + 1 + n0, g:g + n1, g:g + n2],
+        P[g:g + n0, g - 1:g - 1 + n1, g:g + n2], P[g:g + n0, g + 1:g + 1 + n1, g:g + n2],
+        P[g:g + n0, g:g + n1, g - 1:g - 1 + n2], P[g:g + n0, g:g + n1, g + 1:g + 1 + n2],
+    ]
+
+
+def _offsum(faces, P):
+    dt = P.dtype
+    s = None
+    for (c, m), nb in zip(faces, _neighbours(P)):
+        t = np.where(m, dt.type(0), c * nb)
+        s = t if s is None else s + t
+    return s
+
+
+def exchange(lev, data):
+    fill_boundary(data, lev.boxes, lev.domain, lev.periodic, NG)
+
+
+def apply_op(lev, phi):
+    """A phi on every valid cell (ghosts of phi are filled first)."""
+    exchange(lev, phi)
+    out = []
+    for ib, (diag, faces) in enumerate(stencil(lev)):
+        P = phi[ib]
+        out.append(diag * valid(P) - _offsum(faces, P))
+    return out
+
+
+def residual(lev, phi, f):
+    """r = f - A phi (valid cells only)."""
+    Aphi = apply_op(lev, phi)
+    return [f[ib] - Aphi[ib] for ib in range(len(lev.boxes))]
+
+
+def colour_mask(bx, colour):
+    lo, hi = bx
+    I = np.arange(lo[0], hi[0] + 1)[:, None, None]
+    J = np.arange(lo[1], hi[1] + 1)[None, :, None]
+    K = np.arange(lo[2], hi[2] + 1)[None, None, :]
+    return ((I + J + K) % 2) == colour
+
+
+def gsrb_halfsweep(lev, phi, f, colour):
+    """One Gauss-Seidel half-sweep over the cells of one colour.
+
+    phi_i <- (f_i + sum_{non-wall faces} c_f phi_nbr) / diag_i.  Cells of one
+    colour only neighbour cells of the other colour, so updating all of them
+    from the same old values is exact Gauss-Seidel for that colour.
+    """
+    exchange(lev, phi)
+    for ib, (diag, faces) in enumerate(stencil(lev)):
+        P = phi[ib]
+        new = (f[ib] + _offsum(faces, P)) / diag
+        V = valid(P)
+        m = colour_mask(lev.boxes[ib], colour)
+        V[m] = new[m]
+
+
+def restrict(lev_f, r_f):
+    """Coarse value = mean of the 8 children (box b of the coarse level is coarsen(box b))."""
+    out = []
+    for r in r_f:
+        # pairwise: ((x pairs) + (y pairs)) per z layer, then the two z layers, so
+        # that eight equal values average back to exactly that value
+        z0 = ((r[0::2, 0::2, 0::2] + r[1::2, 0::2, 0::2]) + (r[0::2, 1::2, 0::2] + r[1::2, 1::2, 0::2]))
+        z1 = ((r[0::2, 0::2, 1::2] + r[1::2, 0::2, 1::2]) + (r[0::2, 1::2, 1::2] + r[1::2, 1::2, 1::2]))
+        s = z0 + z1
+        out.append((s * r.dtype.type(0.125)).astype(r.dtype))
+    return out
+
+
+def prolong_add(phi_f, e_c):
+    """Fine valid cell += coarse value of its parent (piecewise-constant interpolation)."""
+    for ib in range(len(phi_f)):
+        V = valid(phi_f[ib])
+        E = valid(e_c[ib])
+        V += np.repeat(np.repeat(np.repeat(E, 2, axis=0), 2, axis=1), 2, axis=2)
+
+
+def _dot(u, v):
+    """Sum of products over all valid cells, accumulated in float64."""
+    return float(sum(np.sum(x.astype(np.float64) * y.astype(np.float64)) for x, y in zip(u, v)))
+
+
+def _mean(u):
+    n = sum(x.size for x in u)
+    return float(sum(np.sum(x.astype(np.float64)) for x in u)) / n
+
+
+def is_singular(lev):
+    if not all(lev.periodic):
+        return False
+    if lev.alpha == 0.0:
+        return True
+    return lev.a is not None and all(not np.any(x) for x in lev.a)
+
+
+def cg_bottom(lev, rhs, tol=1e-4, max_iter=None, singular=None):
+    """Unpreconditioned CG on ``A x = rhs`` from x = 0 (the paper's CG "bottom solve").
+
+    Stops when ||r||_2 <= tol * ||rhs||_2 (2-norm over all cells) or after
+    ``max_iter`` iterations (default: number of cells).  For a singular
+    all-periodic problem the mean of rhs is removed first and the mean of x at
+    the end (CG's r and p recurrences do not involve x, so removing it at the
+    end equals removing it from every iterate).  Dot products are accumulated
+    in float64.  Returns (x with ghosts, iterations).
+    """
+    dt = lev.dtype
+    if singular is None:
+        singular = is_singular(lev)
+    ncell = sum(int(np.prod(box_shape(b))) for b in lev.boxes)
+    if max_iter is None:
+        max_iter = ncell
+    x = new_cell_data(lev)
+    r = [np.array(v, dtype=dt, copy=True) for v in rhs]
+    if singular:
+        m = dt(_mean(r))
+        r = [(v - m).astype(dt) for v in r]
+    rho = _dot(r, r)
+    bnorm = math.sqrt(rho)
+    if bnorm == 0.0:
+        return x, 0
+    p = new_cell_data(lev)
+    for ib in range(len(p)):
+        valid(p[ib])[...] = r[ib]
+    it = 0
+    while it < max_iter:
+        q = apply_op(lev, p)
+        pq = _dot([valid(v) for v in p], q)
+        al = rho / pq
+        for ib in range(len(x)):
+            valid(x[ib])[...] += dt(al) * valid(p[ib])
+            r[ib] -= dt(al) * q[ib]
+        it += 1
+        rho_new = _dot(r, r)
+        if math.sqrt(rho_new) <= tol * bnorm:
+            break
+        bt = rho_new / rho
+        for ib in range(len(p)):
+            valid(p[ib])[...] = r[ib] + dt(bt) * valid(p[ib])
+        rho = rho_new
+    if singular:
+        m = dt(_mean([valid(v) for v in x]))
+        for v in x:
+            valid(v)[...] -= m
+    return x, it
+
+
+@dataclass
+class Opts:
+    nu1: int = 2
+    nu2: int = 2
+    max_iter: int = 100
+    bottom_tol: float = 1e-4
+    bottom_max_iter: int = None
+    min_bottom_edge: int = 4
+
+
+def vcycle(levels, l, phi, f, opts, stats=None):
+    """V(l, phi, f): nu1 pre-smoothing sweeps, residual, restrict, recurse on a zero
+    coarse guess, add the interpolated correction, nu2 post-smoothing sweeps; the
+    bottom level is solved by CG on its residual equation."""
+    lev = levels[l]
+    if l == len(levels) - 1:
+        r = residual(lev, phi, f)
+        e, its = cg_bottom(lev, r, opts.bottom_tol, opts.bottom_max_iter)
+        for ib in range(len(phi)):
+            valid(phi[ib])[...] += valid(e[ib])
+        if stats is not None:
+            stats.setdefault("bottom_iters", []).append(its)
+        return
+    for _ in range(opts.nu1):
+        gsrb_halfsweep(lev, phi, f, 0)
+        gsrb_halfsweep(lev, phi, f, 1)
+    r = residual(lev, phi, f)
+    fc = restrict(lev, r)
+    ec = new_cell_data(levels[l + 1])
+    vcycle(levels, l + 1, ec, fc, opts, stats)
+    prolong_add(phi, ec)
+    for _ in range(opts.nu2):
+        gsrb_halfsweep(lev, phi, f, 0)
+        gsrb_halfsweep(lev, phi, f, 1)
+
+
+def max_norm(u):
+    return float(max(np.max(np.abs(x)) for x in u))
+
+
+def build_levels(lev0, min_bottom_edge=4):
+    """Level 0 plus its coarsened copies, following ``boxes.mg_hierarchy``'s rule."""
+    from .boxes import mg_hierarchy
+    nlev = len(mg_hierarchy(lev0.boxes, lev0.domain, min_bottom_edge))
+    levels = [lev0]
+    for _ in range(nlev - 1):
+        levels.append(coarsen_level(levels[-1]))
+    return levels
+
+
+def solve(lev0, phi, f, rel_tol=1e-10, abs_tol=0.0, opts=None, levels=None):
+    """Iterate V-cycles on level 0 until max|f - A phi| <= max(rel_tol*max|f|, abs_tol).
+
+    ``phi`` (per-box arrays with one ghost layer) is the initial guess and is
+    updated in place.  Returns a dict with the per-cycle max-norm residual
+    history (entry k is the residual after k cycles), the cycle count and
+    whether the tolerance was met.  For a singular all-periodic problem the
+    returned phi has its mean removed.
+    """
+    opts = opts or Opts()
+    if levels is None:
+        levels = build_levels(lev0, opts.min_bottom_edge)
+    normf = max_norm(f)
+    info = {"history": [], "iters": 0, "converged": False, "bottom_iters": [],
+            "nlevels": len(levels)}
+    if normf == 0.0:
+        for v in phi:
+            v[...] = 0.0
+        info["converged"] = True
+        return info
+    tol = max(rel_tol * normf, abs_tol)
+    it = 0
+    while True:
+        rn = max_norm(residual(lev0, phi, f))
+        info["history"].append(rn)
+        if not np.isfinite(rn):
+            break
+        if rn <= tol:
+            info["converged"] = True
+            break
+        if it == opts.max_iter:
+            break
+        vcycle(levels, 0, phi, f, opts, info)
+        it += 1
+    info["iters"] = it
+    info["normf"] = normf
+    if is_singular(lev0):
+        m = _mean([valid(v) for v in phi])
+        for v in phi:
+            valid(v)[...] -= m
+    return info
+
+
+def solve_refine(lev0, phi, f, rel_tol=1e-10, abs_tol=0.0, opts=None, inner_dtype=np.float64,
+                 levels=None):
+    """Iterative refinement: float64 residual, one V-cycle in ``inner_dtype`` on the
+    residual equation from a zero guess, float64 update.
+
+    With ``inner_dtype`` float64 the iterates equal those of ``solve`` in exact
+    arithmetic (Gauss-Seidel commutes with the shift phi = phi_k + e).  The
+    coefficient hierarchy is coarsened in float64 and then rounded.
+    """
+    opts = opts or Opts()
+    if levels is None:
+        levels = build_levels(lev0, opts.min_bottom_edge)
+    inner = [cast_level(L, inner_dtype) for L in levels]
+    normf = max_norm(f)
+    info = {"history": [], "iters": 0, "converged": False, "bottom_iters": [],
+            "nlevels": len(levels)}
+    if normf == 0.0:
+        for v in phi:
+            v[...] = 0.0
+        info["converged"] = True
+        return info
+    tol = max(rel_tol * normf, abs_tol)
+    it = 0
+    while True:
+        r = residual(lev0, phi, f)
+        rn = max_norm(r)
+        info["history"].append(rn)
+        if not np.isfinite(rn):
+            break
+        if rn <= tol:
+            info["converged"] = True
+            break
+        if it == opts.max_iter:
+            break
+        r_in = [x.astype(inner_dtype) for x in r]
+        e = new_cell_data(inner[0], dtype=inner_dtype)
+        vcycle(inner, 0, e, r_in, opts, info)
+        for ib in range(len(phi)):
+            valid(phi[ib])[...] += valid(e[ib]).astype(np.float64)
+        it += 1
+    info["iters"] = it
+    info["normf"] = normf
+    if is_singular(lev0):
+        m = _mean([valid(v) for v in phi])
+        for v in phi:
+            valid(v)[...] -= m
+    return info

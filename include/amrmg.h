@@ -1,0 +1,259 @@
+/*
+ * amrmg.h - C ABI of the MI355X (gfx950) multigrid library.
+ *
+ * The library solves the cell-centred variable-coefficient equation of the
+ * AMReX paper's "Linear Solvers" section,
+ *
+ *     alpha * a * phi - beta * div(b grad phi) = f,
+ *
+ * with scalars alpha, beta, a cell coefficient a and a face coefficient b,
+ * on one level held as a MultiFab: a list of non-intersecting boxes, each
+ * with its own array grown by ngrow ghost cells ("Basic data structures",
+ * "Containers for mesh data").  The solver is a geometric multigrid V-cycle
+ * with a CG bottom solve ("Linear Solvers"); ghost cells between boxes are
+ * filled by a fused copy ("Operations on a level", "Communication").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: 0 on success, a negative mg_status_t on failure.  No entry
+ *   point aborts or exits.  mg_last_error() returns a message for the last
+ *   failure on the calling thread.
+ * - Boxes hold inclusive cell indices.  Domain = the geometry's box; the
+ *   physical domain is [prob_lo, prob_hi] and h_d = (prob_hi_d - prob_lo_d) / n_d.
+ * - MultiFab layout: box b's array covers grow(box_b, ngrow) (grown by one
+ *   more cell along d when ixtype[d] = 1, face data) and starts at element
+ *   offsets[b] of `data`; inside it cell (i, j, k) is at
+ *   (i - glo_x) + nx * ((j - glo_y) + ny * (k - glo_z)) over the grown box
+ *   (x fastest, "Fortran" order); components follow one another (struct of
+ *   arrays).  The solver requires the canonical packing: offsets[0] = 0 and
+ *   each box directly after the previous one.
+ * - Device pointers: `data` of an mg_multifab_t, the workspace and the
+ *   global face arrays are device memory on the current HIP device.  Boxes,
+ *   offsets, geometries, options and info structs are host memory.
+ * - Ownership: the caller owns every buffer it passes.  The solver copies
+ *   coefficients into its workspace, keeps host-side metadata (plans, tile
+ *   tables, graphs) until mg_destroy, and never allocates device memory: all
+ *   its device storage lives in the caller's workspace, which must outlive
+ *   the handle.  fill_boundary keeps a process-wide cache of exchange plans;
+ *   each cached plan holds one small device table (released by
+ *   mg_release_caches).
+ * - Streams: work is enqueued on the stream given (NULL = the default
+ *   stream).  mg_solve returns after its result is complete; fill_boundary,
+ *   mg_apply and mg_face_grad_logb are asynchronous with respect to the host.
+ * - Threading: one handle per thread; handles may be used from different
+ *   threads concurrently.
+ */
+#ifndef AMRMG_H
+#define AMRMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MG_OK = 0,
+  MG_ERR_ARG = -1,               /* bad argument (null pointer, bad enum, size)          */
+  MG_ERR_INVALID_BOXARRAY = -2,  /* overlap, outside the domain, incomplete cover,
+                                    not coarsenable                                     */
+  MG_ERR_MISMATCH = -3,          /* a MultiFab does not match the solver's boxes/layout */
+  MG_ERR_WORKSPACE = -4,         /* workspace missing or smaller than required           */
+  MG_ERR_HIP = -5,               /* a HIP runtime call failed                            */
+  MG_ERR_NAN = -6,               /* a non-finite value reached a norm                    */
+  MG_ERR_DIVERGED = -7,          /* residual grew for 3 cycles and exceeds its start     */
+  MG_ERR_NOT_CONVERGED = -8,     /* max_iter reached; phi and info still written         */
+  MG_ERR_SINGULAR = -9           /* all-periodic, alpha*a == 0 and rhs of nonzero mean   */
+} mg_status_t;
+
+enum { MG_BC_PERIODIC = 0, MG_BC_DIRICHLET0 = 1 };   /* "BCRec" subset: periodic, phi = 0 wall */
+enum { MG_F64 = 0, MG_F32 = 1 };                      /* element type of a MultiFab          */
+enum { MG_PREC_F64 = 0, MG_PREC_F32_REFINE = 1 };     /* solve precision                     */
+
+/* A rectangular range of cells, inclusive ("Box"). */
+typedef struct { int32_t lo[3], hi[3]; } mg_box_t;
+
+/* Index <-> physical mapping and periodicity ("Geometry"). */
+typedef struct {
+  mg_box_t domain;
+  double prob_lo[3], prob_hi[3];
+  int32_t is_periodic[3];
+} mg_geom_t;
+
+/* Borrowed view of one level's data ("FabArray"/"MultiFab" + "Array4"). */
+typedef struct {
+  int32_t nbox;
+  const mg_box_t* boxes;       /* host: valid boxes, cell index space          */
+  int32_t ngrow;               /* ghost layers on every side                    */
+  int32_t ncomp;               /* components (the solver uses 1)                */
+  int32_t ixtype[3];           /* 0 = cell centred, 1 = face (nodal) along d    */
+  int32_t dtype;               /* MG_F64 | MG_F32                               */
+  void* data;                  /* device                                        */
+  const int64_t* offsets;      /* host [nbox]: element offset of each box       */
+} mg_multifab_t;
+
+/* Solver options.  mg_default_opts fills the defaults given in brackets. */
+typedef struct {
+  int32_t nu1;                 /* [2] pre-smoothing red/black sweeps            */
+  int32_t nu2;                 /* [2] post-smoothing sweeps                     */
+  int32_t max_iter;            /* [100] V-cycles (refinement steps)             */
+  int32_t bottom_max_iter;     /* [0 = number of bottom cells] CG iterations    */
+  int32_t min_bottom_edge;     /* [4] coarsen while every edge/2 >= this        */
+  int32_t precision;           /* [MG_PREC_F64] or MG_PREC_F32_REFINE           */
+  int32_t use_graph;           /* [1] replay the coarse levels as a HIP graph   */
+  int32_t tune;                /* [1] 0 default tiles, 1 use tune cache,
+                                      2 time the candidates now (and store)     */
+  int32_t verbose;             /* [0] per-cycle log on stderr                   */
+  int32_t aggregate;           /* [0] merge boxes once they stop coarsening and
+                                      keep coarsening the merged box            */
+  double bottom_rel_tol;       /* [1e-4] CG stops at ||r||2 <= tol*||rhs||2     */
+} mg_opts_t;
+
+typedef struct {
+  int32_t iters;               /* V-cycles done                                 */
+  int32_t nlevels;             /* multigrid levels                              */
+  int32_t bottom_iters;        /* CG iterations of the last bottom solve        */
+  int32_t converged;           /* 1 when the tolerance was met                  */
+  double rel_resid;            /* max|f - A phi| / max|f| at return            */
+  double abs_resid;            /* max|f - A phi| at return                      */
+  double setup_ms;             /* mg_create wall time                           */
+  double solve_ms;             /* mg_solve wall time                            */
+} mg_info_t;
+
+/* One ghost-copy item: dst cells in dst_region take src cells at p - shift. */
+typedef struct { int32_t dst, src; mg_box_t dst_region; int32_t shift[3]; } mg_copy_tag_t;
+
+typedef struct mg_solver mg_solver_t;
+
+/* Defaults listed in mg_opts_t. */
+void mg_default_opts(mg_opts_t* opts);
+
+/* Bytes of device workspace mg_create needs for these boxes and options
+ * (has_acoef: whether a cell coefficient a will be given).  Host only; may be
+ * called without a GPU.  Validates the box array like mg_create. */
+int mg_query_workspace(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
+                       const mg_opts_t* opts, int32_t has_acoef, size_t* bytes);
+
+/* Build a solver for one level ("Linear Solvers"; box array and geometry of
+ * "Basic data structures").  Validates the boxes (disjoint, inside, covering
+ * the domain), builds the multigrid hierarchy, the ghost-exchange plans (hash
+ * intersection, "Communication") and the tile tables, copies the coefficients
+ * into the workspace and coarsens them there (averaging restriction,
+ * "Operations between levels").  acoef: cell MultiFab or NULL (a = 1);
+ * bcoef: three face MultiFabs (ixtype e_d, ngrow 0) or NULL (b = 1); both
+ * MG_F64 over the same boxes.  bc_lo/bc_hi: MG_BC_PERIODIC exactly in the
+ * periodic directions of geom, MG_BC_DIRICHLET0 elsewhere.  opts NULL =
+ * defaults.  workspace: device memory of at least mg_query_workspace bytes,
+ * 256-byte aligned.  hip_stream: hipStream_t or NULL. */
+int mg_create(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
+              const int32_t bc_lo[3], const int32_t bc_hi[3], double alpha, double beta,
+              const mg_multifab_t* acoef, const mg_multifab_t* const* bcoef,
+              const mg_opts_t* opts, void* workspace, size_t ws_bytes, void* hip_stream,
+              mg_solver_t** out);
+
+/* Replace the coefficients (same conventions as mg_create) and re-coarsen;
+ * plans, tables and graphs are kept. */
+int mg_set_coefficients(mg_solver_t* s, const mg_multifab_t* acoef,
+                        const mg_multifab_t* const* bcoef);
+
+/* Replace the face coefficients from three global face arrays (device,
+ * MG_F64): array d has n_d + 1 faces along d and n elsewhere, element (i,j,k)
+ * at i + nx_d * (j + ny_d * k) (x fastest), face i on the low side of cell i.
+ * is_log = 1: the arrays hold log b.  acoef_global: NULL (a = 1) or a global
+ * cell array.  Re-coarsens like mg_set_coefficients. */
+int mg_set_coefficients_global(mg_solver_t* s, const void* acoef_global,
+                               const void* const* bface_global, int32_t is_log);
+
+/* Solve A phi = rhs by V-cycles until max|rhs - A phi| <= max(rel_tol *
+ * max|rhs|, abs_tol) ("Linear Solvers"; the stop norm is the max norm of
+ * "Parallel Reductions").  phi: MG_F64 cell MultiFab with ngrow 1, in:
+ * initial guess, out: solution (its ghost cells are overwritten).  rhs:
+ * MG_F64 cell MultiFab, ngrow 0 or 1.  Both over the solver's boxes.  For an
+ * all-periodic singular problem the returned phi has zero mean.
+ * resid_history: host array of max_iter + 1 doubles or NULL; entry k is the
+ * max-norm residual after k cycles.  Returns MG_ERR_NOT_CONVERGED (phi and
+ * info written) when max_iter is reached, MG_ERR_NAN on a non-finite norm. */
+int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, double rel_tol,
+             double abs_tol, mg_info_t* info, double* resid_history);
+
+/* out = A phi on every valid cell (phi's ghosts are filled first).  phi as in
+ * mg_solve; out: MG_F64 cell MultiFab over the same boxes. */
+int mg_apply(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* out);
+
+/* Adjoint face gradient dL/dlog b_f = -b_f * lambda^T (dA/db_f) phi for every
+ * face of every box: -c_f (phi_j - phi_i)(lam_j - lam_i) on an interior or
+ * periodic face, -2 c_f phi_i lam_i on a Dirichlet wall, c_f = beta b_f / h^2
+ * (operator of "Linear Solvers").  phi and lam: as mg_solve's phi (ghosts are
+ * filled).  grad: three MG_F64 face MultiFabs (ngrow 0). */
+int mg_face_grad_logb(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam,
+                      mg_multifab_t* const* grad);
+
+/* Same gradient written to three global face arrays (layout of
+ * mg_set_coefficients_global); each physical face once; in a periodic
+ * direction faces 0 and n both carry the wrap face's value. */
+int mg_face_grad_logb_global(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam,
+                             void* const* grad_global);
+
+/* dst = src on every valid cell (a MultiFab copy between ghost layouts, as
+ * "Containers for mesh data" allows any nGrow).  Both MG_F64 cell MultiFabs
+ * over the solver's boxes with ngrow 0 or 1; ghost cells of dst untouched.
+ * Asynchronous. */
+int mg_copy_valid(mg_solver_t* s, const mg_multifab_t* src, mg_multifab_t* dst);
+
+/* Release the solver's host metadata and graphs (not the caller's memory). */
+void mg_destroy(mg_solver_t* s);
+
+/* Fill every ghost cell of mf whose periodically wrapped index lies in
+ * another box's valid region (or in the same box's periodic image) with that
+ * cell's value ("Operations on a level"): one fused copy kernel over all copy
+ * tags ("Communication").  Ghost cells outside a non-periodic domain face are
+ * left untouched.  mf: cell centred (ixtype 0), any ngrow, ncomp, dtype.
+ * Asynchronous on hip_stream. */
+int fill_boundary(mg_multifab_t* mf, const mg_geom_t* geom, void* hip_stream);
+int mg_fill_boundary(mg_multifab_t* mf, const mg_geom_t* geom, void* hip_stream);
+
+/* The copy tags fill_boundary applies, in canonical order (dst, src, shift,
+ * region lo), built by hash intersection ("Communication").  Host only.
+ * Writes up to cap tags to out (out may be NULL when cap = 0) and the total
+ * count to *n; returns MG_ERR_ARG if cap < *n and out != NULL. */
+int mg_copy_tags(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom, int32_t ngrow,
+                 mg_copy_tag_t* out, int32_t cap, int32_t* n);
+
+/* Number of multigrid levels the solver would build (host only). */
+int mg_num_levels(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
+                  const mg_opts_t* opts, int32_t* nlevels);
+
+/* Kernel timing.  When enabled, mg_solve records HIP events around each
+ * launch of the level-0 kernels of the given family, on the solver's stream;
+ * mg_kernel_stats returns the summed duration and launch count since the last
+ * reset.  family: 0 smoother half-sweep, 1 residual, 2 ghost exchange,
+ * 3 restriction, 4 interpolation, 5 coarse levels (one graph or launch
+ * sequence per cycle), 6 refinement update. */
+int mg_profile(mg_solver_t* s, int32_t enable);
+int mg_kernel_stats(mg_solver_t* s, int32_t family, double* total_ms, int64_t* launches);
+
+/* Time one level-0 smoother half-sweep launched alone `reps` times on the
+ * solver's stream (colour alternating) and return the mean duration; uses
+ * phi/rhs as the data.  For roofline measurements. */
+int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs,
+                     int32_t reps, double* mean_ms);
+
+/* Override the tile shape of the level-0 smoother (kernel 0: block lx x ly
+ * lanes covering 2*lx x ly cells, tz planes per work-group) or of the
+ * level-0 one-lane-per-cell kernels (kernel 1: lx x ly cells).  lx*ly must be
+ * 64, 128 or 256 and the shape one of the tuner's candidates (lx in
+ * {16,32,64} for kernel 0, {32,64,128} for kernel 1; ly, tz powers of two up
+ * to 16 and 64).  Every shape gives bitwise-identical results. */
+int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz);
+
+/* Free the device tables of fill_boundary's plan cache. */
+void mg_release_caches(void);
+
+/* Message for the last failure on this thread ("" if none). */
+const char* mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMRMG_H */

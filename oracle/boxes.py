@@ -86,18 +86,20 @@ def mg_hierarchy(boxes, domain, min_bottom_edge=4):
     multigrid efficiency, section "Regridding and load balancing", but gives no
     rule): level l+1 is every box of level l coarsened by 2, which is done only
     while every edge of every box at level l is even and half of it is at least
-    ``min_bottom_edge``.  Returns a list of ``(boxes, domain)``.
+    ``min_bottom_edge`` and every box (and the domain) starts at an even index,
+    so that each coarse cell has its 8 children in one box.  Returns a list of
+    ``(boxes, domain)``.
     """
     levels = [(list(boxes), domain)]
     while True:
         bs, dom = levels[-1]
         ok = True
         for b in bs:
-            for e in box_shape(b):
-                if e % 2 != 0 or e // 2 < min_bottom_edge:
+            for d, e in enumerate(box_shape(b)):
+                if e % 2 != 0 or e // 2 < min_bottom_edge or b[0][d] % 2 != 0:
                     ok = False
-        for e in box_shape(dom):
-            if e % 2 != 0:
+        for d, e in enumerate(box_shape(dom)):
+            if e % 2 != 0 or dom[0][d] % 2 != 0:
                 ok = False
         if not ok:
             break

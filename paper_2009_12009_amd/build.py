@@ -1,0 +1,78 @@
+"""Build libamrmg.so (host C++ + gfx950 HIP kernels) in-tree with hipcc.
+
+Usage: python -m paper_2009_12009_amd.build   (or build() from Python)
+"""
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(HERE, "libamrmg.so")
+
+SOURCES = ["host.cpp", "fb.cpp", "solver.cpp", "kernels.hip"]
+
+ARCH = os.environ.get("AMRMG_ARCH", "gfx950")
+
+# Packed FP32 instructions are disabled for all device code.
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-result", "-Wno-unused-function", "-Wno-unused-value",
+    "-I", os.path.join(ROOT, "include"),
+]
+
+
+def hipcc():
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def build(verbose=False, jobs=4):
+    os.makedirs(BUILD, exist_ok=True)
+    cc = hipcc()
+    objs = []
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        objs.append(obj)
+        cmd = [cc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        if len(procs) >= jobs:
+            _wait(procs)
+            procs = []
+    _wait(procs)
+    tmp = LIB + ".tmp"
+    cmd = [cc, *FLAGS, "-shared", *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n" + r.stdout.decode())
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def _wait(procs):
+    errs = []
+    for src, p in procs:
+        out, _ = p.communicate()
+        text = out.decode()
+        if p.returncode != 0:
+            errs.append(f"--- {src} ---\n{text}")
+        elif text.strip():
+            print(f"--- {src} ---\n{text}", file=sys.stderr)
+    if errs:
+        raise RuntimeError("compile failed:\n" + "\n".join(errs))
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

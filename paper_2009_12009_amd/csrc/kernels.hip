@@ -1,0 +1,872 @@
+// gfx950 kernels of the multigrid solve.
+//
+// Operator (the cell-centred equation of the paper's "Linear Solvers"
+// section, alpha*a*phi - beta*div(b grad phi) = f, 7-point discretisation):
+//   (A phi)_i = diag_i phi_i - sum_{faces f not on a wall} c_f phi_nbr(f),
+//   c_f = (beta b_f) / h_d^2,  diag_i = alpha a_i + sum_f w_f c_f,
+// w_f = 2 on a homogeneous Dirichlet wall (linear ghost phi_g = -phi_i folded
+// in), 1 elsewhere.  Faces are visited in the order xlo, xhi, ylo, yhi, zlo,
+// zhi everywhere, so the diagonal is the same number in every kernel.
+//
+// All kernels work on box-list tile tables: one launch covers every box of a
+// level; a work-group takes one tile of one box and marches along z, so
+// consecutive planes of the same arrays stay in L2 between iterations.  Every
+// access is x-contiguous across the lanes of a wavefront.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace amrmg {
+
+namespace {
+
+struct BoxDims {
+  int nx, ny, nz;
+};
+
+__device__ __forceinline__ BoxDims dims(const BoxInfo& b) {
+  return {b.hi[0] - b.lo[0] + 1, b.hi[1] - b.lo[1] + 1, b.hi[2] - b.lo[2] + 1};
+}
+
+// Element index of valid cell (il, jl, kl) in a cell array with ng ghosts.
+__device__ __forceinline__ long long cidx(const BoxDims& d, int ng, int il, int jl, int kl) {
+  const long long sy = d.nx + 2 * ng;
+  const long long sz = sy * (d.ny + 2 * ng);
+  return (il + ng) + sy * (jl + ng) + sz * (kl + ng);
+}
+
+__device__ __forceinline__ unsigned long long absbits(double v) {
+  return (unsigned long long)__double_as_longlong(fabs(v));
+}
+__device__ __forceinline__ unsigned long long absbits(float v) { return absbits((double)v); }
+
+// Fold a per-lane value into *dst as an unsigned max over the block.
+__device__ void block_max_u64(unsigned long long v, unsigned long long* dst) {
+  __shared__ unsigned long long red[16];
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long w = (unsigned long long)__shfl_xor((long long)v, o);
+    v = w > v ? w : v;
+  }
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const int nw = (blockDim.x * blockDim.y + 63) / 64;
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long m = red[0];
+    for (int w = 1; w < nw; ++w) m = red[w] > m ? red[w] : m;
+    if (m) atomicMax(dst, m);
+  }
+}
+
+// The stencil at one valid cell.  Returns diag and the neighbour sum.
+template <typename T>
+struct Cell {
+  T diag, off;
+};
+
+template <typename T, bool READ_NBR>
+__device__ __forceinline__ Cell<T> stencil_at(const StencilArgs<T>& op, const BoxInfo& B,
+                                              const BoxDims& d, const T* P, long long pc, int il,
+                                              int jl, int kl) {
+  const long long sy = d.nx + 2, sz = (long long)(d.nx + 2) * (d.ny + 2);
+  const long long fx = il + (long long)(d.nx + 1) * (jl + (long long)d.ny * kl);
+  const long long fy = il + (long long)d.nx * (jl + (long long)(d.ny + 1) * kl);
+  const long long fz = il + (long long)d.nx * (jl + (long long)d.ny * kl);
+  const T* bx = op.b0 + B.off_f[0];
+  const T* by = op.b1 + B.off_f[1];
+  const T* bz = op.b2 + B.off_f[2];
+  const T cxl = (op.beta * bx[fx]) * op.ih0;
+  const T cxh = (op.beta * bx[fx + 1]) * op.ih0;
+  const T cyl = (op.beta * by[fy]) * op.ih1;
+  const T cyh = (op.beta * by[fy + d.nx]) * op.ih1;
+  const T czl = (op.beta * bz[fz]) * op.ih2;
+  const T czh = (op.beta * bz[fz + (long long)d.nx * d.ny]) * op.ih2;
+  const int m = B.bcmask;
+  const bool wxl = (m & 1) && il == 0, wxh = (m & 2) && il == d.nx - 1;
+  const bool wyl = (m & 4) && jl == 0, wyh = (m & 8) && jl == d.ny - 1;
+  const bool wzl = (m & 16) && kl == 0, wzh = (m & 32) && kl == d.nz - 1;
+  T diag = op.a ? op.alpha * op.a[B.off_g0 + fz] : op.alpha;
+  diag = diag + (wxl ? T(2) * cxl : cxl);
+  diag = diag + (wxh ? T(2) * cxh : cxh);
+  diag = diag + (wyl ? T(2) * cyl : cyl);
+  diag = diag + (wyh ? T(2) * cyh : cyh);
+  diag = diag + (wzl ? T(2) * czl : czl);
+  diag = diag + (wzh ? T(2) * czh : czh);
+  T off = T(0);
+  if (READ_NBR) {
+    off = wxl ? T(0) : cxl * P[pc - 1];
+    off = off + (wxh ? T(0) : cxh * P[pc + 1]);
+    off = off + (wyl ? T(0) : cyl * P[pc - sy]);
+    off = off + (wyh ? T(0) : cyh * P[pc + sy]);
+    off = off + (wzl ? T(0) : czl * P[pc - sz]);
+    off = off + (wzh ? T(0) : czh * P[pc + sz]);
+  }
+  return {diag, off};
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_gsrb(const Tile* __restrict__ tiles, StencilArgs<T> op, T* __restrict__ phi,
+           const T* __restrict__ rhs, int rhs_ng, int colour, int tz, int zero_guess) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = op.boxes[t.box];
+  const BoxDims d = dims(B);
+  const int j = t.y0 + threadIdx.y;
+  if (j > B.hi[1]) return;
+  const int jl = j - B.lo[1];
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  T* P = phi + B.off_g1;
+  const T* R = rhs + (rhs_ng ? B.off_g1 : B.off_g0);
+  for (int k = t.z0; k <= kend; ++k) {
+    const int i = t.x0 + 2 * (int)threadIdx.x + ((colour + t.x0 + j + k) & 1);
+    if (i > B.hi[0]) continue;
+    const int il = i - B.lo[0], kl = k - B.lo[2];
+    const long long pc = cidx(d, 1, il, jl, kl);
+    const T f = R[cidx(d, rhs_ng, il, jl, kl)];
+    if (zero_guess) {
+      const Cell<T> c = stencil_at<T, false>(op, B, d, P, pc, il, jl, kl);
+      P[pc] = f / c.diag;
+    } else {
+      const Cell<T> c = stencil_at<T, true>(op, B, d, P, pc, il, jl, kl);
+      P[pc] = (f + c.off) / c.diag;
+    }
+  }
+}
+
+template <typename T, typename TO>
+__global__ void __launch_bounds__(256)
+    k_residual(const Tile* __restrict__ tiles, StencilArgs<T> op, const T* __restrict__ phi,
+               const T* __restrict__ rhs, int rhs_ng, TO* __restrict__ out,
+               unsigned long long* normbits, int tz, int mode) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = op.boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x;
+  const int j = t.y0 + threadIdx.y;
+  const bool act = i <= B.hi[0] && j <= B.hi[1];
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  unsigned long long mx = 0;
+  if (act) {
+    const T* P = phi + B.off_g1;
+    const int il = i - B.lo[0], jl = j - B.lo[1];
+    for (int k = t.z0; k <= kend; ++k) {
+      const int kl = k - B.lo[2];
+      const long long pc = cidx(d, 1, il, jl, kl);
+      const Cell<T> c = stencil_at<T, true>(op, B, d, P, pc, il, jl, kl);
+      const T Aphi = c.diag * P[pc] - c.off;
+      T v;
+      if (mode == 0) {
+        v = rhs[(rhs_ng ? B.off_g1 : B.off_g0) + cidx(d, rhs_ng, il, jl, kl)] - Aphi;
+      } else {
+        v = Aphi;
+      }
+      if (out) out[B.off_g0 + cidx(d, 0, il, jl, kl)] = (TO)v;
+      const unsigned long long bits = absbits(v);
+      mx = bits > mx ? bits : mx;
+    }
+  }
+  if (normbits) block_max_u64(mx, normbits);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_maxabs(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+             const T* __restrict__ v, int ng, unsigned long long* normbits, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  unsigned long long mx = 0;
+  if (i <= B.hi[0] && j <= B.hi[1]) {
+    const int kend = min(t.z0 + tz - 1, B.hi[2]);
+    const T* V = v + (ng ? B.off_g1 : B.off_g0);
+    for (int k = t.z0; k <= kend; ++k) {
+      const unsigned long long bits =
+          absbits(V[cidx(d, ng, i - B.lo[0], j - B.lo[1], k - B.lo[2])]);
+      mx = bits > mx ? bits : mx;
+    }
+  }
+  block_max_u64(mx, normbits);
+}
+
+__device__ __forceinline__ int fdiv2(int a) { return a >= 0 ? a / 2 : -((-a + 1) / 2); }
+
+// Tiles index coarse cells of coarsen(fine box t.box).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_restrict(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ fine,
+               const BoxInfo* __restrict__ coarse, const T* __restrict__ rf,
+               T* __restrict__ rc, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo F = fine[t.box];
+  const BoxInfo C = coarse[F.parent];
+  const BoxDims df = dims(F), dc = dims(C);
+  const int I = t.x0 + threadIdx.x, J = t.y0 + threadIdx.y;
+  const int chx = fdiv2(F.hi[0]), chy = fdiv2(F.hi[1]), chz = fdiv2(F.hi[2]);
+  if (I > chx || J > chy) return;
+  const int kend = min(t.z0 + tz - 1, chz);
+  const T* R = rf + F.off_g0;
+  T* Q = rc + C.off_g0;
+  const long long sy = df.nx, sz = (long long)df.nx * df.ny;
+  for (int K = t.z0; K <= kend; ++K) {
+    const long long b = cidx(df, 0, 2 * I - F.lo[0], 2 * J - F.lo[1], 2 * K - F.lo[2]);
+    const T z0 = (R[b] + R[b + 1]) + (R[b + sy] + R[b + sy + 1]);
+    const T z1 = (R[b + sz] + R[b + sz + 1]) + (R[b + sz + sy] + R[b + sz + sy + 1]);
+    Q[cidx(dc, 0, I - C.lo[0], J - C.lo[1], K - C.lo[2])] = (z0 + z1) * T(0.125);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_prolong_add(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ fine,
+                  const BoxInfo* __restrict__ coarse, T* __restrict__ ef,
+                  const T* __restrict__ ec, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo F = fine[t.box];
+  const BoxInfo C = coarse[F.parent];
+  const BoxDims df = dims(F), dc = dims(C);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  if (i > F.hi[0] || j > F.hi[1]) return;
+  const int kend = min(t.z0 + tz - 1, F.hi[2]);
+  T* E = ef + F.off_g1;
+  const T* EC = ec + C.off_g1;
+  for (int k = t.z0; k <= kend; ++k) {
+    const long long p = cidx(df, 1, i - F.lo[0], j - F.lo[1], k - F.lo[2]);
+    E[p] += EC[cidx(dc, 1, fdiv2(i) - C.lo[0], fdiv2(j) - C.lo[1], fdiv2(k) - C.lo[2])];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_update(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+             double* __restrict__ phi, const float* __restrict__ e, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  if (i > B.hi[0] || j > B.hi[1]) return;
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  for (int k = t.z0; k <= kend; ++k) {
+    const long long p = B.off_g1 + cidx(d, 1, i - B.lo[0], j - B.lo[1], k - B.lo[2]);
+    phi[p] += (double)e[p];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_copy_valid(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+                 const double* __restrict__ src, int sng, double* __restrict__ dst, int dng,
+                 int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  if (i > B.hi[0] || j > B.hi[1]) return;
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  const double* S = src + (sng ? B.off_g1 : B.off_g0);
+  double* D = dst + (dng ? B.off_g1 : B.off_g0);
+  for (int k = t.z0; k <= kend; ++k) {
+    const int il = i - B.lo[0], jl = j - B.lo[1], kl = k - B.lo[2];
+    D[cidx(d, dng, il, jl, kl)] = S[cidx(d, sng, il, jl, kl)];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_zero_valid(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+                 T* __restrict__ v, int ng, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  if (i > B.hi[0] || j > B.hi[1]) return;
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  T* V = v + (ng ? B.off_g1 : B.off_g0);
+  for (int k = t.z0; k <= kend; ++k) V[cidx(d, ng, i - B.lo[0], j - B.lo[1], k - B.lo[2])] = T(0);
+}
+
+// Block sum in a fixed order: lanes by butterfly (every lane ends with the
+// same bits), then waves in index order.
+__device__ double block_sum(double v, double* red, int& phase) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const int nw = (blockDim.x * blockDim.y + 63) / 64;
+  double* buf = red + phase * 16;
+  phase ^= 1;
+  if ((tid & 63) == 0) buf[tid >> 6] = v;
+  __syncthreads();
+  double s = buf[0];
+  for (int w = 1; w < nw; ++w) s += buf[w];
+  return s;
+}
+
+__global__ void __launch_bounds__(256)
+    k_sum_partial(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+                  const double* __restrict__ v, double* __restrict__ partials, int tz) {
+  __shared__ double red[32];
+  int phase = 0;
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  double s = 0.0;
+  if (i <= B.hi[0] && j <= B.hi[1]) {
+    const int kend = min(t.z0 + tz - 1, B.hi[2]);
+    for (int k = t.z0; k <= kend; ++k)
+      s += v[B.off_g1 + cidx(d, 1, i - B.lo[0], j - B.lo[1], k - B.lo[2])];
+  }
+  s = block_sum(s, red, phase);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ partials, int n,
+                                                  double* __restrict__ out) {
+  __shared__ double red[32];
+  int phase = 0;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += partials[i];
+  s = block_sum(s, red, phase);
+  if (threadIdx.x == 0) *out = s;
+}
+
+__global__ void __launch_bounds__(256)
+    k_shift_valid(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+                  double* __restrict__ v, const double* __restrict__ sum, double inv_n, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  if (i > B.hi[0] || j > B.hi[1]) return;
+  const double m = *sum * inv_n;
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  for (int k = t.z0; k <= kend; ++k)
+    v[B.off_g1 + cidx(d, 1, i - B.lo[0], j - B.lo[1], k - B.lo[2])] -= m;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(FB_CHUNK)
+    k_fill_boundary(const FbTag* __restrict__ tags, const FbChunk* __restrict__ chunks,
+                    T* __restrict__ data, int ncomp) {
+  const FbChunk c = chunks[blockIdx.x];
+  const FbTag g = tags[c.tag];
+  const int l = c.start + threadIdx.x;
+  if (l >= g.ncell) return;
+  const int i = l % g.nx;
+  const int r = l / g.nx;
+  const int j = r % g.ny;
+  const int k = r / g.ny;
+  const long long dsti = g.dst_base + i + (long long)j * g.dsy + (long long)k * g.dsz;
+  const long long srci = g.src_base + i + (long long)j * g.ssy + (long long)k * g.ssz;
+  for (int comp = 0; comp < ncomp; ++comp)
+    data[dsti + comp * g.dst_cstride] = data[srci + comp * g.src_cstride];
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename TI, typename TO>
+__global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = (TO)in[i];
+}
+
+__global__ void k_scale_faces(const double* __restrict__ in, double* __restrict__ out,
+                              long long n, double v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = in ? in[i] : v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_coarsen_cell(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ fine,
+                   const BoxInfo* __restrict__ coarse, const T* __restrict__ af,
+                   T* __restrict__ ac, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo F = fine[t.box];
+  const BoxInfo C = coarse[F.parent];
+  const BoxDims df = dims(F), dc = dims(C);
+  const int I = t.x0 + threadIdx.x, J = t.y0 + threadIdx.y;
+  if (I > fdiv2(F.hi[0]) || J > fdiv2(F.hi[1])) return;
+  const int kend = min(t.z0 + tz - 1, fdiv2(F.hi[2]));
+  const T* A = af + F.off_g0;
+  const long long sy = df.nx, sz = (long long)df.nx * df.ny;
+  for (int K = t.z0; K <= kend; ++K) {
+    const long long b = cidx(df, 0, 2 * I - F.lo[0], 2 * J - F.lo[1], 2 * K - F.lo[2]);
+    const T z0 = (A[b] + A[b + 1]) + (A[b + sy] + A[b + sy + 1]);
+    const T z1 = (A[b + sz] + A[b + sz + 1]) + (A[b + sz + sy] + A[b + sz + sy + 1]);
+    ac[C.off_g0 + cidx(dc, 0, I - C.lo[0], J - C.lo[1], K - C.lo[2])] = (z0 + z1) * T(0.125);
+  }
+}
+
+// Face extents of box B along direction d: (nx + (d==0), ny + (d==1), nz + (d==2)).
+__device__ __forceinline__ void face_dims(const BoxDims& bd, int d, int& fx, int& fy, int& fz) {
+  fx = bd.nx + (d == 0);
+  fy = bd.ny + (d == 1);
+  fz = bd.nz + (d == 2);
+}
+
+// grid.y = fine box; coarse face value = mean of the 4 fine faces on it.
+__global__ void __launch_bounds__(256)
+    k_coarsen_face(const BoxInfo* __restrict__ fine, const BoxInfo* __restrict__ coarse, int d,
+                   const double* __restrict__ bf, double* __restrict__ bc) {
+  const BoxInfo F = fine[blockIdx.y];
+  const BoxInfo C = coarse[F.parent];
+  const BoxDims df = dims(F), dc = dims(C);
+  int ffx, ffy, ffz, cfx, cfy, cfz;
+  face_dims(df, d, ffx, ffy, ffz);
+  face_dims(dc, d, cfx, cfy, cfz);
+  // coarse faces lying on coarsen(F): lo/2 .. hi/2 (+1 along d)
+  const int clo[3] = {fdiv2(F.lo[0]), fdiv2(F.lo[1]), fdiv2(F.lo[2])};
+  const int nxc = df.nx / 2 + (d == 0), nyc = df.ny / 2 + (d == 1), nzc = df.nz / 2 + (d == 2);
+  const long long total = (long long)nxc * nyc * nzc;
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  const long long fst[3] = {1, ffx, (long long)ffx * ffy};
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int a = e % nxc;
+    const int b = (e / nxc) % nyc;
+    const int c = e / ((long long)nxc * nyc);
+    const int cl[3] = {a, b, c};  // relative to clo
+    int fl[3];
+    for (int q = 0; q < 3; ++q) fl[q] = 2 * (clo[q] + cl[q]) - F.lo[q];
+    const long long base = F.off_f[d] + fl[0] + fl[1] * fst[1] + fl[2] * fst[2];
+    const double p0 = bf[base], p1 = bf[base + fst[t2]];
+    const double p2 = bf[base + fst[t1]], p3 = bf[base + fst[t1] + fst[t2]];
+    const int gl[3] = {clo[0] + a - C.lo[0], clo[1] + b - C.lo[1], clo[2] + c - C.lo[2]};
+    bc[C.off_f[d] + gl[0] + (long long)gl[1] * cfx + (long long)gl[2] * cfx * cfy] =
+        ((p0 + p1) + (p2 + p3)) * 0.25;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_scatter_faces(const BoxInfo* __restrict__ boxes, int d, int3 dlo, int3 dn,
+                    const double* __restrict__ g, double* __restrict__ out, int is_log) {
+  const BoxInfo B = boxes[blockIdx.y];
+  const BoxDims bd = dims(B);
+  int fx, fy, fz;
+  face_dims(bd, d, fx, fy, fz);
+  const long long gx = dn.x + (d == 0), gy = dn.y + (d == 1);
+  const long long total = (long long)fx * fy * fz;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = e % fx, j = (e / fx) % fy, k = e / ((long long)fx * fy);
+    const long long gi = (B.lo[0] - dlo.x + i) + gx * ((B.lo[1] - dlo.y + j) + gy * (B.lo[2] - dlo.z + k));
+    const double v = g[gi];
+    out[B.off_f[d] + e] = is_log ? exp(v) : v;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_scatter_cells(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes, int3 dlo,
+                    int3 dn, const double* __restrict__ g, double* __restrict__ out, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  if (i > B.hi[0] || j > B.hi[1]) return;
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  for (int k = t.z0; k <= kend; ++k)
+    out[B.off_g0 + cidx(d, 0, i - B.lo[0], j - B.lo[1], k - B.lo[2])] =
+        g[(i - dlo.x) + (long long)dn.x * ((j - dlo.y) + (long long)dn.y * (k - dlo.z))];
+}
+
+// Adjoint gradient on the d-faces of one box (grid.y = box).  mode 0: every
+// face of the box into its face array; mode 1: global array, the box writes
+// its low faces and, on the domain's high side, its high face as well.
+__global__ void __launch_bounds__(256)
+    k_face_grad(StencilArgs<double> op, int d, const double* __restrict__ phi,
+                const double* __restrict__ lam, double* __restrict__ out, int mode, int3 dlo,
+                int3 dn, int periodic_d) {
+  const BoxInfo B = op.boxes[blockIdx.y];
+  const BoxDims bd = dims(B);
+  int fx, fy, fz;
+  face_dims(bd, d, fx, fy, fz);
+  const long long total = (long long)fx * fy * fz;
+  const double* bf = d == 0 ? op.b0 : (d == 1 ? op.b1 : op.b2);
+  const double ih = d == 0 ? op.ih0 : (d == 1 ? op.ih1 : op.ih2);
+  const int nd = d == 0 ? bd.nx : (d == 1 ? bd.ny : bd.nz);
+  const int dom_n = d == 0 ? dn.x : (d == 1 ? dn.y : dn.z);
+  const int dom_lo = d == 0 ? dlo.x : (d == 1 ? dlo.y : dlo.z);
+  const int lo_d = B.lo[d];
+  const bool wall_lo = (B.bcmask >> (2 * d)) & 1, wall_hi = (B.bcmask >> (2 * d + 1)) & 1;
+  const long long sy = bd.nx + 2, sz = (long long)(bd.nx + 2) * (bd.ny + 2);
+  const long long step = d == 0 ? 1 : (d == 1 ? sy : sz);
+  const double* P = phi + B.off_g1;
+  const double* L = lam + B.off_g1;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    int f[3];
+    f[0] = e % fx;
+    f[1] = (e / fx) % fy;
+    f[2] = e / ((long long)fx * fy);
+    const int fl = f[d];  // face index along d, 0..nd
+    if (mode == 1 && fl == nd && !(lo_d + nd - dom_lo == dom_n)) continue;
+    // cell on the high side of the face (local), possibly the ghost at nd
+    const long long ph = (f[0] + 1) + sy * (f[1] + 1) + sz * (f[2] + 1);
+    const long long pl = ph - step;
+    const double c = (op.beta * bf[B.off_f[d] + e]) * ih;
+    double g;
+    if (fl == 0 && wall_lo) {
+      g = -2.0 * c * P[ph] * L[ph];
+    } else if (fl == nd && wall_hi) {
+      g = -2.0 * c * P[pl] * L[pl];
+    } else {
+      g = -c * (P[ph] - P[pl]) * (L[ph] - L[pl]);
+    }
+    if (mode == 0) {
+      out[B.off_f[d] + e] = g;
+    } else {
+      int gi[3] = {B.lo[0] - dlo.x + f[0], B.lo[1] - dlo.y + f[1], B.lo[2] - dlo.z + f[2]};
+      const long long gx = dn.x + (d == 0), gy = dn.y + (d == 1);
+      out[gi[0] + gx * (gi[1] + gy * (long long)gi[2])] = g;
+      if (periodic_d && gi[d] == 0) {
+        gi[d] = dom_n;
+        out[gi[0] + gx * (gi[1] + gy * (long long)gi[2])] = g;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_bottom_setup(BottomTables bt, StencilArgs<T> op, T* __restrict__ diag,
+                               T* __restrict__ coef) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= bt.n) return;
+  const T* bs[3] = {op.b0, op.b1, op.b2};
+  const T ih[3] = {op.ih0, op.ih1, op.ih2};
+  T dg = op.a ? op.alpha * op.a[bt.aidx[c]] : op.alpha;
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1;
+    const T cf = (op.beta * bs[d][bt.fidx[f * bt.n + c]]) * ih[d];
+    const bool wall = bt.nbr[f * bt.n + c] < 0;
+    dg = dg + (wall ? T(2) * cf : cf);
+    coef[f * bt.n + c] = wall ? T(0) : cf;
+  }
+  diag[c] = dg;
+}
+
+// One work-group of 1024 lanes runs the whole CG; lane l owns cells
+// l, l+1024, ...  Vectors x, r, q and the search direction p live in the
+// workspace (L2-resident at bottom sizes); every phase that reads another
+// lane's p is separated by a barrier.  Dot products accumulate in double.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_bottom_cg(BottomTables bt, const T* __restrict__ diag, const T* __restrict__ coef,
+                const T* __restrict__ rhs, T* __restrict__ out, int accumulate, T* work,
+                double tol, int maxiter, int singular, int* iters_out) {
+  __shared__ double red[32];
+  int phase = 0;
+  const int n = bt.n;
+  T* x = work;
+  T* r = work + n;
+  T* p = work + 2 * (long long)n;
+  T* q = work + 3 * (long long)n;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double s = 0.0;
+  for (int c = tid; c < n; c += nt) {
+    const T v = rhs[bt.map_rhs[c]];
+    r[c] = v;
+    x[c] = T(0);
+    s += (double)v;
+  }
+  if (singular) {
+    s = block_sum(s, red, phase);
+    const T m = (T)(s / n);
+    for (int c = tid; c < n; c += nt) r[c] = r[c] - m;
+  }
+  s = 0.0;
+  for (int c = tid; c < n; c += nt) s += (double)r[c] * (double)r[c];
+  double rho = block_sum(s, red, phase);
+  const double bnorm = sqrt(rho);
+  int it = 0;
+  if (bnorm > 0.0) {
+    for (int c = tid; c < n; c += nt) p[c] = r[c];
+    while (it < maxiter) {
+      __syncthreads();
+      s = 0.0;
+      for (int c = tid; c < n; c += nt) {
+        T off = T(0);
+        for (int f = 0; f < 6; ++f) {
+          const int nb = bt.nbr[f * n + c];
+          off = off + (nb < 0 ? T(0) : coef[f * n + c] * p[nb]);
+        }
+        const T qv = diag[c] * p[c] - off;
+        q[c] = qv;
+        s += (double)p[c] * (double)qv;
+      }
+      const double pq = block_sum(s, red, phase);
+      const double al = rho / pq;
+      const T alT = (T)al;
+      s = 0.0;
+      for (int c = tid; c < n; c += nt) {
+        x[c] = x[c] + alT * p[c];
+        const T rv = r[c] - alT * q[c];
+        r[c] = rv;
+        s += (double)rv * (double)rv;
+      }
+      ++it;
+      const double rho_new = block_sum(s, red, phase);
+      if (!(sqrt(rho_new) > tol * bnorm)) break;
+      const T btT = (T)(rho_new / rho);
+      // p is read by other lanes in the next product: barrier before rewriting
+      __syncthreads();
+      for (int c = tid; c < n; c += nt) p[c] = r[c] + btT * p[c];
+      rho = rho_new;
+    }
+  }
+  if (singular) {
+    s = 0.0;
+    for (int c = tid; c < n; c += nt) s += (double)x[c];
+    s = block_sum(s, red, phase);
+    const T m = (T)(s / n);
+    for (int c = tid; c < n; c += nt) x[c] = x[c] - m;
+  }
+  for (int c = tid; c < n; c += nt) {
+    const long long o = bt.map_out[c];
+    out[o] = accumulate ? out[o] + x[c] : x[c];
+  }
+  if (tid == 0) *iters_out = it;
+}
+
+inline dim3 block_of(Shape sh) { return dim3(sh.lx, sh.ly, 1); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                       const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng, int colour,
+                       int zero_guess) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gsrb<T>, dim3(ntiles), block_of(sh), 0, st, tiles, op, phi, rhs, rhs_ng,
+                     colour, sh.tz, zero_guess);
+  return hipGetLastError();
+}
+
+template <typename T, typename TO>
+hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                           const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
+                           TO* out, unsigned long long* normbits, int mode) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_residual<T, TO>), dim3(ntiles), block_of(sh), 0, st, tiles, op, phi, rhs,
+                     rhs_ng, out, normbits, sh.tz, mode);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_maxabs(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                         const BoxInfo* boxes, const T* v, int ng, unsigned long long* normbits) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_maxabs<T>, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, v, ng,
+                     normbits, sh.tz);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                           const BoxInfo* fine, const BoxInfo* coarse, const T* rf, T* rc) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_restrict<T>, dim3(ntiles), block_of(sh), 0, st, tiles, fine, coarse, rf,
+                     rc, sh.tz);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_add(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                              const BoxInfo* fine, const BoxInfo* coarse, T* ef, const T* ec) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prolong_add<T>, dim3(ntiles), block_of(sh), 0, st, tiles, fine, coarse, ef,
+                     ec, sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                         const BoxInfo* boxes, double* phi, const float* e) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, phi, e, sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                             const BoxInfo* boxes, const double* src, int src_ng, double* dst,
+                             int dst_ng) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_valid, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, src, src_ng,
+                     dst, dst_ng, sh.tz);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zero_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                             const BoxInfo* boxes, T* v, int ng) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_valid<T>, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, v, ng,
+                     sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                            const BoxInfo* boxes, const double* v, double* partials,
+                            double* sum) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_partial, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, v, partials,
+                     sh.tz);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partials, ntiles, sum);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                              const BoxInfo* boxes, double* v, const double* sum,
+                              long long ncell) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shift_valid, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, v, sum,
+                     1.0 / (double)ncell, sh.tz);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_boundary(hipStream_t st, const FbTag* tags, const FbChunk* chunks,
+                                int nchunks, T* data, int ncomp) {
+  if (nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_boundary<T>, dim3(nchunks), dim3(FB_CHUNK), 0, st, tags, chunks, data,
+                     ncomp);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(hipStream_t st, unsigned long long* p, int n, unsigned long long v) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3((n + 63) / 64), dim3(64), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+static inline int grid_for(long long n) {
+  long long g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <typename TI, typename TO>
+hipError_t launch_convert(hipStream_t st, const TI* in, TO* out, long long n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_convert<TI, TO>), dim3(grid_for(n)), dim3(256), 0, st, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_faces(hipStream_t st, const double* in, double* out, long long n,
+                              double v) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_faces, dim3(grid_for(n)), dim3(256), 0, st, in, out, n, v);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarsen_cell(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                               const BoxInfo* fine, const BoxInfo* coarse, const T* af, T* ac) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coarsen_cell<T>, dim3(ntiles), block_of(sh), 0, st, tiles, fine, coarse,
+                     af, ac, sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarsen_face(hipStream_t st, const BoxInfo* fine, int nbox_fine,
+                               const BoxInfo* coarse, int d, const double* bf, double* bc,
+                               int max_faces_per_box) {
+  if (nbox_fine <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coarsen_face, dim3(grid_for(max_faces_per_box), nbox_fine), dim3(256), 0,
+                     st, fine, coarse, d, bf, bc);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_faces(hipStream_t st, const BoxInfo* boxes, int nbox, int d,
+                                const int dom_lo[3], const int dom_n[3], const double* g,
+                                double* out, int is_log, int max_faces_per_box) {
+  if (nbox <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_faces, dim3(grid_for(max_faces_per_box), nbox), dim3(256), 0, st,
+                     boxes, d, make_int3(dom_lo[0], dom_lo[1], dom_lo[2]),
+                     make_int3(dom_n[0], dom_n[1], dom_n[2]), g, out, is_log);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_cells(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                                const BoxInfo* boxes, const int dom_lo[3], const int dom_n[3],
+                                const double* g, double* out) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_cells, dim3(ntiles), block_of(sh), 0, st, tiles, boxes,
+                     make_int3(dom_lo[0], dom_lo[1], dom_lo[2]),
+                     make_int3(dom_n[0], dom_n[1], dom_n[2]), g, out, sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_grad(hipStream_t st, const BoxInfo* boxes, int nbox, int d,
+                            const StencilArgs<double>& op, const double* phi, const double* lam,
+                            double* out, int mode, const int dom_lo[3], const int dom_n[3],
+                            int periodic_d, int max_faces_per_box) {
+  if (nbox <= 0) return hipSuccess;
+  (void)boxes;
+  hipLaunchKernelGGL(k_face_grad, dim3(grid_for(max_faces_per_box), nbox), dim3(256), 0, st, op, d,
+                     phi, lam, out, mode, make_int3(dom_lo[0], dom_lo[1], dom_lo[2]),
+                     make_int3(dom_n[0], dom_n[1], dom_n[2]), periodic_d);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bottom_setup(hipStream_t st, const BottomTables& bt, const StencilArgs<T>& op,
+                               T* diag, T* coef) {
+  if (bt.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bottom_setup<T>, dim3((bt.n + 255) / 256), dim3(256), 0, st, bt, op, diag,
+                     coef);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* diag, const T* coef,
+                            const T* rhs, T* out, int accumulate, T* work, double tol,
+                            int maxiter, int singular, int* iters_out) {
+  if (bt.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bottom_cg<T>, dim3(1), dim3(1024), 0, st, bt, diag, coef, rhs, out,
+                     accumulate, work, tol, maxiter, singular, iters_out);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                  \
+  template hipError_t launch_gsrb<T>(hipStream_t, const Tile*, int, Shape, const StencilArgs<T>&, \
+                                     T*, const T*, int, int, int);                               \
+  template hipError_t launch_maxabs<T>(hipStream_t, const Tile*, int, Shape, const BoxInfo*,     \
+                                       const T*, int, unsigned long long*);                      \
+  template hipError_t launch_restrict<T>(hipStream_t, const Tile*, int, Shape, const BoxInfo*,   \
+                                         const BoxInfo*, const T*, T*);                          \
+  template hipError_t launch_prolong_add<T>(hipStream_t, const Tile*, int, Shape,                \
+                                            const BoxInfo*, const BoxInfo*, T*, const T*);       \
+  template hipError_t launch_zero_valid<T>(hipStream_t, const Tile*, int, Shape, const BoxInfo*, \
+                                           T*, int);                                             \
+  template hipError_t launch_fill_boundary<T>(hipStream_t, const FbTag*, const FbChunk*, int, T*, \
+                                              int);                                              \
+  template hipError_t launch_coarsen_cell<T>(hipStream_t, const Tile*, int, Shape,               \
+                                             const BoxInfo*, const BoxInfo*, const T*, T*);      \
+  template hipError_t launch_bottom_setup<T>(hipStream_t, const BottomTables&,                   \
+                                             const StencilArgs<T>&, T*, T*);                     \
+  template hipError_t launch_bottom_cg<T>(hipStream_t, const BottomTables&, const T*, const T*,  \
+                                          const T*, T*, int, T*, double, int, int, int*);
+
+INST(double)
+INST(float)
+#undef INST
+
+template hipError_t launch_residual<double, double>(hipStream_t, const Tile*, int, Shape,
+                                                    const StencilArgs<double>&, const double*,
+                                                    const double*, int, double*,
+                                                    unsigned long long*, int);
+template hipError_t launch_residual<double, float>(hipStream_t, const Tile*, int, Shape,
+                                                   const StencilArgs<double>&, const double*,
+                                                   const double*, int, float*,
+                                                   unsigned long long*, int);
+template hipError_t launch_residual<float, float>(hipStream_t, const Tile*, int, Shape,
+                                                  const StencilArgs<float>&, const float*,
+                                                  const float*, int, float*,
+                                                  unsigned long long*, int);
+template hipError_t launch_convert<double, float>(hipStream_t, const double*, float*, long long);
+template hipError_t launch_convert<float, double>(hipStream_t, const float*, double*, long long);
+
+}  // namespace amrmg

@@ -1,0 +1,140 @@
+// Launchers of the gfx950 kernels.  Every launcher enqueues on the given
+// stream and returns the launch status; none synchronises.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "tables.hpp"
+
+namespace amrmg {
+
+// The operator's data on one level: box table and coefficients.  The face
+// coefficient of the operator is c_f = (beta * b_f) * inv_h2[d].
+template <typename T>
+struct StencilArgs {
+  const BoxInfo* boxes;
+  const T* a;   // cell coefficient (ghost-free layout) or null for a = 1
+  const T* b0;  // face coefficients, ghost-free face layouts
+  const T* b1;
+  const T* b2;
+  T alpha, beta;
+  T ih0, ih1, ih2;  // 1 / h_d^2
+};
+
+// Launch shape of a tiled kernel: block (lx, ly), each block marching tz planes.
+struct Shape {
+  int lx, ly, tz;
+};
+
+// Red/black Gauss-Seidel half-sweep over every box: lane (x, y) of a block
+// updates the cell of colour `colour` among tile cells x0+2x, x0+2x+1 on row
+// y0+y, marching z over tz planes.  zero_guess: phi is taken as 0 (nothing
+// but rhs is read).  rhs_ng: 0 or 1.
+template <typename T>
+hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                       const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng, int colour,
+                       int zero_guess);
+
+// out = rhs - A phi (mode 0) or out = A phi (mode 1) on every valid cell, one
+// lane per cell; out may be null (norm only).  When normbits is non-null the
+// max |out| is folded into *normbits as IEEE-754 bits (NaN-propagating).
+// out uses the ghost-free layout; TO may be narrower than T (the value is
+// computed in T and rounded once).
+template <typename T, typename TO>
+hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                           const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
+                           TO* out, unsigned long long* normbits, int mode);
+
+// max |v| over valid cells folded into *normbits (v: ng 0 or 1 layout).
+template <typename T>
+hipError_t launch_maxabs(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                         const BoxInfo* boxes, const T* v, int ng, unsigned long long* normbits);
+
+// Coarse value = mean of the 8 children (pairwise sum).  Tiles cover the
+// coarse cells of each fine box; fine r is ghost-free, coarse rhs ghost-free.
+template <typename T>
+hipError_t launch_restrict(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                           const BoxInfo* fine, const BoxInfo* coarse, const T* rf, T* rc);
+
+// Fine valid cell += parent coarse value; both with one ghost layer.
+template <typename T>
+hipError_t launch_prolong_add(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                              const BoxInfo* fine, const BoxInfo* coarse, T* ef, const T* ec);
+
+// phi (double, ng 1) += e (float, ng 1) on valid cells.
+hipError_t launch_update(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                         const BoxInfo* boxes, double* phi, const float* e);
+
+// dst = src on valid cells (layouts with ng 0 or 1).
+hipError_t launch_copy_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                             const BoxInfo* boxes, const double* src, int src_ng, double* dst,
+                             int dst_ng);
+
+// v = 0 on valid cells (layout ng).
+template <typename T>
+hipError_t launch_zero_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                             const BoxInfo* boxes, T* v, int ng);
+
+// Deterministic sum of v (ng 1) over valid cells: one partial per tile into
+// partials[ntiles], then one work-group adds them in order into *sum.  Then
+// v -= *sum / ncell on valid cells.
+hipError_t launch_sum_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                            const BoxInfo* boxes, const double* v, double* partials,
+                            double* sum);
+hipError_t launch_shift_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                              const BoxInfo* boxes, double* v, const double* sum,
+                              long long ncell);
+
+// Ghost exchange: every chunk copies FB_CHUNK cells of one tag, ncomp comps.
+template <typename T>
+hipError_t launch_fill_boundary(hipStream_t st, const FbTag* tags, const FbChunk* chunks,
+                                int nchunks, T* data, int ncomp);
+
+// Plain element-wise helpers over n elements.
+hipError_t launch_fill_u64(hipStream_t st, unsigned long long* p, int n, unsigned long long v);
+template <typename TI, typename TO>
+hipError_t launch_convert(hipStream_t st, const TI* in, TO* out, long long n);
+hipError_t launch_scale_faces(hipStream_t st, const double* in, double* out, long long n,
+                              double v_if_null);
+
+// Level coefficients from a coarser copy of the next finer level.
+template <typename T>
+hipError_t launch_coarsen_cell(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                               const BoxInfo* fine, const BoxInfo* coarse, const T* af, T* ac);
+hipError_t launch_coarsen_face(hipStream_t st, const BoxInfo* fine, int nbox_fine,
+                               const BoxInfo* coarse, int d, const double* bf, double* bc,
+                               int max_faces_per_box);
+
+// Global face / cell arrays (x fastest over the domain) -> per-box arrays.
+hipError_t launch_scatter_faces(hipStream_t st, const BoxInfo* boxes, int nbox, int d,
+                                const int dom_lo[3], const int dom_n[3], const double* g,
+                                double* out, int is_log, int max_faces_per_box);
+hipError_t launch_scatter_cells(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                                const BoxInfo* boxes, const int dom_lo[3], const int dom_n[3],
+                                const double* g, double* out);
+
+// Adjoint face gradient: per box face array (mode 0) or global face array
+// (mode 1, each physical face once).
+hipError_t launch_face_grad(hipStream_t st, const BoxInfo* boxes, int nbox, int d,
+                            const StencilArgs<double>& op, const double* phi, const double* lam,
+                            double* out, int mode, const int dom_lo[3], const int dom_n[3],
+                            int periodic_d, int max_faces_per_box);
+
+// Bottom solve: CG on a gathered copy of the bottom level (one work-group).
+struct BottomTables {
+  int n;                 // cells
+  const int* nbr;        // [6*n] neighbour cell or -1 (wall), face-major
+  const int* fidx;       // [6*n] element index of the face in the level's b_d
+  const int* aidx;       // [n] element index of the cell in the level's a (ng 0)
+  const int* map_rhs;    // [n] element index in the rhs MultiFab (ng 0)
+  const int* map_out;    // [n] element index in the output MultiFab (ng 1)
+};
+template <typename T>
+hipError_t launch_bottom_setup(hipStream_t st, const BottomTables& bt, const StencilArgs<T>& op,
+                               T* diag, T* coef);
+template <typename T>
+hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* diag, const T* coef,
+                            const T* rhs, T* out, int accumulate, T* work, double tol,
+                            int maxiter, int singular, int* iters_out);
+
+}  // namespace amrmg

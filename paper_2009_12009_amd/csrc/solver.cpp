@@ -1,0 +1,1405 @@
+// Multigrid driver behind the C ABI: hierarchy and table construction,
+// workspace layout, the V-cycle schedule and the solve loop.
+//
+// Schedule of one V-cycle ("Linear Solvers": geometric multigrid with a CG
+// bottom solve).  Level 0 works on the caller's phi in place:
+//   nu1 x [exchange, red, exchange, black]; exchange; r = f - A phi;
+//   rhs_1 = R r; coarse levels; phi += P e_1; nu2 x [exchange, red, ...]
+// A coarse level l solves for a correction e_l from a zero guess (so its
+// first red half-sweep reads nothing but rhs_l); the bottom level runs CG.
+// The coarse part uses only workspace pointers, so it is captured once into
+// a HIP graph and replayed every cycle.  The stop test reads one max-norm
+// per cycle back to the host.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/amrmg.h"
+#include "host.hpp"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+using namespace amrmg;
+
+namespace {
+
+#define HIPTRY(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      set_error(std::string("HIP error in ") + #expr + ": " + hipGetErrorString(e_)); \
+      return MG_ERR_HIP;                                                              \
+    }                                                                                 \
+  } while (0)
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+IBox to_ibox(const mg_box_t& b) {
+  IBox r;
+  for (int d = 0; d < 3; ++d) { r.lo[d] = b.lo[d]; r.hi[d] = b.hi[d]; }
+  return r;
+}
+
+int pow2ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+int64_t grown_volume(const IBox& b, int ng, int face_d) {
+  int64_t v = 1;
+  for (int d = 0; d < 3; ++d) v *= ext(b, d) + 2 * ng + (d == face_d ? 1 : 0);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace: a bump allocator with 256-byte alignment.  The same code runs in
+// "measure" mode (base = null) for mg_query_workspace.
+struct Bump {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct Level {
+  std::vector<IBox> boxes;
+  IBox domain;
+  bool merged = false;
+  int nbox = 0;
+  double h[3];
+  int64_t ncell = 0, n_g1 = 0, n_g0 = 0, n_f[3] = {0, 0, 0};
+  int max_faces = 0;
+  std::vector<BoxInfo> info;
+  // tile tables (host) and shapes
+  std::vector<Tile> t_gsrb, t_cell, t_rst;
+  Shape s_gsrb{32, 8, 16}, s_cell{64, 4, 16}, s_rst{64, 4, 16};
+  size_t cap_gsrb = 0, cap_cell = 0;  // tile slots reserved in the workspace
+  std::vector<FbTag> tags;
+  std::vector<FbChunk> chunks;
+  // device
+  BoxInfo* d_info = nullptr;
+  Tile *d_gsrb = nullptr, *d_cell = nullptr, *d_rst = nullptr;
+  FbTag* d_tags = nullptr;
+  FbChunk* d_chunks = nullptr;
+  double *b64[3] = {nullptr, nullptr, nullptr}, *a64 = nullptr;
+  double *e64 = nullptr, *rhs64 = nullptr, *r64 = nullptr;
+  float *b32[3] = {nullptr, nullptr, nullptr}, *a32 = nullptr;
+  float *e32 = nullptr, *rhs32 = nullptr, *r32 = nullptr;
+};
+
+struct ProfRec {
+  int fam;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct mg_solver {
+  mg_opts_t opts;
+  IBox domain;
+  int periodic[3];
+  int bc_lo[3], bc_hi[3];
+  double alpha, beta;
+  bool has_a = false;
+  bool singular = false;
+  std::vector<Level> L;
+  // bottom
+  int nb = 0;
+  std::vector<int> h_nbr, h_fidx, h_aidx, h_map_rhs, h_map_out;
+  int *d_nbr = nullptr, *d_fidx = nullptr, *d_aidx = nullptr, *d_map_rhs = nullptr,
+      *d_map_out = nullptr;
+  double *bdiag64 = nullptr, *bcoef64 = nullptr, *bwork64 = nullptr;
+  float *bdiag32 = nullptr, *bcoef32 = nullptr, *bwork32 = nullptr;
+  // scratch
+  unsigned long long* d_norm = nullptr;  // [4]
+  int* d_iters = nullptr;
+  double* d_sum = nullptr;
+  double* d_partials = nullptr;
+  double* tune_scratch = nullptr;
+  // runtime
+  char* ws = nullptr;
+  size_t ws_bytes = 0, ws_need = 0;
+  hipStream_t user = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
+  unsigned long long* h_norm = nullptr;  // pinned
+  int* h_iters = nullptr;
+  bool profile = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  double setup_ms = 0;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Plan construction (host only).
+
+void make_tiles(const std::vector<BoxInfo>& info, Shape sh, int tx, bool coarse_of_box,
+                std::vector<Tile>& out) {
+  out.clear();
+  for (int b = 0; b < (int)info.size(); ++b) {
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = coarse_of_box ? floordiv(info[b].lo[d], 2) : info[b].lo[d];
+      hi[d] = coarse_of_box ? floordiv(info[b].hi[d], 2) : info[b].hi[d];
+    }
+    for (int z = lo[2]; z <= hi[2]; z += sh.tz)
+      for (int y = lo[1]; y <= hi[1]; y += sh.ly)
+        for (int x = lo[0]; x <= hi[0]; x += tx) out.push_back({b, x, y, z});
+  }
+  // Work-groups go to the 8 XCDs round robin (block i -> XCD i % 8); place
+  // contiguous runs of tiles on one XCD so neighbouring tiles share its L2.
+  const size_t n = out.size(), q = n / 8;
+  if (q > 0) {
+    std::vector<Tile> perm(out);
+    for (size_t p = 0; p < 8 * q; ++p) perm[p] = out[(p % 8) * q + p / 8];
+    out.swap(perm);
+  }
+}
+
+Shape shape_gsrb(int nx, int ny, int nz) {
+  int lx = std::min(32, std::max(1, pow2ceil((nx + 1) / 2)));
+  int ly = std::min(256 / lx, pow2ceil(ny));
+  while (lx * ly < 64) ly *= 2;
+  return {lx, ly, std::min(16, nz)};
+}
+Shape shape_cell(int nx, int ny, int nz) {
+  int lx = std::min(64, pow2ceil(nx));
+  int ly = std::min(256 / lx, pow2ceil(ny));
+  while (lx * ly < 64) ly *= 2;
+  return {lx, ly, std::min(16, nz)};
+}
+
+void build_fb(Level& lv, const int periodic[3], int ng) {
+  std::vector<int64_t> offs(lv.nbox);
+  for (int b = 0; b < lv.nbox; ++b) offs[b] = lv.info[b].off_g1;
+  make_fb_tables(lv.boxes, lv.domain, periodic, ng, offs, 1, lv.tags, lv.chunks);
+}
+
+void fill_info(Level& lv, const IBox& domain, const int periodic[3]) {
+  lv.nbox = (int)lv.boxes.size();
+  lv.info.resize(lv.nbox);
+  int64_t o1 = 0, o0 = 0, of[3] = {0, 0, 0};
+  lv.max_faces = 0;
+  for (int b = 0; b < lv.nbox; ++b) {
+    BoxInfo& I = lv.info[b];
+    const IBox& B = lv.boxes[b];
+    int m = 0;
+    for (int d = 0; d < 3; ++d) {
+      I.lo[d] = B.lo[d];
+      I.hi[d] = B.hi[d];
+      if (!periodic[d] && B.lo[d] == domain.lo[d]) m |= 1 << (2 * d);
+      if (!periodic[d] && B.hi[d] == domain.hi[d]) m |= 1 << (2 * d + 1);
+    }
+    I.bcmask = m;
+    I.parent = b;
+    I.off_g1 = o1;
+    I.off_g0 = o0;
+    o1 += grown_volume(B, 1, -1);
+    o0 += volume(B);
+    for (int d = 0; d < 3; ++d) {
+      I.off_f[d] = of[d];
+      const int64_t nf = grown_volume(B, 0, d);
+      of[d] += nf;
+      lv.max_faces = std::max<int64_t>(lv.max_faces, nf);
+    }
+  }
+  lv.ncell = o0;
+  lv.n_g1 = o1;
+  lv.n_g0 = o0;
+  for (int d = 0; d < 3; ++d) lv.n_f[d] = of[d];
+}
+
+bool shape_ok(Shape sh) {
+  const int t = sh.lx * sh.ly;
+  return sh.lx >= 1 && sh.ly >= 1 && sh.tz >= 1 && t >= 64 && t <= 256 && t % 64 == 0;
+}
+
+// Tile shapes the tuner times for the level-0 smoother and residual.
+std::vector<Shape> gsrb_candidates() {
+  std::vector<Shape> c;
+  for (int lx : {16, 32, 64})
+    for (int ly : {1, 2, 4, 8, 16})
+      for (int tz : {4, 8, 16, 32, 64})
+        if (shape_ok({lx, ly, tz})) c.push_back({lx, ly, tz});
+  return c;
+}
+std::vector<Shape> cell_candidates() {
+  std::vector<Shape> c;
+  for (int lx : {32, 64, 128})
+    for (int ly : {1, 2, 4, 8})
+      for (int tz : {4, 8, 16, 32, 64})
+        if (shape_ok({lx, ly, tz})) c.push_back({lx, ly, tz});
+  return c;
+}
+
+size_t tile_count(const std::vector<BoxInfo>& info, Shape sh, int tx) {
+  size_t n = 0;
+  for (const BoxInfo& b : info) {
+    const size_t nx = (b.hi[0] - b.lo[0] + tx) / tx;
+    const size_t ny = (b.hi[1] - b.lo[1] + sh.ly) / sh.ly;
+    const size_t nz = (b.hi[2] - b.lo[2] + sh.tz) / sh.tz;
+    n += nx * ny * nz;
+  }
+  return n;
+}
+
+// Builds every host table; with a Bump in measure mode it also lays out the
+// workspace.  Returns 0 or an error code.
+int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
+  std::string err;
+  if (!validate_boxes(boxes, s->domain, true, &err)) return fail(MG_ERR_INVALID_BOXARRAY, err);
+  std::vector<LevelBoxes> hb =
+      hierarchy(boxes, s->domain, s->opts.min_bottom_edge, s->opts.aggregate != 0);
+  s->L.clear();
+  s->L.resize(hb.size());
+  const int n[3] = {ext(s->domain, 0), ext(s->domain, 1), ext(s->domain, 2)};
+  for (size_t l = 0; l < hb.size(); ++l) {
+    Level& lv = s->L[l];
+    lv.boxes = hb[l].boxes;
+    lv.domain = hb[l].domain;
+    lv.merged = hb[l].merged;
+    for (int d = 0; d < 3; ++d) lv.h[d] = 0;  // set by caller from geometry
+    fill_info(lv, lv.domain, s->periodic);
+    int mx[3] = {1, 1, 1};
+    for (const IBox& b : lv.boxes)
+      for (int d = 0; d < 3; ++d) mx[d] = std::max(mx[d], ext(b, d));
+    lv.s_gsrb = shape_gsrb(mx[0], mx[1], mx[2]);
+    lv.s_cell = shape_cell(mx[0], mx[1], mx[2]);
+    lv.s_rst = shape_cell(std::max(1, mx[0] / 2), std::max(1, mx[1] / 2), std::max(1, mx[2] / 2));
+    make_tiles(lv.info, lv.s_gsrb, 2 * lv.s_gsrb.lx, false, lv.t_gsrb);
+    make_tiles(lv.info, lv.s_cell, lv.s_cell.lx, false, lv.t_cell);
+    if (l + 1 < hb.size()) make_tiles(lv.info, lv.s_rst, lv.s_rst.lx, true, lv.t_rst);
+    build_fb(lv, s->periodic, 1);
+    lv.cap_gsrb = lv.t_gsrb.size();
+    lv.cap_cell = lv.t_cell.size();
+    if (l == 0) {
+      for (Shape c : gsrb_candidates())
+        lv.cap_gsrb = std::max(lv.cap_gsrb, tile_count(lv.info, c, 2 * c.lx));
+      for (Shape c : cell_candidates())
+        lv.cap_cell = std::max(lv.cap_cell, tile_count(lv.info, c, c.lx));
+    }
+  }
+  (void)n;
+  // parent links: box b of level l -> box of level l+1 holding coarsen(b)
+  for (size_t l = 0; l + 1 < s->L.size(); ++l)
+    for (int b = 0; b < s->L[l].nbox; ++b) s->L[l].info[b].parent = s->L[l + 1].merged ? 0 : b;
+
+  // bottom tables: cells of the bottom level enumerated box by box, x fastest
+  Level& bl = s->L.back();
+  s->nb = (int)bl.ncell;
+  const int nb = s->nb;
+  s->h_nbr.assign(6 * (size_t)nb, -1);
+  s->h_fidx.assign(6 * (size_t)nb, 0);
+  s->h_aidx.assign(nb, 0);
+  s->h_map_rhs.assign(nb, 0);
+  s->h_map_out.assign(nb, 0);
+  {
+    const IBox& D = bl.domain;
+    const int gn[3] = {ext(D, 0), ext(D, 1), ext(D, 2)};
+    std::vector<int> gmap((size_t)gn[0] * gn[1] * gn[2], -1);
+    int c = 0;
+    for (int b = 0; b < bl.nbox; ++b) {
+      const IBox& B = bl.boxes[b];
+      for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+        for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+          for (int i = B.lo[0]; i <= B.hi[0]; ++i)
+            gmap[(i - D.lo[0]) + (size_t)gn[0] * ((j - D.lo[1]) + (size_t)gn[1] * (k - D.lo[2]))] =
+                c++;
+    }
+    c = 0;
+    for (int b = 0; b < bl.nbox; ++b) {
+      const IBox& B = bl.boxes[b];
+      const BoxInfo& I = bl.info[b];
+      const int nx = ext(B, 0), ny = ext(B, 1);
+      for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+        for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+          for (int i = B.lo[0]; i <= B.hi[0]; ++i, ++c) {
+            const int il = i - B.lo[0], jl = j - B.lo[1], kl = k - B.lo[2];
+            const int64_t g0 = il + (int64_t)nx * (jl + (int64_t)ny * kl);
+            s->h_aidx[c] = (int)(I.off_g0 + g0);
+            s->h_map_rhs[c] = (int)(I.off_g0 + g0);
+            s->h_map_out[c] =
+                (int)(I.off_g1 + (il + 1) + (int64_t)(nx + 2) * ((jl + 1) + (int64_t)(ny + 2) * (kl + 1)));
+            const int p[3] = {i, j, k};
+            const int loc[3] = {il, jl, kl};
+            for (int f = 0; f < 6; ++f) {
+              const int d = f >> 1, side = f & 1;
+              // face element index in b_d of this box
+              int fl[3] = {loc[0], loc[1], loc[2]};
+              fl[d] += side;
+              const int fnx = nx + (d == 0), fny = ny + (d == 1);
+              s->h_fidx[(size_t)f * nb + c] =
+                  (int)(I.off_f[d] + fl[0] + (int64_t)fnx * (fl[1] + (int64_t)fny * fl[2]));
+              int q[3] = {p[0], p[1], p[2]};
+              q[d] += side ? 1 : -1;
+              if (q[d] < D.lo[d] || q[d] > D.hi[d]) {
+                if (!s->periodic[d]) continue;  // wall: -1
+                q[d] = q[d] < D.lo[d] ? D.hi[d] : D.lo[d];
+              }
+              s->h_nbr[(size_t)f * nb + c] =
+                  gmap[(q[0] - D.lo[0]) + (size_t)gn[0] * ((q[1] - D.lo[1]) + (size_t)gn[1] * (q[2] - D.lo[2]))];
+            }
+          }
+    }
+  }
+
+  // workspace layout
+  const bool f32 = s->opts.precision == MG_PREC_F32_REFINE;
+  const size_t nlev = s->L.size();
+  for (size_t l = 0; l < nlev; ++l) {
+    Level& lv = s->L[l];
+    lv.d_info = bump.take<BoxInfo>(lv.info.size());
+    lv.d_gsrb = bump.take<Tile>(lv.cap_gsrb);
+    lv.d_cell = bump.take<Tile>(lv.cap_cell);
+    lv.d_rst = bump.take<Tile>(lv.t_rst.size());
+    lv.d_tags = bump.take<FbTag>(lv.tags.size());
+    lv.d_chunks = bump.take<FbChunk>(lv.chunks.size());
+    for (int d = 0; d < 3; ++d) lv.b64[d] = bump.take<double>(lv.n_f[d]);
+    if (s->has_a) lv.a64 = bump.take<double>(lv.n_g0);
+    const bool bottom = l + 1 == nlev;
+    if (l == 0) {
+      lv.r64 = bump.take<double>(lv.n_g0);
+    } else if (!f32) {
+      lv.e64 = bump.take<double>(lv.n_g1);
+      lv.rhs64 = bump.take<double>(lv.n_g0);
+      if (!bottom) lv.r64 = bump.take<double>(lv.n_g0);
+    }
+    if (f32) {
+      for (int d = 0; d < 3; ++d) lv.b32[d] = bump.take<float>(lv.n_f[d]);
+      if (s->has_a) lv.a32 = bump.take<float>(lv.n_g0);
+      lv.e32 = bump.take<float>(lv.n_g1);
+      lv.rhs32 = bump.take<float>(lv.n_g0);
+      if (!bottom) lv.r32 = bump.take<float>(lv.n_g0);
+    }
+  }
+  s->d_nbr = bump.take<int>(6 * (size_t)nb);
+  s->d_fidx = bump.take<int>(6 * (size_t)nb);
+  s->d_aidx = bump.take<int>(nb);
+  s->d_map_rhs = bump.take<int>(nb);
+  s->d_map_out = bump.take<int>(nb);
+  if (f32) {
+    s->bdiag32 = bump.take<float>(nb);
+    s->bcoef32 = bump.take<float>(6 * (size_t)nb);
+    s->bwork32 = bump.take<float>(4 * (size_t)nb);
+  } else {
+    s->bdiag64 = bump.take<double>(nb);
+    s->bcoef64 = bump.take<double>(6 * (size_t)nb);
+    s->bwork64 = bump.take<double>(4 * (size_t)nb);
+  }
+  s->d_norm = bump.take<unsigned long long>(4);
+  s->d_iters = bump.take<int>(4);
+  s->d_sum = bump.take<double>(2);
+  s->d_partials = bump.take<double>(std::max<size_t>(1, s->L[0].cap_cell));
+  if (s->opts.tune == 2) s->tune_scratch = bump.take<double>(s->L[0].n_g1);
+  s->ws_need = bump.off + 256;
+  return MG_OK;
+}
+
+int check_geom(const mg_geom_t* geom, const int32_t* bc_lo, const int32_t* bc_hi, mg_solver* s) {
+  if (!geom) return fail(MG_ERR_ARG, "geometry is null");
+  s->domain = to_ibox(geom->domain);
+  if (!ok(s->domain)) return fail(MG_ERR_ARG, "empty domain");
+  for (int d = 0; d < 3; ++d) {
+    s->periodic[d] = geom->is_periodic[d] ? 1 : 0;
+    const int lo = bc_lo ? bc_lo[d] : (s->periodic[d] ? MG_BC_PERIODIC : MG_BC_DIRICHLET0);
+    const int hi = bc_hi ? bc_hi[d] : (s->periodic[d] ? MG_BC_PERIODIC : MG_BC_DIRICHLET0);
+    if (lo != MG_BC_PERIODIC && lo != MG_BC_DIRICHLET0) return fail(MG_ERR_ARG, "bad bc_lo");
+    if (hi != MG_BC_PERIODIC && hi != MG_BC_DIRICHLET0) return fail(MG_ERR_ARG, "bad bc_hi");
+    if ((lo == MG_BC_PERIODIC) != (s->periodic[d] != 0) ||
+        (hi == MG_BC_PERIODIC) != (s->periodic[d] != 0))
+      return fail(MG_ERR_ARG, "bc must be MG_BC_PERIODIC exactly in the periodic directions");
+    s->bc_lo[d] = lo;
+    s->bc_hi[d] = hi;
+    if (!(geom->prob_hi[d] > geom->prob_lo[d])) return fail(MG_ERR_ARG, "prob_hi <= prob_lo");
+  }
+  return MG_OK;
+}
+
+void set_h(mg_solver* s, const mg_geom_t* geom) {
+  for (size_t l = 0; l < s->L.size(); ++l)
+    for (int d = 0; d < 3; ++d)
+      s->L[l].h[d] = (geom->prob_hi[d] - geom->prob_lo[d]) / ext(s->L[l].domain, d);
+}
+
+template <typename T>
+StencilArgs<T> stencil_of(const mg_solver* s, const Level& lv, bool f32) {
+  StencilArgs<T> op;
+  op.boxes = lv.d_info;
+  if (f32) {
+    op.a = (const T*)lv.a32;
+    op.b0 = (const T*)lv.b32[0];
+    op.b1 = (const T*)lv.b32[1];
+    op.b2 = (const T*)lv.b32[2];
+  } else {
+    op.a = (const T*)lv.a64;
+    op.b0 = (const T*)lv.b64[0];
+    op.b1 = (const T*)lv.b64[1];
+    op.b2 = (const T*)lv.b64[2];
+  }
+  op.alpha = (T)s->alpha;
+  op.beta = (T)s->beta;
+  op.ih0 = (T)(1.0 / (lv.h[0] * lv.h[0]));
+  op.ih1 = (T)(1.0 / (lv.h[1] * lv.h[1]));
+  op.ih2 = (T)(1.0 / (lv.h[2] * lv.h[2]));
+  return op;
+}
+
+BottomTables bottom_tables(const mg_solver* s) {
+  BottomTables bt;
+  bt.n = s->nb;
+  bt.nbr = s->d_nbr;
+  bt.fidx = s->d_fidx;
+  bt.aidx = s->d_aidx;
+  bt.map_rhs = s->d_map_rhs;
+  bt.map_out = s->d_map_out;
+  return bt;
+}
+
+// MultiFab check: same boxes, the canonical packing for (ngrow, ixtype).
+int check_mf(const mg_solver* s, const mg_multifab_t* mf, int want_dtype, int ng_min, int ng_max,
+             int face_d, const char* what) {
+  if (!mf) return fail(MG_ERR_ARG, std::string(what) + " is null");
+  const Level& lv = s->L[0];
+  if (mf->nbox != lv.nbox || !mf->boxes || !mf->offsets || !mf->data)
+    return fail(MG_ERR_MISMATCH, std::string(what) + ": box count or pointers differ");
+  if (mf->dtype != want_dtype) return fail(MG_ERR_MISMATCH, std::string(what) + ": wrong dtype");
+  if (mf->ncomp != 1) return fail(MG_ERR_MISMATCH, std::string(what) + ": ncomp must be 1");
+  if (mf->ngrow < ng_min || mf->ngrow > ng_max)
+    return fail(MG_ERR_MISMATCH, std::string(what) + ": unsupported ngrow");
+  for (int d = 0; d < 3; ++d)
+    if (mf->ixtype[d] != (d == face_d ? 1 : 0))
+      return fail(MG_ERR_MISMATCH, std::string(what) + ": wrong index type");
+  int64_t off = 0;
+  for (int b = 0; b < lv.nbox; ++b) {
+    if (!same(to_ibox(mf->boxes[b]), lv.boxes[b]))
+      return fail(MG_ERR_MISMATCH, std::string(what) + ": box " + std::to_string(b) + " differs");
+    if (mf->offsets[b] != off)
+      return fail(MG_ERR_MISMATCH, std::string(what) + ": non-canonical offsets");
+    off += grown_volume(lv.boxes[b], mf->ngrow, face_d);
+  }
+  return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Profiling helpers
+
+hipEvent_t take_event(mg_solver* s) {
+  if (s->ev_used == s->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    s->ev_pool.push_back(e);
+  }
+  return s->ev_pool[s->ev_used++];
+}
+
+struct ProfScope {
+  mg_solver* s;
+  int fam;
+  hipEvent_t b = nullptr;
+  ProfScope(mg_solver* s_, int f, bool on) : s(s_), fam(f) {
+    if (on && s->profile) {
+      hipEvent_t a = take_event(s);
+      b = take_event(s);
+      if (a && b) {
+        hipEventRecord(a, s->st);
+        s->prof.push_back({fam, a, b});
+      } else {
+        b = nullptr;
+      }
+    }
+  }
+  ~ProfScope() {
+    if (b) hipEventRecord(b, s->st);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Setup: coefficient copies and coarsening.
+
+int setup_coefficients(mg_solver* s, const mg_multifab_t* acoef, const mg_multifab_t* const* bcoef) {
+  Level& l0 = s->L[0];
+  for (int d = 0; d < 3; ++d) {
+    const double* src = bcoef ? (const double*)bcoef[d]->data : nullptr;
+    HIPTRY(launch_scale_faces(s->st, src, l0.b64[d], l0.n_f[d], 1.0));
+  }
+  if (s->has_a)
+    HIPTRY(hipMemcpyAsync(l0.a64, acoef->data, sizeof(double) * l0.n_g0, hipMemcpyDeviceToDevice,
+                          s->st));
+  return MG_OK;
+}
+
+int coarsen_all(mg_solver* s) {
+  const bool f32 = s->opts.precision == MG_PREC_F32_REFINE;
+  for (size_t l = 0; l + 1 < s->L.size(); ++l) {
+    Level& f = s->L[l];
+    Level& c = s->L[l + 1];
+    for (int d = 0; d < 3; ++d)
+      HIPTRY(launch_coarsen_face(s->st, f.d_info, f.nbox, c.d_info, d, f.b64[d], c.b64[d],
+                                 f.max_faces));
+    if (s->has_a)
+      HIPTRY(launch_coarsen_cell<double>(s->st, f.d_rst, (int)f.t_rst.size(), f.s_rst, f.d_info,
+                                         c.d_info, f.a64, c.a64));
+  }
+  if (f32) {
+    for (Level& lv : s->L) {
+      for (int d = 0; d < 3; ++d)
+        HIPTRY((launch_convert<double, float>(s->st, lv.b64[d], lv.b32[d], lv.n_f[d])));
+      if (s->has_a) HIPTRY((launch_convert<double, float>(s->st, lv.a64, lv.a32, lv.n_g0)));
+    }
+  }
+  const Level& bl = s->L.back();
+  BottomTables bt = bottom_tables(s);
+  if (f32)
+    HIPTRY(launch_bottom_setup<float>(s->st, bt, stencil_of<float>(s, bl, true), s->bdiag32,
+                                      s->bcoef32));
+  else
+    HIPTRY(launch_bottom_setup<double>(s->st, bt, stencil_of<double>(s, bl, false), s->bdiag64,
+                                       s->bcoef64));
+  return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The V-cycle.
+
+template <typename T>
+struct LevelData {
+  T *e, *rhs, *r;
+};
+
+template <typename T>
+LevelData<T> ldata(Level& lv, bool f32) {
+  if (f32) return {(T*)lv.e32, (T*)lv.rhs32, (T*)lv.r32};
+  return {(T*)lv.e64, (T*)lv.rhs64, (T*)lv.r64};
+}
+
+template <typename T>
+int exchange(mg_solver* s, Level& lv, T* v, bool prof) {
+  ProfScope ps(s, 2, prof);
+  HIPTRY(launch_fill_boundary<T>(s->st, lv.d_tags, lv.d_chunks, (int)lv.chunks.size(), v, 1));
+  return MG_OK;
+}
+
+template <typename T>
+int smooth(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng,
+           int sweeps, bool zero_first, bool prof) {
+  int rc;
+  for (int k = 0; k < sweeps; ++k) {
+    const bool zg = zero_first && k == 0;
+    if (!zg && (rc = exchange<T>(s, lv, phi, prof))) return rc;
+    {
+      ProfScope ps(s, 0, prof);
+      HIPTRY(launch_gsrb<T>(s->st, lv.d_gsrb, (int)lv.t_gsrb.size(), lv.s_gsrb, op, phi, rhs,
+                            rhs_ng, 0, zg ? 1 : 0));
+    }
+    if ((rc = exchange<T>(s, lv, phi, prof))) return rc;
+    {
+      ProfScope ps(s, 0, prof);
+      HIPTRY(launch_gsrb<T>(s->st, lv.d_gsrb, (int)lv.t_gsrb.size(), lv.s_gsrb, op, phi, rhs,
+                            rhs_ng, 1, 0));
+    }
+  }
+  return MG_OK;
+}
+
+// Coarse levels l >= lstart in correction form (zero initial guess).
+template <typename T>
+int coarse_cycle(mg_solver* s, size_t l, bool f32) {
+  Level& lv = s->L[l];
+  LevelData<T> D = ldata<T>(lv, f32);
+  const StencilArgs<T> op = stencil_of<T>(s, lv, f32);
+  const bool prof = l == 0;
+  int rc;
+  if (l + 1 == s->L.size()) {
+    const BottomTables bt = bottom_tables(s);
+    const T* diag = f32 ? (const T*)s->bdiag32 : (const T*)s->bdiag64;
+    const T* coef = f32 ? (const T*)s->bcoef32 : (const T*)s->bcoef64;
+    T* work = f32 ? (T*)s->bwork32 : (T*)s->bwork64;
+    const int maxit = s->opts.bottom_max_iter > 0 ? s->opts.bottom_max_iter : s->nb;
+    HIPTRY(launch_bottom_cg<T>(s->st, bt, diag, coef, D.rhs, D.e, 0, work,
+                               s->opts.bottom_rel_tol, maxit, s->singular ? 1 : 0, s->d_iters));
+    return MG_OK;
+  }
+  if (s->opts.nu1 == 0)
+    HIPTRY(launch_zero_valid<T>(s->st, lv.d_cell, (int)lv.t_cell.size(), lv.s_cell, lv.d_info, D.e,
+                                1));
+  if ((rc = smooth<T>(s, lv, op, D.e, D.rhs, 0, s->opts.nu1, s->opts.nu1 > 0, prof))) return rc;
+  if ((rc = exchange<T>(s, lv, D.e, prof))) return rc;
+  {
+    ProfScope ps(s, 1, prof);
+    HIPTRY((launch_residual<T, T>(s->st, lv.d_cell, (int)lv.t_cell.size(), lv.s_cell, op, D.e,
+                                  D.rhs, 0, D.r, nullptr, 0)));
+  }
+  Level& cl = s->L[l + 1];
+  LevelData<T> C = ldata<T>(cl, f32);
+  {
+    ProfScope ps(s, 3, prof);
+    HIPTRY(launch_restrict<T>(s->st, lv.d_rst, (int)lv.t_rst.size(), lv.s_rst, lv.d_info,
+                              cl.d_info, D.r, C.rhs));
+  }
+  if (l == 0 && s->opts.use_graph) {
+    hipGraphExec_t g = f32 ? s->graph32 : s->graph64;
+    ProfScope ps(s, 5, true);
+    HIPTRY(hipGraphLaunch(g, s->st));
+  } else {
+    ProfScope ps(s, 5, l == 0);
+    if ((rc = coarse_cycle<T>(s, l + 1, f32))) return rc;
+  }
+  {
+    ProfScope ps(s, 4, prof);
+    HIPTRY(launch_prolong_add<T>(s->st, lv.d_cell, (int)lv.t_cell.size(), lv.s_cell, lv.d_info,
+                                 cl.d_info, D.e, C.e));
+  }
+  return smooth<T>(s, lv, op, D.e, D.rhs, 0, s->opts.nu2, false, prof);
+}
+
+int capture_graphs(mg_solver* s) {
+  if (!s->opts.use_graph || s->L.size() < 2) {
+    s->opts.use_graph = 0;
+    return MG_OK;
+  }
+  const bool f32 = s->opts.precision == MG_PREC_F32_REFINE;
+  hipGraph_t g;
+  HIPTRY(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
+  const bool saved = s->profile;
+  s->profile = false;
+  int rc = f32 ? coarse_cycle<float>(s, 1, true) : coarse_cycle<double>(s, 1, false);
+  s->profile = saved;
+  hipError_t e = hipStreamEndCapture(s->st, &g);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(MG_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  hipGraphExec_t ex;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(MG_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  if (f32)
+    s->graph32 = ex;
+  else
+    s->graph64 = ex;
+  return MG_OK;
+}
+
+// Level-0 V-cycle on the caller's phi (direct form, FP64).
+int vcycle64(mg_solver* s, double* phi, const double* rhs, int rhs_ng) {
+  Level& l0 = s->L[0];
+  const StencilArgs<double> op = stencil_of<double>(s, l0, false);
+  int rc;
+  if (s->L.size() == 1) {
+    if ((rc = exchange<double>(s, l0, phi, true))) return rc;
+    HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, op,
+                                            phi, rhs, rhs_ng, l0.r64, nullptr, 0)));
+    const int maxit = s->opts.bottom_max_iter > 0 ? s->opts.bottom_max_iter : s->nb;
+    HIPTRY(launch_bottom_cg<double>(s->st, bottom_tables(s), s->bdiag64, s->bcoef64, l0.r64, phi, 1,
+                                    s->bwork64, s->opts.bottom_rel_tol, maxit, s->singular ? 1 : 0,
+                                    s->d_iters));
+    return MG_OK;
+  }
+  if ((rc = smooth<double>(s, l0, op, phi, rhs, rhs_ng, s->opts.nu1, false, true))) return rc;
+  if ((rc = exchange<double>(s, l0, phi, true))) return rc;
+  {
+    ProfScope ps(s, 1, true);
+    HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, op,
+                                            phi, rhs, rhs_ng, l0.r64, nullptr, 0)));
+  }
+  Level& l1 = s->L[1];
+  {
+    ProfScope ps(s, 3, true);
+    HIPTRY(launch_restrict<double>(s->st, l0.d_rst, (int)l0.t_rst.size(), l0.s_rst, l0.d_info,
+                                   l1.d_info, l0.r64, l1.rhs64));
+  }
+  if (s->opts.use_graph) {
+    ProfScope ps(s, 5, true);
+    HIPTRY(hipGraphLaunch(s->graph64, s->st));
+  } else {
+    ProfScope ps(s, 5, true);
+    if ((rc = coarse_cycle<double>(s, 1, false))) return rc;
+  }
+  {
+    ProfScope ps(s, 4, true);
+    HIPTRY(launch_prolong_add<double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell,
+                                      l0.d_info, l1.d_info, phi, l1.e64));
+  }
+  return smooth<double>(s, l0, op, phi, rhs, rhs_ng, s->opts.nu2, false, true);
+}
+
+int read_norm(mg_solver* s, int slot, double* out) {
+  HIPTRY(hipMemcpyAsync(s->h_norm, s->d_norm + slot, sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, s->st));
+  HIPTRY(hipStreamSynchronize(s->st));
+  double v;
+  std::memcpy(&v, s->h_norm, sizeof(double));
+  *out = v;
+  return MG_OK;
+}
+
+int begin_call(mg_solver* s) {
+  HIPTRY(hipEventRecord(s->ev_in, s->user));
+  HIPTRY(hipStreamWaitEvent(s->st, s->ev_in, 0));
+  return MG_OK;
+}
+int end_call(mg_solver* s) {
+  HIPTRY(hipEventRecord(s->ev_out, s->st));
+  HIPTRY(hipStreamWaitEvent(s->user, s->ev_out, 0));
+  return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tile-shape tuning of the level-0 smoother and residual.
+
+std::string tune_key(const mg_solver* s, const char* kern, bool f32) {
+  const Level& l0 = s->L[0];
+  int mx[3] = {0, 0, 0};
+  for (const IBox& b : l0.boxes)
+    for (int d = 0; d < 3; ++d) mx[d] = std::max(mx[d], ext(b, d));
+  hipDeviceProp_t p;
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&p, dev) == hipSuccess) arch = p.gcnArchName;
+  std::ostringstream o;
+  o << arch << "|" << kern << "|" << (f32 ? "f32" : "f64") << "|" << mx[0] << "x" << mx[1] << "x"
+    << mx[2] << "|" << l0.nbox;
+  return o.str();
+}
+
+const char* tune_path() {
+  const char* p = std::getenv("AMRMG_TUNE_CACHE");
+  return p && *p ? p : nullptr;
+}
+
+std::map<std::string, Shape> read_cache() {
+  std::map<std::string, Shape> m;
+  const char* p = tune_path();
+  if (!p) return m;
+  std::ifstream in(p);
+  std::string key;
+  Shape sh;
+  while (in >> key >> sh.lx >> sh.ly >> sh.tz) m[key] = sh;
+  return m;
+}
+
+void write_cache(const std::map<std::string, Shape>& m) {
+  const char* p = tune_path();
+  if (!p) return;
+  std::ofstream out(p);
+  for (auto& kv : m) out << kv.first << " " << kv.second.lx << " " << kv.second.ly << " " << kv.second.tz << "\n";
+}
+
+int apply_shape(mg_solver* s, Shape sh, bool gsrb) {
+  Level& l0 = s->L[0];
+  if (gsrb) {
+    std::vector<Tile> t;
+    make_tiles(l0.info, sh, 2 * sh.lx, false, t);
+    if (t.size() > l0.cap_gsrb) return fail(MG_ERR_ARG, "tile table larger than its reservation");
+    l0.t_gsrb = t;
+    l0.s_gsrb = sh;
+    HIPTRY(hipMemcpyAsync(l0.d_gsrb, l0.t_gsrb.data(), sizeof(Tile) * l0.t_gsrb.size(),
+                          hipMemcpyHostToDevice, s->st));
+  } else {
+    std::vector<Tile> t;
+    make_tiles(l0.info, sh, sh.lx, false, t);
+    if (t.size() > l0.cap_cell) return fail(MG_ERR_ARG, "tile table larger than its reservation");
+    l0.t_cell = t;
+    l0.s_cell = sh;
+    HIPTRY(hipMemcpyAsync(l0.d_cell, l0.t_cell.data(), sizeof(Tile) * l0.t_cell.size(),
+                          hipMemcpyHostToDevice, s->st));
+  }
+  HIPTRY(hipStreamSynchronize(s->st));
+  return MG_OK;
+}
+
+template <typename T>
+int time_gsrb(mg_solver* s, Shape sh, T* phi, const T* rhs, const StencilArgs<T>& op, float* ms) {
+  int rc;
+  if ((rc = apply_shape(s, sh, true))) return rc;
+  hipEvent_t a = take_event(s), b = take_event(s);
+  Level& l0 = s->L[0];
+  for (int w = 0; w < 2; ++w)
+    HIPTRY(launch_gsrb<T>(s->st, l0.d_gsrb, (int)l0.t_gsrb.size(), sh, op, phi, rhs, 0, w & 1, 0));
+  HIPTRY(hipEventRecord(a, s->st));
+  const int reps = 6;
+  for (int w = 0; w < reps; ++w)
+    HIPTRY(launch_gsrb<T>(s->st, l0.d_gsrb, (int)l0.t_gsrb.size(), sh, op, phi, rhs, 0, w & 1, 0));
+  HIPTRY(hipEventRecord(b, s->st));
+  HIPTRY(hipEventSynchronize(b));
+  float t;
+  HIPTRY(hipEventElapsedTime(&t, a, b));
+  *ms = t / reps;
+  s->ev_used -= 2;
+  return MG_OK;
+}
+
+template <typename T>
+int time_resid(mg_solver* s, Shape sh, const T* phi, const T* rhs, const StencilArgs<T>& op,
+               T* out, float* ms) {
+  int rc;
+  if ((rc = apply_shape(s, sh, false))) return rc;
+  hipEvent_t a = take_event(s), b = take_event(s);
+  Level& l0 = s->L[0];
+  for (int w = 0; w < 2; ++w)
+    HIPTRY((launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi, rhs, 0,
+                                  out, nullptr, 0)));
+  HIPTRY(hipEventRecord(a, s->st));
+  const int reps = 6;
+  for (int w = 0; w < reps; ++w)
+    HIPTRY((launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi, rhs, 0,
+                                  out, nullptr, 0)));
+  HIPTRY(hipEventRecord(b, s->st));
+  HIPTRY(hipEventSynchronize(b));
+  float t;
+  HIPTRY(hipEventElapsedTime(&t, a, b));
+  *ms = t / reps;
+  s->ev_used -= 2;
+  return MG_OK;
+}
+
+int autotune(mg_solver* s) {
+  const bool f32 = s->opts.precision == MG_PREC_F32_REFINE;
+  Level& l0 = s->L[0];
+  auto cache = read_cache();
+  const std::string kg = tune_key(s, "gsrb", f32), kr = tune_key(s, "resid", f32);
+  int rc;
+  if (s->opts.tune == 1) {
+    auto it = cache.find(kg);
+    if (it != cache.end() && shape_ok(it->second)) {
+      std::vector<Tile> t;
+      make_tiles(l0.info, it->second, 2 * it->second.lx, false, t);
+      if (t.size() <= l0.cap_gsrb && (rc = apply_shape(s, it->second, true))) return rc;
+    }
+    it = cache.find(kr);
+    if (it != cache.end() && shape_ok(it->second)) {
+      std::vector<Tile> t;
+      make_tiles(l0.info, it->second, it->second.lx, false, t);
+      if (t.size() <= l0.cap_cell && (rc = apply_shape(s, it->second, false))) return rc;
+    }
+    return MG_OK;
+  }
+  if (s->opts.tune != 2) return MG_OK;
+  // data: the scratch array (ng 1) as phi, level-0 coefficients as rhs-sized input
+  const Shape g0 = l0.s_gsrb, c0 = l0.s_cell;
+  Shape best_g = g0, best_c = c0;
+  float tg = 1e30f, tr = 1e30f, t;
+  if (f32) {
+    float* phi = (float*)s->tune_scratch;
+    HIPTRY(hipMemsetAsync(phi, 0, sizeof(float) * l0.n_g1, s->st));
+    const StencilArgs<float> op = stencil_of<float>(s, l0, true);
+    for (Shape sh : gsrb_candidates()) {
+      if ((rc = time_gsrb<float>(s, sh, phi, l0.rhs32, op, &t))) return rc;
+      if (t < tg) { tg = t; best_g = sh; }
+    }
+    for (Shape sh : cell_candidates()) {
+      if ((rc = time_resid<float>(s, sh, phi, l0.rhs32, op, l0.r32, &t))) return rc;
+      if (t < tr) { tr = t; best_c = sh; }
+    }
+  } else {
+    double* phi = s->tune_scratch;
+    HIPTRY(hipMemsetAsync(phi, 0, sizeof(double) * l0.n_g1, s->st));
+    const StencilArgs<double> op = stencil_of<double>(s, l0, false);
+    for (Shape sh : gsrb_candidates()) {
+      if ((rc = time_gsrb<double>(s, sh, phi, l0.r64, op, &t))) return rc;
+      if (t < tg) { tg = t; best_g = sh; }
+    }
+    for (Shape sh : cell_candidates()) {
+      if ((rc = time_resid<double>(s, sh, phi, l0.r64, op, l0.r64, &t))) return rc;
+      if (t < tr) { tr = t; best_c = sh; }
+    }
+  }
+  if ((rc = apply_shape(s, best_g, true))) return rc;
+  if ((rc = apply_shape(s, best_c, false))) return rc;
+  if (s->opts.verbose)
+    fprintf(stderr, "amrmg tune: gsrb %dx%dx%d %.4f ms, resid %dx%dx%d %.4f ms\n", best_g.lx,
+            best_g.ly, best_g.tz, tg, best_c.lx, best_c.ly, best_c.tz, tr);
+  cache[kg] = best_g;
+  cache[kr] = best_c;
+  write_cache(cache);
+  return MG_OK;
+}
+
+int upload_tables(mg_solver* s) {
+  for (Level& lv : s->L) {
+    HIPTRY(hipMemcpyAsync(lv.d_info, lv.info.data(), sizeof(BoxInfo) * lv.info.size(),
+                          hipMemcpyHostToDevice, s->st));
+    if (!lv.t_gsrb.empty())
+      HIPTRY(hipMemcpyAsync(lv.d_gsrb, lv.t_gsrb.data(), sizeof(Tile) * lv.t_gsrb.size(),
+                            hipMemcpyHostToDevice, s->st));
+    if (!lv.t_cell.empty())
+      HIPTRY(hipMemcpyAsync(lv.d_cell, lv.t_cell.data(), sizeof(Tile) * lv.t_cell.size(),
+                            hipMemcpyHostToDevice, s->st));
+    if (!lv.t_rst.empty())
+      HIPTRY(hipMemcpyAsync(lv.d_rst, lv.t_rst.data(), sizeof(Tile) * lv.t_rst.size(),
+                            hipMemcpyHostToDevice, s->st));
+    if (!lv.tags.empty())
+      HIPTRY(hipMemcpyAsync(lv.d_tags, lv.tags.data(), sizeof(FbTag) * lv.tags.size(),
+                            hipMemcpyHostToDevice, s->st));
+    if (!lv.chunks.empty())
+      HIPTRY(hipMemcpyAsync(lv.d_chunks, lv.chunks.data(), sizeof(FbChunk) * lv.chunks.size(),
+                            hipMemcpyHostToDevice, s->st));
+  }
+  const size_t nb = s->nb;
+  HIPTRY(hipMemcpyAsync(s->d_nbr, s->h_nbr.data(), sizeof(int) * 6 * nb, hipMemcpyHostToDevice, s->st));
+  HIPTRY(hipMemcpyAsync(s->d_fidx, s->h_fidx.data(), sizeof(int) * 6 * nb, hipMemcpyHostToDevice, s->st));
+  HIPTRY(hipMemcpyAsync(s->d_aidx, s->h_aidx.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s->st));
+  HIPTRY(hipMemcpyAsync(s->d_map_rhs, s->h_map_rhs.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s->st));
+  HIPTRY(hipMemcpyAsync(s->d_map_out, s->h_map_out.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s->st));
+  return MG_OK;
+}
+
+bool is_singular_problem(const mg_solver* s) {
+  return s->periodic[0] && s->periodic[1] && s->periodic[2] && s->alpha == 0.0;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+
+extern "C" {
+
+void mg_default_opts(mg_opts_t* o) {
+  if (!o) return;
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->max_iter = 100;
+  o->bottom_max_iter = 0;
+  o->min_bottom_edge = 4;
+  o->precision = MG_PREC_F64;
+  o->use_graph = 1;
+  o->tune = 1;
+  o->verbose = 0;
+  o->aggregate = 0;
+  o->bottom_rel_tol = 1e-4;
+}
+
+static int check_opts(const mg_opts_t* o) {
+  if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 == 0) return fail(MG_ERR_ARG, "bad nu1/nu2");
+  if (o->max_iter < 0) return fail(MG_ERR_ARG, "max_iter < 0");
+  if (o->min_bottom_edge < 1) return fail(MG_ERR_ARG, "min_bottom_edge < 1");
+  if (o->precision != MG_PREC_F64 && o->precision != MG_PREC_F32_REFINE)
+    return fail(MG_ERR_ARG, "bad precision");
+  if (o->tune < 0 || o->tune > 2) return fail(MG_ERR_ARG, "bad tune");
+  if (!(o->bottom_rel_tol >= 0)) return fail(MG_ERR_ARG, "bad bottom_rel_tol");
+  return MG_OK;
+}
+
+int mg_query_workspace(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
+                       const mg_opts_t* opts, int32_t has_acoef, size_t* bytes) {
+  if (!boxes || nbox <= 0 || !bytes) return fail(MG_ERR_ARG, "null boxes or size pointer");
+  std::unique_ptr<mg_solver> s(new mg_solver());
+  if (opts)
+    s->opts = *opts;
+  else
+    mg_default_opts(&s->opts);
+  int rc;
+  if ((rc = check_opts(&s->opts))) return rc;
+  if ((rc = check_geom(geom, nullptr, nullptr, s.get()))) return rc;
+  s->has_a = has_acoef != 0;
+  std::vector<IBox> bx(nbox);
+  for (int i = 0; i < nbox; ++i) bx[i] = to_ibox(boxes[i]);
+  Bump bump{nullptr};
+  if ((rc = build_plan(s.get(), bx, bump))) return rc;
+  *bytes = s->ws_need;
+  return MG_OK;
+}
+
+int mg_num_levels(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
+                  const mg_opts_t* opts, int32_t* nlevels) {
+  if (!boxes || nbox <= 0 || !nlevels || !geom) return fail(MG_ERR_ARG, "null argument");
+  mg_opts_t o;
+  if (opts)
+    o = *opts;
+  else
+    mg_default_opts(&o);
+  std::vector<IBox> bx(nbox);
+  for (int i = 0; i < nbox; ++i) bx[i] = to_ibox(boxes[i]);
+  std::string err;
+  const IBox dom = to_ibox(geom->domain);
+  if (!validate_boxes(bx, dom, true, &err)) return fail(MG_ERR_INVALID_BOXARRAY, err);
+  *nlevels = (int32_t)hierarchy(bx, dom, o.min_bottom_edge, o.aggregate != 0).size();
+  return MG_OK;
+}
+
+int mg_create(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom, const int32_t bc_lo[3],
+              const int32_t bc_hi[3], double alpha, double beta, const mg_multifab_t* acoef,
+              const mg_multifab_t* const* bcoef, const mg_opts_t* opts, void* workspace,
+              size_t ws_bytes, void* hip_stream, mg_solver_t** out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!out) return fail(MG_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (!boxes || nbox <= 0) return fail(MG_ERR_ARG, "no boxes");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(MG_ERR_ARG, "alpha/beta not finite");
+  std::unique_ptr<mg_solver> s(new mg_solver());
+  if (opts)
+    s->opts = *opts;
+  else
+    mg_default_opts(&s->opts);
+  int rc;
+  if ((rc = check_opts(&s->opts))) return rc;
+  if ((rc = check_geom(geom, bc_lo, bc_hi, s.get()))) return rc;
+  s->alpha = alpha;
+  s->beta = beta;
+  s->has_a = acoef != nullptr;
+  std::vector<IBox> bx(nbox);
+  for (int i = 0; i < nbox; ++i) bx[i] = to_ibox(boxes[i]);
+  {
+    Bump measure{nullptr};
+    if ((rc = build_plan(s.get(), bx, measure))) return rc;
+  }
+  if (!workspace) return fail(MG_ERR_WORKSPACE, "workspace is null");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return fail(MG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < s->ws_need)
+    return fail(MG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(s->ws_need) +
+                                      " bytes, got " + std::to_string(ws_bytes));
+  {
+    Bump real{static_cast<char*>(workspace)};
+    if ((rc = build_plan(s.get(), bx, real))) return rc;
+  }
+  set_h(s.get(), geom);
+  s->ws = static_cast<char*>(workspace);
+  s->ws_bytes = ws_bytes;
+  s->singular = is_singular_problem(s.get());
+  // coefficient MultiFabs
+  if (acoef && (rc = check_mf(s.get(), acoef, MG_F64, 0, 0, -1, "acoef"))) return rc;
+  if (bcoef)
+    for (int d = 0; d < 3; ++d)
+      if ((rc = check_mf(s.get(), bcoef[d], MG_F64, 0, 0, d, "bcoef"))) return rc;
+  s->user = static_cast<hipStream_t>(hip_stream);
+  HIPTRY(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+  HIPTRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
+  HIPTRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
+  HIPTRY(hipHostMalloc((void**)&s->h_norm, 64, hipHostMallocDefault));
+  s->h_iters = reinterpret_cast<int*>(s->h_norm + 4);
+  if ((rc = begin_call(s.get()))) return rc;
+  if ((rc = upload_tables(s.get()))) return rc;
+  if ((rc = setup_coefficients(s.get(), acoef, bcoef))) return rc;
+  if ((rc = coarsen_all(s.get()))) return rc;
+  if ((rc = autotune(s.get()))) return rc;
+  if ((rc = capture_graphs(s.get()))) return rc;
+  HIPTRY(hipStreamSynchronize(s->st));
+  if ((rc = end_call(s.get()))) return rc;
+  s->setup_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = s.release();
+  return MG_OK;
+}
+
+int mg_set_coefficients(mg_solver_t* s, const mg_multifab_t* acoef,
+                        const mg_multifab_t* const* bcoef) {
+  if (!s) return fail(MG_ERR_ARG, "null solver");
+  if ((acoef != nullptr) != s->has_a)
+    return fail(MG_ERR_ARG, "acoef presence must match mg_create");
+  int rc;
+  if (acoef && (rc = check_mf(s, acoef, MG_F64, 0, 0, -1, "acoef"))) return rc;
+  if (bcoef)
+    for (int d = 0; d < 3; ++d)
+      if ((rc = check_mf(s, bcoef[d], MG_F64, 0, 0, d, "bcoef"))) return rc;
+  if ((rc = begin_call(s))) return rc;
+  if ((rc = setup_coefficients(s, acoef, bcoef))) return rc;
+  if ((rc = coarsen_all(s))) return rc;
+  return end_call(s);
+}
+
+int mg_set_coefficients_global(mg_solver_t* s, const void* acoef_global,
+                               const void* const* bface_global, int32_t is_log) {
+  if (!s) return fail(MG_ERR_ARG, "null solver");
+  if ((acoef_global != nullptr) != s->has_a)
+    return fail(MG_ERR_ARG, "acoef presence must match mg_create");
+  if (!bface_global) return fail(MG_ERR_ARG, "bface_global is null");
+  int rc;
+  if ((rc = begin_call(s))) return rc;
+  Level& l0 = s->L[0];
+  const int dlo[3] = {s->domain.lo[0], s->domain.lo[1], s->domain.lo[2]};
+  const int dn[3] = {ext(s->domain, 0), ext(s->domain, 1), ext(s->domain, 2)};
+  for (int d = 0; d < 3; ++d) {
+    if (!bface_global[d]) return fail(MG_ERR_ARG, "bface_global entry is null");
+    HIPTRY(launch_scatter_faces(s->st, l0.d_info, l0.nbox, d, dlo, dn,
+                                (const double*)bface_global[d], l0.b64[d], is_log ? 1 : 0,
+                                l0.max_faces));
+  }
+  if (acoef_global)
+    HIPTRY(launch_scatter_cells(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info, dlo,
+                                dn, (const double*)acoef_global, l0.a64));
+  if ((rc = coarsen_all(s))) return rc;
+  return end_call(s);
+}
+
+int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, double rel_tol,
+             double abs_tol, mg_info_t* info, double* resid_history) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!s) return fail(MG_ERR_ARG, "null solver");
+  int rc;
+  if ((rc = check_mf(s, phi, MG_F64, 1, 1, -1, "phi"))) return rc;
+  if ((rc = check_mf(s, rhs, MG_F64, 0, 1, -1, "rhs"))) return rc;
+  if (!(rel_tol >= 0) || !(abs_tol >= 0)) return fail(MG_ERR_ARG, "negative tolerance");
+  if ((rc = begin_call(s))) return rc;
+  Level& l0 = s->L[0];
+  double* P = static_cast<double*>(phi->data);
+  const double* F = static_cast<const double*>(rhs->data);
+  const int rng = rhs->ngrow;
+  const bool f32 = s->opts.precision == MG_PREC_F32_REFINE;
+  const StencilArgs<double> op = stencil_of<double>(s, l0, false);
+  mg_info_t inf;
+  std::memset(&inf, 0, sizeof(inf));
+  inf.nlevels = (int)s->L.size();
+  inf.setup_ms = s->setup_ms;
+
+  HIPTRY(launch_fill_u64(s->st, s->d_norm, 4, 0ull));
+  HIPTRY(launch_maxabs<double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info, F,
+                               rng, s->d_norm));
+  double normf;
+  if ((rc = read_norm(s, 0, &normf))) return rc;
+  int status = MG_OK;
+  if (!std::isfinite(normf)) {
+    end_call(s);
+    return fail(MG_ERR_NAN, "rhs holds a non-finite value");
+  }
+  if (normf == 0.0) {
+    HIPTRY(launch_zero_valid<double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info,
+                                     P, 1));
+    HIPTRY(hipStreamSynchronize(s->st));
+    inf.converged = 1;
+    if (resid_history) resid_history[0] = 0.0;
+  } else {
+    const double tol = std::max(rel_tol * normf, abs_tol);
+    int it = 0, rising = 0;
+    double rn = 0, first = 0, prev = 0;
+    while (true) {
+      HIPTRY(launch_fill_u64(s->st, s->d_norm + 1, 1, 0ull));
+      if ((rc = exchange<double>(s, l0, P, false))) return rc;
+      {
+        ProfScope ps(s, 1, true);
+        if (f32)
+          HIPTRY((launch_residual<double, float>(s->st, l0.d_cell, (int)l0.t_cell.size(),
+                                                 l0.s_cell, op, P, F, rng, l0.rhs32, s->d_norm + 1,
+                                                 0)));
+        else
+          HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(),
+                                                  l0.s_cell, op, P, F, rng, nullptr,
+                                                  s->d_norm + 1, 0)));
+      }
+      if ((rc = read_norm(s, 1, &rn))) return rc;
+      if (resid_history) resid_history[it] = rn;
+      if (s->opts.verbose) fprintf(stderr, "amrmg cycle %d  max|r| = %.6e\n", it, rn);
+      if (!std::isfinite(rn)) {
+        status = fail(MG_ERR_NAN, "residual norm is not finite");
+        break;
+      }
+      if (it == 0) first = rn;
+      if (rn <= tol) {
+        inf.converged = 1;
+        break;
+      }
+      if (it == s->opts.max_iter) {
+        status = fail(MG_ERR_NOT_CONVERGED, "max_iter reached");
+        break;
+      }
+      if (it > 0) rising = rn > prev ? rising + 1 : 0;
+      if (rising >= 3 && rn > first) {
+        status = fail(MG_ERR_DIVERGED, "residual grew for 3 cycles");
+        break;
+      }
+      prev = rn;
+      if (f32) {
+        if ((rc = coarse_cycle<float>(s, 0, true))) return rc;
+        ProfScope ps(s, 6, true);
+        HIPTRY(launch_update(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info, P,
+                             l0.e32));
+      } else {
+        if ((rc = vcycle64(s, P, F, rng))) return rc;
+      }
+      ++it;
+    }
+    inf.iters = it;
+    inf.abs_resid = rn;
+    inf.rel_resid = rn / normf;
+  }
+  if (s->singular) {
+    HIPTRY(launch_sum_valid(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info, P,
+                            s->d_partials, s->d_sum));
+    HIPTRY(launch_shift_valid(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info, P,
+                              s->d_sum, l0.ncell));
+  }
+  HIPTRY(hipMemcpyAsync(s->h_iters, s->d_iters, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPTRY(hipStreamSynchronize(s->st));
+  inf.bottom_iters = *s->h_iters;
+  if ((rc = end_call(s))) return rc;
+  inf.solve_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return status;
+}
+
+int mg_apply(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* out) {
+  if (!s) return fail(MG_ERR_ARG, "null solver");
+  int rc;
+  if ((rc = check_mf(s, phi, MG_F64, 1, 1, -1, "phi"))) return rc;
+  if ((rc = check_mf(s, out, MG_F64, 0, 0, -1, "out"))) return rc;
+  if ((rc = begin_call(s))) return rc;
+  Level& l0 = s->L[0];
+  if ((rc = exchange<double>(s, l0, (double*)phi->data, false))) return rc;
+  HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell,
+                                          stencil_of<double>(s, l0, false),
+                                          (const double*)phi->data, nullptr, 0,
+                                          (double*)out->data, nullptr, 1)));
+  return end_call(s);
+}
+
+static int face_grad_common(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam) {
+  int rc;
+  if ((rc = check_mf(s, phi, MG_F64, 1, 1, -1, "phi"))) return rc;
+  if ((rc = check_mf(s, lam, MG_F64, 1, 1, -1, "lam"))) return rc;
+  if ((rc = begin_call(s))) return rc;
+  Level& l0 = s->L[0];
+  if ((rc = exchange<double>(s, l0, (double*)phi->data, false))) return rc;
+  if ((rc = exchange<double>(s, l0, (double*)lam->data, false))) return rc;
+  return MG_OK;
+}
+
+int mg_face_grad_logb(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam,
+                      mg_multifab_t* const* grad) {
+  if (!s || !grad) return fail(MG_ERR_ARG, "null argument");
+  int rc;
+  for (int d = 0; d < 3; ++d)
+    if ((rc = check_mf(s, grad[d], MG_F64, 0, 0, d, "grad"))) return rc;
+  if ((rc = face_grad_common(s, phi, lam))) return rc;
+  Level& l0 = s->L[0];
+  const int dlo[3] = {s->domain.lo[0], s->domain.lo[1], s->domain.lo[2]};
+  const int dn[3] = {ext(s->domain, 0), ext(s->domain, 1), ext(s->domain, 2)};
+  for (int d = 0; d < 3; ++d)
+    HIPTRY(launch_face_grad(s->st, l0.d_info, l0.nbox, d, stencil_of<double>(s, l0, false),
+                            (const double*)phi->data, (const double*)lam->data,
+                            (double*)grad[d]->data, 0, dlo, dn, s->periodic[d], l0.max_faces));
+  return end_call(s);
+}
+
+int mg_face_grad_logb_global(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam,
+                             void* const* grad_global) {
+  if (!s || !grad_global) return fail(MG_ERR_ARG, "null argument");
+  for (int d = 0; d < 3; ++d)
+    if (!grad_global[d]) return fail(MG_ERR_ARG, "null gradient array");
+  int rc;
+  if ((rc = face_grad_common(s, phi, lam))) return rc;
+  Level& l0 = s->L[0];
+  const int dlo[3] = {s->domain.lo[0], s->domain.lo[1], s->domain.lo[2]};
+  const int dn[3] = {ext(s->domain, 0), ext(s->domain, 1), ext(s->domain, 2)};
+  for (int d = 0; d < 3; ++d)
+    HIPTRY(launch_face_grad(s->st, l0.d_info, l0.nbox, d, stencil_of<double>(s, l0, false),
+                            (const double*)phi->data, (const double*)lam->data,
+                            (double*)grad_global[d], 1, dlo, dn, s->periodic[d], l0.max_faces));
+  return end_call(s);
+}
+
+int mg_copy_valid(mg_solver_t* s, const mg_multifab_t* src, mg_multifab_t* dst) {
+  if (!s) return fail(MG_ERR_ARG, "null solver");
+  int rc;
+  if ((rc = check_mf(s, src, MG_F64, 0, 1, -1, "src"))) return rc;
+  if ((rc = check_mf(s, dst, MG_F64, 0, 1, -1, "dst"))) return rc;
+  if ((rc = begin_call(s))) return rc;
+  Level& l0 = s->L[0];
+  HIPTRY(launch_copy_valid(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info,
+                           (const double*)src->data, src->ngrow, (double*)dst->data, dst->ngrow));
+  return end_call(s);
+}
+
+void mg_destroy(mg_solver_t* s) {
+  if (!s) return;
+  if (s->st) hipStreamSynchronize(s->st);
+  if (s->graph64) hipGraphExecDestroy(s->graph64);
+  if (s->graph32) hipGraphExecDestroy(s->graph32);
+  for (hipEvent_t e : s->ev_pool) hipEventDestroy(e);
+  if (s->ev_in) hipEventDestroy(s->ev_in);
+  if (s->ev_out) hipEventDestroy(s->ev_out);
+  if (s->h_norm) hipHostFree(s->h_norm);
+  if (s->st) hipStreamDestroy(s->st);
+  delete s;
+}
+
+int mg_profile(mg_solver_t* s, int32_t enable) {
+  if (!s) return fail(MG_ERR_ARG, "null solver");
+  HIPTRY(hipStreamSynchronize(s->st));
+  s->prof.clear();
+  s->ev_used = 0;
+  s->profile = enable != 0;
+  return MG_OK;
+}
+
+int mg_kernel_stats(mg_solver_t* s, int32_t family, double* total_ms, int64_t* launches) {
+  if (!s || !total_ms || !launches) return fail(MG_ERR_ARG, "null argument");
+  HIPTRY(hipStreamSynchronize(s->st));
+  double t = 0;
+  int64_t n = 0;
+  for (const ProfRec& r : s->prof) {
+    if (r.fam != family) continue;
+    float ms = 0;
+    HIPTRY(hipEventElapsedTime(&ms, r.a, r.b));
+    t += ms;
+    ++n;
+  }
+  *total_ms = t;
+  *launches = n;
+  return MG_OK;
+}
+
+int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, int32_t reps,
+                     double* mean_ms) {
+  if (!s || !mean_ms || reps <= 0) return fail(MG_ERR_ARG, "bad argument");
+  int rc;
+  if ((rc = check_mf(s, phi, MG_F64, 1, 1, -1, "phi"))) return rc;
+  if ((rc = check_mf(s, rhs, MG_F64, 0, 1, -1, "rhs"))) return rc;
+  if ((rc = begin_call(s))) return rc;
+  Level& l0 = s->L[0];
+  const StencilArgs<double> op = stencil_of<double>(s, l0, false);
+  hipEvent_t a, b;
+  HIPTRY(hipEventCreate(&a));
+  HIPTRY(hipEventCreate(&b));
+  HIPTRY(hipEventRecord(a, s->st));
+  for (int k = 0; k < reps; ++k)
+    HIPTRY(launch_gsrb<double>(s->st, l0.d_gsrb, (int)l0.t_gsrb.size(), l0.s_gsrb, op,
+                               (double*)phi->data, (const double*)rhs->data, rhs->ngrow, k & 1, 0));
+  HIPTRY(hipEventRecord(b, s->st));
+  HIPTRY(hipEventSynchronize(b));
+  float ms;
+  HIPTRY(hipEventElapsedTime(&ms, a, b));
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  *mean_ms = ms / reps;
+  return end_call(s);
+}
+
+int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz) {
+  if (!s) return fail(MG_ERR_ARG, "null solver");
+  const Shape sh{lx, ly, tz};
+  bool found = false;
+  for (Shape c : kernel == 0 ? gsrb_candidates() : cell_candidates())
+    if (c.lx == lx && c.ly == ly && c.tz == tz) found = true;
+  if ((kernel != 0 && kernel != 1) || !found) return fail(MG_ERR_ARG, "shape is not a candidate");
+  return apply_shape(s, sh, kernel == 0);
+}
+
+const char* mg_last_error(void) { return amrmg::last_error(); }
+
+}  // extern "C"

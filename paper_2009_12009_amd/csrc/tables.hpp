@@ -1,0 +1,48 @@
+// Plain structs shared by the host driver and the device kernels: the per-box
+// table of a level, tile work items and ghost-copy items.  Everything a kernel
+// needs to find a cell of a box is in these tables, so one launch covers every
+// box of a level (the box-list form of "MFIter" with tiling off on the GPU).
+#pragma once
+
+#include <cstdint>
+
+namespace amrmg {
+
+// bcmask bits: 2*d set = the low face along d is a Dirichlet wall, 2*d+1 = the
+// high face.
+struct BoxInfo {
+  int lo[3];
+  int hi[3];
+  int bcmask;
+  int parent;          // box of the next coarser level that holds coarsen(this box)
+  long long off_g1;    // element offset of this box in cell data with 1 ghost layer
+  long long off_g0;    // ... in cell data without ghosts
+  long long off_f[3];  // ... in face data of direction d (ghost-free, +1 along d)
+};
+
+// One work-group's share: a tile of one box starting at cell (x0, y0, z0); the
+// tile extent is set by the launch (see the kernels).
+struct Tile {
+  int box;
+  int x0, y0, z0;
+};
+
+// One ghost-copy item, resolved to element offsets: region cell (i, j, k)
+// (0-based inside the region) goes to dst_base + i + j*dsy + k*dsz from
+// src_base + i + j*ssy + k*ssz; component c adds c*cstride.
+struct FbTag {
+  long long dst_base, src_base;
+  long long dst_cstride, src_cstride;
+  int nx, ny, ncell, pad;
+  int dsy, dsz, ssy, ssz;
+};
+
+// FB_CHUNK consecutive cells of one tag, handled by one work-group.
+struct FbChunk {
+  int tag;
+  int start;
+};
+
+constexpr int FB_CHUNK = 256;
+
+}  // namespace amrmg

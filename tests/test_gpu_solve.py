@@ -1,0 +1,229 @@
+"""GPU multigrid solve against the CPU oracle.
+
+Small cases (seconds for the oracle, several tiles and boxes per level):
+per-cycle residual histories, one-cycle iterates element by element and
+converged solutions.  Full 256^3 size (the benchmark's launch
+configuration): the residual of the GPU solution recomputed by the oracle's
+operator on every cell, and the GPU operator checked against the oracle's.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from gpu_util import gpu_solver, lib, oracle_level, rel_l2, to_global
+
+TIGHT = 1e-12  # bottom CG tolerance for parity: roundoff cannot move its stopping point
+
+
+def _run_pair(cfg, opts=None, rel_tol=1e-10, max_iter=100, a_cells=None, min_edge=4,
+              aggregate=0):
+    P = lib()
+    n, boxes = cfg["n"], cfg["boxes"]
+    gopts = dict(bottom_rel_tol=TIGHT, max_iter=max_iter, min_bottom_edge=min_edge,
+                 aggregate=aggregate)
+    gopts.update(opts or {})
+    s = gpu_solver(cfg, opts=gopts, a_cells=a_cells)
+    f_boxes = W.scatter_cells(cfg["rhs"], boxes)
+    rhs = P.MultiFab.from_numpy(boxes, f_boxes, 0)
+    phi = s.cell_mf(1, fill=0.0)
+    ginfo = s.solve(phi, rhs, rel_tol, history=True, raise_on_fail=False)
+    torch.cuda.synchronize()
+    gphi = to_global(phi, boxes, n)
+    lev = oracle_level(cfg, a_cells=a_cells)
+    ophi = O.new_cell_data(lev)
+    oinfo = O.solve(lev, ophi, f_boxes, rel_tol,
+                    opts=O.Opts(bottom_tol=TIGHT, max_iter=max_iter, min_bottom_edge=min_edge))
+    s.close()
+    return ginfo, gphi, oinfo, W.gather_cells(ophi, boxes, n, ng=1)
+
+
+def _check_history(g, o, rtol=1e-6):
+    assert g["iters"] == o["iters"], (g["history"], o["history"])
+    nf = float(o["normf"])
+    for k, (a, b) in enumerate(zip(g["history"], o["history"])):
+        assert abs(a - b) <= rtol * b + 1e-14 * nf, (k, a, b)
+
+
+@pytest.mark.gpu
+def test_c0_periodic_poisson():
+    print("[solve] C0 32^3 periodic Poisson", flush=True)
+    cfg = W.config_c0()
+    g, gphi, o, ophi = _run_pair(cfg)
+    assert g["converged"] and g["nlevels"] == 3
+    _check_history(g, o)
+    assert rel_l2(gphi, ophi) <= 1e-9
+    h = 1.0 / 32
+    lam = 12 * np.sin(np.pi * h) ** 2 / h ** 2
+    assert rel_l2(gphi, cfg["rhs"] / lam) <= 1e-9
+    assert abs(gphi.mean()) <= 1e-14
+
+
+@pytest.mark.gpu
+def test_lognormal_dirichlet_64():
+    print("[solve] lognormal 64^3, 8 boxes of 32^3", flush=True)
+    cfg = W.config_lognormal(64, 32)
+    g, gphi, o, ophi = _run_pair(cfg)
+    assert g["converged"] and g["nlevels"] == 4
+    _check_history(g, o)
+    assert rel_l2(gphi, ophi) <= 1e-9
+
+
+@pytest.mark.gpu
+def test_mixed_bc_with_cell_coefficient():
+    print("[solve] 32^3 periodic-x, a != 1, alpha 0.5", flush=True)
+    cfg = W.config_lognormal(32, 16)
+    cfg["periodic"] = (True, False, False)
+    cfg["faces"] = W.harmonic_faces(W.lognormal_cells(32, 1.0, 1), cfg["periodic"])
+    cfg["alpha"] = 0.5
+    a = W.lognormal_cells(32, 0.3, 9)
+    g, gphi, o, ophi = _run_pair(cfg, a_cells=a)
+    assert g["converged"]
+    _check_history(g, o)
+    assert rel_l2(gphi, ophi) <= 1e-9
+
+
+@pytest.mark.gpu
+def test_one_cycle_elementwise():
+    """After exactly one V-cycle the iterates agree cell by cell."""
+    print("[solve] one V-cycle, 48^3 in 8 boxes of 24^3", flush=True)
+    cfg = W.config_lognormal(48, 24)
+    g, gphi, o, ophi = _run_pair(cfg, max_iter=1, min_edge=3)
+    assert g["iters"] == 1 and not g["converged"]
+    scale = np.max(np.abs(ophi))
+    assert np.max(np.abs(gphi - ophi)) <= 1e-12 * scale
+
+
+@pytest.mark.gpu
+def test_single_level_bottom_only():
+    """Boxes too small to coarsen: the solve is CG on level 0."""
+    print("[solve] 12^3 in 8 boxes of 6^3 (one level)", flush=True)
+    cfg = W.config_lognormal(12, 6)
+    g, gphi, o, ophi = _run_pair(cfg)
+    assert g["nlevels"] == 1 and o["nlevels"] == 1
+    assert g["converged"]
+    _check_history(g, o, rtol=1e-5)
+    assert rel_l2(gphi, ophi) <= 1e-9
+
+
+@pytest.mark.gpu
+def test_uneven_boxes():
+    print("[solve] 128^3 guillotine boxes", flush=True)
+    boxes = W.guillotine_boxes(128, seed=4)
+    cfg = W.config_lognormal(128, None, boxes=boxes)
+    assert len(boxes) > 1
+    g, gphi, o, ophi = _run_pair(cfg)
+    assert g["converged"]
+    _check_history(g, o)
+    assert rel_l2(gphi, ophi) <= 1e-9
+
+
+@pytest.mark.gpu
+def test_float32_refinement_vs_fp64_oracle():
+    print("[solve] FP32 V-cycle + FP64 refinement, 64^3", flush=True)
+    P = lib()
+    cfg = W.config_lognormal(64, 32)
+    boxes = cfg["boxes"]
+    s = gpu_solver(cfg, opts=dict(precision=1))
+    f_boxes = W.scatter_cells(cfg["rhs"], boxes)
+    rhs = P.MultiFab.from_numpy(boxes, f_boxes, 0)
+    phi = s.cell_mf(1, fill=0.0)
+    info = s.solve(phi, rhs, 1e-10, history=True)
+    assert info["converged"] and info["rel_resid"] <= 1e-10
+    lev = oracle_level(cfg)
+    ophi = O.new_cell_data(lev)
+    O.solve(lev, ophi, f_boxes, 1e-12, opts=O.Opts(bottom_tol=TIGHT))
+    err = rel_l2(to_global(phi, boxes, 64), W.gather_cells(ophi, boxes, 64, ng=1))
+    print(f"FP32+refine rel-L2 vs FP64 oracle: {err:.3e} ({info['iters']} refinement steps)")
+    assert err <= 1e-8
+    s.close()
+
+
+@pytest.mark.gpu
+def test_tile_shapes_and_graph_bitwise_identical():
+    """Red/black updates within a colour are independent: any tiling, with or
+    without graph replay, must give the same bits (a race or overlap would not)."""
+    print("[solve] tile-shape invariance 64^3", flush=True)
+    P = lib()
+    cfg = W.config_lognormal(64, 32)
+    boxes = cfg["boxes"]
+    rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(cfg["rhs"], boxes), 0)
+    outs = []
+    shapes = [None, (0, 16, 4, 4), (0, 32, 8, 32), (0, 64, 4, 64), (1, 32, 2, 8), (1, 128, 2, 64)]
+    for graph in (1, 0):
+        for sh in shapes:
+            s = gpu_solver(cfg, opts=dict(max_iter=2, use_graph=graph, tune=0))
+            if sh is not None:
+                s.set_tile_shape(*sh)
+            phi = s.cell_mf(1, fill=0.0)
+            s.solve(phi, rhs, 1e-10, raise_on_fail=False)
+            torch.cuda.synchronize()
+            outs.append(phi.data.cpu().numpy().copy())
+            s.close()
+    ref = outs[0]
+    m = np.isfinite(ref)
+    for o in outs[1:]:
+        assert np.array_equal(o[m], ref[m])
+
+
+@pytest.mark.gpu
+def test_error_paths():
+    print("[solve] error paths", flush=True)
+    P = lib()
+    cfg = W.config_lognormal(16, 8)
+    boxes = cfg["boxes"]
+    s = gpu_solver(cfg, opts=dict(max_iter=1))
+    f = W.scatter_cells(cfg["rhs"], boxes)
+    rhs = P.MultiFab.from_numpy(boxes, f, 0)
+    phi = s.cell_mf(1, fill=0.0)
+    info = s.solve(phi, rhs, 1e-10, raise_on_fail=False)
+    assert info["status"] == P._lib.MG_ERR_NOT_CONVERGED and info["iters"] == 1
+    assert np.all(np.isfinite(to_global(phi, boxes, 16)))
+    bad = [x.copy() for x in f]
+    bad[3][1, 2, 3] = np.nan
+    with pytest.raises(P.MGError) as e:
+        s.solve(s.cell_mf(1, fill=0.0), P.MultiFab.from_numpy(boxes, bad, 0), 1e-10)
+    assert e.value.code == P._lib.MG_ERR_NAN
+    zero = P.MultiFab.from_numpy(boxes, [np.zeros_like(x) for x in f], 0)
+    phi = s.cell_mf(1, fill=5.0)
+    info = s.solve(phi, zero, 1e-10)
+    assert info["converged"] and not np.any(to_global(phi, boxes, 16))
+    other = P.MultiFab(W.uniform_boxes(16, 16), 1, fill=0.0)
+    with pytest.raises(P.MGError) as e:
+        s.solve(other, rhs, 1e-10)
+    assert e.value.code == P._lib.MG_ERR_MISMATCH
+    s.close()
+
+
+@pytest.mark.gpu
+def test_c1_full_size_residual_and_operator():
+    """256^3, 64 boxes of 64^3, lognormal b: the launch configuration of the
+    benchmark.  The oracle's operator recomputes f - A phi on every cell."""
+    print("[solve] C1 256^3 full size", flush=True)
+    P = lib()
+    cfg = W.config_c1()
+    n, boxes = cfg["n"], cfg["boxes"]
+    s = gpu_solver(cfg)
+    f_boxes = W.scatter_cells(cfg["rhs"], boxes)
+    rhs = P.MultiFab.from_numpy(boxes, f_boxes, 0)
+    phi = s.cell_mf(1, fill=0.0)
+    info = s.solve(phi, rhs, 1e-10, history=True)
+    print(f"C1: {info['iters']} cycles, {info['solve_ms']:.1f} ms, rel {info['rel_resid']:.2e}")
+    assert info["converged"] and info["nlevels"] == 5
+    out = s.cell_mf(0)
+    s.apply(phi, out)
+    torch.cuda.synchronize()
+    lev = oracle_level(cfg)
+    ophi = phi.to_numpy()
+    oA = O.apply_op(lev, ophi)
+    gA = out.valid_numpy()
+    scale = max(float(np.max(np.abs(x))) for x in oA)
+    err = max(float(np.max(np.abs(a - b))) for a, b in zip(gA, oA))
+    assert err <= 1e-12 * scale * 10
+    r = max(float(np.max(np.abs(fb - a))) for fb, a in zip(f_boxes, oA))
+    normf = max(float(np.max(np.abs(x))) for x in f_boxes)
+    assert abs(r - info["abs_resid"]) <= 1e-6 * r + 1e-13 * scale
+    assert r <= 1e-10 * normf * (1 + 1e-3)
+    s.close()

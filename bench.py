@@ -1,0 +1,218 @@
+"""Benchmark: time to relative residual 1e-10 on the 256^3 variable-coefficient
+problem (64 boxes of 64^3, Dirichlet walls, lognormal b with sigma 1, uniform
+rhs), FP64 V-cycles and FP32 V-cycles inside FP64 refinement, on one GPU.
+
+One step = one FP64 solve plus one FP32+refine solve from phi = 0 on the same
+device-resident input.  The JSON line reports the FP64 time as `value`, both
+times, the level-0 smoother's achieved bandwidth (algorithmic bytes / mean
+launch duration from HIP events on the solver's stream) and a CPU-oracle
+baseline timed on a bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time to 1e-10 rel residual, 256^3 var-coef (FP64 vs FP32+refine); smoother GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--tune", type=int, default=1, help="0 default tiles, 1 cache, 2 search")
+    p.add_argument("--aggregate", type=int, default=0)
+    p.add_argument("--cpu-cycles", type=int, default=1, help="oracle V-cycles in the CPU sample")
+    p.add_argument("--quiet", action="store_true")
+    return p.parse_args()
+
+
+def log(msg, quiet=False):
+    if not quiet:
+        print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
+              "a design, not a build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2009_12009_amd as P
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    q = args.quiet
+    t0 = time.perf_counter()
+    cfg = W.config_c1()
+    n, boxes = cfg["n"], cfg["boxes"]
+    dom = W.domain_box(n)
+    f_boxes = W.scatter_cells(cfg["rhs"], boxes)
+    rhs = P.MultiFab.from_numpy(boxes, f_boxes, 0)
+    bmf = []
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        bmf.append(P.MultiFab.from_numpy(boxes, W.scatter_faces(cfg["faces"][d], boxes, d), 0,
+                                         ixtype=tuple(e)))
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s", q)
+
+    common = dict(tune=args.tune, aggregate=args.aggregate)
+    solvers = {
+        "f64": P.MLMG(boxes, dom, cfg["periodic"], 1.0, 1.0, b=bmf, opts=dict(precision=0, **common)),
+        "f32_refine": P.MLMG(boxes, dom, cfg["periodic"], 1.0, 1.0, b=bmf,
+                             opts=dict(precision=1, **common)),
+    }
+    phis = {k: s.cell_mf(1, fill=0.0) for k, s in solvers.items()}
+    setup_ms = {k: s.solve(phis[k], rhs, 1e-10)["setup_ms"] for k, s in solvers.items()}
+
+    def step(record):
+        out = {}
+        for k, s in solvers.items():
+            phis[k].data.zero_()
+            info = s.solve(phis[k], rhs, 1e-10)
+            assert info["converged"], (k, info)
+            out[k] = info
+            if record is not None:
+                record[k].append(info)
+        return out
+
+    for _ in range(args.warmup):
+        step(None)
+    for s in solvers.values():
+        s.profile(True)
+    rec = {k: [] for k in solvers}
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t1) * 1e3
+    ms_step = wall / args.steps
+
+    # level-0 smoother: mean launch duration over the timed steps (HIP events)
+    ncell = n ** 3
+    gs = {}
+    for k, s in solvers.items():
+        tot, cnt = s.kernel_stats(P._lib.FAM_SMOOTH)
+        word = 8 if k == "f64" else 4
+        mean_ms = tot / max(cnt, 1)
+        alg_bytes = 6 * word * ncell  # phi in, phi out, f, b_x, b_y, b_z
+        gs[k] = dict(mean_ms=mean_ms, launches=cnt, bytes=alg_bytes,
+                     gbps=alg_bytes / (mean_ms * 1e-3) / 1e9 if cnt else None)
+        fam = {}
+        for name, fid in (("smooth", 0), ("residual", 1), ("exchange", 2), ("restrict", 3),
+                          ("prolong", 4), ("coarse_levels", 5), ("update", 6)):
+            t, c = s.kernel_stats(fid)
+            fam[name] = dict(ms_per_solve=t / args.steps, launches_per_solve=c / args.steps)
+        gs[k]["families"] = fam
+        s.profile(False)
+
+    # plain device copy as the achievable ceiling
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+
+    t64 = [r["solve_ms"] for r in rec["f64"]]
+    t32 = [r["solve_ms"] for r in rec["f32_refine"]]
+    result = {
+        "metric": METRIC,
+        "value": float(np.median(t64)),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "n": n, "boxes": len(boxes), "box_edge": 64,
+                   "bc": "dirichlet0", "alpha": 1.0, "beta": 1.0, "b": "exp(N(0,1)) seed 1, "
+                   "harmonic faces", "rhs": "U[-1,1] seed 2", "rel_tol": 1e-10,
+                   "nu1": 2, "nu2": 2, "levels": rec["f64"][0]["nlevels"],
+                   "bottom": "CG rel 1e-4", "tune": args.tune, "aggregate": args.aggregate},
+        "time_to_tol_ms": {"f64": float(np.median(t64)), "f32_refine": float(np.median(t32))},
+        "cycles": {"f64": rec["f64"][0]["iters"], "f32_refine": rec["f32_refine"][0]["iters"]},
+        "final_rel_resid": {"f64": rec["f64"][-1]["rel_resid"],
+                            "f32_refine": rec["f32_refine"][-1]["rel_resid"]},
+        "setup_ms": setup_ms,
+        "smoother": {k: {kk: v for kk, v in g.items() if kk != "families"} for k, g in gs.items()},
+        "time_by_family_ms": {k: g["families"] for k, g in gs.items()},
+        "copy_kernel_gbps": copy_gbps,
+    }
+    g64 = gs["f64"]
+    result["roofline"] = {
+        "bound": "hbm",
+        "achieved": g64["gbps"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": g64["gbps"] / HBM_PEAK_GBS if g64["gbps"] else None,
+        "traffic": None,
+        "kernel": "k_gsrb<double> level 0 (64 boxes of 64^3)",
+        "alg_bytes_per_launch": g64["bytes"],
+        "mean_launch_ms": g64["mean_ms"],
+    }
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(cfg, f_boxes, result["cycles"]["f64"], args, q)
+    print(json.dumps(result), flush=True)
+    for s in solvers.values():
+        s.close()
+
+
+def cpu_baseline(cfg, f_boxes, cycles, args, q):
+    """The oracle on the host: one residual plus `cpu_cycles` V-cycles at full
+    256^3 size, scaled to the cycle count of the solve."""
+    import numpy as np
+
+    import oracle as O
+    import workloads as W
+
+    boxes = cfg["boxes"]
+    lev = O.make_level(boxes, W.domain_box(cfg["n"]), cfg["periodic"], 1.0, 1.0, None,
+                       [W.scatter_faces(cfg["faces"][d], boxes, d) for d in range(3)])
+    levels = O.build_levels(lev)
+    phi = O.new_cell_data(lev)
+    opts = O.Opts()
+    t0 = time.perf_counter()
+    r0 = O.max_norm(O.residual(lev, phi, f_boxes))
+    t1 = time.perf_counter()
+    for _ in range(args.cpu_cycles):
+        O.vcycle(levels, 0, phi, f_boxes, opts)
+    t2 = time.perf_counter()
+    r1 = O.max_norm(O.residual(lev, phi, f_boxes))
+    per_cycle = (t2 - t1) / args.cpu_cycles
+    resid = t1 - t0
+    est_ms = (cycles * per_cycle + (cycles + 1) * resid) * 1e3
+    log(f"oracle: residual {resid:.2f} s, V-cycle {per_cycle:.2f} s, rho {r1 / r0:.3f}", q)
+    return {"value": est_ms, "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"{args.cpu_cycles} V-cycle(s) + 1 residual of the NumPy oracle at 256^3, "
+                      f"scaled to {cycles} cycles + {cycles + 1} residuals",
+            "host_cpus": os.cpu_count(), "oracle_cycle_s": per_cycle, "oracle_residual_s": resid}
+
+
+if __name__ == "__main__":
+    main()

@@ -28,8 +28,8 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--tune", type=int, default=1, help="0 default tiles, 1 cache, 2 search")
-    p.add_argument("--aggregate", type=int, default=0)
+    p.add_argument("--tune", type=int, default=2, help="0 default tiles, 1 cache, 2 search")
+    p.add_argument("--aggregate", type=int, default=1)
     p.add_argument("--cpu-cycles", type=int, default=1, help="oracle V-cycles in the CPU sample")
     p.add_argument("--quiet", action="store_true")
     return p.parse_args()

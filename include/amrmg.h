@@ -241,11 +241,14 @@ int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rh
 
 /* Override the tile shape of the level-0 smoother (kernel 0: block lx x ly
  * lanes covering 2*lx x ly cells, tz planes per work-group) or of the
- * level-0 one-lane-per-cell kernels (kernel 1: lx x ly cells).  lx*ly must be
- * 64, 128 or 256 and the shape one of the tuner's candidates (lx in
- * {16,32,64} for kernel 0, {32,64,128} for kernel 1; ly, tz powers of two up
- * to 16 and 64).  Every shape gives bitwise-identical results. */
-int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz);
+ * level-0 one-lane-per-cell kernels (kernel 1: lx x ly cells); unroll = the
+ * number of planes whose loads a lane issues together (1, 2 or 4, <= tz).
+ * lx*ly must be 64, 128 or 256 and the shape one of the tuner's candidates
+ * (lx in {16,32,64} for kernel 0, {32,64,128} for kernel 1; ly a power of two
+ * up to 16 (kernel 0) or 8 (kernel 1); tz in {2,...,64}).  Every shape gives
+ * bitwise-identical results. */
+int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz,
+                      int32_t unroll);
 
 /* Free the device tables of fill_boundary's plan cache. */
 void mg_release_caches(void);

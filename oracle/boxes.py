@@ -79,7 +79,18 @@ def validate_boxarray(boxes, domain, require_cover=True):
             raise ValueError("box array does not cover the domain")
 
 
-def mg_hierarchy(boxes, domain, min_bottom_edge=4):
+def _coarsenable(bs, dom, min_bottom_edge):
+    for b in bs:
+        for d, e in enumerate(box_shape(b)):
+            if e % 2 != 0 or e // 2 < min_bottom_edge or b[0][d] % 2 != 0:
+                return False
+    for d, e in enumerate(box_shape(dom)):
+        if e % 2 != 0 or dom[0][d] % 2 != 0:
+            return False
+    return True
+
+
+def mg_hierarchy(boxes, domain, min_bottom_edge=4, aggregate=False):
     """Box arrays of the multigrid levels.
 
     Reading taken (the paper names coarsening and "blocking_factor" improving
@@ -87,23 +98,33 @@ def mg_hierarchy(boxes, domain, min_bottom_edge=4):
     rule): level l+1 is every box of level l coarsened by 2, which is done only
     while every edge of every box at level l is even and half of it is at least
     ``min_bottom_edge`` and every box (and the domain) starts at an even index,
-    so that each coarse cell has its 8 children in one box.  Returns a list of
-    ``(boxes, domain)``.
+    so that each coarse cell has its 8 children in one box.
+
+    Aggregation (the paper's "Linear Solvers" section: merging boxes at a level
+    of the hierarchy to allow further coarsening): when that rule stops and
+    ``aggregate`` is set, a level whose boxes cover its domain in whole 2x2x2
+    blocks gets a next level made of the single box coarsen(domain) (if the
+    domain passes the rule), and coarsening continues from there.
+
+    Returns a list of ``(boxes, domain, merged)``; ``merged`` marks a level
+    that is one box covering several boxes of the level above.
     """
-    levels = [(list(boxes), domain)]
+    levels = [(list(boxes), domain, False)]
     while True:
-        bs, dom = levels[-1]
-        ok = True
-        for b in bs:
-            for d, e in enumerate(box_shape(b)):
-                if e % 2 != 0 or e // 2 < min_bottom_edge or b[0][d] % 2 != 0:
-                    ok = False
-        for d, e in enumerate(box_shape(dom)):
-            if e % 2 != 0 or dom[0][d] % 2 != 0:
-                ok = False
-        if not ok:
+        bs, dom, _ = levels[-1]
+        if _coarsenable(bs, dom, min_bottom_edge):
+            levels.append(([coarsen_box(b) for b in bs], coarsen_box(dom), False))
+            continue
+        if not aggregate or len(bs) == 1:
             break
-        levels.append(([coarsen_box(b) for b in bs], coarsen_box(dom)))
+        ncell = sum(int(np.prod(box_shape(b))) for b in bs)
+        even = all(b[0][d] % 2 == 0 and box_shape(b)[d] % 2 == 0 for b in bs for d in range(3))
+        if not even or ncell != int(np.prod(box_shape(dom))):
+            break
+        if not _coarsenable([dom], dom, min_bottom_edge):
+            break
+        cd = coarsen_box(dom)
+        levels.append(([cd], cd, True))
     return levels
 
 

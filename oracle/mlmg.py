@@ -50,6 +50,7 @@ class Level:
     a: list            # per box, valid shape; None means a == 1
     b: list            # b[d][box], face arrays (valid shape + e_d)
     dtype: type = np.float64
+    merged: bool = False   # one box covering several boxes of the level above
     _stencil: list = field(default=None, repr=False)
 
 
@@ -81,29 +82,50 @@ def valid(arr, ng=NG):
     return arr[ng:-ng, ng:-ng, ng:-ng] if ng > 0 else arr
 
 
-def coarsen_level(lev):
+def _parent(lev_c, ib):
+    """Box of the coarse level holding the coarsened fine box ib."""
+    return 0 if lev_c.merged else ib
+
+
+def _place(out, ib_parent, lev_c, sub, fine_box, extra=(0, 0, 0), ng=0):
+    """Write ``sub`` (an array over coarsen(fine_box), grown by ``extra`` at the
+    high end) into the coarse box's array at the matching position."""
+    clo = coarsen_box(fine_box)[0]
+    plo = lev_c.boxes[ib_parent][0]
+    sl = tuple(slice(clo[a] - plo[a] + ng, clo[a] - plo[a] + ng + sub.shape[a]) for a in range(3))
+    out[ib_parent][sl] = sub
+
+
+def coarsen_level(lev, merged=False):
     """Next multigrid level: boxes coarsened by 2, coefficients averaged.
 
     a_c = mean of the 8 child cells; b_c on a coarse d-face = mean of the 4 fine
-    d-faces that make it up.  Coarsening is done in float64.
+    d-faces that make it up.  Coarsening is done in float64.  With ``merged``
+    the next level is the single box coarsen(domain) and each fine box's
+    averages land in their place inside it.
     """
-    boxes = [coarsen_box(bx) for bx in lev.boxes]
+    cdom = coarsen_box(lev.domain)
+    boxes = [cdom] if merged else [coarsen_box(bx) for bx in lev.boxes]
+    h = tuple(2.0 * x for x in lev.h)
+    out = Level(boxes, cdom, lev.periodic, h, lev.alpha, lev.beta, None, None, np.float64,
+                merged)
     a = None
     if lev.a is not None:
-        a = []
-        for af in lev.a:
+        a = [np.zeros(box_shape(b)) for b in boxes]
+        for ib, af in enumerate(lev.a):
             af = af.astype(np.float64)
             z0 = ((af[0::2, 0::2, 0::2] + af[1::2, 0::2, 0::2])
                   + (af[0::2, 1::2, 0::2] + af[1::2, 1::2, 0::2]))
             z1 = ((af[0::2, 0::2, 1::2] + af[1::2, 0::2, 1::2])
                   + (af[0::2, 1::2, 1::2] + af[1::2, 1::2, 1::2]))
-            s = z0 + z1
-            a.append(s * 0.125)
+            _place(a, _parent(out, ib), out, (z0 + z1) * 0.125, lev.boxes[ib])
     b = []
     for d in range(3):
         t1, t2 = [x for x in range(3) if x != d]
-        bl = []
-        for bf in lev.b[d]:
+        e = [0, 0, 0]
+        e[d] = 1
+        bl = [np.zeros(tuple(box_shape(bx)[q] + e[q] for q in range(3))) for bx in boxes]
+        for ib, bf in enumerate(lev.b[d]):
             bf = bf.astype(np.float64)
             sl = [slice(None)] * 3
             sl[d] = slice(0, None, 2)       # fine faces 0, 2, ..., n_d lie on coarse faces
@@ -115,11 +137,11 @@ def coarsen_level(lev):
                     s2[t1] = slice(o1, None, 2)
                     s2[t2] = slice(o2, None, 2)
                     parts.append(sub[tuple(s2)])
-            bl.append(((parts[0] + parts[1]) + (parts[2] + parts[3])) * 0.25)
+            _place(bl, _parent(out, ib), out, ((parts[0] + parts[1]) + (parts[2] + parts[3])) * 0.25,
+                   lev.boxes[ib])
         b.append(bl)
-    h = tuple(2.0 * x for x in lev.h)
-    out = Level(boxes, coarsen_box(lev.domain), lev.periodic, h, lev.alpha, lev.beta, a, b,
-                np.float64)
+    out.a = a
+    out.b = b
     return out
 
 
@@ -127,7 +149,8 @@ def cast_level(lev, dtype):
     """Same level with its coefficients rounded to ``dtype``."""
     a = None if lev.a is None else [x.astype(dtype) for x in lev.a]
     b = [[x.astype(dtype) for x in lev.b[d]] for d in range(3)]
-    return Level(lev.boxes, lev.domain, lev.periodic, lev.h, lev.alpha, lev.beta, a, b, dtype)
+    return Level(lev.boxes, lev.domain, lev.periodic, lev.h, lev.alpha, lev.beta, a, b, dtype,
+                 lev.merged)
 
 
 def stencil(lev):
@@ -239,24 +262,40 @@ def gsrb_halfsweep(lev, phi, f, colour):
         V[m] = new[m]
 
 
-def restrict(lev_f, r_f):
-    """Coarse value = mean of the 8 children (box b of the coarse level is coarsen(box b))."""
-    out = []
-    for r in r_f:
-        # pairwise: ((x pairs) + (y pairs)) per z layer, then the two z layers, so
-        # that eight equal values average back to exactly that value
-        z0 = ((r[0::2, 0::2, 0::2] + r[1::2, 0::2, 0::2]) + (r[0::2, 1::2, 0::2] + r[1::2, 1::2, 0::2]))
-        z1 = ((r[0::2, 0::2, 1::2] + r[1::2, 0::2, 1::2]) + (r[0::2, 1::2, 1::2] + r[1::2, 1::2, 1::2]))
-        s = z0 + z1
-        out.append((s * r.dtype.type(0.125)).astype(r.dtype))
+def restrict(lev_f, r_f, lev_c=None):
+    """Coarse value = mean of the 8 children.  Box b of the coarse level is
+    coarsen(box b), or, for a merged coarse level, each fine box's averages go
+    to their place in its single box."""
+    if lev_c is None or not lev_c.merged:
+        out = []
+        for r in r_f:
+            out.append(_avg8(r))
+        return out
+    out = [np.zeros(box_shape(b), dtype=r_f[0].dtype) for b in lev_c.boxes]
+    for ib, r in enumerate(r_f):
+        _place(out, 0, lev_c, _avg8(r), lev_f.boxes[ib])
     return out
 
 
-def prolong_add(phi_f, e_c):
+def _avg8(r):
+    # pairwise: ((x pairs) + (y pairs)) per z layer, then the two z layers, so
+    # that eight equal values average back to exactly that value
+    z0 = ((r[0::2, 0::2, 0::2] + r[1::2, 0::2, 0::2]) + (r[0::2, 1::2, 0::2] + r[1::2, 1::2, 0::2]))
+    z1 = ((r[0::2, 0::2, 1::2] + r[1::2, 0::2, 1::2]) + (r[0::2, 1::2, 1::2] + r[1::2, 1::2, 1::2]))
+    return ((z0 + z1) * r.dtype.type(0.125)).astype(r.dtype)
+
+
+def prolong_add(phi_f, e_c, lev_f=None, lev_c=None):
     """Fine valid cell += coarse value of its parent (piecewise-constant interpolation)."""
     for ib in range(len(phi_f)):
         V = valid(phi_f[ib])
-        E = valid(e_c[ib])
+        if lev_c is not None and lev_c.merged:
+            cb = coarsen_box(lev_f.boxes[ib])
+            plo = lev_c.boxes[0][0]
+            E = e_c[0][tuple(slice(cb[0][a] - plo[a] + NG, cb[1][a] - plo[a] + NG + 1)
+                             for a in range(3))]
+        else:
+            E = valid(e_c[ib])
         V += np.repeat(np.repeat(np.repeat(E, 2, axis=0), 2, axis=1), 2, axis=2)
 
 
@@ -337,6 +376,7 @@ class Opts:
     bottom_tol: float = 1e-4
     bottom_max_iter: int = None
     min_bottom_edge: int = 4
+    aggregate: bool = False
 
 
 def vcycle(levels, l, phi, f, opts, stats=None):
@@ -356,10 +396,10 @@ def vcycle(levels, l, phi, f, opts, stats=None):
         gsrb_halfsweep(lev, phi, f, 0)
         gsrb_halfsweep(lev, phi, f, 1)
     r = residual(lev, phi, f)
-    fc = restrict(lev, r)
+    fc = restrict(lev, r, levels[l + 1])
     ec = new_cell_data(levels[l + 1])
     vcycle(levels, l + 1, ec, fc, opts, stats)
-    prolong_add(phi, ec)
+    prolong_add(phi, ec, lev, levels[l + 1])
     for _ in range(opts.nu2):
         gsrb_halfsweep(lev, phi, f, 0)
         gsrb_halfsweep(lev, phi, f, 1)
@@ -369,13 +409,13 @@ def max_norm(u):
     return float(max(np.max(np.abs(x)) for x in u))
 
 
-def build_levels(lev0, min_bottom_edge=4):
+def build_levels(lev0, min_bottom_edge=4, aggregate=False):
     """Level 0 plus its coarsened copies, following ``boxes.mg_hierarchy``'s rule."""
     from .boxes import mg_hierarchy
-    nlev = len(mg_hierarchy(lev0.boxes, lev0.domain, min_bottom_edge))
+    hier = mg_hierarchy(lev0.boxes, lev0.domain, min_bottom_edge, aggregate)
     levels = [lev0]
-    for _ in range(nlev - 1):
-        levels.append(coarsen_level(levels[-1]))
+    for (_, _, merged) in hier[1:]:
+        levels.append(coarsen_level(levels[-1], merged))
     return levels
 
 
@@ -390,7 +430,7 @@ def solve(lev0, phi, f, rel_tol=1e-10, abs_tol=0.0, opts=None, levels=None):
     """
     opts = opts or Opts()
     if levels is None:
-        levels = build_levels(lev0, opts.min_bottom_edge)
+        levels = build_levels(lev0, opts.min_bottom_edge, opts.aggregate)
     normf = max_norm(f)
     info = {"history": [], "iters": 0, "converged": False, "bottom_iters": [],
             "nlevels": len(levels)}
@@ -433,7 +473,7 @@ def solve_refine(lev0, phi, f, rel_tol=1e-10, abs_tol=0.0, opts=None, inner_dtyp
     """
     opts = opts or Opts()
     if levels is None:
-        levels = build_levels(lev0, opts.min_bottom_edge)
+        levels = build_levels(lev0, opts.min_bottom_edge, opts.aggregate)
     inner = [cast_level(L, inner_dtype) for L in levels]
     normf = max_norm(f)
     info = {"history": [], "iters": 0, "converged": False, "bottom_iters": [],

@@ -64,28 +64,72 @@ struct Cell {
   T diag, off;
 };
 
-template <typename T, bool READ_NBR>
-__device__ __forceinline__ Cell<T> stencil_at(const StencilArgs<T>& op, const BoxInfo& B,
-                                              const BoxDims& d, const T* P, long long pc, int il,
-                                              int jl, int kl) {
-  const long long sy = d.nx + 2, sz = (long long)(d.nx + 2) * (d.ny + 2);
-  const long long fx = il + (long long)(d.nx + 1) * (jl + (long long)d.ny * kl);
-  const long long fy = il + (long long)d.nx * (jl + (long long)(d.ny + 1) * kl);
-  const long long fz = il + (long long)d.nx * (jl + (long long)d.ny * kl);
-  const T* bx = op.b0 + B.off_f[0];
-  const T* by = op.b1 + B.off_f[1];
-  const T* bz = op.b2 + B.off_f[2];
-  const T cxl = (op.beta * bx[fx]) * op.ih0;
-  const T cxh = (op.beta * bx[fx + 1]) * op.ih0;
-  const T cyl = (op.beta * by[fy]) * op.ih1;
-  const T cyh = (op.beta * by[fy + d.nx]) * op.ih1;
-  const T czl = (op.beta * bz[fz]) * op.ih2;
-  const T czh = (op.beta * bz[fz + (long long)d.nx * d.ny]) * op.ih2;
-  const int m = B.bcmask;
-  const bool wxl = (m & 1) && il == 0, wxh = (m & 2) && il == d.nx - 1;
-  const bool wyl = (m & 4) && jl == 0, wyh = (m & 8) && jl == d.ny - 1;
-  const bool wzl = (m & 16) && kl == 0, wzh = (m & 32) && kl == d.nz - 1;
-  T diag = op.a ? op.alpha * op.a[B.off_g0 + fz] : op.alpha;
+// Values one cell's stencil needs, gathered before any arithmetic so that a
+// lane can have the loads of several cells in flight at once.
+template <typename T>
+struct Nbr {
+  T f, a, bxl, bxh, byl, byh, bzl, bzh, pc, pxl, pxh, pyl, pyh, pzl, pzh;
+};
+
+// 32-bit strides of one box's arrays (a box's grown array holds < 2^31 cells).
+struct Strides {
+  int nx, ny, nz, sy, sz, rsy, rsz;
+};
+
+__device__ __forceinline__ Strides strides_of(const BoxInfo& B, int rhs_ng) {
+  Strides s;
+  s.nx = B.hi[0] - B.lo[0] + 1;
+  s.ny = B.hi[1] - B.lo[1] + 1;
+  s.nz = B.hi[2] - B.lo[2] + 1;
+  s.sy = s.nx + 2;
+  s.sz = s.sy * (s.ny + 2);
+  s.rsy = s.nx + 2 * rhs_ng;
+  s.rsz = s.rsy * (s.ny + 2 * rhs_ng);
+  return s;
+}
+
+template <typename T, bool READ_PHI, bool READ_CENTRE>
+__device__ __forceinline__ void gather(Nbr<T>& v, const Strides& s, const T* P, const T* R,
+                                       int rhs_ng, const T* BX, const T* BY, const T* BZ,
+                                       const T* A, int il, int jl, int kl, int pc) {
+  if (R) v.f = R[(il + rhs_ng) + s.rsy * (jl + rhs_ng) + s.rsz * (kl + rhs_ng)];
+  const int fx = il + (s.nx + 1) * (jl + s.ny * kl);
+  const int fy = il + s.nx * (jl + (s.ny + 1) * kl);
+  const int fz = il + s.nx * (jl + s.ny * kl);
+  v.bxl = BX[fx];
+  v.bxh = BX[fx + 1];
+  v.byl = BY[fy];
+  v.byh = BY[fy + s.nx];
+  v.bzl = BZ[fz];
+  v.bzh = BZ[fz + s.nx * s.ny];
+  if (A) v.a = A[fz];
+  if (READ_CENTRE) v.pc = P[pc];
+  if (READ_PHI) {
+    v.pxl = P[pc - 1];
+    v.pxh = P[pc + 1];
+    v.pyl = P[pc - s.sy];
+    v.pyh = P[pc + s.sy];
+    v.pzl = P[pc - s.sz];
+    v.pzh = P[pc + s.sz];
+  }
+}
+
+// diag and neighbour sum from gathered values.  Every kernel that applies
+// the operator goes through this one function, so all of them compute the
+// same numbers for a cell.
+template <typename T, bool READ_PHI>
+__device__ __forceinline__ Cell<T> eval(const StencilArgs<T>& op, const Nbr<T>& v, bool has_a,
+                                        int m, const Strides& s, int il, int jl, int kl) {
+  const T cxl = (op.beta * v.bxl) * op.ih0;
+  const T cxh = (op.beta * v.bxh) * op.ih0;
+  const T cyl = (op.beta * v.byl) * op.ih1;
+  const T cyh = (op.beta * v.byh) * op.ih1;
+  const T czl = (op.beta * v.bzl) * op.ih2;
+  const T czh = (op.beta * v.bzh) * op.ih2;
+  const bool wxl = (m & 1) && il == 0, wxh = (m & 2) && il == s.nx - 1;
+  const bool wyl = (m & 4) && jl == 0, wyh = (m & 8) && jl == s.ny - 1;
+  const bool wzl = (m & 16) && kl == 0, wzh = (m & 32) && kl == s.nz - 1;
+  T diag = has_a ? op.alpha * v.a : op.alpha;
   diag = diag + (wxl ? T(2) * cxl : cxl);
   diag = diag + (wxh ? T(2) * cxh : cxh);
   diag = diag + (wyl ? T(2) * cyl : cyl);
@@ -93,76 +137,106 @@ __device__ __forceinline__ Cell<T> stencil_at(const StencilArgs<T>& op, const Bo
   diag = diag + (wzl ? T(2) * czl : czl);
   diag = diag + (wzh ? T(2) * czh : czh);
   T off = T(0);
-  if (READ_NBR) {
-    off = wxl ? T(0) : cxl * P[pc - 1];
-    off = off + (wxh ? T(0) : cxh * P[pc + 1]);
-    off = off + (wyl ? T(0) : cyl * P[pc - sy]);
-    off = off + (wyh ? T(0) : cyh * P[pc + sy]);
-    off = off + (wzl ? T(0) : czl * P[pc - sz]);
-    off = off + (wzh ? T(0) : czh * P[pc + sz]);
+  if (READ_PHI) {
+    off = wxl ? T(0) : cxl * v.pxl;
+    off = off + (wxh ? T(0) : cxh * v.pxh);
+    off = off + (wyl ? T(0) : cyl * v.pyl);
+    off = off + (wyh ? T(0) : cyh * v.pyh);
+    off = off + (wzl ? T(0) : czl * v.pzl);
+    off = off + (wzh ? T(0) : czh * v.pzh);
   }
   return {diag, off};
 }
 
-template <typename T>
+// Red/black half-sweep.  Cells of one colour never read each other, so a lane
+// gathers the inputs of U planes first and then updates them: U independent
+// load groups in flight per lane instead of one.
+template <typename T, int U, bool ZG>
 __global__ void __launch_bounds__(256)
     k_gsrb(const Tile* __restrict__ tiles, StencilArgs<T> op, T* __restrict__ phi,
-           const T* __restrict__ rhs, int rhs_ng, int colour, int tz, int zero_guess) {
+           const T* __restrict__ rhs, int rhs_ng, int colour, int tz) {
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = op.boxes[t.box];
-  const BoxDims d = dims(B);
   const int j = t.y0 + threadIdx.y;
   if (j > B.hi[1]) return;
+  const Strides s = strides_of(B, rhs_ng);
   const int jl = j - B.lo[1];
   const int kend = min(t.z0 + tz - 1, B.hi[2]);
   T* P = phi + B.off_g1;
   const T* R = rhs + (rhs_ng ? B.off_g1 : B.off_g0);
-  for (int k = t.z0; k <= kend; ++k) {
-    const int i = t.x0 + 2 * (int)threadIdx.x + ((colour + t.x0 + j + k) & 1);
-    if (i > B.hi[0]) continue;
-    const int il = i - B.lo[0], kl = k - B.lo[2];
-    const long long pc = cidx(d, 1, il, jl, kl);
-    const T f = R[cidx(d, rhs_ng, il, jl, kl)];
-    if (zero_guess) {
-      const Cell<T> c = stencil_at<T, false>(op, B, d, P, pc, il, jl, kl);
-      P[pc] = f / c.diag;
-    } else {
-      const Cell<T> c = stencil_at<T, true>(op, B, d, P, pc, il, jl, kl);
-      P[pc] = (f + c.off) / c.diag;
+  const T* BX = op.b0 + B.off_f[0];
+  const T* BY = op.b1 + B.off_f[1];
+  const T* BZ = op.b2 + B.off_f[2];
+  const T* A = op.a ? op.a + B.off_g0 : nullptr;
+  const int m = B.bcmask;
+  for (int k0 = t.z0; k0 <= kend; k0 += U) {
+    Nbr<T> v[U];
+    int il[U], pc[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u;
+      const int i = t.x0 + 2 * (int)threadIdx.x + ((colour + t.x0 + j + k) & 1);
+      ok[u] = k <= kend && i <= B.hi[0];
+      il[u] = i - B.lo[0];
+      pc[u] = (il[u] + 1) + s.sy * (jl + 1) + s.sz * (k - B.lo[2] + 1);
+      if (ok[u])
+        gather<T, !ZG, false>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il[u], jl, k - B.lo[2], pc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!ok[u]) continue;
+      const Cell<T> c = eval<T, !ZG>(op, v[u], A != nullptr, m, s, il[u], jl, k0 + u - B.lo[2]);
+      P[pc[u]] = ZG ? v[u].f / c.diag : (v[u].f + c.off) / c.diag;
     }
   }
 }
 
-template <typename T, typename TO>
+// out = rhs - A phi (mode 0) or A phi (mode 1), one lane per cell, U planes
+// gathered at a time; optional NaN-propagating max |out|.
+template <typename T, typename TO, int U>
 __global__ void __launch_bounds__(256)
     k_residual(const Tile* __restrict__ tiles, StencilArgs<T> op, const T* __restrict__ phi,
                const T* __restrict__ rhs, int rhs_ng, TO* __restrict__ out,
                unsigned long long* normbits, int tz, int mode) {
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = op.boxes[t.box];
-  const BoxDims d = dims(B);
   const int i = t.x0 + threadIdx.x;
   const int j = t.y0 + threadIdx.y;
   const bool act = i <= B.hi[0] && j <= B.hi[1];
-  const int kend = min(t.z0 + tz - 1, B.hi[2]);
   unsigned long long mx = 0;
   if (act) {
+    const Strides s = strides_of(B, rhs_ng);
+    const int kend = min(t.z0 + tz - 1, B.hi[2]);
     const T* P = phi + B.off_g1;
+    const T* R = mode == 0 ? rhs + (rhs_ng ? B.off_g1 : B.off_g0) : nullptr;
+    const T* BX = op.b0 + B.off_f[0];
+    const T* BY = op.b1 + B.off_f[1];
+    const T* BZ = op.b2 + B.off_f[2];
+    const T* A = op.a ? op.a + B.off_g0 : nullptr;
+    TO* O = out ? out + B.off_g0 : nullptr;
     const int il = i - B.lo[0], jl = j - B.lo[1];
-    for (int k = t.z0; k <= kend; ++k) {
-      const int kl = k - B.lo[2];
-      const long long pc = cidx(d, 1, il, jl, kl);
-      const Cell<T> c = stencil_at<T, true>(op, B, d, P, pc, il, jl, kl);
-      const T Aphi = c.diag * P[pc] - c.off;
-      T v;
-      if (mode == 0) {
-        v = rhs[(rhs_ng ? B.off_g1 : B.off_g0) + cidx(d, rhs_ng, il, jl, kl)] - Aphi;
-      } else {
-        v = Aphi;
+    const int m = B.bcmask;
+    for (int k0 = t.z0; k0 <= kend; k0 += U) {
+      Nbr<T> v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int kl = k0 + u - B.lo[2];
+        if (k0 + u <= kend)
+          gather<T, true, true>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il, jl, kl,
+                                (il + 1) + s.sy * (jl + 1) + s.sz * (kl + 1));
       }
-      if (out) out[B.off_g0 + cidx(d, 0, il, jl, kl)] = (TO)v;
-      const unsigned long long bits = absbits(v);
-      mx = bits > mx ? bits : mx;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (k0 + u > kend) continue;
+        const int kl = k0 + u - B.lo[2];
+        const Cell<T> c = eval<T, true>(op, v[u], A != nullptr, m, s, il, jl, kl);
+        const T Aphi = c.diag * v[u].pc - c.off;
+        const T r = mode == 0 ? v[u].f - Aphi : Aphi;
+        if (O) O[il + s.nx * (jl + s.ny * kl)] = (TO)r;
+        const unsigned long long bits = absbits(r);
+        mx = bits > mx ? bits : mx;
+      }
     }
   }
   if (normbits) block_max_u64(mx, normbits);
@@ -639,8 +713,15 @@ hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                        const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng, int colour,
                        int zero_guess) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gsrb<T>, dim3(ntiles), block_of(sh), 0, st, tiles, op, phi, rhs, rhs_ng,
-                     colour, sh.tz, zero_guess);
+  const dim3 g(ntiles), b = block_of(sh);
+#define GS(U, Z) \
+  hipLaunchKernelGGL((k_gsrb<T, U, Z>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng, colour, sh.tz)
+  if (zero_guess) {
+    if (sh.u >= 4) GS(4, true); else if (sh.u == 2) GS(2, true); else GS(1, true);
+  } else {
+    if (sh.u >= 4) GS(4, false); else if (sh.u == 2) GS(2, false); else GS(1, false);
+  }
+#undef GS
   return hipGetLastError();
 }
 
@@ -649,8 +730,12 @@ hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape 
                            const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
                            TO* out, unsigned long long* normbits, int mode) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_residual<T, TO>), dim3(ntiles), block_of(sh), 0, st, tiles, op, phi, rhs,
-                     rhs_ng, out, normbits, sh.tz, mode);
+  const dim3 g(ntiles), b = block_of(sh);
+#define RS(U) \
+  hipLaunchKernelGGL((k_residual<T, TO, U>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng, out, \
+                     normbits, sh.tz, mode)
+  if (sh.u >= 4) RS(4); else if (sh.u == 2) RS(2); else RS(1);
+#undef RS
   return hipGetLastError();
 }
 

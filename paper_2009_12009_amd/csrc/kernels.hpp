@@ -21,9 +21,11 @@ struct StencilArgs {
   T ih0, ih1, ih2;  // 1 / h_d^2
 };
 
-// Launch shape of a tiled kernel: block (lx, ly), each block marching tz planes.
+// Launch shape of a tiled kernel: block (lx, ly), each block marching tz
+// planes, u planes gathered per step (smoother and residual only).
 struct Shape {
   int lx, ly, tz;
+  int u = 1;
 };
 
 // Red/black Gauss-Seidel half-sweep over every box: lane (x, y) of a block

@@ -185,13 +185,13 @@ Shape shape_gsrb(int nx, int ny, int nz) {
   int lx = std::min(32, std::max(1, pow2ceil((nx + 1) / 2)));
   int ly = std::min(256 / lx, pow2ceil(ny));
   while (lx * ly < 64) ly *= 2;
-  return {lx, ly, std::min(16, nz)};
+  return {lx, ly, std::min(16, pow2ceil(nz)), 2};
 }
 Shape shape_cell(int nx, int ny, int nz) {
   int lx = std::min(64, pow2ceil(nx));
   int ly = std::min(256 / lx, pow2ceil(ny));
   while (lx * ly < 64) ly *= 2;
-  return {lx, ly, std::min(16, nz)};
+  return {lx, ly, std::min(16, pow2ceil(nz)), 2};
 }
 
 void build_fb(Level& lv, const int periodic[3], int ng) {
@@ -244,16 +244,18 @@ std::vector<Shape> gsrb_candidates() {
   std::vector<Shape> c;
   for (int lx : {16, 32, 64})
     for (int ly : {1, 2, 4, 8, 16})
-      for (int tz : {4, 8, 16, 32, 64})
-        if (shape_ok({lx, ly, tz})) c.push_back({lx, ly, tz});
+      for (int tz : {2, 4, 8, 16, 32, 64})
+        for (int u : {1, 2, 4})
+          if (shape_ok({lx, ly, tz, u}) && u <= tz) c.push_back({lx, ly, tz, u});
   return c;
 }
 std::vector<Shape> cell_candidates() {
   std::vector<Shape> c;
   for (int lx : {32, 64, 128})
     for (int ly : {1, 2, 4, 8})
-      for (int tz : {4, 8, 16, 32, 64})
-        if (shape_ok({lx, ly, tz})) c.push_back({lx, ly, tz});
+      for (int tz : {2, 4, 8, 16, 32, 64})
+        for (int u : {1, 2, 4})
+          if (shape_ok({lx, ly, tz, u}) && u <= tz) c.push_back({lx, ly, tz, u});
   return c;
 }
 
@@ -268,11 +270,33 @@ size_t tile_count(const std::vector<BoxInfo>& info, Shape sh, int tx) {
   return n;
 }
 
+size_t tile_count_c(const std::vector<BoxInfo>& info, Shape sh, int tx, bool coarse) {
+  size_t n = 0;
+  for (const BoxInfo& b : info) {
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = coarse ? floordiv(b.lo[d], 2) : b.lo[d];
+      hi[d] = coarse ? floordiv(b.hi[d], 2) : b.hi[d];
+    }
+    n += (size_t)((hi[0] - lo[0] + tx) / tx) * ((hi[1] - lo[1] + sh.ly) / sh.ly) *
+         ((hi[2] - lo[2] + sh.tz) / sh.tz);
+  }
+  return n;
+}
+
+Shape fit_tz(const std::vector<BoxInfo>& info, Shape sh, int xmul, bool coarse) {
+  while (sh.tz > 1 && tile_count_c(info, sh, xmul * sh.lx, coarse) < 2048) sh.tz /= 2;
+  return sh;
+}
+
 // Builds every host table; with a Bump in measure mode it also lays out the
 // workspace.  Returns 0 or an error code.
 int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
   std::string err;
   if (!validate_boxes(boxes, s->domain, true, &err)) return fail(MG_ERR_INVALID_BOXARRAY, err);
+  for (const IBox& b : boxes)
+    if (grown_volume(b, 1, 0) >= (int64_t(1) << 31))
+      return fail(MG_ERR_INVALID_BOXARRAY, "a box holds 2^31 or more cells; split it");
   std::vector<LevelBoxes> hb =
       hierarchy(boxes, s->domain, s->opts.min_bottom_edge, s->opts.aggregate != 0);
   s->L.clear();
@@ -288,9 +312,14 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     int mx[3] = {1, 1, 1};
     for (const IBox& b : lv.boxes)
       for (int d = 0; d < 3; ++d) mx[d] = std::max(mx[d], ext(b, d));
-    lv.s_gsrb = shape_gsrb(mx[0], mx[1], mx[2]);
-    lv.s_cell = shape_cell(mx[0], mx[1], mx[2]);
-    lv.s_rst = shape_cell(std::max(1, mx[0] / 2), std::max(1, mx[1] / 2), std::max(1, mx[2] / 2));
+    // z-depth of a tile: as deep as 16 planes while the level still gets
+    // >= 2048 work-groups (8 per CU); coarse levels use shallow tiles so that
+    // their launches are not a handful of long serial z-marches
+    lv.s_gsrb = fit_tz(lv.info, shape_gsrb(mx[0], mx[1], mx[2]), 2, false);
+    lv.s_cell = fit_tz(lv.info, shape_cell(mx[0], mx[1], mx[2]), 1, false);
+    lv.s_rst = fit_tz(lv.info,
+                      shape_cell(std::max(1, mx[0] / 2), std::max(1, mx[1] / 2), std::max(1, mx[2] / 2)),
+                      1, true);
     make_tiles(lv.info, lv.s_gsrb, 2 * lv.s_gsrb.lx, false, lv.t_gsrb);
     make_tiles(lv.info, lv.s_cell, lv.s_cell.lx, false, lv.t_cell);
     if (l + 1 < hb.size()) make_tiles(lv.info, lv.s_rst, lv.s_rst.lx, true, lv.t_rst);
@@ -798,7 +827,7 @@ std::map<std::string, Shape> read_cache() {
   std::ifstream in(p);
   std::string key;
   Shape sh;
-  while (in >> key >> sh.lx >> sh.ly >> sh.tz) m[key] = sh;
+  while (in >> key >> sh.lx >> sh.ly >> sh.tz >> sh.u) m[key] = sh;
   return m;
 }
 
@@ -806,7 +835,9 @@ void write_cache(const std::map<std::string, Shape>& m) {
   const char* p = tune_path();
   if (!p) return;
   std::ofstream out(p);
-  for (auto& kv : m) out << kv.first << " " << kv.second.lx << " " << kv.second.ly << " " << kv.second.tz << "\n";
+  for (auto& kv : m)
+    out << kv.first << " " << kv.second.lx << " " << kv.second.ly << " " << kv.second.tz << " "
+        << kv.second.u << "\n";
 }
 
 int apply_shape(mg_solver* s, Shape sh, bool gsrb) {
@@ -931,8 +962,9 @@ int autotune(mg_solver* s) {
   if ((rc = apply_shape(s, best_g, true))) return rc;
   if ((rc = apply_shape(s, best_c, false))) return rc;
   if (s->opts.verbose)
-    fprintf(stderr, "amrmg tune: gsrb %dx%dx%d %.4f ms, resid %dx%dx%d %.4f ms\n", best_g.lx,
-            best_g.ly, best_g.tz, tg, best_c.lx, best_c.ly, best_c.tz, tr);
+    fprintf(stderr, "amrmg tune: gsrb %dx%dx%d u%d %.4f ms, resid %dx%dx%d u%d %.4f ms\n",
+            best_g.lx, best_g.ly, best_g.tz, best_g.u, tg, best_c.lx, best_c.ly, best_c.tz,
+            best_c.u, tr);
   cache[kg] = best_g;
   cache[kr] = best_c;
   write_cache(cache);
@@ -1390,12 +1422,13 @@ int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rh
   return end_call(s);
 }
 
-int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz) {
+int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz,
+                      int32_t unroll) {
   if (!s) return fail(MG_ERR_ARG, "null solver");
-  const Shape sh{lx, ly, tz};
+  const Shape sh{lx, ly, tz, unroll};
   bool found = false;
   for (Shape c : kernel == 0 ? gsrb_candidates() : cell_candidates())
-    if (c.lx == lx && c.ly == ly && c.tz == tz) found = true;
+    if (c.lx == lx && c.ly == ly && c.tz == tz && c.u == unroll) found = true;
   if ((kernel != 0 && kernel != 1) || !found) return fail(MG_ERR_ARG, "shape is not a candidate");
   return apply_shape(s, sh, kernel == 0);
 }

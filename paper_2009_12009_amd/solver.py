@@ -203,8 +203,9 @@ class MLMG:
                 "mg_kernel_stats")
         return t.value, n.value
 
-    def set_tile_shape(self, kernel, lx, ly, tz):
-        L.check(L.lib.mg_set_tile_shape(self.handle, kernel, lx, ly, tz), "mg_set_tile_shape")
+    def set_tile_shape(self, kernel, lx, ly, tz, unroll=1):
+        L.check(L.lib.mg_set_tile_shape(self.handle, kernel, lx, ly, tz, unroll),
+                "mg_set_tile_shape")
 
     def time_smoother(self, phi, rhs, reps=20):
         pm, rm = phi.c_struct(), rhs.c_struct()

@@ -35,7 +35,8 @@ def _run_pair(cfg, opts=None, rel_tol=1e-10, max_iter=100, a_cells=None, min_edg
     lev = oracle_level(cfg, a_cells=a_cells)
     ophi = O.new_cell_data(lev)
     oinfo = O.solve(lev, ophi, f_boxes, rel_tol,
-                    opts=O.Opts(bottom_tol=TIGHT, max_iter=max_iter, min_bottom_edge=min_edge))
+                    opts=O.Opts(bottom_tol=TIGHT, max_iter=max_iter, min_bottom_edge=min_edge,
+                                aggregate=bool(aggregate)))
     s.close()
     return ginfo, gphi, oinfo, W.gather_cells(ophi, boxes, n, ng=1)
 
@@ -70,6 +71,23 @@ def test_lognormal_dirichlet_64():
     cfg = W.config_lognormal(64, 32)
     g, gphi, o, ophi = _run_pair(cfg)
     assert g["converged"] and g["nlevels"] == 4
+    _check_history(g, o)
+    assert rel_l2(gphi, ophi) <= 1e-9
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("which", ["c0", "lognormal64", "uneven96"])
+def test_aggregated_hierarchy(which):
+    """Boxes merged once they stop coarsening (one box down to 4^3)."""
+    print(f"[solve] aggregated hierarchy {which}", flush=True)
+    if which == "c0":
+        cfg = W.config_c0()
+    elif which == "lognormal64":
+        cfg = W.config_lognormal(64, 16)
+    else:
+        cfg = W.config_lognormal(96, None, boxes=_uneven_boxes_96())
+    g, gphi, o, ophi = _run_pair(cfg, aggregate=1)
+    assert g["converged"] and g["nlevels"] == o["nlevels"]
     _check_history(g, o)
     assert rel_l2(gphi, ophi) <= 1e-9
 
@@ -187,7 +205,8 @@ def test_tile_shapes_and_graph_bitwise_identical():
     boxes = cfg["boxes"]
     rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(cfg["rhs"], boxes), 0)
     outs = []
-    shapes = [None, (0, 16, 4, 4), (0, 32, 8, 32), (0, 64, 4, 64), (1, 32, 2, 8), (1, 128, 2, 64)]
+    shapes = [None, (0, 16, 4, 4, 1), (0, 32, 8, 32, 2), (0, 64, 4, 64, 4), (0, 32, 2, 2, 2),
+              (1, 32, 2, 8, 1), (1, 128, 2, 64, 4), (1, 64, 4, 4, 2)]
     for graph in (1, 0):
         for sh in shapes:
             s = gpu_solver(cfg, opts=dict(max_iter=2, use_graph=graph, tune=0))

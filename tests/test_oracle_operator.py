@@ -199,3 +199,42 @@ def test_coefficient_coarsening_values():
     # coarse x-face 2 (between coarse cells 1 and 2) at (j, k) = (1, 3)
     got = [x for bx, x in zip(c.boxes, c.b[0]) if bx[0] == (0, 0, 2)][0][2, 1, 1]
     assert np.isclose(got, faces[0][4, 2:4, 6:8].mean(), rtol=1e-15)
+
+
+def test_merged_level_transfers_and_coefficients():
+    """Coarsening onto a merged single box equals coarsening the same data held
+    as one box; R P = I and P^T = 8 R hold across the merge."""
+    n = 16
+    lev8, faces, _ = _level(n, 8, (False, False, False), with_a=True)
+    one = [W.domain_box(n)]
+    lev1 = O.make_level(one, W.domain_box(n), (False,) * 3, 1.0, 1.0,
+                        [W.gather_cells(lev8.a, lev8.boxes, n)],
+                        [W.scatter_faces(faces[d], one, d) for d in range(3)])
+    cm = O.coarsen_level(lev8, merged=True)
+    c1 = O.coarsen_level(lev1)
+    assert cm.boxes == c1.boxes and cm.merged
+    assert np.array_equal(cm.a[0], c1.a[0])
+    for d in range(3):
+        assert np.array_equal(cm.b[d][0], c1.b[d][0])
+    rng = np.random.default_rng(9)
+    ec = rng.standard_normal((n // 2,) * 3)
+    phi = W.scatter_cells(np.zeros((n, n, n)), lev8.boxes, 1)
+    O.prolong_add(phi, W.scatter_cells(ec, cm.boxes, 1), lev8, cm)
+    Pe = W.gather_cells(phi, lev8.boxes, n, ng=1)
+    assert np.array_equal(Pe, np.repeat(np.repeat(np.repeat(ec, 2, 0), 2, 1), 2, 2))
+    RPe = O.restrict(lev8, W.scatter_cells(Pe, lev8.boxes), cm)[0]
+    assert np.array_equal(RPe, ec)
+    r = rng.standard_normal((n, n, n))
+    Rr = O.restrict(lev8, W.scatter_cells(r, lev8.boxes), cm)[0]
+    assert abs(np.sum(Pe * r) - 8 * np.sum(ec * Rr)) <= 1e-12 * np.sum(np.abs(Pe * r))
+
+
+def test_aggregated_hierarchy_depths():
+    def depth(boxes, n, m=4):
+        return [O.box_shape(b[1])[0] for b in O.mg_hierarchy(boxes, W.domain_box(n), m, True)]
+    assert depth(W.uniform_boxes(256, 64), 256) == [256, 128, 64, 32, 16, 8, 4]
+    assert depth(W.uniform_boxes(32, 16), 32) == [32, 16, 8, 4]
+    assert depth(W.uniform_boxes(128, 64), 128) == [128, 64, 32, 16, 8, 4]
+    assert depth(W.guillotine_boxes(512), 512) == [512, 256, 128, 64, 32, 16, 8, 4]
+    h = O.mg_hierarchy(W.uniform_boxes(256, 64), W.domain_box(256), 4, True)
+    assert [m for _, _, m in h] == [False] * 5 + [True, False]

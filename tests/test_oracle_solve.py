@@ -233,3 +233,33 @@ def test_not_converged_and_zero_rhs():
     bad[0][1, 1, 1] = np.nan
     info = O.solve(lev, O.new_cell_data(lev), bad, 1e-10)
     assert not info["converged"]
+
+
+def test_aggregated_solve_matches_dense_and_plain():
+    n = 8
+    bc = W.lognormal_cells(n, 1.0, 17)
+    faces = W.harmonic_faces(bc)
+    f = W.uniform_rhs(n, 18)
+    boxes = W.uniform_boxes(n, 4)
+    lev = O.make_level(boxes, W.domain_box(n), (False,) * 3, 1.0, 1.0, None,
+                       [W.scatter_faces(faces[d], boxes, d) for d in range(3)])
+    opts = O.Opts(min_bottom_edge=2, bottom_tol=1e-12, aggregate=True)
+    phi = O.new_cell_data(lev)
+    info = O.solve(lev, phi, W.scatter_cells(f, boxes), 1e-12, opts=opts)
+    assert info["converged"] and info["nlevels"] == 3
+    x = np.linalg.solve(assemble(n, faces, 1.0, 1.0, (False,) * 3), f.ravel()).reshape(n, n, n)
+    assert np.linalg.norm(W.gather_cells(phi, boxes, n, ng=1) - x) / np.linalg.norm(x) <= 1e-10
+
+
+def test_aggregation_speeds_convergence_not_answer():
+    cfg, lev = _small_lognormal(64, 16)
+    f = W.scatter_cells(cfg["rhs"], lev.boxes)
+    p1 = O.new_cell_data(lev)
+    i1 = O.solve(lev, p1, f, 1e-10)
+    p2 = O.new_cell_data(lev)
+    i2 = O.solve(lev, p2, f, 1e-10, opts=O.Opts(aggregate=True))
+    assert i2["nlevels"] > i1["nlevels"] and i1["converged"] and i2["converged"]
+    G1 = W.gather_cells(p1, lev.boxes, 64, ng=1)
+    G2 = W.gather_cells(p2, lev.boxes, 64, ng=1)
+    assert np.linalg.norm(G1 - G2) / np.linalg.norm(G1) <= 1e-9
+    assert i2["iters"] <= i1["iters"] + 1

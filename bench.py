@@ -194,9 +194,9 @@ def cpu_baseline(cfg, f_boxes, cycles, args, q):
     boxes = cfg["boxes"]
     lev = O.make_level(boxes, W.domain_box(cfg["n"]), cfg["periodic"], 1.0, 1.0, None,
                        [W.scatter_faces(cfg["faces"][d], boxes, d) for d in range(3)])
-    levels = O.build_levels(lev)
+    levels = O.build_levels(lev, 4, bool(args.aggregate))
     phi = O.new_cell_data(lev)
-    opts = O.Opts()
+    opts = O.Opts(aggregate=bool(args.aggregate))
     t0 = time.perf_counter()
     r0 = O.max_norm(O.residual(lev, phi, f_boxes))
     t1 = time.perf_counter()

@@ -32,6 +32,9 @@ def parse():
     p.add_argument("--aggregate", type=int, default=1)
     p.add_argument("--cpu-cycles", type=int, default=1, help="oracle V-cycles in the CPU sample")
     p.add_argument("--quiet", action="store_true")
+    p.add_argument("--workload", default="c1", choices=["c1", "c2", "c3"],
+                   help="c1: the headline 256^3 line; c2: 512^3 uneven boxes, four variants; "
+                        "c3: 128^3 adjoint gradient (supplementary lines)")
     return p.parse_args()
 
 
@@ -54,6 +57,10 @@ def main():
 
     torch.cuda.set_device(0)
     q = args.quiet
+    if args.workload == "c2":
+        return bench_c2(args)
+    if args.workload == "c3":
+        return bench_c3(args)
     t0 = time.perf_counter()
     cfg = W.config_c1()
     n, boxes = cfg["n"], cfg["boxes"]
@@ -181,6 +188,129 @@ def main():
     print(json.dumps(result), flush=True)
     for s in solvers.values():
         s.close()
+
+
+def _face_mfs(P, W, cfg, boxes):
+    out = []
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        out.append(P.MultiFab.from_numpy(boxes, W.scatter_faces(cfg["faces"][d], boxes, d), 0,
+                                         ixtype=tuple(e)))
+    return out
+
+
+def bench_c2(args):
+    """512^3 guillotine boxes: {FP64, FP32+refine} x {graph + tuned tiles, plain launches with
+    default tiles}, time to 1e-10 from phi = 0 (median of the timed solves)."""
+    import numpy as np
+    import torch
+
+    import paper_2009_12009_amd as P
+    import workloads as W
+
+    t0 = time.perf_counter()
+    cfg = W.config_c2()
+    n, boxes = cfg["n"], cfg["boxes"]
+    rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(cfg["rhs"], boxes), 0)
+    bmf = _face_mfs(P, W, cfg, boxes)
+    del cfg["rhs"], cfg["bcell"]
+    log(f"c2 inputs ({len(boxes)} boxes) in {time.perf_counter() - t0:.1f} s", args.quiet)
+    edges = {}
+    for b in boxes:
+        for d in range(3):
+            e = b[1][d] - b[0][d] + 1
+            edges[e] = edges.get(e, 0) + 1
+    out = {"metric": "time to 1e-10 rel residual, 512^3 uneven boxes", "unit": "ms",
+           "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": "abec512_guillotine", "boxes": len(boxes), "edge_histogram": edges,
+                      "aggregate": args.aggregate}, "variants": {}}
+    phi = P.MultiFab(boxes, 1, fill=0.0)
+    for prec in (0, 1):
+        for fast in (1, 0):
+            name = f"{'f64' if prec == 0 else 'f32_refine'}_{'graph_tuned' if fast else 'plain'}"
+            s = P.MLMG(boxes, W.domain_box(n), cfg["periodic"], 1.0, 1.0, b=bmf,
+                       opts=dict(precision=prec, use_graph=fast, tune=2 if fast else 0,
+                                 aggregate=args.aggregate))
+            times = []
+            for k in range(args.warmup + args.steps):
+                phi.data.zero_()
+                info = s.solve(phi, rhs, 1e-10)
+                assert info["converged"], info
+                if k >= args.warmup:
+                    times.append(info["solve_ms"])
+            out["variants"][name] = {"time_to_tol_ms": float(np.median(times)),
+                                     "cycles": info["iters"], "levels": info["nlevels"],
+                                     "rel_resid": info["rel_resid"], "setup_ms": info["setup_ms"]}
+            log(f"{name}: {np.median(times):.1f} ms, {info['iters']} cycles", args.quiet)
+            s.close()
+            torch.cuda.synchronize()
+    out["value"] = out["variants"]["f64_graph_tuned"]["time_to_tol_ms"]
+    print(json.dumps(out), flush=True)
+
+
+def bench_c3(args):
+    """128^3, 8 boxes of 64^3, sigma 0.5: forward solve, backward (adjoint solve + face
+    gradient), and the face-gradient kernel's bandwidth."""
+    import numpy as np
+    import torch
+
+    import paper_2009_12009_amd as P
+    import workloads as W
+
+    cfg = W.config_c3()
+    n, boxes = cfg["n"], cfg["boxes"]
+    s = P.MLMG(boxes, W.domain_box(n), cfg["periodic"], 1.0, 1.0,
+               opts=dict(tune=2, aggregate=args.aggregate))
+    f = torch.from_numpy(np.concatenate([x.ravel(order="F") for x in
+                                         W.scatter_cells(cfg["rhs"], boxes)])).cuda()
+    logb = [torch.from_numpy(P.global_to_xfast(np.log(cfg["faces"][d]))).cuda() for d in range(3)]
+    logbt = [torch.from_numpy(P.global_to_xfast(np.log(cfg["faces_target"][d]))).cuda()
+             for d in range(3)]
+    with torch.no_grad():
+        phi_t = P.mg_solve(f, *logbt, s, 1e-10)
+    fw, bw = [], []
+    for k in range(args.warmup + args.steps):
+        fr = f.clone().requires_grad_(True)
+        lb = [x.clone().requires_grad_(True) for x in logb]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi = P.mg_solve(fr, *lb, s, 1e-10)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = 0.5 * torch.sum((phi - phi_t) ** 2)
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if k >= args.warmup:
+            fw.append((t1 - t0) * 1e3)
+            bw.append((t2 - t1) * 1e3)
+    # face-gradient kernel alone
+    ph = P.MultiFab(boxes, 1, fill=0.5)
+    lm = P.MultiFab(boxes, 1, fill=0.25)
+    for _ in range(2):
+        s.face_grad_logb_global(ph, lm)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        s.face_grad_logb_global(ph, lm)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nf = 3 * (n + 1) * n * n
+    # per face: b, grad out, and the two cells' phi and lambda (cells read ~once per direction)
+    alg = nf * 8 * 2 + 3 * 2 * n ** 3 * 8
+    out = {"metric": "adjoint gradient, 128^3 (8 boxes of 64^3)", "unit": "ms", "n_gpus": 1,
+           "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": "adjoint128", "sigma": 0.5, "rel_tol": 1e-10},
+           "value": float(np.median(fw) + np.median(bw)),
+           "forward_ms": float(np.median(fw)), "backward_ms": float(np.median(bw)),
+           "face_grad_ms": ms, "face_grad_gbps": alg / (ms * 1e-3) / 1e9,
+           "face_grad_alg_bytes": alg}
+    print(json.dumps(out), flush=True)
+    s.close()
 
 
 def cpu_baseline(cfg, f_boxes, cycles, args, q):

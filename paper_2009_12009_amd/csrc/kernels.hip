@@ -704,6 +704,95 @@ __global__ void __launch_bounds__(1024)
   if (tid == 0) *iters_out = it;
 }
 
+// Coarse cells of coarsen(fine box): mean of the 8 children or zero.
+__global__ void __launch_bounds__(256)
+    k_avgdown(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ fine,
+              const BoxInfo* __restrict__ coarse, const double* __restrict__ f, int fng,
+              double* __restrict__ c, int cng, int zero_only, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo F = fine[t.box];
+  const BoxInfo C = coarse[F.parent];
+  const BoxDims df = dims(F), dc = dims(C);
+  const int I = t.x0 + threadIdx.x, J = t.y0 + threadIdx.y;
+  if (I > fdiv2(F.hi[0]) || J > fdiv2(F.hi[1])) return;
+  const int kend = min(t.z0 + tz - 1, fdiv2(F.hi[2]));
+  const double* R = f + (fng ? F.off_g1 : F.off_g0);
+  double* Q = c + (cng ? C.off_g1 : C.off_g0);
+  const long long sy = df.nx + 2 * fng, sz = sy * (df.ny + 2 * fng);
+  for (int K = t.z0; K <= kend; ++K) {
+    const long long q = cidx(dc, cng, I - C.lo[0], J - C.lo[1], K - C.lo[2]);
+    if (zero_only) {
+      Q[q] = 0.0;
+      continue;
+    }
+    const long long b = cidx(df, fng, 2 * I - F.lo[0], 2 * J - F.lo[1], 2 * K - F.lo[2]);
+    const double z0 = (R[b] + R[b + 1]) + (R[b + sy] + R[b + sy + 1]);
+    const double z1 = (R[b + sz] + R[b + sz + 1]) + (R[b + sz + sy] + R[b + sz + sy + 1]);
+    Q[q] = (z0 + z1) * 0.125;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_cf_ghost(const CfGhost* __restrict__ g, int n, const double* __restrict__ coarse,
+               double* __restrict__ fine) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const CfGhost e = g[i];
+  const double vc = coarse[e.c];
+  double acc = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double lo = e.nb[2 * d] >= 0 ? coarse[e.nb[2 * d]] : -vc;
+    const double hi = e.nb[2 * d + 1] >= 0 ? coarse[e.nb[2 * d + 1]] : -vc;
+    const double s = 0.5 * (hi - lo);
+    acc = acc + (((e.sign >> d) & 1) ? s : -s);
+  }
+  fine[e.dst] = vc + 0.25 * acc;
+}
+
+__global__ void __launch_bounds__(256)
+    k_cf_reflux(const CfCell* __restrict__ cells, int ncell, const CfFace* __restrict__ faces,
+                const double* __restrict__ phic, const double* __restrict__ phif,
+                const double* __restrict__ bc0, const double* __restrict__ bc1,
+                const double* __restrict__ bc2, const double* __restrict__ bf0,
+                const double* __restrict__ bf1, const double* __restrict__ bf2, double beta,
+                double3 ihc, double3 ihf, double* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncell) return;
+  const CfCell cc = cells[i];
+  const double pI = phic[cc.phi_idx];
+  double acc = r[cc.r_idx];
+  for (int k = 0; k < cc.count; ++k) {
+    const CfFace f = faces[cc.first + k];
+    const double* bc = f.d == 0 ? bc0 : (f.d == 1 ? bc1 : bc2);
+    const double* bf = f.d == 0 ? bf0 : (f.d == 1 ? bf1 : bf2);
+    const double ic = f.d == 0 ? ihc.x : (f.d == 1 ? ihc.y : ihc.z);
+    const double ifn = f.d == 0 ? ihf.x : (f.d == 1 ? ihf.y : ihf.z);
+    const double c = (beta * bc[f.cb_idx]) * ic;
+    const double term_c = c * (pI - phic[f.j_idx]);
+    double fl[4];
+    for (int q = 0; q < 4; ++q) fl[q] = beta * bf[f.fb[q]] * (phif[f.fg[q]] - phif[f.fv[q]]);
+    // mean fine flux / h_c, ifn = 1 / (h_f h_c)
+    const double term_f = (((fl[0] + fl[1]) + (fl[2] + fl[3])) * 0.25) * ifn;
+    acc = acc + (term_c - term_f);
+  }
+  r[cc.r_idx] = acc;
+}
+
+__global__ void __launch_bounds__(256)
+    k_axpy_valid(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+                 double* __restrict__ v, const double* __restrict__ w, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  if (i > B.hi[0] || j > B.hi[1]) return;
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  for (int k = t.z0; k <= kend; ++k) {
+    const long long p = B.off_g1 + cidx(d, 1, i - B.lo[0], j - B.lo[1], k - B.lo[2]);
+    v[p] += w[p];
+  }
+}
+
 inline dim3 block_of(Shape sh) { return dim3(sh.lx, sh.ly, 1); }
 
 }  // namespace
@@ -893,6 +982,41 @@ hipError_t launch_face_grad(hipStream_t st, const BoxInfo* boxes, int nbox, int 
   hipLaunchKernelGGL(k_face_grad, dim3(grid_for(max_faces_per_box), nbox), dim3(256), 0, st, op, d,
                      phi, lam, out, mode, make_int3(dom_lo[0], dom_lo[1], dom_lo[2]),
                      make_int3(dom_n[0], dom_n[1], dom_n[2]), periodic_d);
+  return hipGetLastError();
+}
+
+hipError_t launch_avgdown(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                          const BoxInfo* fine, const BoxInfo* coarse, const double* f, int fng,
+                          double* c, int cng, int zero_only) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_avgdown, dim3(ntiles), block_of(sh), 0, st, tiles, fine, coarse, f, fng, c,
+                     cng, zero_only, sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_cf_ghost(hipStream_t st, const CfGhost* g, int n, const double* coarse,
+                           double* fine) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cf_ghost, dim3((n + 255) / 256), dim3(256), 0, st, g, n, coarse, fine);
+  return hipGetLastError();
+}
+
+hipError_t launch_cf_reflux(hipStream_t st, const CfCell* cells, int ncell, const CfFace* faces,
+                            const double* phic, const double* phif, const double* bc0,
+                            const double* bc1, const double* bc2, const double* bf0,
+                            const double* bf1, const double* bf2, double beta,
+                            const double ihc[3], const double ihf[3], double* r) {
+  if (ncell <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cf_reflux, dim3((ncell + 255) / 256), dim3(256), 0, st, cells, ncell,
+                     faces, phic, phif, bc0, bc1, bc2, bf0, bf1, bf2, beta,
+                     make_double3(ihc[0], ihc[1], ihc[2]), make_double3(ihf[0], ihf[1], ihf[2]), r);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                             const BoxInfo* boxes, double* v, const double* w) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy_valid, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, v, w, sh.tz);
   return hipGetLastError();
 }
 

@@ -45,4 +45,37 @@ struct FbChunk {
 
 constexpr int FB_CHUNK = 256;
 
+// A fine ghost cell filled from the coarse level: dst (element in the fine
+// array, one ghost layer) = v_C + 1/4 sum_d sigma_d (v_{C+e_d} - v_{C-e_d}) / 2.
+// c and nb[] are elements of the coarse array (ghost layer 1, each in the box
+// that owns the cell); nb[2d] / nb[2d+1] = low / high neighbour along d, -1
+// past a Dirichlet wall (then -v_C).  sign bit d set = high half along d.
+struct CfGhost {
+  long long dst;
+  long long c;
+  long long nb[6];
+  int sign;
+  int pad;
+};
+
+// An uncovered coarse cell next to the fine region: its residual (element
+// r_idx, ghost-free layout) gets, for each of its count coarse/fine faces,
+// the coarse face term put back and the mean fine flux taken off.
+struct CfCell {
+  long long r_idx;
+  long long phi_idx;  // element of the cell in the coarse array (ghost layer 1)
+  int first, count;
+};
+
+// One coarse/fine face of a CfCell: the covered neighbour J, the coarse face,
+// and the 4 fine cells of J next to the face with their ghosts in I.
+struct CfFace {
+  long long j_idx;     // coarse array element of J (ghost layer 1, J's own box)
+  long long cb_idx;    // element of the coarse face coefficient (direction d)
+  long long fv[4];     // fine array elements (ghost layer 1) of the fine cells in J
+  long long fg[4];     // fine array elements of their ghosts in I
+  long long fb[4];     // fine face coefficient elements (direction d)
+  int d, pad;
+};
+
 }  // namespace amrmg

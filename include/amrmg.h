@@ -129,6 +129,35 @@ typedef struct mg_solver mg_solver_t;
 /* Defaults listed in mg_opts_t. */
 void mg_default_opts(mg_opts_t* opts);
 
+/* Two-level composite solve (coarse level + one level refined by 2; the
+ * paper's multi-level multigrid, coarse-to-fine interpolation, averaging and
+ * refluxing of "Linear Solvers" and "Operations between levels").
+ *
+ * Coarse boxes cover the (Dirichlet-walled) domain; fine boxes, in the coarse
+ * index space refined by 2, are disjoint unions of whole coarse cells, each
+ * inside one coarse box.  Unknowns are the fine cells and the coarse cells no
+ * fine box covers; covered coarse cells hold the mean of their children.
+ * Fine ghost cells no fine box supplies are interpolated from the coarse
+ * level (central slopes, unlimited); an uncovered coarse cell's flux across
+ * a coarse/fine face is the mean of the 4 fine fluxes.  a = 1; FP64 only.
+ * bcoef_c / bcoef_f: three face MultiFabs per level, or NULL for b = 1.
+ * mg_solve_amr stops when the max-norm composite residual (fine cells and
+ * uncovered coarse cells) is <= max(rel_tol * max|rhs| over the same cells,
+ * abs_tol); phi_c, phi_f: ngrow 1 (in: guess, out: solution, covered coarse
+ * cells averaged); rhs_c, rhs_f: ngrow 0 or 1 (covered coarse rhs unused).
+ * Destroy with mg_destroy. */
+int mg_query_workspace_amr(const mg_box_t* cboxes, int32_t ncb, const mg_box_t* fboxes,
+                           int32_t nfb, const mg_geom_t* geom, const mg_opts_t* opts,
+                           size_t* bytes);
+int mg_create_amr(const mg_box_t* cboxes, int32_t ncb, const mg_box_t* fboxes, int32_t nfb,
+                  const mg_geom_t* geom, double alpha, double beta,
+                  const mg_multifab_t* const* bcoef_c, const mg_multifab_t* const* bcoef_f,
+                  const mg_opts_t* opts, void* workspace, size_t ws_bytes, void* hip_stream,
+                  mg_solver_t** out);
+int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
+                 const mg_multifab_t* rhs_c, const mg_multifab_t* rhs_f, double rel_tol,
+                 double abs_tol, mg_info_t* info, double* resid_history);
+
 /* Bytes of device workspace mg_create needs for these boxes and options
  * (has_acoef: whether a cell coefficient a will be given).  Host only; may be
  * called without a GPU.  Validates the box array like mg_create. */

@@ -10,6 +10,7 @@ from ._lib import MGError  # noqa: F401
 from .multifab import MultiFab, global_to_xfast, xfast_to_global  # noqa: F401
 from .solver import (  # noqa: F401
     MLMG,
+    CompositeMLMG,
     copy_tags,
     fill_boundary,
     num_levels,

@@ -97,6 +97,13 @@ SIGNATURES = {
                                    P(C.c_double)]),
     "mg_set_tile_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                     C.c_int32]),
+    "mg_query_workspace_amr": (C.c_int, [P(MgBox), C.c_int32, P(MgBox), C.c_int32, P(MgGeom),
+                                         P(MgOpts), P(C.c_size_t)]),
+    "mg_create_amr": (C.c_int, [P(MgBox), C.c_int32, P(MgBox), C.c_int32, P(MgGeom), C.c_double,
+                                C.c_double, P(P(MgMultiFab)), P(P(MgMultiFab)), P(MgOpts),
+                                C.c_void_p, C.c_size_t, C.c_void_p, P(C.c_void_p)]),
+    "mg_solve_amr": (C.c_int, [C.c_void_p, P(MgMultiFab), P(MgMultiFab), P(MgMultiFab),
+                               P(MgMultiFab), C.c_double, C.c_double, P(MgInfo), P(C.c_double)]),
     "mg_release_caches": (None, []),
     "mg_last_error": (C.c_char_p, []),
 }

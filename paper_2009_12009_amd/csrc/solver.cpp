@@ -151,6 +151,19 @@ struct mg_solver {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   double setup_ms = 0;
+  // two-level composite (fine level over part of the coarse level 0)
+  bool composite = false;
+  Level F;
+  std::vector<Tile> t_fcov;  // coarse cells under each fine box
+  Shape s_fcov{64, 4, 16, 1};
+  Tile* d_fcov = nullptr;
+  std::vector<CfGhost> h_ghost;
+  std::vector<CfCell> h_cfcell;
+  std::vector<CfFace> h_cfface;
+  CfGhost* d_ghost = nullptr;
+  CfCell* d_cfcell = nullptr;
+  CfFace* d_cfface = nullptr;
+  double *Rc = nullptr, *ef = nullptr, *Rf = nullptr, *rf2 = nullptr;
 };
 
 namespace {
@@ -413,6 +426,10 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     const bool bottom = l + 1 == nlev;
     if (l == 0) {
       lv.r64 = bump.take<double>(lv.n_g0);
+      if (s->composite) {
+        lv.e64 = bump.take<double>(lv.n_g1);
+        lv.rhs64 = bump.take<double>(lv.n_g0);
+      }
     } else if (!f32) {
       lv.e64 = bump.take<double>(lv.n_g1);
       lv.rhs64 = bump.take<double>(lv.n_g0);
@@ -1004,6 +1021,360 @@ bool is_singular_problem(const mg_solver* s) {
   return s->periodic[0] && s->periodic[1] && s->periodic[2] && s->alpha == 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Two-level composite: plan and cycle.
+//
+// Fine boxes live in the index space of the coarse level refined by 2; each is
+// a union of whole coarse cells inside one coarse box.  The fine level gets
+// its own box table, tiles and exchange tags; the coarse/fine coupling is
+// three tables built here: fine ghosts to interpolate, and per uncovered
+// coarse cell the coarse/fine faces whose coarse flux is replaced by the mean
+// fine flux.
+
+struct CoarseIndex {
+  IBox dom;
+  int n[3];
+  std::vector<int> owner;  // coarse cell -> box
+  const std::vector<BoxInfo>* info;
+  explicit CoarseIndex(const Level& lv) : dom(lv.domain), info(&lv.info) {
+    for (int d = 0; d < 3; ++d) n[d] = ext(dom, d);
+    owner.assign((size_t)n[0] * n[1] * n[2], -1);
+    for (int b = 0; b < lv.nbox; ++b) {
+      const IBox& B = lv.boxes[b];
+      for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+        for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+          for (int i = B.lo[0]; i <= B.hi[0]; ++i) owner[lin(i, j, k)] = b;
+    }
+  }
+  size_t lin(int i, int j, int k) const {
+    return (size_t)(i - dom.lo[0]) + (size_t)n[0] * ((j - dom.lo[1]) + (size_t)n[1] * (k - dom.lo[2]));
+  }
+  bool inside(const int p[3]) const {
+    for (int d = 0; d < 3; ++d)
+      if (p[d] < dom.lo[d] || p[d] > dom.hi[d]) return false;
+    return true;
+  }
+  long long elem(const int p[3], int ng) const {
+    const BoxInfo& B = (*info)[owner[lin(p[0], p[1], p[2])]];
+    const long long nx = B.hi[0] - B.lo[0] + 1 + 2 * ng, ny = B.hi[1] - B.lo[1] + 1 + 2 * ng;
+    return (ng ? B.off_g1 : B.off_g0) + (p[0] - B.lo[0] + ng) + nx * ((p[1] - B.lo[1] + ng) +
+                                                                      ny * (p[2] - B.lo[2] + ng));
+  }
+  long long face_elem(const int p[3], int d, int f) const {  // face f along d of cell p's box
+    const BoxInfo& B = (*info)[owner[lin(p[0], p[1], p[2])]];
+    int q[3] = {p[0], p[1], p[2]};
+    q[d] = f;
+    const long long fx = B.hi[0] - B.lo[0] + 1 + (d == 0), fy = B.hi[1] - B.lo[1] + 1 + (d == 1);
+    return B.off_f[d] + (q[0] - B.lo[0]) + fx * ((q[1] - B.lo[1]) + fy * (long long)(q[2] - B.lo[2]));
+  }
+};
+
+long long fine_elem(const BoxInfo& B, const int q[3]) {
+  const long long nx = B.hi[0] - B.lo[0] + 3, ny = B.hi[1] - B.lo[1] + 3;
+  return B.off_g1 + (q[0] - B.lo[0] + 1) + nx * ((q[1] - B.lo[1] + 1) + ny * (q[2] - B.lo[2] + 1));
+}
+long long fine_face_elem(const BoxInfo& B, int d, const int q[3]) {
+  const long long fx = B.hi[0] - B.lo[0] + 1 + (d == 0), fy = B.hi[1] - B.lo[1] + 1 + (d == 1);
+  return B.off_f[d] + (q[0] - B.lo[0]) + fx * ((q[1] - B.lo[1]) + fy * (long long)(q[2] - B.lo[2]));
+}
+
+int build_composite(mg_solver* s, const std::vector<IBox>& fboxes, Bump& bump) {
+  const Level& L0 = s->L[0];
+  IBox fdom;
+  for (int d = 0; d < 3; ++d) {
+    fdom.lo[d] = 2 * s->domain.lo[d];
+    fdom.hi[d] = 2 * s->domain.hi[d] + 1;
+  }
+  std::string err;
+  if (!validate_boxes(fboxes, fdom, false, &err)) return fail(MG_ERR_INVALID_BOXARRAY, "fine: " + err);
+  Level& F = s->F;
+  F.boxes = fboxes;
+  F.domain = fdom;
+  F.merged = false;
+  fill_info(F, fdom, s->periodic);
+  for (int b = 0; b < F.nbox; ++b) {
+    const IBox& B = fboxes[b];
+    for (int d = 0; d < 3; ++d)
+      if (((B.lo[d] % 2) + 2) % 2 != 0 || ext(B, d) % 2 != 0)
+        return fail(MG_ERR_INVALID_BOXARRAY, "fine box " + std::to_string(b) +
+                                                 " is not a union of whole coarse cells");
+    const IBox cb = coarsen(B, 2);
+    int par = -1;
+    for (int c = 0; c < L0.nbox; ++c)
+      if (same(intersect(L0.boxes[c], cb), cb)) par = c;
+    if (par < 0)
+      return fail(MG_ERR_INVALID_BOXARRAY, "fine box " + std::to_string(b) +
+                                               " does not lie inside one coarse box");
+    F.info[b].parent = par;
+    if (grown_volume(B, 1, 0) >= (int64_t(1) << 31))
+      return fail(MG_ERR_INVALID_BOXARRAY, "a fine box holds 2^31 or more cells");
+  }
+  int mx[3] = {1, 1, 1};
+  for (const IBox& b : F.boxes)
+    for (int d = 0; d < 3; ++d) mx[d] = std::max(mx[d], ext(b, d));
+  F.s_gsrb = fit_tz(F.info, shape_gsrb(mx[0], mx[1], mx[2]), 2, false);
+  F.s_cell = fit_tz(F.info, shape_cell(mx[0], mx[1], mx[2]), 1, false);
+  make_tiles(F.info, F.s_gsrb, 2 * F.s_gsrb.lx, false, F.t_gsrb);
+  make_tiles(F.info, F.s_cell, F.s_cell.lx, false, F.t_cell);
+  F.cap_gsrb = F.t_gsrb.size();
+  F.cap_cell = F.t_cell.size();
+  build_fb(F, s->periodic, 1);
+  s->s_fcov = fit_tz(F.info, shape_cell(std::max(1, mx[0] / 2), std::max(1, mx[1] / 2),
+                                        std::max(1, mx[2] / 2)), 1, true);
+  make_tiles(F.info, s->s_fcov, s->s_fcov.lx, true, s->t_fcov);
+
+  // coverage of the coarse level
+  CoarseIndex ci(L0);
+  std::vector<char> covered(ci.owner.size(), 0);
+  for (const IBox& B : fboxes) {
+    const IBox cb = coarsen(B, 2);
+    for (int k = cb.lo[2]; k <= cb.hi[2]; ++k)
+      for (int j = cb.lo[1]; j <= cb.hi[1]; ++j)
+        for (int i = cb.lo[0]; i <= cb.hi[0]; ++i) covered[ci.lin(i, j, k)] = 1;
+  }
+  // fine ghosts no fine box supplies: face slabs of each box, inside the domain,
+  // whose coarse parent is uncovered (fine boxes are unions of coarse cells)
+  s->h_ghost.clear();
+  for (int b = 0; b < F.nbox; ++b) {
+    const IBox& B = fboxes[b];
+    for (int d = 0; d < 3; ++d)
+      for (int side = -1; side <= 1; side += 2) {
+        IBox slab = B;
+        slab.lo[d] = slab.hi[d] = side < 0 ? B.lo[d] - 1 : B.hi[d] + 1;
+        for (int k = slab.lo[2]; k <= slab.hi[2]; ++k)
+          for (int j = slab.lo[1]; j <= slab.hi[1]; ++j)
+            for (int i = slab.lo[0]; i <= slab.hi[0]; ++i) {
+              const int g[3] = {i, j, k};
+              bool in = true;
+              for (int a = 0; a < 3; ++a)
+                if (g[a] < fdom.lo[a] || g[a] > fdom.hi[a]) in = false;
+              if (!in) continue;
+              const int C[3] = {floordiv(i, 2), floordiv(j, 2), floordiv(k, 2)};
+              if (covered[ci.lin(C[0], C[1], C[2])]) continue;
+              CfGhost e;
+              e.dst = fine_elem(F.info[b], g);
+              e.c = ci.elem(C, 1);
+              e.sign = 0;
+              e.pad = 0;
+              for (int a = 0; a < 3; ++a) {
+                for (int o = 0; o < 2; ++o) {
+                  int q[3] = {C[0], C[1], C[2]};
+                  q[a] += o ? 1 : -1;
+                  e.nb[2 * a + o] = ci.inside(q) ? ci.elem(q, 1) : -1;
+                }
+                if (((g[a] % 2) + 2) % 2 == 1) e.sign |= 1 << a;
+              }
+              s->h_ghost.push_back(e);
+            }
+      }
+  }
+  // coarse/fine faces grouped by uncovered coarse cell (ordered by cell index)
+  std::map<size_t, std::vector<CfFace>> byI;
+  std::map<size_t, std::pair<long long, long long>> cellIdx;
+  for (int b = 0; b < F.nbox; ++b) {
+    const IBox cb = coarsen(fboxes[b], 2);
+    for (int d = 0; d < 3; ++d)
+      for (int side = -1; side <= 1; side += 2) {
+        IBox slab = cb;
+        slab.lo[d] = slab.hi[d] = side < 0 ? cb.lo[d] - 1 : cb.hi[d] + 1;
+        for (int k = slab.lo[2]; k <= slab.hi[2]; ++k)
+          for (int j = slab.lo[1]; j <= slab.hi[1]; ++j)
+            for (int i = slab.lo[0]; i <= slab.hi[0]; ++i) {
+              const int I[3] = {i, j, k};
+              if (!ci.inside(I) || covered[ci.lin(i, j, k)]) continue;
+              int J[3] = {i, j, k};
+              J[d] -= side;
+              CfFace f;
+              f.d = d;
+              f.pad = 0;
+              f.j_idx = ci.elem(J, 1);
+              f.cb_idx = ci.face_elem(I, d, side > 0 ? I[d] : I[d] + 1);
+              int tr[2], t = 0;
+              for (int a = 0; a < 3; ++a)
+                if (a != d) tr[t++] = a;
+              int q = 0;
+              for (int o1 = 0; o1 < 2; ++o1)
+                for (int o2 = 0; o2 < 2; ++o2, ++q) {
+                  int fc[3];
+                  fc[tr[0]] = 2 * J[tr[0]] + o1;
+                  fc[tr[1]] = 2 * J[tr[1]] + o2;
+                  fc[d] = 2 * J[d] + (side < 0 ? 0 : 1);
+                  int gc[3] = {fc[0], fc[1], fc[2]};
+                  gc[d] += side;
+                  int face[3] = {fc[0], fc[1], fc[2]};
+                  if (side > 0) face[d] += 1;
+                  f.fv[q] = fine_elem(F.info[b], fc);
+                  f.fg[q] = fine_elem(F.info[b], gc);
+                  f.fb[q] = fine_face_elem(F.info[b], d, face);
+                }
+              const size_t key = ci.lin(i, j, k);
+              byI[key].push_back(f);
+              cellIdx[key] = {ci.elem(I, 0), ci.elem(I, 1)};
+            }
+      }
+  }
+  s->h_cfcell.clear();
+  s->h_cfface.clear();
+  for (auto& kv : byI) {
+    CfCell c;
+    c.r_idx = cellIdx[kv.first].first;
+    c.phi_idx = cellIdx[kv.first].second;
+    c.first = (int)s->h_cfface.size();
+    c.count = (int)kv.second.size();
+    s->h_cfcell.push_back(c);
+    for (const CfFace& f : kv.second) s->h_cfface.push_back(f);
+  }
+  // workspace
+  F.d_info = bump.take<BoxInfo>(F.info.size());
+  F.d_gsrb = bump.take<Tile>(F.t_gsrb.size());
+  F.d_cell = bump.take<Tile>(F.t_cell.size());
+  F.d_tags = bump.take<FbTag>(F.tags.size());
+  F.d_chunks = bump.take<FbChunk>(F.chunks.size());
+  for (int d = 0; d < 3; ++d) F.b64[d] = bump.take<double>(F.n_f[d]);
+  s->d_fcov = bump.take<Tile>(s->t_fcov.size());
+  s->d_ghost = bump.take<CfGhost>(s->h_ghost.size());
+  s->d_cfcell = bump.take<CfCell>(s->h_cfcell.size());
+  s->d_cfface = bump.take<CfFace>(s->h_cfface.size());
+  s->Rc = bump.take<double>(L0.n_g0);
+  s->ef = bump.take<double>(F.n_g1);
+  s->Rf = bump.take<double>(F.n_g0);
+  s->rf2 = bump.take<double>(F.n_g0);
+  s->ws_need = bump.off + 256;
+  return MG_OK;
+}
+
+int upload_composite(mg_solver* s) {
+  Level& F = s->F;
+  auto up = [&](void* d, const void* h, size_t n) -> hipError_t {
+    return n ? hipMemcpyAsync(d, h, n, hipMemcpyHostToDevice, s->st) : hipSuccess;
+  };
+  HIPTRY(up(F.d_info, F.info.data(), sizeof(BoxInfo) * F.info.size()));
+  HIPTRY(up(F.d_gsrb, F.t_gsrb.data(), sizeof(Tile) * F.t_gsrb.size()));
+  HIPTRY(up(F.d_cell, F.t_cell.data(), sizeof(Tile) * F.t_cell.size()));
+  HIPTRY(up(F.d_tags, F.tags.data(), sizeof(FbTag) * F.tags.size()));
+  HIPTRY(up(F.d_chunks, F.chunks.data(), sizeof(FbChunk) * F.chunks.size()));
+  HIPTRY(up(s->d_fcov, s->t_fcov.data(), sizeof(Tile) * s->t_fcov.size()));
+  HIPTRY(up(s->d_ghost, s->h_ghost.data(), sizeof(CfGhost) * s->h_ghost.size()));
+  HIPTRY(up(s->d_cfcell, s->h_cfcell.data(), sizeof(CfCell) * s->h_cfcell.size()));
+  HIPTRY(up(s->d_cfface, s->h_cfface.data(), sizeof(CfFace) * s->h_cfface.size()));
+  return MG_OK;
+}
+
+// fine ghosts: other fine boxes, then coarse interpolation (covered coarse
+// cells must already hold the average of their children)
+int fine_ghosts(mg_solver* s, double* fine, const double* coarse) {
+  int rc;
+  if ((rc = exchange<double>(s, s->F, fine, false))) return rc;
+  HIPTRY(launch_cf_ghost(s->st, s->d_ghost, (int)s->h_ghost.size(), coarse, fine));
+  return MG_OK;
+}
+
+int avgdown(mg_solver* s, const double* f, int fng, double* c, int cng, int zero_only) {
+  HIPTRY(launch_avgdown(s->st, s->d_fcov, (int)s->t_fcov.size(), s->s_fcov, s->F.d_info,
+                        s->L[0].d_info, f, fng, c, cng, zero_only));
+  return MG_OK;
+}
+
+// composite residual: Rf = ff - A_f phi_f, Rc = fc - A_c phi_c with refluxing,
+// covered Rc = 0 (or, with cover_from, the mean of cover_from's children).
+// Norms (when normbits != null) over fine cells and uncovered coarse cells.
+int composite_residual(mg_solver* s, double* phic, double* phif, const double* fc, int fc_ng,
+                       const double* ff, int ff_ng, double* Rc, double* Rf,
+                       unsigned long long* normbits, const double* cover_from) {
+  Level& L0 = s->L[0];
+  Level& F = s->F;
+  int rc;
+  if ((rc = avgdown(s, phif, 1, phic, 1, 0))) return rc;
+  if ((rc = exchange<double>(s, L0, phic, false))) return rc;
+  if ((rc = fine_ghosts(s, phif, phic))) return rc;
+  const StencilArgs<double> opf = stencil_of<double>(s, F, false);
+  const StencilArgs<double> opc = stencil_of<double>(s, L0, false);
+  HIPTRY((launch_residual<double, double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, opf,
+                                          phif, ff, ff_ng, Rf, normbits, 0)));
+  HIPTRY((launch_residual<double, double>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, opc,
+                                          phic, fc, fc_ng, Rc, nullptr, 0)));
+  double ihc[3], ihf[3];
+  for (int d = 0; d < 3; ++d) {
+    ihc[d] = 1.0 / (L0.h[d] * L0.h[d]);
+    ihf[d] = 1.0 / (F.h[d] * L0.h[d]);
+  }
+  HIPTRY(launch_cf_reflux(s->st, s->d_cfcell, (int)s->h_cfcell.size(), s->d_cfface, phic, phif,
+                          L0.b64[0], L0.b64[1], L0.b64[2], F.b64[0], F.b64[1], F.b64[2], s->beta,
+                          ihc, ihf, Rc));
+  if (cover_from) {
+    if ((rc = avgdown(s, cover_from, 0, Rc, 0, 0))) return rc;
+  } else {
+    if ((rc = avgdown(s, nullptr, 0, Rc, 0, 1))) return rc;
+  }
+  if (normbits)
+    HIPTRY(launch_maxabs<double>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, Rc,
+                                 0, normbits));
+  return MG_OK;
+}
+
+int fine_sweeps(mg_solver* s, double* ef, double* ec, const double* rhs, int sweeps) {
+  Level& F = s->F;
+  const StencilArgs<double> opf = stencil_of<double>(s, F, false);
+  int rc;
+  for (int k = 0; k < sweeps; ++k)
+    for (int colour = 0; colour < 2; ++colour) {
+      if ((rc = avgdown(s, ef, 1, ec, 1, 0))) return rc;
+      if ((rc = fine_ghosts(s, ef, ec))) return rc;
+      HIPTRY(launch_gsrb<double>(s->st, F.d_gsrb, (int)F.t_gsrb.size(), F.s_gsrb, opf, ef, rhs, 0,
+                                 colour, 0));
+    }
+  return MG_OK;
+}
+
+// One two-level correction of the composite residual (Rc, Rf) applied to phi.
+int composite_correction(mg_solver* s, double* phic, double* phif) {
+  Level& L0 = s->L[0];
+  Level& F = s->F;
+  int rc;
+  HIPTRY(launch_zero_valid<double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, s->ef,
+                                   1));
+  HIPTRY(launch_zero_valid<double>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info,
+                                   L0.e64, 1));
+  if ((rc = fine_sweeps(s, s->ef, L0.e64, s->Rf, s->opts.nu1))) return rc;
+  // residual the fine correction leaves: fine part into rf2, coarse part into
+  // L0.rhs64 with covered cells = mean of rf2's children
+  if ((rc = composite_residual(s, L0.e64, s->ef, s->Rc, 0, s->Rf, 0, L0.rhs64, s->rf2, nullptr,
+                               s->rf2)))
+    return rc;
+  // one coarse V-cycle from zero on the whole coarse level
+  if ((rc = coarse_cycle<double>(s, 0, false))) return rc;
+  HIPTRY(launch_prolong_add<double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info,
+                                    L0.d_info, s->ef, L0.e64));
+  if ((rc = fine_sweeps(s, s->ef, L0.e64, s->Rf, s->opts.nu2))) return rc;
+  HIPTRY(launch_axpy_valid(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, phif, s->ef));
+  HIPTRY(launch_axpy_valid(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, phic,
+                           L0.e64));
+  return avgdown(s, phif, 1, phic, 1, 0);
+}
+
+int check_mf_boxes(const std::vector<IBox>& boxes, const mg_multifab_t* mf, int ng_min, int ng_max,
+                   int face_d, const char* what) {
+  if (!mf) return fail(MG_ERR_ARG, std::string(what) + " is null");
+  if (mf->nbox != (int)boxes.size() || !mf->boxes || !mf->offsets || !mf->data)
+    return fail(MG_ERR_MISMATCH, std::string(what) + ": box count or pointers differ");
+  if (mf->dtype != MG_F64 || mf->ncomp != 1)
+    return fail(MG_ERR_MISMATCH, std::string(what) + ": must be MG_F64 with one component");
+  if (mf->ngrow < ng_min || mf->ngrow > ng_max)
+    return fail(MG_ERR_MISMATCH, std::string(what) + ": unsupported ngrow");
+  for (int d = 0; d < 3; ++d)
+    if (mf->ixtype[d] != (d == face_d ? 1 : 0))
+      return fail(MG_ERR_MISMATCH, std::string(what) + ": wrong index type");
+  int64_t off = 0;
+  for (size_t b = 0; b < boxes.size(); ++b) {
+    if (!same(to_ibox(mf->boxes[b]), boxes[b]))
+      return fail(MG_ERR_MISMATCH, std::string(what) + ": box " + std::to_string(b) + " differs");
+    if (mf->offsets[b] != off)
+      return fail(MG_ERR_MISMATCH, std::string(what) + ": non-canonical offsets");
+    off += grown_volume(boxes[b], mf->ngrow, face_d);
+  }
+  return MG_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1420,6 +1791,185 @@ int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rh
   hipEventDestroy(b);
   *mean_ms = ms / reps;
   return end_call(s);
+}
+
+static int amr_plan(mg_solver* s, const mg_box_t* cboxes, int32_t ncb, const mg_box_t* fboxes,
+                    int32_t nfb, const mg_geom_t* geom, const mg_opts_t* opts, char* ws) {
+  if (!cboxes || ncb <= 0 || !fboxes || nfb <= 0) return fail(MG_ERR_ARG, "no boxes");
+  if (opts)
+    s->opts = *opts;
+  else
+    mg_default_opts(&s->opts);
+  int rc;
+  if ((rc = check_opts(&s->opts))) return rc;
+  if (s->opts.precision != MG_PREC_F64)
+    return fail(MG_ERR_ARG, "the composite solve runs in FP64 only");
+  if ((rc = check_geom(geom, nullptr, nullptr, s))) return rc;
+  for (int d = 0; d < 3; ++d)
+    if (s->periodic[d]) return fail(MG_ERR_ARG, "the composite solve needs Dirichlet walls");
+  s->composite = true;
+  s->has_a = false;
+  std::vector<IBox> cb(ncb), fb(nfb);
+  for (int i = 0; i < ncb; ++i) cb[i] = to_ibox(cboxes[i]);
+  for (int i = 0; i < nfb; ++i) fb[i] = to_ibox(fboxes[i]);
+  Bump bump{ws};
+  if ((rc = build_plan(s, cb, bump))) return rc;
+  if ((rc = build_composite(s, fb, bump))) return rc;
+  return MG_OK;
+}
+
+int mg_query_workspace_amr(const mg_box_t* cboxes, int32_t ncb, const mg_box_t* fboxes,
+                           int32_t nfb, const mg_geom_t* geom, const mg_opts_t* opts,
+                           size_t* bytes) {
+  if (!bytes) return fail(MG_ERR_ARG, "bytes is null");
+  std::unique_ptr<mg_solver> s(new mg_solver());
+  int rc;
+  if ((rc = amr_plan(s.get(), cboxes, ncb, fboxes, nfb, geom, opts, nullptr))) return rc;
+  *bytes = s->ws_need;
+  return MG_OK;
+}
+
+int mg_create_amr(const mg_box_t* cboxes, int32_t ncb, const mg_box_t* fboxes, int32_t nfb,
+                  const mg_geom_t* geom, double alpha, double beta,
+                  const mg_multifab_t* const* bcoef_c, const mg_multifab_t* const* bcoef_f,
+                  const mg_opts_t* opts, void* workspace, size_t ws_bytes, void* hip_stream,
+                  mg_solver_t** out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!out) return fail(MG_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(MG_ERR_ARG, "alpha/beta not finite");
+  std::unique_ptr<mg_solver> s(new mg_solver());
+  int rc;
+  if ((rc = amr_plan(s.get(), cboxes, ncb, fboxes, nfb, geom, opts, nullptr))) return rc;
+  if (!workspace) return fail(MG_ERR_WORKSPACE, "workspace is null");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return fail(MG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < s->ws_need)
+    return fail(MG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(s->ws_need) +
+                                      " bytes, got " + std::to_string(ws_bytes));
+  std::unique_ptr<mg_solver> r(new mg_solver());
+  if ((rc = amr_plan(r.get(), cboxes, ncb, fboxes, nfb, geom, opts, (char*)workspace))) return rc;
+  s.swap(r);
+  set_h(s.get(), geom);
+  for (int d = 0; d < 3; ++d) s->F.h[d] = 0.5 * s->L[0].h[d];
+  s->alpha = alpha;
+  s->beta = beta;
+  s->singular = false;
+  s->ws = static_cast<char*>(workspace);
+  s->ws_bytes = ws_bytes;
+  if (bcoef_c)
+    for (int d = 0; d < 3; ++d)
+      if ((rc = check_mf(s.get(), bcoef_c[d], MG_F64, 0, 0, d, "bcoef_c"))) return rc;
+  if (bcoef_f)
+    for (int d = 0; d < 3; ++d)
+      if ((rc = check_mf_boxes(s->F.boxes, bcoef_f[d], 0, 0, d, "bcoef_f"))) return rc;
+  s->user = static_cast<hipStream_t>(hip_stream);
+  HIPTRY(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+  HIPTRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
+  HIPTRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
+  HIPTRY(hipHostMalloc((void**)&s->h_norm, 64, hipHostMallocDefault));
+  s->h_iters = reinterpret_cast<int*>(s->h_norm + 4);
+  if ((rc = begin_call(s.get()))) return rc;
+  if ((rc = upload_tables(s.get()))) return rc;
+  if ((rc = upload_composite(s.get()))) return rc;
+  if ((rc = setup_coefficients(s.get(), nullptr, bcoef_c))) return rc;
+  for (int d = 0; d < 3; ++d)
+    HIPTRY(launch_scale_faces(s->st, bcoef_f ? (const double*)bcoef_f[d]->data : nullptr,
+                              s->F.b64[d], s->F.n_f[d], 1.0));
+  if ((rc = coarsen_all(s.get()))) return rc;
+  if ((rc = autotune(s.get()))) return rc;
+  if ((rc = capture_graphs(s.get()))) return rc;
+  HIPTRY(hipStreamSynchronize(s->st));
+  if ((rc = end_call(s.get()))) return rc;
+  s->setup_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = s.release();
+  return MG_OK;
+}
+
+int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
+                 const mg_multifab_t* rhs_c, const mg_multifab_t* rhs_f, double rel_tol,
+                 double abs_tol, mg_info_t* info, double* resid_history) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!s || !s->composite) return fail(MG_ERR_ARG, "not a composite solver");
+  int rc;
+  if ((rc = check_mf(s, phi_c, MG_F64, 1, 1, -1, "phi_c"))) return rc;
+  if ((rc = check_mf(s, rhs_c, MG_F64, 0, 1, -1, "rhs_c"))) return rc;
+  if ((rc = check_mf_boxes(s->F.boxes, phi_f, 1, 1, -1, "phi_f"))) return rc;
+  if ((rc = check_mf_boxes(s->F.boxes, rhs_f, 0, 1, -1, "rhs_f"))) return rc;
+  if (!(rel_tol >= 0) || !(abs_tol >= 0)) return fail(MG_ERR_ARG, "negative tolerance");
+  if ((rc = begin_call(s))) return rc;
+  Level& L0 = s->L[0];
+  Level& F = s->F;
+  double* Pc = (double*)phi_c->data;
+  double* Pf = (double*)phi_f->data;
+  const double* Fc = (const double*)rhs_c->data;
+  const double* Ff = (const double*)rhs_f->data;
+  mg_info_t inf;
+  std::memset(&inf, 0, sizeof(inf));
+  inf.nlevels = (int)s->L.size() + 1;
+  inf.setup_ms = s->setup_ms;
+  HIPTRY(launch_fill_u64(s->st, s->d_norm, 4, 0ull));
+  HIPTRY(launch_copy_valid(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, Fc,
+                           rhs_c->ngrow, s->Rc, 0));
+  if ((rc = avgdown(s, nullptr, 0, s->Rc, 0, 1))) return rc;
+  HIPTRY(launch_maxabs<double>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, s->Rc,
+                               0, s->d_norm));
+  HIPTRY(launch_maxabs<double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, Ff,
+                               rhs_f->ngrow, s->d_norm));
+  double normf;
+  if ((rc = read_norm(s, 0, &normf))) return rc;
+  int status = MG_OK;
+  if (!std::isfinite(normf)) {
+    end_call(s);
+    return fail(MG_ERR_NAN, "rhs holds a non-finite value");
+  }
+  if (normf == 0.0) {
+    HIPTRY(launch_zero_valid<double>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info,
+                                     Pc, 1));
+    HIPTRY(launch_zero_valid<double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, Pf,
+                                     1));
+    inf.converged = 1;
+    if (resid_history) resid_history[0] = 0.0;
+  } else {
+    const double tol = std::max(rel_tol * normf, abs_tol);
+    int it = 0;
+    double rn = 0;
+    while (true) {
+      HIPTRY(launch_fill_u64(s->st, s->d_norm + 1, 1, 0ull));
+      if ((rc = composite_residual(s, Pc, Pf, Fc, rhs_c->ngrow, Ff, rhs_f->ngrow, s->Rc, s->Rf,
+                                   s->d_norm + 1, nullptr)))
+        return rc;
+      if ((rc = read_norm(s, 1, &rn))) return rc;
+      if (resid_history) resid_history[it] = rn;
+      if (s->opts.verbose) fprintf(stderr, "amrmg composite cycle %d  max|R| = %.6e\n", it, rn);
+      if (!std::isfinite(rn)) {
+        status = fail(MG_ERR_NAN, "residual norm is not finite");
+        break;
+      }
+      if (rn <= tol) {
+        inf.converged = 1;
+        break;
+      }
+      if (it == s->opts.max_iter) {
+        status = fail(MG_ERR_NOT_CONVERGED, "max_iter reached");
+        break;
+      }
+      if ((rc = composite_correction(s, Pc, Pf))) return rc;
+      ++it;
+    }
+    inf.iters = it;
+    inf.abs_resid = rn;
+    inf.rel_resid = rn / normf;
+  }
+  HIPTRY(hipMemcpyAsync(s->h_iters, s->d_iters, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPTRY(hipStreamSynchronize(s->st));
+  inf.bottom_iters = *s->h_iters;
+  if ((rc = end_call(s))) return rc;
+  inf.solve_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return status;
 }
 
 int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz,

@@ -217,3 +217,78 @@ class MLMG:
 
 def release_caches():
     L.lib.mg_release_caches()
+
+
+class CompositeMLMG:
+    """Two-level composite solve: coarse boxes covering a Dirichlet-walled domain
+    and fine boxes (coarse index space refined by 2) over part of it.
+
+    b_c / b_f: three face MultiFabs on the coarse / fine boxes, or None for b = 1."""
+
+    def __init__(self, coarse_boxes, fine_boxes, domain, alpha, beta, b_c=None, b_f=None,
+                 opts=None, prob_lo=(0.0, 0.0, 0.0), prob_hi=(1.0, 1.0, 1.0), stream=None):
+        self.boxes = [(tuple(lo), tuple(hi)) for lo, hi in coarse_boxes]
+        self.fine_boxes = [(tuple(lo), tuple(hi)) for lo, hi in fine_boxes]
+        self.domain = domain
+        self.opts = L.default_opts(**(opts or {}))
+        self._cb = L.boxes_array(self.boxes)
+        self._fb = L.boxes_array(self.fine_boxes)
+        self._geom = L.geom_struct(domain, (False, False, False), prob_lo, prob_hi)
+        n = C.c_size_t(0)
+        L.check(L.lib.mg_query_workspace_amr(self._cb, len(self.boxes), self._fb,
+                                             len(self.fine_boxes), C.byref(self._geom),
+                                             C.byref(self.opts), C.byref(n)),
+                "mg_query_workspace_amr")
+        nbytes = n.value
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        ws = (self.workspace.data_ptr() + 255) // 256 * 256
+
+        def faces(mfs):
+            if mfs is None:
+                return None, None
+            ms = [x.c_struct() for x in mfs]
+            arr = (C.POINTER(L.MgMultiFab) * 3)(*[C.pointer(x) for x in ms])
+            return C.cast(arr, C.POINTER(C.POINTER(L.MgMultiFab))), (ms, arr)
+
+        bc, keep_c = faces(b_c)
+        bf, keep_f = faces(b_f)
+        h = C.c_void_p()
+        L.check(L.lib.mg_create_amr(self._cb, len(self.boxes), self._fb, len(self.fine_boxes),
+                                    C.byref(self._geom), float(alpha), float(beta), bc, bf,
+                                    C.byref(self.opts), C.c_void_p(ws), nbytes,
+                                    _stream_handle(stream), C.byref(h)), "mg_create_amr")
+        del keep_c, keep_f
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.lib.mg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def coarse_mf(self, ngrow=0, fill=None):
+        return MultiFab(self.boxes, ngrow, fill=fill)
+
+    def fine_mf(self, ngrow=0, fill=None):
+        return MultiFab(self.fine_boxes, ngrow, fill=fill)
+
+    def solve(self, phi_c, phi_f, rhs_c, rhs_f, rel_tol=1e-10, abs_tol=0.0, history=False,
+              raise_on_fail=True):
+        pc, pf, rc, rf = phi_c.c_struct(), phi_f.c_struct(), rhs_c.c_struct(), rhs_f.c_struct()
+        info = L.MgInfo()
+        hist = (C.c_double * (self.opts.max_iter + 1))() if history else None
+        code = L.lib.mg_solve_amr(self.handle, C.byref(pc), C.byref(pf), C.byref(rc), C.byref(rf),
+                                  float(rel_tol), float(abs_tol), C.byref(info), hist)
+        if raise_on_fail and code != L.MG_OK:
+            L.check(code, "mg_solve_amr")
+        out = {"status": code, "iters": info.iters, "nlevels": info.nlevels,
+               "converged": bool(info.converged), "rel_resid": info.rel_resid,
+               "abs_resid": info.abs_resid, "setup_ms": info.setup_ms, "solve_ms": info.solve_ms}
+        if history:
+            out["history"] = list(hist[:info.iters + 1])
+        return out

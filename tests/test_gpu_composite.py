@@ -1,0 +1,150 @@
+"""GPU two-level composite solve against the oracle's composite solve, and the
+full-size two-level problem (256^3 coarse, blob-tagged fine boxes) checked by
+the oracle's composite operator."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from gpu_util import lib, rel_l2
+from oracle import composite as OC
+from workloads import amr
+
+TIGHT = 1e-12
+
+
+def _case(nc, cbox, fboxes, seed=31):
+    bc = W.lognormal_cells(nc, 1.0, seed)
+    cf = W.harmonic_faces(bc)
+    cboxes = W.uniform_boxes(nc, cbox)
+    ffaces = [amr.fine_faces(bc, cf, fboxes, d) for d in range(3)]
+    return dict(nc=nc, cboxes=cboxes, fboxes=fboxes, bc=bc, cf=cf, ffaces=ffaces)
+
+
+def _gpu(case, opts):
+    P = lib()
+    cb, fb = case["cboxes"], case["fboxes"]
+    bcm, bfm = [], []
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        bcm.append(P.MultiFab.from_numpy(cb, W.scatter_faces(case["cf"][d], cb, d), 0,
+                                         ixtype=tuple(e)))
+        bfm.append(P.MultiFab.from_numpy(fb, case["ffaces"][d], 0, ixtype=tuple(e)))
+    return P.CompositeMLMG(cb, fb, W.domain_box(case["nc"]), 1.0, 1.0, b_c=bcm, b_f=bfm,
+                           opts=opts)
+
+
+def _oracle_comp(case):
+    cb = case["cboxes"]
+    lc = O.make_level(cb, W.domain_box(case["nc"]), (False,) * 3, 1.0, 1.0, None,
+                      [W.scatter_faces(case["cf"][d], cb, d) for d in range(3)])
+    return OC.make_composite(lc, case["fboxes"], case["ffaces"])
+
+
+def _pair(case, fc, f_f, max_iter=100, rel=1e-10):
+    P = lib()
+    cb, fb = case["cboxes"], case["fboxes"]
+    s = _gpu(case, dict(bottom_rel_tol=TIGHT, min_bottom_edge=2, max_iter=max_iter))
+    rc = P.MultiFab.from_numpy(cb, W.scatter_cells(fc, cb), 0)
+    rf = P.MultiFab.from_numpy(fb, f_f, 0)
+    pc = s.coarse_mf(1, fill=0.0)
+    pf = s.fine_mf(1, fill=0.0)
+    g = s.solve(pc, pf, rc, rf, rel, history=True, raise_on_fail=False)
+    torch.cuda.synchronize()
+    comp = _oracle_comp(case)
+    opc = O.new_cell_data(comp.lc)
+    opf = O.new_cell_data(comp.lf)
+    o = OC.composite_solve(comp, opf, opc, f_f, W.scatter_cells(fc, cb), rel,
+                           opts=O.Opts(min_bottom_edge=2, bottom_tol=TIGHT, max_iter=max_iter))
+    s.close()
+    return g, pc, pf, o, opc, opf, comp
+
+
+def _patch():
+    return amr.chop([((12, 12, 12), (19, 19, 19))], 8, 2, 16)
+
+
+@pytest.mark.gpu
+def test_composite_patch_matches_oracle():
+    print("[composite] 16^3 coarse + 8^3 fine patch", flush=True)
+    case = _case(16, 8, _patch())
+    rng = np.random.default_rng(4)
+    fc = rng.uniform(-1, 1, (16,) * 3)
+    f_f = [rng.uniform(-1, 1, O.box_shape(b)) for b in case["fboxes"]]
+    g, pc, pf, o, opc, opf, comp = _pair(case, fc, f_f)
+    assert g["converged"] and o["converged"] and g["iters"] == o["iters"], (g, o["history"])
+    nf = o["normf"]
+    for a, b in zip(g["history"], o["history"]):
+        assert abs(a - b) <= 1e-6 * b + 1e-12 * nf
+    gf = np.concatenate([x.ravel() for x in pf.valid_numpy()])
+    of = np.concatenate([O.valid(x).ravel() for x in opf])
+    gc = W.gather_cells(pc.valid_numpy(), case["cboxes"], 16)
+    oc = W.gather_cells(opc, case["cboxes"], 16, ng=1)
+    assert rel_l2(gf, of) <= 1e-9 and rel_l2(gc, oc) <= 1e-9
+
+
+@pytest.mark.gpu
+def test_composite_one_cycle_elementwise():
+    print("[composite] one cycle, generated boxes 32^3", flush=True)
+    nc = 32
+    fcg = amr.blob_rhs(nc, amr.blob_centres())
+    fboxes = amr.fine_boxes(fcg, block=2, coarse_box=16)
+    case = _case(nc, 16, fboxes)
+    f_f = amr.fine_rhs(fboxes, amr.blob_centres(), 2 * nc)
+    g, pc, pf, o, opc, opf, comp = _pair(case, fcg, f_f, max_iter=1)
+    assert g["iters"] == 1
+    gf = np.concatenate([x.ravel() for x in pf.valid_numpy()])
+    of = np.concatenate([O.valid(x).ravel() for x in opf])
+    assert np.max(np.abs(gf - of)) <= 1e-12 * np.max(np.abs(of))
+    gc = W.gather_cells(pc.valid_numpy(), case["cboxes"], nc)
+    oc = W.gather_cells(opc, case["cboxes"], nc, ng=1)
+    assert np.max(np.abs(gc - oc)) <= 1e-12 * np.max(np.abs(oc))
+
+
+@pytest.mark.gpu
+def test_composite_generated_boxes_converge_to_oracle():
+    print("[composite] generated boxes 32^3 to 1e-10", flush=True)
+    nc = 32
+    fcg = amr.blob_rhs(nc, amr.blob_centres())
+    fboxes = amr.fine_boxes(fcg, block=2, coarse_box=16)
+    case = _case(nc, 16, fboxes)
+    f_f = amr.fine_rhs(fboxes, amr.blob_centres(), 2 * nc)
+    g, pc, pf, o, opc, opf, comp = _pair(case, fcg, f_f)
+    assert g["converged"] and g["iters"] == o["iters"]
+    gf = np.concatenate([x.ravel() for x in pf.valid_numpy()])
+    of = np.concatenate([O.valid(x).ravel() for x in opf])
+    assert rel_l2(gf, of) <= 1e-9
+
+
+@pytest.mark.gpu
+def test_c4_full_size_composite_residual():
+    """256^3 coarse in 64 boxes, blob-tagged fine boxes: the oracle's composite
+    operator recomputes the residual of the GPU solution on every composite cell."""
+    print("[composite] C4 256^3", flush=True)
+    P = lib()
+    cfg = amr.config_c4()
+    fboxes = cfg["fine_boxes"]
+    case = dict(nc=256, cboxes=cfg["boxes"], fboxes=fboxes, bc=cfg["bcell"], cf=cfg["faces"],
+                ffaces=[amr.fine_faces(cfg["bcell"], cfg["faces"], fboxes, d) for d in range(3)])
+    s = _gpu(case, dict(aggregate=1))
+    cb = cfg["boxes"]
+    fc_boxes = W.scatter_cells(cfg["rhs"], cb)
+    f_f = amr.fine_rhs(fboxes, cfg["centres"], 512)
+    rc = P.MultiFab.from_numpy(cb, fc_boxes, 0)
+    rf = P.MultiFab.from_numpy(fboxes, f_f, 0)
+    pc = s.coarse_mf(1, fill=0.0)
+    pf = s.fine_mf(1, fill=0.0)
+    info = s.solve(pc, pf, rc, rf, 1e-10)
+    print(f"C4: {len(fboxes)} fine boxes, {info['iters']} cycles, {info['solve_ms']:.1f} ms", flush=True)
+    assert info["converged"]
+    comp = _oracle_comp(case)
+    Rf, Rc = OC.composite_residual(comp, pf.to_numpy(), pc.to_numpy(), f_f, fc_boxes)
+    r = OC.composite_norm(comp, Rf, Rc)
+    normf = max(max(float(np.max(np.abs(x))) for x in f_f),
+                max(float(np.max(np.abs(x))) for x in fc_boxes))
+    assert r <= 1e-10 * normf * (1 + 1e-3)
+    assert abs(r - info["abs_resid"]) <= 1e-6 * r + 1e-12 * normf
+    s.close()

@@ -716,7 +716,7 @@ __global__ void __launch_bounds__(256)
   const int I = t.x0 + threadIdx.x, J = t.y0 + threadIdx.y;
   if (I > fdiv2(F.hi[0]) || J > fdiv2(F.hi[1])) return;
   const int kend = min(t.z0 + tz - 1, fdiv2(F.hi[2]));
-  const double* R = f + (fng ? F.off_g1 : F.off_g0);
+  const double* R = zero_only ? nullptr : f + (fng ? F.off_g1 : F.off_g0);
   double* Q = c + (cng ? C.off_g1 : C.off_g0);
   const long long sy = df.nx + 2 * fng, sz = sy * (df.ny + 2 * fng);
   for (int K = t.z0; K <= kend; ++K) {

@@ -32,9 +32,9 @@ def parse():
     p.add_argument("--aggregate", type=int, default=1)
     p.add_argument("--cpu-cycles", type=int, default=1, help="oracle V-cycles in the CPU sample")
     p.add_argument("--quiet", action="store_true")
-    p.add_argument("--workload", default="c1", choices=["c1", "c2", "c3"],
+    p.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"],
                    help="c1: the headline 256^3 line; c2: 512^3 uneven boxes, four variants; "
-                        "c3: 128^3 adjoint gradient (supplementary lines)")
+                        "c3: 128^3 adjoint gradient; c4: two-level composite (supplementary)")
     return p.parse_args()
 
 
@@ -61,6 +61,8 @@ def main():
         return bench_c2(args)
     if args.workload == "c3":
         return bench_c3(args)
+    if args.workload == "c4":
+        return bench_c4(args)
     t0 = time.perf_counter()
     cfg = W.config_c1()
     n, boxes = cfg["n"], cfg["boxes"]
@@ -311,6 +313,53 @@ def bench_c3(args):
            "face_grad_alg_bytes": alg}
     print(json.dumps(out), flush=True)
     s.close()
+
+
+def bench_c4(args):
+    """Two-level composite: 256^3 coarse in 64 boxes, fine boxes over the cells
+    where the 4-blob rhs exceeds half its maximum; FP64 to composite 1e-10."""
+    import numpy as np
+    import torch
+
+    import paper_2009_12009_amd as P
+    import workloads as W
+    from workloads import amr
+
+    t0 = time.perf_counter()
+    cfg = amr.config_c4()
+    cb, fb = cfg["boxes"], cfg["fine_boxes"]
+    bcm = _face_mfs(P, W, cfg, cb)
+    bfm = []
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        bfm.append(P.MultiFab.from_numpy(fb, amr.fine_faces(cfg["bcell"], cfg["faces"], fb, d), 0,
+                                         ixtype=tuple(e)))
+    rc = P.MultiFab.from_numpy(cb, W.scatter_cells(cfg["rhs"], cb), 0)
+    rf = P.MultiFab.from_numpy(fb, amr.fine_rhs(fb, cfg["centres"], 2 * cfg["n"]), 0)
+    log(f"c4 inputs ({len(fb)} fine boxes) in {time.perf_counter() - t0:.1f} s", args.quiet)
+    s = P.CompositeMLMG(cb, fb, W.domain_box(cfg["n"]), 1.0, 1.0, b_c=bcm, b_f=bfm,
+                        opts=dict(tune=2, aggregate=args.aggregate))
+    pc = s.coarse_mf(1, fill=0.0)
+    pf = s.fine_mf(1, fill=0.0)
+    times = []
+    for k in range(args.warmup + args.steps):
+        pc.data.zero_()
+        pf.data.zero_()
+        info = s.solve(pc, pf, rc, rf, 1e-10)
+        assert info["converged"], info
+        if k >= args.warmup:
+            times.append(info["solve_ms"])
+    fine_cells = sum(int(np.prod([h - l + 1 for l, h in zip(*b)])) for b in fb)
+    out = {"metric": "time to 1e-10 composite rel residual, two-level 256^3 + blob refinement",
+           "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "dtype": "f64", "value": float(np.median(times)),
+           "config": {"workload": "composite256", "fine_boxes": len(fb), "fine_cells": fine_cells,
+                      "aggregate": args.aggregate},
+           "cycles": info["iters"], "rel_resid": info["rel_resid"], "setup_ms": info["setup_ms"]}
+    print(json.dumps(out), flush=True)
+    s.close()
+    torch.cuda.synchronize()
 
 
 def cpu_baseline(cfg, f_boxes, cycles, args, q):

@@ -793,6 +793,112 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The same CG with the search direction p held in LDS and each lane's x, r, q
+// in registers (CPT cells per lane, lane l owns l, l+1024, ...): only the
+// stencil tables are read from memory inside the loop.  Same arithmetic and
+// reduction order as k_bottom_cg.
+template <typename T, int CPT>
+__global__ void __launch_bounds__(1024)
+    k_bottom_cg_lds(BottomTables bt, const T* __restrict__ diag, const T* __restrict__ coef,
+                    const T* __restrict__ rhs, T* __restrict__ out, int accumulate, double tol,
+                    int maxiter, int singular, int* iters_out) {
+  extern __shared__ unsigned char lds_raw[];
+  T* p = reinterpret_cast<T*>(lds_raw);
+  __shared__ double red[32];
+  int phase = 0;
+  const int n = bt.n;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  T x[CPT], r[CPT], q[CPT];
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < CPT; ++m) {
+    const int c = tid + m * nt;
+    x[m] = T(0);
+    r[m] = T(0);
+    if (c < n) {
+      r[m] = rhs[bt.map_rhs[c]];
+      s += (double)r[m];
+    }
+  }
+  if (singular) {
+    s = block_sum(s, red, phase);
+    const T mean = (T)(s / n);
+#pragma unroll
+    for (int m = 0; m < CPT; ++m)
+      if (tid + m * nt < n) r[m] = r[m] - mean;
+  }
+  s = 0.0;
+#pragma unroll
+  for (int m = 0; m < CPT; ++m) s += (double)r[m] * (double)r[m];
+  double rho = block_sum(s, red, phase);
+  const double bnorm = sqrt(rho);
+  int it = 0;
+  if (bnorm > 0.0) {
+#pragma unroll
+    for (int m = 0; m < CPT; ++m)
+      if (tid + m * nt < n) p[tid + m * nt] = r[m];
+    while (it < maxiter) {
+      __syncthreads();
+      s = 0.0;
+#pragma unroll
+      for (int m = 0; m < CPT; ++m) {
+        const int c = tid + m * nt;
+        q[m] = T(0);
+        if (c < n) {
+          T off = T(0);
+          for (int f = 0; f < 6; ++f) {
+            const int nb = bt.nbr[f * n + c];
+            off = off + (nb < 0 ? T(0) : coef[f * n + c] * p[nb]);
+          }
+          q[m] = diag[c] * p[c] - off;
+          s += (double)p[c] * (double)q[m];
+        }
+      }
+      const double pq = block_sum(s, red, phase);
+      const T alT = (T)(rho / pq);
+      s = 0.0;
+#pragma unroll
+      for (int m = 0; m < CPT; ++m) {
+        const int c = tid + m * nt;
+        if (c < n) {
+          x[m] = x[m] + alT * p[c];
+          r[m] = r[m] - alT * q[m];
+          s += (double)r[m] * (double)r[m];
+        }
+      }
+      ++it;
+      const double rho_new = block_sum(s, red, phase);
+      if (!(sqrt(rho_new) > tol * bnorm)) break;
+      const T btT = (T)(rho_new / rho);
+#pragma unroll
+      for (int m = 0; m < CPT; ++m) {
+        const int c = tid + m * nt;
+        if (c < n) p[c] = r[m] + btT * p[c];
+      }
+      rho = rho_new;
+    }
+  }
+  if (singular) {
+    s = 0.0;
+#pragma unroll
+    for (int m = 0; m < CPT; ++m)
+      if (tid + m * nt < n) s += (double)x[m];
+    s = block_sum(s, red, phase);
+    const T mean = (T)(s / n);
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) x[m] = x[m] - mean;
+  }
+#pragma unroll
+  for (int m = 0; m < CPT; ++m) {
+    const int c = tid + m * nt;
+    if (c < n) {
+      const long long o = bt.map_out[c];
+      out[o] = accumulate ? out[o] + x[m] : x[m];
+    }
+  }
+  if (tid == 0) *iters_out = it;
+}
+
 inline dim3 block_of(Shape sh) { return dim3(sh.lx, sh.ly, 1); }
 
 }  // namespace
@@ -1034,6 +1140,16 @@ hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* dia
                             const T* rhs, T* out, int accumulate, T* work, double tol,
                             int maxiter, int singular, int* iters_out) {
   if (bt.n <= 0) return hipSuccess;
+  const size_t lds = sizeof(T) * (size_t)bt.n;
+  if (lds <= 65536 && bt.n <= 8 * 1024) {
+#define CGL(C) \
+  hipLaunchKernelGGL((k_bottom_cg_lds<T, C>), dim3(1), dim3(1024), lds, st, bt, diag, coef, rhs, \
+                     out, accumulate, tol, maxiter, singular, iters_out)
+    if (bt.n <= 1024) CGL(1); else if (bt.n <= 2048) CGL(2); else if (bt.n <= 4096) CGL(4);
+    else CGL(8);
+#undef CGL
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_bottom_cg<T>, dim3(1), dim3(1024), 0, st, bt, diag, coef, rhs, out,
                      accumulate, work, tol, maxiter, singular, iters_out);
   return hipGetLastError();

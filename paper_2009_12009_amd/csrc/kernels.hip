@@ -1141,7 +1141,7 @@ hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* dia
                             int maxiter, int singular, int* iters_out) {
   if (bt.n <= 0) return hipSuccess;
   const size_t lds = sizeof(T) * (size_t)bt.n;
-  if (lds <= 65536 && bt.n <= 8 * 1024) {
+  if (lds <= 61440 && bt.n <= 8 * 1024) {  // stays under 64 KiB with the reduction scratch
 #define CGL(C) \
   hipLaunchKernelGGL((k_bottom_cg_lds<T, C>), dim3(1), dim3(1024), lds, st, bt, diag, coef, rhs, \
                      out, accumulate, tol, maxiter, singular, iters_out)

@@ -270,7 +270,9 @@ int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rh
 
 /* Override the tile shape of the level-0 smoother (kernel 0: block lx x ly
  * lanes covering 2*lx x ly cells, tz planes per work-group) or of the
- * level-0 one-lane-per-cell kernels (kernel 1: lx x ly cells); unroll = the
+ * level-0 one-lane-per-cell kernels (kernel 1: lx x ly cells); kernel 2 = the
+ * smoother variant that also stores each lane's unchanged pair cell, so cache
+ * lines are written whole; unroll = the
  * number of planes whose loads a lane issues together (1, 2 or 4, <= tz).
  * lx*ly must be 64, 128 or 256 and the shape one of the tuner's candidates
  * (lx in {16,32,64} for kernel 0, {32,64,128} for kernel 1; ly a power of two

@@ -151,7 +151,11 @@ __device__ __forceinline__ Cell<T> eval(const StencilArgs<T>& op, const Nbr<T>& 
 // Red/black half-sweep.  Cells of one colour never read each other, so a lane
 // gathers the inputs of U planes first and then updates them: U independent
 // load groups in flight per lane instead of one.
-template <typename T, int U, bool ZG>
+// WP: also store the unchanged other cell of the lane's x-pair (its value was
+// read as an x-neighbour), so that every cache line is written whole instead
+// of one double in two.  No other lane writes that cell in a half-sweep, so
+// the result is the same either way.
+template <typename T, int U, bool ZG, bool WP>
 __global__ void __launch_bounds__(256)
     k_gsrb(const Tile* __restrict__ tiles, StencilArgs<T> op, T* __restrict__ phi,
            const T* __restrict__ rhs, int rhs_ng, int colour, int tz) {
@@ -188,6 +192,12 @@ __global__ void __launch_bounds__(256)
       if (!ok[u]) continue;
       const Cell<T> c = eval<T, !ZG>(op, v[u], A != nullptr, m, s, il[u], jl, k0 + u - B.lo[2]);
       P[pc[u]] = ZG ? v[u].f / c.diag : (v[u].f + c.off) / c.diag;
+      if (WP && !ZG) {
+        // partner = the pair's other cell: x+1 when the active cell is the pair's first
+        const bool first = ((il[u] + B.lo[0] - t.x0) & 1) == 0;
+        const int pil = first ? il[u] + 1 : il[u] - 1;
+        if (pil >= 0 && pil < s.nx) P[first ? pc[u] + 1 : pc[u] - 1] = first ? v[u].pxh : v[u].pxl;
+      }
     }
   }
 }
@@ -909,12 +919,17 @@ hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                        int zero_guess) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 g(ntiles), b = block_of(sh);
-#define GS(U, Z) \
-  hipLaunchKernelGGL((k_gsrb<T, U, Z>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng, colour, sh.tz)
+#define GS(U, Z, W) \
+  hipLaunchKernelGGL((k_gsrb<T, U, Z, W>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng, colour, sh.tz)
   if (zero_guess) {
-    if (sh.u >= 4) GS(4, true); else if (sh.u == 2) GS(2, true); else GS(1, true);
+    if (sh.u >= 4) GS(4, true, false); else if (sh.u == 2) GS(2, true, false);
+    else GS(1, true, false);
+  } else if (sh.wp) {
+    if (sh.u >= 4) GS(4, false, true); else if (sh.u == 2) GS(2, false, true);
+    else GS(1, false, true);
   } else {
-    if (sh.u >= 4) GS(4, false); else if (sh.u == 2) GS(2, false); else GS(1, false);
+    if (sh.u >= 4) GS(4, false, false); else if (sh.u == 2) GS(2, false, false);
+    else GS(1, false, false);
   }
 #undef GS
   return hipGetLastError();

@@ -26,6 +26,7 @@ struct StencilArgs {
 struct Shape {
   int lx, ly, tz;
   int u = 1;
+  int wp = 0;  // smoother: store whole x-pairs (see k_gsrb)
 };
 
 // Red/black Gauss-Seidel half-sweep over every box: lane (x, y) of a block

@@ -259,7 +259,8 @@ std::vector<Shape> gsrb_candidates() {
     for (int ly : {1, 2, 4, 8, 16})
       for (int tz : {2, 4, 8, 16, 32, 64})
         for (int u : {1, 2, 4})
-          if (shape_ok({lx, ly, tz, u}) && u <= tz) c.push_back({lx, ly, tz, u});
+          for (int wp : {0, 1})
+            if (shape_ok({lx, ly, tz, u}) && u <= tz) c.push_back({lx, ly, tz, u, wp});
   return c;
 }
 std::vector<Shape> cell_candidates() {
@@ -844,7 +845,7 @@ std::map<std::string, Shape> read_cache() {
   std::ifstream in(p);
   std::string key;
   Shape sh;
-  while (in >> key >> sh.lx >> sh.ly >> sh.tz >> sh.u) m[key] = sh;
+  while (in >> key >> sh.lx >> sh.ly >> sh.tz >> sh.u >> sh.wp) m[key] = sh;
   return m;
 }
 
@@ -854,7 +855,7 @@ void write_cache(const std::map<std::string, Shape>& m) {
   std::ofstream out(p);
   for (auto& kv : m)
     out << kv.first << " " << kv.second.lx << " " << kv.second.ly << " " << kv.second.tz << " "
-        << kv.second.u << "\n";
+        << kv.second.u << " " << kv.second.wp << "\n";
 }
 
 int apply_shape(mg_solver* s, Shape sh, bool gsrb) {
@@ -979,9 +980,9 @@ int autotune(mg_solver* s) {
   if ((rc = apply_shape(s, best_g, true))) return rc;
   if ((rc = apply_shape(s, best_c, false))) return rc;
   if (s->opts.verbose)
-    fprintf(stderr, "amrmg tune: gsrb %dx%dx%d u%d %.4f ms, resid %dx%dx%d u%d %.4f ms\n",
-            best_g.lx, best_g.ly, best_g.tz, best_g.u, tg, best_c.lx, best_c.ly, best_c.tz,
-            best_c.u, tr);
+    fprintf(stderr, "amrmg tune: gsrb %dx%dx%d u%d wp%d %.4f ms, resid %dx%dx%d u%d %.4f ms\n",
+            best_g.lx, best_g.ly, best_g.tz, best_g.u, best_g.wp, tg, best_c.lx, best_c.ly,
+            best_c.tz, best_c.u, tr);
   cache[kg] = best_g;
   cache[kr] = best_c;
   write_cache(cache);
@@ -1975,11 +1976,14 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
 int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz,
                       int32_t unroll) {
   if (!s) return fail(MG_ERR_ARG, "null solver");
-  const Shape sh{lx, ly, tz, unroll};
+  // kernel 2: the smoother storing whole x-pairs
+  const int wp = kernel == 2 ? 1 : 0;
+  if (kernel == 2) kernel = 0;
+  const Shape sh{lx, ly, tz, unroll, wp};
   bool found = false;
   for (Shape c : kernel == 0 ? gsrb_candidates() : cell_candidates())
-    if (c.lx == lx && c.ly == ly && c.tz == tz && c.u == unroll) found = true;
-  if ((kernel != 0 && kernel != 1) || !found) return fail(MG_ERR_ARG, "shape is not a candidate");
+    if (c.lx == lx && c.ly == ly && c.tz == tz && c.u == unroll && c.wp == wp) found = true;
+  if (!found) return fail(MG_ERR_ARG, "shape is not a candidate");
   return apply_shape(s, sh, kernel == 0);
 }
 

@@ -206,7 +206,8 @@ def test_tile_shapes_and_graph_bitwise_identical():
     rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(cfg["rhs"], boxes), 0)
     outs = []
     shapes = [None, (0, 16, 4, 4, 1), (0, 32, 8, 32, 2), (0, 64, 4, 64, 4), (0, 32, 2, 2, 2),
-              (1, 32, 2, 8, 1), (1, 128, 2, 64, 4), (1, 64, 4, 4, 2)]
+              (2, 32, 4, 4, 2), (2, 16, 4, 8, 1), (1, 32, 2, 8, 1), (1, 128, 2, 64, 4),
+              (1, 64, 4, 4, 2)]
     for graph in (1, 0):
         for sh in shapes:
             s = gpu_solver(cfg, opts=dict(max_iter=2, use_graph=graph, tune=0))

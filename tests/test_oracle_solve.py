@@ -252,7 +252,7 @@ def test_aggregated_solve_matches_dense_and_plain():
 
 
 def test_aggregation_speeds_convergence_not_answer():
-    cfg, lev = _small_lognormal(64, 16)
+    cfg, lev = _small_lognormal(64, 32)
     f = W.scatter_cells(cfg["rhs"], lev.boxes)
     p1 = O.new_cell_data(lev)
     i1 = O.solve(lev, p1, f, 1e-10)

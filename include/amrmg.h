@@ -140,6 +140,7 @@ void mg_default_opts(mg_opts_t* opts);
  * Fine ghost cells no fine box supplies are interpolated from the coarse
  * level (central slopes, unlimited); an uncovered coarse cell's flux across
  * a coarse/fine face is the mean of the 4 fine fluxes.  a = 1; FP64 only.
+ * Each outer step: 2*nu1 fine sweeps, one coarse V-cycle, 2*nu2 fine sweeps.
  * bcoef_c / bcoef_f: three face MultiFabs per level, or NULL for b = 1.
  * mg_solve_amr stops when the max-norm composite residual (fine cells and
  * uncovered coarse cells) is <= max(rel_tol * max|rhs| over the same cells,

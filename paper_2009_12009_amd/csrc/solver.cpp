@@ -1336,7 +1336,10 @@ int composite_correction(mg_solver* s, double* phic, double* phif) {
                                    1));
   HIPTRY(launch_zero_valid<double>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info,
                                    L0.e64, 1));
-  if ((rc = fine_sweeps(s, s->ef, L0.e64, s->Rf, s->opts.nu1))) return rc;
+  // the fine level gets twice the sweeps of the coarse V-cycle on each side: it
+  // is a small share of the cells, and two sweeps leave its error decaying at
+  // about 0.5 per correction against about 0.35 with four
+  if ((rc = fine_sweeps(s, s->ef, L0.e64, s->Rf, 2 * s->opts.nu1))) return rc;
   // residual the fine correction leaves: fine part into rf2, coarse part into
   // L0.rhs64 with covered cells = mean of rf2's children
   if ((rc = composite_residual(s, L0.e64, s->ef, s->Rc, 0, s->Rf, 0, L0.rhs64, s->rf2, nullptr,
@@ -1346,7 +1349,7 @@ int composite_correction(mg_solver* s, double* phic, double* phif) {
   if ((rc = coarse_cycle<double>(s, 0, false))) return rc;
   HIPTRY(launch_prolong_add<double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info,
                                     L0.d_info, s->ef, L0.e64));
-  if ((rc = fine_sweeps(s, s->ef, L0.e64, s->Rf, s->opts.nu2))) return rc;
+  if ((rc = fine_sweeps(s, s->ef, L0.e64, s->Rf, 2 * s->opts.nu2))) return rc;
   HIPTRY(launch_axpy_valid(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, phif, s->ef));
   HIPTRY(launch_axpy_valid(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, phic,
                            L0.e64));

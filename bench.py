@@ -30,6 +30,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--tune", type=int, default=2, help="0 default tiles, 1 cache, 2 search")
     p.add_argument("--aggregate", type=int, default=1)
+    p.add_argument("--fused-min-edge", type=int, default=0,
+                   help="fused red/black sweeps on levels whose boxes are all this large (0 = off)")
     p.add_argument("--cpu-cycles", type=int, default=1, help="oracle V-cycles in the CPU sample")
     p.add_argument("--quiet", action="store_true")
     p.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"],
@@ -77,7 +79,7 @@ def main():
                                          ixtype=tuple(e)))
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s", q)
 
-    common = dict(tune=args.tune, aggregate=args.aggregate)
+    common = dict(tune=args.tune, aggregate=args.aggregate, fused_min_edge=args.fused_min_edge)
     solvers = {
         "f64": P.MLMG(boxes, dom, cfg["periodic"], 1.0, 1.0, b=bmf, opts=dict(precision=0, **common)),
         "f32_refine": P.MLMG(boxes, dom, cfg["periodic"], 1.0, 1.0, b=bmf,
@@ -122,10 +124,12 @@ def main():
                      gbps=alg_bytes / (mean_ms * 1e-3) / 1e9 if cnt else None)
         fam = {}
         for name, fid in (("smooth", 0), ("residual", 1), ("exchange", 2), ("restrict", 3),
-                          ("prolong", 4), ("coarse_levels", 5), ("update", 6)):
+                          ("prolong", 4), ("coarse_levels", 5), ("update", 6), ("rim", 7)):
             t, c = s.kernel_stats(fid)
             fam[name] = dict(ms_per_solve=t / args.steps, launches_per_solve=c / args.steps)
         gs[k]["families"] = fam
+        # rim launches only come with fused sweeps (the tuner may have kept half-sweeps)
+        gs[k]["fused"] = fam["rim"]["launches_per_solve"] > 0
         s.profile(False)
 
     # plain device copy as the achievable ceiling
@@ -162,7 +166,8 @@ def main():
                    "bc": "dirichlet0", "alpha": 1.0, "beta": 1.0, "b": "exp(N(0,1)) seed 1, "
                    "harmonic faces", "rhs": "U[-1,1] seed 2", "rel_tol": 1e-10,
                    "nu1": 2, "nu2": 2, "levels": rec["f64"][0]["nlevels"],
-                   "bottom": "CG rel 1e-4", "tune": args.tune, "aggregate": args.aggregate},
+                   "bottom": "CG rel 1e-4", "tune": args.tune, "aggregate": args.aggregate,
+                   "fused_min_edge": args.fused_min_edge},
         "time_to_tol_ms": {"f64": float(np.median(t64)), "f32_refine": float(np.median(t32))},
         "cycles": {"f64": rec["f64"][0]["iters"], "f32_refine": rec["f32_refine"][0]["iters"]},
         "final_rel_resid": {"f64": rec["f64"][-1]["rel_resid"],
@@ -180,7 +185,8 @@ def main():
         "unit": "GB/s",
         "frac": g64["gbps"] / HBM_PEAK_GBS if g64["gbps"] else None,
         "traffic": None,
-        "kernel": "k_gsrb<double> level 0 (64 boxes of 64^3)",
+        "kernel": ("k_sweep<double> level 0, one fused red+black sweep (64 boxes of 64^3)"
+                   if g64["fused"] else "k_gsrb<double> level 0, one half-sweep (64 boxes of 64^3)"),
         "alg_bytes_per_launch": g64["bytes"],
         "mean_launch_ms": g64["mean_ms"],
     }

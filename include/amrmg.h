@@ -108,6 +108,12 @@ typedef struct {
   int32_t aggregate;           /* [0] merge boxes once they stop coarsening and
                                       keep coarsening the merged box            */
   double bottom_rel_tol;       /* [1e-4] CG stops at ||r||2 <= tol*||rhs||2     */
+  int32_t fused_min_edge;      /* [0] levels (above the bottom) whose box
+                                      edges are all >= this run each red/black
+                                      sweep as one pass into a second buffer
+                                      plus a pass over the box boundary layers
+                                      (same result as two half-sweeps);
+                                      0 = half-sweeps everywhere               */
 } mg_opts_t;
 
 typedef struct {
@@ -257,9 +263,11 @@ int mg_num_levels(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
 /* Kernel timing.  When enabled, mg_solve records HIP events around each
  * launch of the level-0 kernels of the given family, on the solver's stream;
  * mg_kernel_stats returns the summed duration and launch count since the last
- * reset.  family: 0 smoother half-sweep, 1 residual, 2 ghost exchange,
+ * reset.  family: 0 smoother (a half-sweep, or the fused pass of a whole
+ * sweep when the level uses fused sweeps), 1 residual, 2 ghost exchange,
  * 3 restriction, 4 interpolation, 5 coarse levels (one graph or launch
- * sequence per cycle), 6 refinement update. */
+ * sequence per cycle), 6 refinement update, 7 the rim pass that ends a fused
+ * sweep. */
 int mg_profile(mg_solver_t* s, int32_t enable);
 int mg_kernel_stats(mg_solver_t* s, int32_t family, double* total_ms, int64_t* launches);
 
@@ -277,8 +285,11 @@ int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rh
  * number of planes whose loads a lane issues together (1, 2 or 4, <= tz).
  * lx*ly must be 64, 128 or 256 and the shape one of the tuner's candidates
  * (lx in {16,32,64} for kernel 0, {32,64,128} for kernel 1; ly a power of two
- * up to 16 (kernel 0) or 8 (kernel 1); tz in {2,...,64}).  Every shape gives
- * bitwise-identical results. */
+ * up to 16 (kernel 0) or 8 (kernel 1); tz in {2,...,64}).  kernel 3: the
+ * fused sweep of level 0 (lx x ly x tz cells per work-group of lx/2*ly lanes;
+ * lx in {32,64}, ly in {2,4,8,16}, tz in {4,8,16,32}, within 64 KiB of LDS;
+ * unroll ignored; MG_ERR_ARG when level 0 does not use fused sweeps).  Every
+ * shape gives bitwise-identical results. */
 int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz,
                       int32_t unroll);
 

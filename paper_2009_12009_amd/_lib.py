@@ -31,7 +31,8 @@ MG_PREC_F64 = 0
 MG_PREC_F32_REFINE = 1
 
 # profiling families (mg_kernel_stats)
-FAM_SMOOTH, FAM_RESID, FAM_EXCHANGE, FAM_RESTRICT, FAM_PROLONG, FAM_COARSE, FAM_UPDATE = range(7)
+(FAM_SMOOTH, FAM_RESID, FAM_EXCHANGE, FAM_RESTRICT, FAM_PROLONG, FAM_COARSE, FAM_UPDATE,
+ FAM_RIM) = range(8)
 
 
 class MgBox(C.Structure):
@@ -53,7 +54,8 @@ class MgOpts(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("max_iter", C.c_int32),
                 ("bottom_max_iter", C.c_int32), ("min_bottom_edge", C.c_int32),
                 ("precision", C.c_int32), ("use_graph", C.c_int32), ("tune", C.c_int32),
-                ("verbose", C.c_int32), ("aggregate", C.c_int32), ("bottom_rel_tol", C.c_double)]
+                ("verbose", C.c_int32), ("aggregate", C.c_int32), ("bottom_rel_tol", C.c_double),
+                ("fused_min_edge", C.c_int32)]
 
 
 class MgInfo(C.Structure):

@@ -202,6 +202,170 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// One full red/black sweep, out of place (see launch_sweep).  Box-local
+// coordinates throughout; colour of local cell (i, j, k) = (i+j+k+par) & 1,
+// red = 0.  LDS holds a ring of 5 old planes over the tile grown by 2 in x
+// and y (old values of both colours, ghosts included) and a ring of 3 planes
+// of new red values over the tile grown by 1.  Step k computes red on plane
+// k over the grown tile (needs old planes k-1..k+1), then black on plane
+// k-1 over the tile (needs new red on planes k-2..k) and writes plane k-1.
+// Ring sizes make two barriers per step enough: the old slot loaded at step
+// k+1 last held plane k-4, read at step k-1 at the latest, and the red slot
+// written at step k+1 last held plane k-2, read at step k before the
+// barrier that opens step k+1's red phase.
+template <typename T, bool ZG, bool NORM>
+__global__ void __launch_bounds__(256)
+    k_sweep(const Tile* __restrict__ tiles, StencilArgs<T> op, const T* __restrict__ pin,
+            T* __restrict__ pout, const T* __restrict__ rhs, int rhs_ng, int lx, int ly, int tz,
+            unsigned long long* normbits) {
+  extern __shared__ double lds_sweep[];
+  T* OLD = reinterpret_cast<T*>(lds_sweep);
+  const int W2 = lx + 4, P2 = W2 * (ly + 4);
+  const int W1 = lx + 2, P1 = W1 * (ly + 2);
+  T* RED = OLD + 5 * P2;
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = op.boxes[t.box];
+  const Strides s = strides_of(B, rhs_ng);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int x0 = t.x0 - B.lo[0], y0 = t.y0 - B.lo[1], z0 = t.z0 - B.lo[2];
+  const int x1 = min(x0 + lx, s.nx) - 1, y1 = min(y0 + ly, s.ny) - 1, z1 = min(z0 + tz, s.nz) - 1;
+  const int par = (B.lo[0] + B.lo[1] + B.lo[2]) & 1;
+  const T* Pin = pin + B.off_g1;
+  T* Pout = pout + B.off_g1;
+  const T* R = rhs + (rhs_ng ? B.off_g1 : B.off_g0);
+  const T* BX = op.b0 + B.off_f[0];
+  const T* BY = op.b1 + B.off_f[1];
+  const T* BZ = op.b2 + B.off_f[2];
+  const T* A = op.a ? op.a + B.off_g0 : nullptr;
+  const int m = B.bcmask;
+  unsigned long long mx = 0;
+
+  auto oslot = [](int k) { return ((k % 5) + 5) % 5; };
+  auto rslot = [](int k) { return ((k % 3) + 3) % 3; };
+  // old plane k (-1 <= k <= nz) over the tile grown by 2, clipped to the grown box
+  auto load = [&](int k) {
+    T* dst = OLD + oslot(k) * P2;
+    for (int q = tid; q < P2; q += nt) {
+      const int il = x0 - 2 + q % W2, jl = y0 - 2 + q / W2;
+      if (il >= -1 && il <= s.nx && jl >= -1 && jl <= s.ny)
+        dst[q] = ZG ? T(0) : Pin[(il + 1) + s.sy * (jl + 1) + s.sz * (k + 1)];
+    }
+  };
+  // old value at local (il, jl, k) from the ring
+  auto old_at = [&](int il, int jl, int k) -> T {
+    return OLD[oslot(k) * P2 + (jl - y0 + 2) * W2 + (il - x0 + 2)];
+  };
+  auto red_at = [&](int il, int jl, int k) -> T {
+    return RED[rslot(k) * P1 + (jl - y0 + 1) * W1 + (il - x0 + 1)];
+  };
+
+  const int kb = z0 - 1, ke = z1 + 1;
+  for (int k = kb - 1; k <= kb; ++k)
+    if (k >= -1 && k <= s.nz) load(k);
+  for (int k = kb; k <= ke; ++k) {
+    if (k + 1 <= s.nz) load(k + 1);
+    __syncthreads();
+    // red on plane k over the tile grown by 1 (valid cells only)
+    if (k >= 0 && k < s.nz) {
+      const int hp = W1 / 2, np = hp * (ly + 2);
+      for (int q = tid; q < np; q += nt) {
+        const int jl = y0 - 1 + q / hp;
+        const int il = x0 - 1 + 2 * (q % hp) + ((x0 - 1 + jl + k + par) & 1);
+        if (il < 0 || il >= s.nx || jl < 0 || jl >= s.ny) continue;
+        Nbr<T> v;
+        gather<T, false, false>(v, s, nullptr, R, rhs_ng, BX, BY, BZ, A, il, jl, k, 0);
+        v.pxl = old_at(il - 1, jl, k);
+        v.pxh = old_at(il + 1, jl, k);
+        v.pyl = old_at(il, jl - 1, k);
+        v.pyh = old_at(il, jl + 1, k);
+        v.pzl = old_at(il, jl, k - 1);
+        v.pzh = old_at(il, jl, k + 1);
+        const Cell<T> c = eval<T, true>(op, v, A != nullptr, m, s, il, jl, k);
+        RED[rslot(k) * P1 + (jl - y0 + 1) * W1 + (il - x0 + 1)] = (v.f + c.off) / c.diag;
+        if (NORM && il >= x0 && il <= x1 && jl >= y0 && jl <= y1 && k >= z0 && k <= z1) {
+          const T r = v.f - (c.diag * old_at(il, jl, k) - c.off);
+          const unsigned long long bits = absbits(r);
+          mx = bits > mx ? bits : mx;
+        }
+      }
+    }
+    __syncthreads();
+    // black on plane k-1 over the tile; write both cells of each x-pair
+    const int kk = k - 1;
+    if (kk >= z0 && kk <= z1) {
+      const int hp = lx / 2, np = hp * ly;
+      for (int q = tid; q < np; q += nt) {
+        const int jl = y0 + q / hp;
+        const int i0 = x0 + 2 * (q % hp);
+        if (jl > y1 || i0 > x1) continue;
+        const bool first_black = ((i0 + jl + kk + par) & 1) == 1;
+        const int ib = first_black ? i0 : i0 + 1;
+        const int ir = first_black ? i0 + 1 : i0;
+        const int base = s.sy * (jl + 1) + s.sz * (kk + 1) + 1;
+        if (ir <= x1) Pout[base + ir] = red_at(ir, jl, kk);
+        if (ib <= x1) {
+          const bool rim = ib == 0 || ib == s.nx - 1 || jl == 0 || jl == s.ny - 1 || kk == 0 ||
+                           kk == s.nz - 1;
+          Nbr<T> v;
+          if (!rim || NORM)
+            gather<T, false, false>(v, s, nullptr, R, rhs_ng, BX, BY, BZ, A, ib, jl, kk, 0);
+          T out = old_at(ib, jl, kk);
+          if (!rim) {
+            v.pxl = red_at(ib - 1, jl, kk);
+            v.pxh = red_at(ib + 1, jl, kk);
+            v.pyl = red_at(ib, jl - 1, kk);
+            v.pyh = red_at(ib, jl + 1, kk);
+            v.pzl = red_at(ib, jl, kk - 1);
+            v.pzh = red_at(ib, jl, kk + 1);
+            const Cell<T> c = eval<T, true>(op, v, A != nullptr, m, s, ib, jl, kk);
+            out = (v.f + c.off) / c.diag;
+          }
+          if (NORM) {
+            v.pxl = old_at(ib - 1, jl, kk);
+            v.pxh = old_at(ib + 1, jl, kk);
+            v.pyl = old_at(ib, jl - 1, kk);
+            v.pyh = old_at(ib, jl + 1, kk);
+            v.pzl = old_at(ib, jl, kk - 1);
+            v.pzh = old_at(ib, jl, kk + 1);
+            const Cell<T> c = eval<T, true>(op, v, A != nullptr, m, s, ib, jl, kk);
+            const T r = v.f - (c.diag * old_at(ib, jl, kk) - c.off);
+            const unsigned long long bits = absbits(r);
+            mx = bits > mx ? bits : mx;
+          }
+          Pout[base + ib] = out;
+        }
+      }
+    }
+  }
+  if (NORM) block_max_u64(mx, normbits);
+}
+
+// Black update of the rim cells left by k_sweep (phi holds new red values,
+// ghosts included).  One lane per cell of a rim tile; red lanes idle.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_rim(const RimTile* __restrict__ tiles, StencilArgs<T> op, T* __restrict__ phi,
+          const T* __restrict__ rhs, int rhs_ng) {
+  const RimTile t = tiles[blockIdx.x];
+  const int q = threadIdx.x;
+  if (q >= t.ni * t.nj * t.nk) return;
+  const BoxInfo B = op.boxes[t.box];
+  const int il = t.i0 + q % t.ni;
+  const int jl = t.j0 + (q / t.ni) % t.nj;
+  const int kl = t.k0 + q / (t.ni * t.nj);
+  if (((il + jl + kl + B.lo[0] + B.lo[1] + B.lo[2]) & 1) != 1) return;
+  const Strides s = strides_of(B, rhs_ng);
+  T* P = phi + B.off_g1;
+  const T* R = rhs + (rhs_ng ? B.off_g1 : B.off_g0);
+  const T* A = op.a ? op.a + B.off_g0 : nullptr;
+  const int pc = (il + 1) + s.sy * (jl + 1) + s.sz * (kl + 1);
+  Nbr<T> v;
+  gather<T, true, false>(v, s, P, R, rhs_ng, op.b0 + B.off_f[0], op.b1 + B.off_f[1],
+                         op.b2 + B.off_f[2], A, il, jl, kl, pc);
+  const Cell<T> c = eval<T, true>(op, v, A != nullptr, B.bcmask, s, il, jl, kl);
+  P[pc] = (v.f + c.off) / c.diag;
+}
+
 // out = rhs - A phi (mode 0) or A phi (mode 1), one lane per cell, U planes
 // gathered at a time; optional NaN-propagating max |out|.
 template <typename T, typename TO, int U>
@@ -935,6 +1099,41 @@ hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
   return hipGetLastError();
 }
 
+size_t sweep_lds_bytes(Shape sh, size_t elem) {
+  if (sh.lx < 4 || (sh.lx & 1) || sh.ly < 1 || sh.tz < 1) return 0;
+  const int nt = (sh.lx / 2) * sh.ly;
+  if (nt < 64 || nt > 256 || (nt & 63)) return 0;
+  const size_t n = 5 * (size_t)(sh.lx + 4) * (sh.ly + 4) + 3 * (size_t)(sh.lx + 2) * (sh.ly + 2);
+  const size_t b = n * elem;
+  return b <= 65536 ? b : 0;
+}
+
+template <typename T>
+hipError_t launch_sweep(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                        const StencilArgs<T>& op, const T* pin, T* pout, const T* rhs,
+                        int rhs_ng, int zero_guess, unsigned long long* normbits) {
+  if (ntiles <= 0) return hipSuccess;
+  const size_t lds = sweep_lds_bytes(sh, sizeof(T));
+  if (!lds) return hipErrorInvalidValue;
+  const dim3 g(ntiles), b((sh.lx / 2) * sh.ly);
+#define SW(Z, N)                                                                              \
+  hipLaunchKernelGGL((k_sweep<T, Z, N>), g, b, lds, st, tiles, op, pin, pout, rhs, rhs_ng,     \
+                     sh.lx, sh.ly, sh.tz, normbits)
+  if (zero_guess) SW(true, false);
+  else if (normbits) SW(false, true);
+  else SW(false, false);
+#undef SW
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rim(hipStream_t st, const RimTile* tiles, int ntiles, const StencilArgs<T>& op,
+                      T* phi, const T* rhs, int rhs_ng) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rim<T>, dim3(ntiles), dim3(256), 0, st, tiles, op, phi, rhs, rhs_ng);
+  return hipGetLastError();
+}
+
 template <typename T, typename TO>
 hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                            const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
@@ -1173,6 +1372,11 @@ hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* dia
 #define INST(T)                                                                                  \
   template hipError_t launch_gsrb<T>(hipStream_t, const Tile*, int, Shape, const StencilArgs<T>&, \
                                      T*, const T*, int, int, int);                               \
+  template hipError_t launch_sweep<T>(hipStream_t, const Tile*, int, Shape,                      \
+                                      const StencilArgs<T>&, const T*, T*, const T*, int, int,   \
+                                      unsigned long long*);                                      \
+  template hipError_t launch_rim<T>(hipStream_t, const RimTile*, int, const StencilArgs<T>&, T*, \
+                                    const T*, int);                                              \
   template hipError_t launch_maxabs<T>(hipStream_t, const Tile*, int, Shape, const BoxInfo*,     \
                                        const T*, int, unsigned long long*);                      \
   template hipError_t launch_restrict<T>(hipStream_t, const Tile*, int, Shape, const BoxInfo*,   \

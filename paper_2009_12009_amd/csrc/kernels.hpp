@@ -38,6 +38,29 @@ hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                        const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng, int colour,
                        int zero_guess);
 
+// One full red/black sweep, both colours in one pass, out of place: pout
+// receives the result of a red half-sweep followed by a black half-sweep of
+// pin, except the black cells on each box's boundary layer (which need the
+// neighbouring boxes' new red values); those get their old value and are
+// finished by launch_rim after a ghost exchange of pout.  pin's ghosts must
+// hold the neighbours' values (not read when zero_guess: pin taken as 0).
+// A block of (lx/2)*ly lanes takes an lx x ly x tz tile of one box and
+// marches along z, staging pin planes and new red values in LDS and
+// recomputing the red cells of a one-cell ring around the tile.  When
+// normbits is non-null, max |rhs - A pin| over the tile's cells is folded
+// into *normbits (the residual of the state before the sweep).
+template <typename T>
+hipError_t launch_sweep(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                        const StencilArgs<T>& op, const T* pin, T* pout, const T* rhs,
+                        int rhs_ng, int zero_guess, unsigned long long* normbits);
+// LDS bytes of one launch_sweep block (0 when the shape is not supported).
+size_t sweep_lds_bytes(Shape sh, size_t elem);
+
+// Black half-sweep restricted to the cells of the rim tiles (in place).
+template <typename T>
+hipError_t launch_rim(hipStream_t st, const RimTile* tiles, int ntiles, const StencilArgs<T>& op,
+                      T* phi, const T* rhs, int rhs_ng);
+
 // out = rhs - A phi (mode 0) or out = A phi (mode 1) on every valid cell, one
 // lane per cell; out may be null (norm only).  When normbits is non-null the
 // max |out| is folded into *normbits as IEEE-754 bits (NaN-propagating).

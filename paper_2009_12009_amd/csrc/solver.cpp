@@ -95,6 +95,16 @@ struct Level {
   std::vector<Tile> t_gsrb, t_cell, t_rst;
   Shape s_gsrb{32, 8, 16}, s_cell{64, 4, 16}, s_rst{64, 4, 16};
   size_t cap_gsrb = 0, cap_cell = 0;  // tile slots reserved in the workspace
+  // fused sweeps (both colours in one pass, out of place, rim pass after)
+  bool fused = false;
+  Shape s_sweep{64, 8, 16};
+  std::vector<Tile> t_sweep;
+  std::vector<RimTile> t_rim;
+  size_t cap_sweep = 0;
+  Tile* d_sweep = nullptr;
+  RimTile* d_rim = nullptr;
+  double* alt64 = nullptr;  // second buffer of the smoothed array (ng 1)
+  float* alt32 = nullptr;
   std::vector<FbTag> tags;
   std::vector<FbChunk> chunks;
   // device
@@ -273,6 +283,45 @@ std::vector<Shape> cell_candidates() {
   return c;
 }
 
+std::vector<Shape> sweep_candidates() {
+  std::vector<Shape> c;
+  for (int lx : {32, 64})
+    for (int ly : {2, 4, 8, 16})
+      for (int tz : {4, 8, 16, 32})
+        if (sweep_lds_bytes({lx, ly, tz}, sizeof(double))) c.push_back({lx, ly, tz});
+  return c;
+}
+
+Shape shape_sweep(int nx) { return nx >= 64 ? Shape{64, 8, 16} : Shape{32, 8, 8}; }
+
+// The boundary layer of every box, as blocks of <= 256 cells: the two z
+// faces, then the two y faces without their z-edge rows, then the two x faces
+// without any edge.  Blocks of a face are x-rows, or y-columns of the x faces.
+void make_rim_tiles(const std::vector<BoxInfo>& info, std::vector<RimTile>& out) {
+  out.clear();
+  auto emit = [&](int b, int i0, int j0, int k0, int ni, int nj, int nk) {
+    if (ni <= 0 || nj <= 0 || nk <= 0) return;
+    const int px = std::min(ni, 256);
+    const int ry = std::min(nj, 256 / px);
+    const int rz = ry == nj ? std::max(1, std::min(nk, 256 / (px * nj))) : 1;
+    for (int k = 0; k < nk; k += rz)
+      for (int j = 0; j < nj; j += ry)
+        for (int i = 0; i < ni; i += px)
+          out.push_back({b, i0 + i, j0 + j, k0 + k, std::min(px, ni - i), std::min(ry, nj - j),
+                         std::min(rz, nk - k), 0});
+  };
+  for (int b = 0; b < (int)info.size(); ++b) {
+    const BoxInfo& B = info[b];
+    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
+    emit(b, 0, 0, 0, nx, ny, 1);
+    if (nz > 1) emit(b, 0, 0, nz - 1, nx, ny, 1);
+    emit(b, 0, 0, 1, nx, 1, nz - 2);
+    if (ny > 1) emit(b, 0, ny - 1, 1, nx, 1, nz - 2);
+    emit(b, 0, 1, 1, 1, ny - 2, nz - 2);
+    if (nx > 1) emit(b, nx - 1, 1, 1, 1, ny - 2, nz - 2);
+  }
+}
+
 size_t tile_count(const std::vector<BoxInfo>& info, Shape sh, int tx) {
   size_t n = 0;
   for (const BoxInfo& b : info) {
@@ -345,6 +394,21 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
         lv.cap_gsrb = std::max(lv.cap_gsrb, tile_count(lv.info, c, 2 * c.lx));
       for (Shape c : cell_candidates())
         lv.cap_cell = std::max(lv.cap_cell, tile_count(lv.info, c, c.lx));
+    }
+    int mn = 1 << 30;
+    for (const IBox& b : lv.boxes)
+      for (int d = 0; d < 3; ++d) mn = std::min(mn, ext(b, d));
+    // small boxes leave most cells to the rim pass; opts.fused_min_edge says
+    // how small is too small
+    lv.fused = s->opts.fused_min_edge > 0 && l + 1 < hb.size() && mn >= s->opts.fused_min_edge;
+    if (lv.fused) {
+      lv.s_sweep = shape_sweep(mx[0]);
+      make_tiles(lv.info, lv.s_sweep, lv.s_sweep.lx, false, lv.t_sweep);
+      make_rim_tiles(lv.info, lv.t_rim);
+      lv.cap_sweep = lv.t_sweep.size();
+      if (l == 0)
+        for (Shape c : sweep_candidates())
+          lv.cap_sweep = std::max(lv.cap_sweep, tile_count(lv.info, c, c.lx));
     }
   }
   (void)n;
@@ -435,6 +499,13 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
       lv.e64 = bump.take<double>(lv.n_g1);
       lv.rhs64 = bump.take<double>(lv.n_g0);
       if (!bottom) lv.r64 = bump.take<double>(lv.n_g0);
+    }
+    if (lv.fused) {
+      lv.d_sweep = bump.take<Tile>(lv.cap_sweep);
+      lv.d_rim = bump.take<RimTile>(lv.t_rim.size());
+      // the array each precision smooths on this level gets a twin
+      if (!f32 || (l == 0 && s->composite)) lv.alt64 = bump.take<double>(lv.n_g1);
+      if (f32) lv.alt32 = bump.take<float>(lv.n_g1);
     }
     if (f32) {
       for (int d = 0; d < 3; ++d) lv.b32[d] = bump.take<float>(lv.n_f[d]);
@@ -652,8 +723,46 @@ int exchange(mg_solver* s, Level& lv, T* v, bool prof) {
 }
 
 template <typename T>
+T* alt_of(Level& lv);
+template <>
+double* alt_of<double>(Level& lv) { return lv.alt64; }
+template <>
+float* alt_of<float>(Level& lv) { return lv.alt32; }
+
+// Fused sweeps: phi -> alt -> phi ...; each sweep is the fused pass, an
+// exchange of its output and the rim pass.  An odd count ends with a copy
+// back into phi.
+template <typename T>
+int smooth_fused(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, const T* rhs,
+                 int rhs_ng, int sweeps, bool zero_first, bool prof) {
+  T* cur = phi;
+  T* nxt = alt_of<T>(lv);
+  if (!nxt) return fail(MG_ERR_ARG, "fused sweep without its second buffer");
+  int rc;
+  for (int k = 0; k < sweeps; ++k) {
+    const bool zg = zero_first && k == 0;
+    if (!zg && (rc = exchange<T>(s, lv, cur, prof))) return rc;
+    {
+      ProfScope ps(s, 0, prof);
+      HIPTRY(launch_sweep<T>(s->st, lv.d_sweep, (int)lv.t_sweep.size(), lv.s_sweep, op, cur, nxt,
+                             rhs, rhs_ng, zg ? 1 : 0, nullptr));
+    }
+    if ((rc = exchange<T>(s, lv, nxt, prof))) return rc;
+    {
+      ProfScope ps(s, 7, prof);
+      HIPTRY(launch_rim<T>(s->st, lv.d_rim, (int)lv.t_rim.size(), op, nxt, rhs, rhs_ng));
+    }
+    std::swap(cur, nxt);
+  }
+  if (cur != phi)
+    HIPTRY(hipMemcpyAsync(phi, cur, sizeof(T) * lv.n_g1, hipMemcpyDeviceToDevice, s->st));
+  return MG_OK;
+}
+
+template <typename T>
 int smooth(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng,
            int sweeps, bool zero_first, bool prof) {
+  if (lv.fused) return smooth_fused<T>(s, lv, op, phi, rhs, rhs_ng, sweeps, zero_first, prof);
   int rc;
   for (int k = 0; k < sweeps; ++k) {
     const bool zg = zero_first && k == 0;
@@ -881,6 +990,49 @@ int apply_shape(mg_solver* s, Shape sh, bool gsrb) {
   return MG_OK;
 }
 
+int apply_sweep_shape(mg_solver* s, Shape sh) {
+  Level& l0 = s->L[0];
+  if (!l0.fused || !sweep_lds_bytes(sh, sizeof(double))) return fail(MG_ERR_ARG, "no fused sweep shape");
+  std::vector<Tile> t;
+  make_tiles(l0.info, sh, sh.lx, false, t);
+  if (t.size() > l0.cap_sweep) return fail(MG_ERR_ARG, "tile table larger than its reservation");
+  l0.t_sweep = t;
+  l0.s_sweep = sh;
+  HIPTRY(hipMemcpyAsync(l0.d_sweep, l0.t_sweep.data(), sizeof(Tile) * l0.t_sweep.size(),
+                        hipMemcpyHostToDevice, s->st));
+  return MG_OK;
+}
+
+// Mean time of one fused sweep (fused pass + rim pass, no exchanges) with
+// shape sh, ping-ponging between phi and the level's second buffer.
+template <typename T>
+int time_sweep(mg_solver* s, Shape sh, T* phi, const T* rhs, const StencilArgs<T>& op, float* ms) {
+  int rc;
+  if ((rc = apply_sweep_shape(s, sh))) return rc;
+  Level& l0 = s->L[0];
+  T* alt = alt_of<T>(l0);
+  hipEvent_t a = take_event(s), b = take_event(s);
+  auto one = [&](int w) -> hipError_t {
+    T* in = (w & 1) ? alt : phi;
+    T* out = (w & 1) ? phi : alt;
+    hipError_t e = launch_sweep<T>(s->st, l0.d_sweep, (int)l0.t_sweep.size(), sh, op, in, out,
+                                   rhs, 0, 0, nullptr);
+    if (e != hipSuccess) return e;
+    return launch_rim<T>(s->st, l0.d_rim, (int)l0.t_rim.size(), op, out, rhs, 0);
+  };
+  for (int w = 0; w < 2; ++w) HIPTRY(one(w));
+  HIPTRY(hipEventRecord(a, s->st));
+  const int reps = 6;
+  for (int w = 0; w < reps; ++w) HIPTRY(one(w));
+  HIPTRY(hipEventRecord(b, s->st));
+  HIPTRY(hipEventSynchronize(b));
+  float t;
+  HIPTRY(hipEventElapsedTime(&t, a, b));
+  *ms = t / reps;
+  s->ev_used -= 2;
+  return MG_OK;
+}
+
 template <typename T>
 int time_gsrb(mg_solver* s, Shape sh, T* phi, const T* rhs, const StencilArgs<T>& op, float* ms) {
   int rc;
@@ -931,8 +1083,19 @@ int autotune(mg_solver* s) {
   Level& l0 = s->L[0];
   auto cache = read_cache();
   const std::string kg = tune_key(s, "gsrb", f32), kr = tune_key(s, "resid", f32);
+  const std::string ks = tune_key(s, "sweep", f32);
   int rc;
   if (s->opts.tune == 1) {
+    // sweep entry: the fused shape, u = 1 when it beat two half-sweeps
+    auto is = cache.find(ks);
+    if (l0.fused && is != cache.end()) {
+      std::vector<Tile> t;
+      make_tiles(l0.info, is->second, is->second.lx, false, t);
+      if (sweep_lds_bytes(is->second, sizeof(double)) && t.size() <= l0.cap_sweep &&
+          (rc = apply_sweep_shape(s, is->second)))
+        return rc;
+      if (is->second.u == 0) l0.fused = false;
+    }
     auto it = cache.find(kg);
     if (it != cache.end() && shape_ok(it->second)) {
       std::vector<Tile> t;
@@ -949,13 +1112,18 @@ int autotune(mg_solver* s) {
   }
   if (s->opts.tune != 2) return MG_OK;
   // data: the scratch array (ng 1) as phi, level-0 coefficients as rhs-sized input
-  const Shape g0 = l0.s_gsrb, c0 = l0.s_cell;
-  Shape best_g = g0, best_c = c0;
-  float tg = 1e30f, tr = 1e30f, t;
+  const Shape g0 = l0.s_gsrb, c0 = l0.s_cell, w0 = l0.s_sweep;
+  Shape best_g = g0, best_c = c0, best_w = w0;
+  float tg = 1e30f, tr = 1e30f, tw = 1e30f, t;
   if (f32) {
     float* phi = (float*)s->tune_scratch;
     HIPTRY(hipMemsetAsync(phi, 0, sizeof(float) * l0.n_g1, s->st));
     const StencilArgs<float> op = stencil_of<float>(s, l0, true);
+    if (l0.fused)
+      for (Shape sh : sweep_candidates()) {
+        if ((rc = time_sweep<float>(s, sh, phi, l0.rhs32, op, &t))) return rc;
+        if (t < tw) { tw = t; best_w = sh; }
+      }
     for (Shape sh : gsrb_candidates()) {
       if ((rc = time_gsrb<float>(s, sh, phi, l0.rhs32, op, &t))) return rc;
       if (t < tg) { tg = t; best_g = sh; }
@@ -968,6 +1136,11 @@ int autotune(mg_solver* s) {
     double* phi = s->tune_scratch;
     HIPTRY(hipMemsetAsync(phi, 0, sizeof(double) * l0.n_g1, s->st));
     const StencilArgs<double> op = stencil_of<double>(s, l0, false);
+    if (l0.fused)
+      for (Shape sh : sweep_candidates()) {
+        if ((rc = time_sweep<double>(s, sh, phi, l0.r64, op, &t))) return rc;
+        if (t < tw) { tw = t; best_w = sh; }
+      }
     for (Shape sh : gsrb_candidates()) {
       if ((rc = time_gsrb<double>(s, sh, phi, l0.r64, op, &t))) return rc;
       if (t < tg) { tg = t; best_g = sh; }
@@ -979,10 +1152,21 @@ int autotune(mg_solver* s) {
   }
   if ((rc = apply_shape(s, best_g, true))) return rc;
   if ((rc = apply_shape(s, best_c, false))) return rc;
+  if (l0.fused) {
+    if ((rc = apply_sweep_shape(s, best_w))) return rc;
+    // a fused sweep also saves nothing on exchanges, so it must beat the two
+    // half-sweeps it replaces on its own
+    best_w.u = tw < 2 * tg ? 1 : 0;
+    l0.fused = best_w.u == 1;
+    cache[ks] = best_w;
+  }
   if (s->opts.verbose)
-    fprintf(stderr, "amrmg tune: gsrb %dx%dx%d u%d wp%d %.4f ms, resid %dx%dx%d u%d %.4f ms\n",
+    fprintf(stderr,
+            "amrmg tune: gsrb %dx%dx%d u%d wp%d %.4f ms, resid %dx%dx%d u%d %.4f ms, "
+            "sweep %dx%dx%d %.4f ms (%s)\n",
             best_g.lx, best_g.ly, best_g.tz, best_g.u, best_g.wp, tg, best_c.lx, best_c.ly,
-            best_c.tz, best_c.u, tr);
+            best_c.tz, best_c.u, tr, best_w.lx, best_w.ly, best_w.tz, tw,
+            l0.fused ? "fused" : "half-sweeps");
   cache[kg] = best_g;
   cache[kr] = best_c;
   write_cache(cache);
@@ -1002,6 +1186,13 @@ int upload_tables(mg_solver* s) {
     if (!lv.t_rst.empty())
       HIPTRY(hipMemcpyAsync(lv.d_rst, lv.t_rst.data(), sizeof(Tile) * lv.t_rst.size(),
                             hipMemcpyHostToDevice, s->st));
+    if (lv.fused) {
+      HIPTRY(hipMemcpyAsync(lv.d_sweep, lv.t_sweep.data(), sizeof(Tile) * lv.t_sweep.size(),
+                            hipMemcpyHostToDevice, s->st));
+      if (!lv.t_rim.empty())
+        HIPTRY(hipMemcpyAsync(lv.d_rim, lv.t_rim.data(), sizeof(RimTile) * lv.t_rim.size(),
+                              hipMemcpyHostToDevice, s->st));
+    }
     if (!lv.tags.empty())
       HIPTRY(hipMemcpyAsync(lv.d_tags, lv.tags.data(), sizeof(FbTag) * lv.tags.size(),
                             hipMemcpyHostToDevice, s->st));
@@ -1399,6 +1590,7 @@ void mg_default_opts(mg_opts_t* o) {
   o->verbose = 0;
   o->aggregate = 0;
   o->bottom_rel_tol = 1e-4;
+  o->fused_min_edge = 0;
 }
 
 static int check_opts(const mg_opts_t* o) {
@@ -1409,6 +1601,7 @@ static int check_opts(const mg_opts_t* o) {
     return fail(MG_ERR_ARG, "bad precision");
   if (o->tune < 0 || o->tune > 2) return fail(MG_ERR_ARG, "bad tune");
   if (!(o->bottom_rel_tol >= 0)) return fail(MG_ERR_ARG, "bad bottom_rel_tol");
+  if (o->fused_min_edge < 0) return fail(MG_ERR_ARG, "fused_min_edge < 0");
   return MG_OK;
 }
 
@@ -1979,6 +2172,13 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
 int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz,
                       int32_t unroll) {
   if (!s) return fail(MG_ERR_ARG, "null solver");
+  if (kernel == 3) {
+    bool ok = false;
+    for (Shape c : sweep_candidates())
+      if (c.lx == lx && c.ly == ly && c.tz == tz) ok = true;
+    if (!ok) return fail(MG_ERR_ARG, "shape is not a candidate");
+    return apply_sweep_shape(s, Shape{lx, ly, tz});
+  }
   // kernel 2: the smoother storing whole x-pairs
   const int wp = kernel == 2 ? 1 : 0;
   if (kernel == 2) kernel = 0;

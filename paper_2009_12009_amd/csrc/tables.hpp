@@ -45,6 +45,17 @@ struct FbChunk {
 
 constexpr int FB_CHUNK = 256;
 
+// A block of cells of one box (box-local offsets i0, j0, k0 from the box's
+// low corner, extents ni, nj, nk, at most 256 cells) on the box's boundary
+// layer, where the fused sweep leaves the second colour's update to a pass
+// of its own.
+struct RimTile {
+  int box;
+  int i0, j0, k0;
+  int ni, nj, nk;
+  int pad;
+};
+
 // A fine ghost cell filled from the coarse level: dst (element in the fine
 // array, one ghost layer) = v_C + 1/4 sum_d sigma_d (v_{C+e_d} - v_{C-e_d}) / 2.
 // c and nb[] are elements of the coarse array (ghost layer 1, each in the box

@@ -205,12 +205,16 @@ def test_tile_shapes_and_graph_bitwise_identical():
     boxes = cfg["boxes"]
     rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(cfg["rhs"], boxes), 0)
     outs = []
+    # kernels 0-2 on half-sweep levels (fused sweeps off), kernel 3 = fused sweep
     shapes = [None, (0, 16, 4, 4, 1), (0, 32, 8, 32, 2), (0, 64, 4, 64, 4), (0, 32, 2, 2, 2),
               (2, 32, 4, 4, 2), (2, 16, 4, 8, 1), (1, 32, 2, 8, 1), (1, 128, 2, 64, 4),
-              (1, 64, 4, 4, 2)]
+              (1, 64, 4, 4, 2), (3, 64, 8, 16, 1), (3, 32, 4, 4, 1), (3, 64, 2, 32, 1),
+              (3, 32, 16, 8, 1)]
     for graph in (1, 0):
         for sh in shapes:
-            s = gpu_solver(cfg, opts=dict(max_iter=2, use_graph=graph, tune=0))
+            fused = 32 if sh is not None and sh[0] == 3 else 0
+            s = gpu_solver(cfg, opts=dict(max_iter=2, use_graph=graph, tune=0,
+                                          fused_min_edge=fused))
             if sh is not None:
                 s.set_tile_shape(*sh)
             phi = s.cell_mf(1, fill=0.0)
@@ -222,6 +226,45 @@ def test_tile_shapes_and_graph_bitwise_identical():
     m = np.isfinite(ref)
     for o in outs[1:]:
         assert np.array_equal(o[m], ref[m])
+
+
+FUSED_CASES = [
+    # (name, cfg, boxes or None, fused_min_edge, precision)
+    ("lognormal64_32boxes_f64", lambda: W.config_lognormal(64, 32), None, 32, 0),
+    ("lognormal64_32boxes_f32", lambda: W.config_lognormal(64, 32), None, 32, 1),
+    ("lognormal64_16boxes_all_levels", lambda: W.config_lognormal(64, 16), None, 4, 0),
+    ("poisson32_periodic", W.config_c0, None, 8, 0),
+    ("uneven_periodic_y", lambda: dict(W.config_c0(), periodic=(False, True, False)),
+     [((0, 0, 0), (15, 31, 31)), ((16, 0, 0), (31, 15, 31)), ((16, 16, 0), (31, 31, 15)),
+      ((16, 16, 16), (31, 31, 31))], 8, 0),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,make,boxes,edge,prec", FUSED_CASES, ids=[c[0] for c in FUSED_CASES])
+def test_fused_sweeps_bitwise_equal_half_sweeps(name, make, boxes, edge, prec):
+    """A fused sweep (one pass into a second buffer, rim pass after an
+    exchange) performs the same arithmetic on the same values as a red and a
+    black half-sweep: solutions after a few cycles must agree bit for bit."""
+    print(f"[solve] fused vs half-sweeps {name}", flush=True)
+    P = lib()
+    cfg = make()
+    boxes = boxes or cfg["boxes"]
+    f = cfg["rhs"] - (cfg["rhs"].mean() if all(cfg["periodic"]) else 0.0)
+    rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(f, boxes), 0)
+    outs, iters = [], []
+    for fme in (edge, 0):
+        s = gpu_solver(cfg, boxes=boxes, opts=dict(max_iter=3, tune=0, fused_min_edge=fme,
+                                                   precision=prec))
+        phi = s.cell_mf(1, fill=0.0)
+        info = s.solve(phi, rhs, 1e-10, raise_on_fail=False, history=True)
+        torch.cuda.synchronize()
+        outs.append(to_global(phi, boxes, cfg["n"]))
+        iters.append(list(info["history"]))
+        s.close()
+    assert np.all(np.isfinite(outs[0]))
+    assert np.array_equal(outs[0], outs[1])
+    assert iters[0] == iters[1]
 
 
 @pytest.mark.gpu

@@ -40,7 +40,11 @@ __device__ __forceinline__ unsigned long long absbits(double v) {
 }
 __device__ __forceinline__ unsigned long long absbits(float v) { return absbits((double)v); }
 
-// Fold a per-lane value into *dst as an unsigned max over the block.
+// Fold a per-lane value into *dst as an unsigned max over the block.  The
+// block's atomic is skipped when *dst already holds at least its value: *dst
+// only grows, so a value read at any time that is >= m makes the atomic a
+// no-op.  With tens of thousands of blocks this avoids queueing one atomic
+// per block on the single L2 channel that holds *dst.
 __device__ void block_max_u64(unsigned long long v, unsigned long long* dst) {
   __shared__ unsigned long long red[16];
   for (int o = 32; o > 0; o >>= 1) {
@@ -54,7 +58,7 @@ __device__ void block_max_u64(unsigned long long v, unsigned long long* dst) {
   if (tid == 0) {
     unsigned long long m = red[0];
     for (int w = 1; w < nw; ++w) m = red[w] > m ? red[w] : m;
-    if (m) atomicMax(dst, m);
+    if (m > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dst, m);
   }
 }
 

@@ -40,6 +40,44 @@ def parse():
     return p.parse_args()
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_gsrb_abec256_lognormal_64boxes.md")
+
+
+def kernel_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "tables.hpp"):
+        with open(os.path.join(ROOT, "paper_2009_12009_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, shape):
+    """HBM bytes per launch of the level-0 half-sweep from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
+    None when the summary is missing, was taken on other kernel sources, or for
+    another kernel or tile shape than the one this run uses."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    block = text.split("```")[1] if text.count("```") >= 2 else ""
+    kv = {}
+    for line in block.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if (kv.get("source_sha256") != kernel_source_sha256() or kv.get("kernel") != kernel
+                or tuple(int(x) for x in kv["shape"].split()) != tuple(shape)):
+            return None
+        return (float(kv["fetch_kib_per_dispatch"]) * 1024 * float(kv["fetch_scale"])
+                + float(kv["write_kib_per_dispatch"]) * 1024 * float(kv["write_scale"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def log(msg, quiet=False):
     if not quiet:
         print(msg, file=sys.stderr, flush=True)
@@ -130,6 +168,8 @@ def main():
         gs[k]["families"] = fam
         # rim launches only come with fused sweeps (the tuner may have kept half-sweeps)
         gs[k]["fused"] = fam["rim"]["launches_per_solve"] > 0
+        gs[k]["tile_shapes"] = {"smoother": s.tile_shape(0), "cell": s.tile_shape(1),
+                                "fused_sweep": s.tile_shape(3)}
         s.profile(False)
 
     # plain device copy as the achievable ceiling
@@ -175,18 +215,22 @@ def main():
         "setup_ms": setup_ms,
         "smoother": {k: {kk: v for kk, v in g.items() if kk != "families"} for k, g in gs.items()},
         "time_by_family_ms": {k: g["families"] for k, g in gs.items()},
+        "tile_shapes": {k: g["tile_shapes"] for k, g in gs.items()},
         "copy_kernel_gbps": copy_gbps,
     }
     g64 = gs["f64"]
+    kname = ("k_sweep<double> level 0, one fused red+black sweep (64 boxes of 64^3)"
+             if g64["fused"] else "k_gsrb<double> level 0, one half-sweep (64 boxes of 64^3)")
+    traffic = None if g64["fused"] else measured_traffic("k_gsrb<double>",
+                                                         g64["tile_shapes"]["smoother"])
     result["roofline"] = {
         "bound": "hbm",
         "achieved": g64["gbps"],
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": g64["gbps"] / HBM_PEAK_GBS if g64["gbps"] else None,
-        "traffic": None,
-        "kernel": ("k_sweep<double> level 0, one fused red+black sweep (64 boxes of 64^3)"
-                   if g64["fused"] else "k_gsrb<double> level 0, one half-sweep (64 boxes of 64^3)"),
+        "traffic": traffic,
+        "kernel": kname,
         "alg_bytes_per_launch": g64["bytes"],
         "mean_launch_ms": g64["mean_ms"],
     }

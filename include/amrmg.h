@@ -287,11 +287,18 @@ int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rh
  * (lx in {16,32,64} for kernel 0, {32,64,128} for kernel 1; ly a power of two
  * up to 16 (kernel 0) or 8 (kernel 1); tz in {2,...,64}).  kernel 3: the
  * fused sweep of level 0 (lx x ly x tz cells per work-group of lx/2*ly lanes;
- * lx in {32,64}, ly in {2,4,8,16}, tz in {4,8,16,32}, within 64 KiB of LDS;
- * unroll ignored; MG_ERR_ARG when level 0 does not use fused sweeps).  Every
+ * (lx, ly) in {(64,4), (64,8), (32,8), (32,16)}, tz in {4,8,16,32}; unroll
+ * ignored; MG_ERR_ARG when level 0 does not use fused sweeps).  Every
  * shape gives bitwise-identical results. */
 int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz,
                       int32_t unroll);
+
+/* The level-0 tile shapes in use (after tuning), for reports: kernel 0 the
+ * half-sweep smoother -> {lx, ly, tz, unroll, whole_pairs}; kernel 1 the
+ * one-lane-per-cell kernels -> {lx, ly, tz, unroll, 0}; kernel 3 the fused
+ * sweep -> {lx, ly, tz, in_use, 0} (in_use 0 when level 0 runs half-sweeps;
+ * lx = 0 when it has no fused sweep at all).  shape: host int32_t[5]. */
+int mg_get_tile_shape(mg_solver_t* s, int32_t kernel, int32_t* shape);
 
 /* Free the device tables of fill_boundary's plan cache. */
 void mg_release_caches(void);

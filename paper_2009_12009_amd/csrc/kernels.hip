@@ -213,26 +213,31 @@ __global__ void __launch_bounds__(256)
 // of new red values over the tile grown by 1.  Step k computes red on plane
 // k over the grown tile (needs old planes k-1..k+1), then black on plane
 // k-1 over the tile (needs new red on planes k-2..k) and writes plane k-1.
+// Every global load of a step (old plane k+1, red and black coefficients) is
+// issued before its first barrier, so a step waits for memory once.
 // Ring sizes make two barriers per step enough: the old slot loaded at step
 // k+1 last held plane k-4, read at step k-1 at the latest, and the red slot
 // written at step k+1 last held plane k-2, read at step k before the
 // barrier that opens step k+1's red phase.
-template <typename T, bool ZG, bool NORM>
-__global__ void __launch_bounds__(256)
+template <typename T, int LX, int LY, bool ZG, bool NORM>
+__global__ void __launch_bounds__(LX / 2 * LY)
     k_sweep(const Tile* __restrict__ tiles, StencilArgs<T> op, const T* __restrict__ pin,
-            T* __restrict__ pout, const T* __restrict__ rhs, int rhs_ng, int lx, int ly, int tz,
+            T* __restrict__ pout, const T* __restrict__ rhs, int rhs_ng, int tz,
             unsigned long long* normbits) {
+  constexpr int NT = LX / 2 * LY;
+  constexpr int W2 = LX + 4, P2 = W2 * (LY + 4);
+  constexpr int W1 = LX + 2, P1 = W1 * (LY + 2);
+  constexpr int HP = W1 / 2, NRP = HP * (LY + 2);  // red pair slots of the grown tile
+  constexpr int R1 = (P2 + NT - 1) / NT, R2 = (NRP + NT - 1) / NT;
   extern __shared__ double lds_sweep[];
   T* OLD = reinterpret_cast<T*>(lds_sweep);
-  const int W2 = lx + 4, P2 = W2 * (ly + 4);
-  const int W1 = lx + 2, P1 = W1 * (ly + 2);
   T* RED = OLD + 5 * P2;
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = op.boxes[t.box];
   const Strides s = strides_of(B, rhs_ng);
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
   const int x0 = t.x0 - B.lo[0], y0 = t.y0 - B.lo[1], z0 = t.z0 - B.lo[2];
-  const int x1 = min(x0 + lx, s.nx) - 1, y1 = min(y0 + ly, s.ny) - 1, z1 = min(z0 + tz, s.nz) - 1;
+  const int x1 = min(x0 + LX, s.nx) - 1, y1 = min(y0 + LY, s.ny) - 1, z1 = min(z0 + tz, s.nz) - 1;
   const int par = (B.lo[0] + B.lo[1] + B.lo[2]) & 1;
   const T* Pin = pin + B.off_g1;
   T* Pout = pout + B.off_g1;
@@ -244,100 +249,133 @@ __global__ void __launch_bounds__(256)
   const int m = B.bcmask;
   unsigned long long mx = 0;
 
+  // this lane's old-plane positions (fixed for the whole z-march)
+  int o_off[R1];  // element offset in the grown box array without the plane term, -1 = skip
+#pragma unroll
+  for (int r = 0; r < R1; ++r) {
+    const int q = tid + r * NT;
+    const int il = x0 - 2 + q % W2, jl = y0 - 2 + q / W2;
+    o_off[r] = (q < P2 && il >= -1 && il <= s.nx && jl >= -1 && jl <= s.ny)
+                   ? (il + 1) + s.sy * (jl + 1)
+                   : -1;
+  }
+  // this lane's red pair slots and black pair
+  int r_jl[R2], r_i0[R2];
+#pragma unroll
+  for (int r = 0; r < R2; ++r) {
+    const int q = tid + r * NT;
+    r_jl[r] = q < NRP ? y0 - 1 + q / HP : -2;
+    r_i0[r] = x0 - 1 + 2 * (q % HP);
+  }
+  const int b_jl = y0 + tid / (LX / 2), b_i0 = x0 + 2 * (tid % (LX / 2));
+  const bool b_ok = b_jl <= y1 && b_i0 <= x1;
+
   auto oslot = [](int k) { return ((k % 5) + 5) % 5; };
   auto rslot = [](int k) { return ((k % 3) + 3) % 3; };
-  // old plane k (-1 <= k <= nz) over the tile grown by 2, clipped to the grown box
-  auto load = [&](int k) {
-    T* dst = OLD + oslot(k) * P2;
-    for (int q = tid; q < P2; q += nt) {
-      const int il = x0 - 2 + q % W2, jl = y0 - 2 + q / W2;
-      if (il >= -1 && il <= s.nx && jl >= -1 && jl <= s.ny)
-        dst[q] = ZG ? T(0) : Pin[(il + 1) + s.sy * (jl + 1) + s.sz * (k + 1)];
-    }
-  };
-  // old value at local (il, jl, k) from the ring
   auto old_at = [&](int il, int jl, int k) -> T {
     return OLD[oslot(k) * P2 + (jl - y0 + 2) * W2 + (il - x0 + 2)];
   };
   auto red_at = [&](int il, int jl, int k) -> T {
     return RED[rslot(k) * P1 + (jl - y0 + 1) * W1 + (il - x0 + 1)];
   };
+  auto load_now = [&](int k) {  // direct load of old plane k (prologue only)
+    T* dst = OLD + oslot(k) * P2;
+#pragma unroll
+    for (int r = 0; r < R1; ++r)
+      if (o_off[r] >= 0) dst[tid + r * NT] = ZG ? T(0) : Pin[o_off[r] + s.sz * (k + 1)];
+  };
 
   const int kb = z0 - 1, ke = z1 + 1;
   for (int k = kb - 1; k <= kb; ++k)
-    if (k >= -1 && k <= s.nz) load(k);
+    if (k >= -1 && k <= s.nz) load_now(k);
   for (int k = kb; k <= ke; ++k) {
-    if (k + 1 <= s.nz) load(k + 1);
+    // ---- issue this step's global loads
+    T ov[R1];
+    const bool load_next = k + 1 <= s.nz;
+#pragma unroll
+    for (int r = 0; r < R1; ++r)
+      if (!ZG && load_next && o_off[r] >= 0) ov[r] = Pin[o_off[r] + s.sz * (k + 2)];
+    Nbr<T> vr[R2];
+    int r_il[R2];
+    bool r_ok[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int jl = r_jl[r];
+      const int il = r_i0[r] + ((r_i0[r] + jl + k + par) & 1);
+      r_il[r] = il;
+      r_ok[r] = k >= 0 && k < s.nz && il >= 0 && il < s.nx && jl >= 0 && jl < s.ny;
+      if (r_ok[r]) gather<T, false, false>(vr[r], s, nullptr, R, rhs_ng, BX, BY, BZ, A, il, jl, k, 0);
+    }
+    const int kk = k - 1;
+    const bool first_black = ((b_i0 + b_jl + kk + par) & 1) == 1;
+    const int ib = first_black ? b_i0 : b_i0 + 1;
+    const int ir = first_black ? b_i0 + 1 : b_i0;
+    const bool bk = b_ok && kk >= z0 && kk <= z1;
+    const bool bb = bk && ib <= x1;
+    const bool rim = ib == 0 || ib == s.nx - 1 || b_jl == 0 || b_jl == s.ny - 1 || kk == 0 ||
+                     kk == s.nz - 1;
+    Nbr<T> vb;
+    if (bb && (!rim || NORM))
+      gather<T, false, false>(vb, s, nullptr, R, rhs_ng, BX, BY, BZ, A, ib, b_jl, kk, 0);
+    // ---- old plane k+1 into LDS
+    if (load_next) {
+      T* dst = OLD + oslot(k + 1) * P2;
+#pragma unroll
+      for (int r = 0; r < R1; ++r)
+        if (o_off[r] >= 0) dst[tid + r * NT] = ZG ? T(0) : ov[r];
+    }
     __syncthreads();
-    // red on plane k over the tile grown by 1 (valid cells only)
-    if (k >= 0 && k < s.nz) {
-      const int hp = W1 / 2, np = hp * (ly + 2);
-      for (int q = tid; q < np; q += nt) {
-        const int jl = y0 - 1 + q / hp;
-        const int il = x0 - 1 + 2 * (q % hp) + ((x0 - 1 + jl + k + par) & 1);
-        if (il < 0 || il >= s.nx || jl < 0 || jl >= s.ny) continue;
-        Nbr<T> v;
-        gather<T, false, false>(v, s, nullptr, R, rhs_ng, BX, BY, BZ, A, il, jl, k, 0);
-        v.pxl = old_at(il - 1, jl, k);
-        v.pxh = old_at(il + 1, jl, k);
-        v.pyl = old_at(il, jl - 1, k);
-        v.pyh = old_at(il, jl + 1, k);
-        v.pzl = old_at(il, jl, k - 1);
-        v.pzh = old_at(il, jl, k + 1);
-        const Cell<T> c = eval<T, true>(op, v, A != nullptr, m, s, il, jl, k);
-        RED[rslot(k) * P1 + (jl - y0 + 1) * W1 + (il - x0 + 1)] = (v.f + c.off) / c.diag;
-        if (NORM && il >= x0 && il <= x1 && jl >= y0 && jl <= y1 && k >= z0 && k <= z1) {
-          const T r = v.f - (c.diag * old_at(il, jl, k) - c.off);
-          const unsigned long long bits = absbits(r);
-          mx = bits > mx ? bits : mx;
-        }
+    // ---- red on plane k over the tile grown by 1
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      if (!r_ok[r]) continue;
+      const int il = r_il[r], jl = r_jl[r];
+      Nbr<T>& v = vr[r];
+      v.pxl = old_at(il - 1, jl, k);
+      v.pxh = old_at(il + 1, jl, k);
+      v.pyl = old_at(il, jl - 1, k);
+      v.pyh = old_at(il, jl + 1, k);
+      v.pzl = old_at(il, jl, k - 1);
+      v.pzh = old_at(il, jl, k + 1);
+      const Cell<T> c = eval<T, true>(op, v, A != nullptr, m, s, il, jl, k);
+      RED[rslot(k) * P1 + (jl - y0 + 1) * W1 + (il - x0 + 1)] = (v.f + c.off) / c.diag;
+      if (NORM && il >= x0 && il <= x1 && jl >= y0 && jl <= y1 && k >= z0 && k <= z1) {
+        const T res = v.f - (c.diag * old_at(il, jl, k) - c.off);
+        const unsigned long long bits = absbits(res);
+        mx = bits > mx ? bits : mx;
       }
     }
     __syncthreads();
-    // black on plane k-1 over the tile; write both cells of each x-pair
-    const int kk = k - 1;
-    if (kk >= z0 && kk <= z1) {
-      const int hp = lx / 2, np = hp * ly;
-      for (int q = tid; q < np; q += nt) {
-        const int jl = y0 + q / hp;
-        const int i0 = x0 + 2 * (q % hp);
-        if (jl > y1 || i0 > x1) continue;
-        const bool first_black = ((i0 + jl + kk + par) & 1) == 1;
-        const int ib = first_black ? i0 : i0 + 1;
-        const int ir = first_black ? i0 + 1 : i0;
-        const int base = s.sy * (jl + 1) + s.sz * (kk + 1) + 1;
-        if (ir <= x1) Pout[base + ir] = red_at(ir, jl, kk);
-        if (ib <= x1) {
-          const bool rim = ib == 0 || ib == s.nx - 1 || jl == 0 || jl == s.ny - 1 || kk == 0 ||
-                           kk == s.nz - 1;
-          Nbr<T> v;
-          if (!rim || NORM)
-            gather<T, false, false>(v, s, nullptr, R, rhs_ng, BX, BY, BZ, A, ib, jl, kk, 0);
-          T out = old_at(ib, jl, kk);
-          if (!rim) {
-            v.pxl = red_at(ib - 1, jl, kk);
-            v.pxh = red_at(ib + 1, jl, kk);
-            v.pyl = red_at(ib, jl - 1, kk);
-            v.pyh = red_at(ib, jl + 1, kk);
-            v.pzl = red_at(ib, jl, kk - 1);
-            v.pzh = red_at(ib, jl, kk + 1);
-            const Cell<T> c = eval<T, true>(op, v, A != nullptr, m, s, ib, jl, kk);
-            out = (v.f + c.off) / c.diag;
-          }
-          if (NORM) {
-            v.pxl = old_at(ib - 1, jl, kk);
-            v.pxh = old_at(ib + 1, jl, kk);
-            v.pyl = old_at(ib, jl - 1, kk);
-            v.pyh = old_at(ib, jl + 1, kk);
-            v.pzl = old_at(ib, jl, kk - 1);
-            v.pzh = old_at(ib, jl, kk + 1);
-            const Cell<T> c = eval<T, true>(op, v, A != nullptr, m, s, ib, jl, kk);
-            const T r = v.f - (c.diag * old_at(ib, jl, kk) - c.off);
-            const unsigned long long bits = absbits(r);
-            mx = bits > mx ? bits : mx;
-          }
-          Pout[base + ib] = out;
+    // ---- black on plane k-1 over the tile; write both cells of the pair
+    if (bk) {
+      const int jl = b_jl;
+      const int base = s.sy * (jl + 1) + s.sz * (kk + 1) + 1;
+      if (ir <= x1) Pout[base + ir] = red_at(ir, jl, kk);
+      if (bb) {
+        T out = old_at(ib, jl, kk);
+        if (!rim) {
+          vb.pxl = red_at(ib - 1, jl, kk);
+          vb.pxh = red_at(ib + 1, jl, kk);
+          vb.pyl = red_at(ib, jl - 1, kk);
+          vb.pyh = red_at(ib, jl + 1, kk);
+          vb.pzl = red_at(ib, jl, kk - 1);
+          vb.pzh = red_at(ib, jl, kk + 1);
+          const Cell<T> c = eval<T, true>(op, vb, A != nullptr, m, s, ib, jl, kk);
+          out = (vb.f + c.off) / c.diag;
         }
+        if (NORM) {
+          vb.pxl = old_at(ib - 1, jl, kk);
+          vb.pxh = old_at(ib + 1, jl, kk);
+          vb.pyl = old_at(ib, jl - 1, kk);
+          vb.pyh = old_at(ib, jl + 1, kk);
+          vb.pzl = old_at(ib, jl, kk - 1);
+          vb.pzh = old_at(ib, jl, kk + 1);
+          const Cell<T> c = eval<T, true>(op, vb, A != nullptr, m, s, ib, jl, kk);
+          const T res = vb.f - (c.diag * old_at(ib, jl, kk) - c.off);
+          const unsigned long long bits = absbits(res);
+          mx = bits > mx ? bits : mx;
+        }
+        Pout[base + ib] = out;
       }
     }
   }
@@ -1103,13 +1141,16 @@ hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
   return hipGetLastError();
 }
 
+// Tile shapes the fused sweep is instantiated for: (lx, ly) cells.
+bool sweep_shape_ok(Shape sh) {
+  return ((sh.lx == 64 && (sh.ly == 4 || sh.ly == 8)) || (sh.lx == 32 && (sh.ly == 8 || sh.ly == 16))) &&
+         sh.tz >= 1;
+}
+
 size_t sweep_lds_bytes(Shape sh, size_t elem) {
-  if (sh.lx < 4 || (sh.lx & 1) || sh.ly < 1 || sh.tz < 1) return 0;
-  const int nt = (sh.lx / 2) * sh.ly;
-  if (nt < 64 || nt > 256 || (nt & 63)) return 0;
+  if (!sweep_shape_ok(sh)) return 0;
   const size_t n = 5 * (size_t)(sh.lx + 4) * (sh.ly + 4) + 3 * (size_t)(sh.lx + 2) * (sh.ly + 2);
-  const size_t b = n * elem;
-  return b <= 65536 ? b : 0;
+  return n * elem;
 }
 
 template <typename T>
@@ -1120,12 +1161,18 @@ hipError_t launch_sweep(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
   const size_t lds = sweep_lds_bytes(sh, sizeof(T));
   if (!lds) return hipErrorInvalidValue;
   const dim3 g(ntiles), b((sh.lx / 2) * sh.ly);
-#define SW(Z, N)                                                                              \
-  hipLaunchKernelGGL((k_sweep<T, Z, N>), g, b, lds, st, tiles, op, pin, pout, rhs, rhs_ng,     \
-                     sh.lx, sh.ly, sh.tz, normbits)
-  if (zero_guess) SW(true, false);
-  else if (normbits) SW(false, true);
-  else SW(false, false);
+#define SW(X, Y, Z, N)                                                                        \
+  hipLaunchKernelGGL((k_sweep<T, X, Y, Z, N>), g, b, lds, st, tiles, op, pin, pout, rhs,       \
+                     rhs_ng, sh.tz, normbits)
+#define SWS(X, Y)                                 \
+  if (zero_guess) SW(X, Y, true, false);          \
+  else if (normbits) SW(X, Y, false, true);       \
+  else SW(X, Y, false, false);
+  if (sh.lx == 64 && sh.ly == 4) { SWS(64, 4) }
+  else if (sh.lx == 64) { SWS(64, 8) }
+  else if (sh.ly == 8) { SWS(32, 8) }
+  else { SWS(32, 16) }
+#undef SWS
 #undef SW
   return hipGetLastError();
 }

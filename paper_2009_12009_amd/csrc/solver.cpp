@@ -2190,6 +2190,28 @@ int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, in
   return apply_shape(s, sh, kernel == 0);
 }
 
+int mg_get_tile_shape(mg_solver_t* s, int32_t kernel, int32_t* shape) {
+  if (!s || !shape) return fail(MG_ERR_ARG, "null argument");
+  const Level& l0 = s->L[0];
+  if (kernel == 0) {
+    const Shape& g = l0.s_gsrb;
+    const int32_t v[5] = {g.lx, g.ly, g.tz, g.u, g.wp};
+    std::memcpy(shape, v, sizeof(v));
+  } else if (kernel == 1) {
+    const Shape& c = l0.s_cell;
+    const int32_t v[5] = {c.lx, c.ly, c.tz, c.u, 0};
+    std::memcpy(shape, v, sizeof(v));
+  } else if (kernel == 3) {
+    const Shape& w = l0.s_sweep;
+    const bool has = !l0.t_sweep.empty();
+    const int32_t v[5] = {has ? w.lx : 0, has ? w.ly : 0, has ? w.tz : 0, l0.fused ? 1 : 0, 0};
+    std::memcpy(shape, v, sizeof(v));
+  } else {
+    return fail(MG_ERR_ARG, "kernel must be 0, 1 or 3");
+  }
+  return MG_OK;
+}
+
 const char* mg_last_error(void) { return amrmg::last_error(); }
 
 }  // extern "C"

@@ -203,6 +203,13 @@ class MLMG:
                 "mg_kernel_stats")
         return t.value, n.value
 
+    def tile_shape(self, kernel):
+        """Level-0 tile shape in use: kernel 0 smoother (lx, ly, tz, unroll, whole_pairs),
+        1 cell kernels (lx, ly, tz, unroll, 0), 3 fused sweep (lx, ly, tz, in_use, 0)."""
+        out = (C.c_int32 * 5)()
+        L.check(L.lib.mg_get_tile_shape(self.handle, kernel, out), "mg_get_tile_shape")
+        return tuple(out)
+
     def set_tile_shape(self, kernel, lx, ly, tz, unroll=1):
         L.check(L.lib.mg_set_tile_shape(self.handle, kernel, lx, ly, tz, unroll),
                 "mg_set_tile_shape")

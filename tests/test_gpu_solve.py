@@ -208,7 +208,7 @@ def test_tile_shapes_and_graph_bitwise_identical():
     # kernels 0-2 on half-sweep levels (fused sweeps off), kernel 3 = fused sweep
     shapes = [None, (0, 16, 4, 4, 1), (0, 32, 8, 32, 2), (0, 64, 4, 64, 4), (0, 32, 2, 2, 2),
               (2, 32, 4, 4, 2), (2, 16, 4, 8, 1), (1, 32, 2, 8, 1), (1, 128, 2, 64, 4),
-              (1, 64, 4, 4, 2), (3, 64, 8, 16, 1), (3, 32, 4, 4, 1), (3, 64, 2, 32, 1),
+              (1, 64, 4, 4, 2), (3, 64, 8, 16, 1), (3, 32, 8, 4, 1), (3, 64, 4, 32, 1),
               (3, 32, 16, 8, 1)]
     for graph in (1, 0):
         for sh in shapes:

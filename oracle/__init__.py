@@ -54,6 +54,8 @@ from .mlmg import (  # noqa: F401
     vcycle,
     solve,
     solve_refine,
+    pcg_solve,
+    vcycle_precond,
     max_norm,
     Opts,
     build_levels,

@@ -377,6 +377,10 @@ class Opts:
     bottom_max_iter: int = None
     min_bottom_edge: int = 4
     aggregate: bool = False
+    # post-smoothing in black-then-red order on every level, which makes the
+    # V-cycle (from a zero guess, exact bottom solve, nu1 = nu2) a symmetric
+    # operator: the preconditioner of pcg_solve
+    symmetric: bool = False
 
 
 def vcycle(levels, l, phi, f, opts, stats=None):
@@ -400,9 +404,10 @@ def vcycle(levels, l, phi, f, opts, stats=None):
     ec = new_cell_data(levels[l + 1])
     vcycle(levels, l + 1, ec, fc, opts, stats)
     prolong_add(phi, ec, lev, levels[l + 1])
+    first, second = (1, 0) if opts.symmetric else (0, 1)
     for _ in range(opts.nu2):
-        gsrb_halfsweep(lev, phi, f, 0)
-        gsrb_halfsweep(lev, phi, f, 1)
+        gsrb_halfsweep(lev, phi, f, first)
+        gsrb_halfsweep(lev, phi, f, second)
 
 
 def max_norm(u):
@@ -505,6 +510,102 @@ def solve_refine(lev0, phi, f, rel_tol=1e-10, abs_tol=0.0, opts=None, inner_dtyp
     info["iters"] = it
     info["normf"] = normf
     if is_singular(lev0):
+        m = _mean([valid(v) for v in phi])
+        for v in phi:
+            valid(v)[...] -= m
+    return info
+
+
+def vcycle_precond(levels, r, opts):
+    """z = M r: one V-cycle on A z = r from z = 0 (mean removed for a singular
+    all-periodic problem)."""
+    z = new_cell_data(levels[0])
+    vcycle(levels, 0, z, r, opts)
+    if is_singular(levels[0]):
+        m = levels[0].dtype(_mean([valid(v) for v in z]))
+        for v in z:
+            valid(v)[...] -= m
+    return z
+
+
+def pcg_solve(lev0, phi, f, rel_tol=1e-10, abs_tol=0.0, opts=None, levels=None, precond=None):
+    """Preconditioned conjugate gradients on A phi = f (the paper's Krylov CG
+    with its multigrid as preconditioner; "Linear Solvers").
+
+    Default preconditioner: one symmetric V-cycle from a zero guess
+    (``opts.symmetric`` is forced on).  ``precond(r) -> z`` replaces it
+    (identity gives plain CG).  From r = f - A phi, z = M r, p = z, rho = r.z,
+    each iteration: q = A p, alpha = rho / p.q, phi += alpha p, r -= alpha q;
+    stop when max|r| <= tol (tol as in ``solve``), confirmed on the true
+    residual f - A phi (if that is still above tol, r is replaced by it and the
+    recurrence restarts with p = M r); else z = M r, rho' = r.z,
+    p = z + (rho'/rho) p.  Dots accumulate in float64.  For a singular
+    all-periodic problem the mean is taken out of r at the start and of phi at
+    the end.  Returns a dict like ``solve``: history[k] = max|r| after k
+    iterations, iters, converged.
+    """
+    opts = opts or Opts()
+    opts = Opts(**{**opts.__dict__, "symmetric": True})
+    if levels is None:
+        levels = build_levels(lev0, opts.min_bottom_edge, opts.aggregate)
+    if precond is None:
+        def precond(r):
+            return vcycle_precond(levels, r, opts)
+    singular = is_singular(lev0)
+    normf = max_norm(f)
+    info = {"history": [], "iters": 0, "converged": False, "nlevels": len(levels),
+            "restarts": 0}
+    if normf == 0.0:
+        for v in phi:
+            v[...] = 0.0
+        info["converged"] = True
+        return info
+    tol = max(rel_tol * normf, abs_tol)
+
+    def true_residual():
+        r = residual(lev0, phi, f)
+        if singular:
+            m = _mean(r)
+            r = [x - m for x in r]
+        return r
+
+    r = true_residual()
+    it = 0
+    p = rho = None
+    while True:
+        rn = max_norm(r)
+        info["history"].append(rn)
+        if not np.isfinite(rn):
+            break
+        if rn <= tol:
+            rt = true_residual()
+            if max_norm(rt) <= tol:
+                info["converged"] = True
+                break
+            r = rt
+            p = None
+            info["restarts"] += 1
+        if it == opts.max_iter:
+            break
+        z = precond(r)
+        rho_new = _dot(r, [valid(v) for v in z])
+        if p is None:
+            p = [np.array(v, copy=True) for v in z]
+        else:
+            bt = rho_new / rho
+            for ib in range(len(p)):
+                valid(p[ib])[...] = valid(z[ib]) + bt * valid(p[ib])
+        rho = rho_new
+        q = apply_op(lev0, p)
+        pq = _dot([valid(v) for v in p], q)
+        al = rho / pq
+        for ib in range(len(phi)):
+            valid(phi[ib])[...] += al * valid(p[ib])
+            r[ib] = r[ib] - al * q[ib]
+        it += 1
+    info["iters"] = it
+    info["normf"] = normf
+    if singular:
         m = _mean([valid(v) for v in phi])
         for v in phi:
             valid(v)[...] -= m

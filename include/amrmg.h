@@ -114,6 +114,14 @@ typedef struct {
                                       plus a pass over the box boundary layers
                                       (same result as two half-sweeps);
                                       0 = half-sweeps everywhere               */
+  int32_t krylov;              /* [0] 0: V-cycles until the tolerance (the
+                                      paper's multigrid solve); 1: conjugate
+                                      gradients preconditioned by one symmetric
+                                      V-cycle per iteration (post-smoothing black
+                                      then red on every level; the paper's
+                                      Krylov CG, "Linear Solvers"); FP64 only,
+                                      not for the composite solve. iters then
+                                      counts CG iterations                    */
 } mg_opts_t;
 
 typedef struct {

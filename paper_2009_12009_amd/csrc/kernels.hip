@@ -590,7 +590,7 @@ __device__ double block_sum(double v, double* red, int& phase) {
 
 __global__ void __launch_bounds__(256)
     k_sum_partial(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
-                  const double* __restrict__ v, double* __restrict__ partials, int tz) {
+                  const double* __restrict__ v, int ng, double* __restrict__ partials, int tz) {
   __shared__ double red[32];
   int phase = 0;
   const Tile t = tiles[blockIdx.x];
@@ -600,11 +600,89 @@ __global__ void __launch_bounds__(256)
   double s = 0.0;
   if (i <= B.hi[0] && j <= B.hi[1]) {
     const int kend = min(t.z0 + tz - 1, B.hi[2]);
-    for (int k = t.z0; k <= kend; ++k)
-      s += v[B.off_g1 + cidx(d, 1, i - B.lo[0], j - B.lo[1], k - B.lo[2])];
+    const double* V = v + (ng ? B.off_g1 : B.off_g0);
+    for (int k = t.z0; k <= kend; ++k) s += V[cidx(d, ng, i - B.lo[0], j - B.lo[1], k - B.lo[2])];
   }
   s = block_sum(s, red, phase);
   if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.x] = s;
+}
+
+// Per-tile partial of sum a*b over valid cells (a, b: layouts with ng 0 or 1),
+// reduced in a fixed order; k_sum_final adds the partials in order.
+__global__ void __launch_bounds__(256)
+    k_dot_partial(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+                  const double* __restrict__ a, int ang, const double* __restrict__ b, int bng,
+                  double* __restrict__ partials, int tz) {
+  __shared__ double red[32];
+  int phase = 0;
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  double s = 0.0;
+  if (i <= B.hi[0] && j <= B.hi[1]) {
+    const int kend = min(t.z0 + tz - 1, B.hi[2]);
+    const double* A = a + (ang ? B.off_g1 : B.off_g0);
+    const double* Bv = b + (bng ? B.off_g1 : B.off_g0);
+    const int il = i - B.lo[0], jl = j - B.lo[1];
+    for (int k = t.z0; k <= kend; ++k) {
+      const int kl = k - B.lo[2];
+      s += A[cidx(d, ang, il, jl, kl)] * Bv[cidx(d, bng, il, jl, kl)];
+    }
+  }
+  s = block_sum(s, red, phase);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.x] = s;
+}
+
+// Conjugate-gradient updates with the scalars kept on the device.
+// x += alpha p, r -= alpha q with alpha = *num / *den; max |r| -> normbits.
+// Products and sums are rounded separately (no fused multiply-add), as in
+// the plain formulation.
+__global__ void __launch_bounds__(256)
+    k_cg_xr(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes, double* __restrict__ x,
+            const double* __restrict__ p, double* __restrict__ r, const double* __restrict__ q,
+            const double* __restrict__ num, const double* __restrict__ den,
+            unsigned long long* normbits, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  unsigned long long mx = 0;
+  if (i <= B.hi[0] && j <= B.hi[1]) {
+    const double alpha = *num / *den;
+    const int kend = min(t.z0 + tz - 1, B.hi[2]);
+    const int il = i - B.lo[0], jl = j - B.lo[1];
+    for (int k = t.z0; k <= kend; ++k) {
+      const int kl = k - B.lo[2];
+      const long long c1 = B.off_g1 + cidx(d, 1, il, jl, kl);
+      const long long c0 = B.off_g0 + cidx(d, 0, il, jl, kl);
+      x[c1] = __dadd_rn(x[c1], __dmul_rn(alpha, p[c1]));
+      const double rv = __dsub_rn(r[c0], __dmul_rn(alpha, q[c0]));
+      r[c0] = rv;
+      const unsigned long long bits = absbits(rv);
+      mx = bits > mx ? bits : mx;
+    }
+  }
+  block_max_u64(mx, normbits);
+}
+
+// p = z (first) or p = z + (*num / *den) p, both with one ghost layer.
+__global__ void __launch_bounds__(256)
+    k_cg_p(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes, double* __restrict__ p,
+           const double* __restrict__ z, const double* __restrict__ num,
+           const double* __restrict__ den, int first, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  if (i > B.hi[0] || j > B.hi[1]) return;
+  const double beta = first ? 0.0 : *num / *den;
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  const int il = i - B.lo[0], jl = j - B.lo[1];
+  for (int k = t.z0; k <= kend; ++k) {
+    const long long c = B.off_g1 + cidx(d, 1, il, jl, k - B.lo[2]);
+    p[c] = first ? z[c] : __dadd_rn(z[c], __dmul_rn(beta, p[c]));
+  }
 }
 
 __global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ partials, int n,
@@ -619,7 +697,8 @@ __global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ pa
 
 __global__ void __launch_bounds__(256)
     k_shift_valid(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
-                  double* __restrict__ v, const double* __restrict__ sum, double inv_n, int tz) {
+                  double* __restrict__ v, int ng, const double* __restrict__ sum, double inv_n,
+                  int tz) {
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = boxes[t.box];
   const BoxDims d = dims(B);
@@ -627,8 +706,8 @@ __global__ void __launch_bounds__(256)
   if (i > B.hi[0] || j > B.hi[1]) return;
   const double m = *sum * inv_n;
   const int kend = min(t.z0 + tz - 1, B.hi[2]);
-  for (int k = t.z0; k <= kend; ++k)
-    v[B.off_g1 + cidx(d, 1, i - B.lo[0], j - B.lo[1], k - B.lo[2])] -= m;
+  double* V = v + (ng ? B.off_g1 : B.off_g0);
+  for (int k = t.z0; k <= kend; ++k) V[cidx(d, ng, i - B.lo[0], j - B.lo[1], k - B.lo[2])] -= m;
 }
 
 template <typename T>
@@ -1252,21 +1331,50 @@ hipError_t launch_zero_valid(hipStream_t st, const Tile* tiles, int ntiles, Shap
 }
 
 hipError_t launch_sum_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
-                            const BoxInfo* boxes, const double* v, double* partials,
+                            const BoxInfo* boxes, const double* v, int ng, double* partials,
                             double* sum) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sum_partial, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, v, partials,
-                     sh.tz);
+  hipLaunchKernelGGL(k_sum_partial, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, v, ng,
+                     partials, sh.tz);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partials, ntiles, sum);
   return hipGetLastError();
 }
 
 hipError_t launch_shift_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
-                              const BoxInfo* boxes, double* v, const double* sum,
+                              const BoxInfo* boxes, double* v, int ng, const double* sum,
                               long long ncell) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_shift_valid, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, v, sum,
+  hipLaunchKernelGGL(k_shift_valid, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, v, ng, sum,
                      1.0 / (double)ncell, sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                      const BoxInfo* boxes, const double* a, int ang, const double* b, int bng,
+                      double* partials, double* out) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dot_partial, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, a, ang, b,
+                     bng, partials, sh.tz);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partials, ntiles, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_xr(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                        const BoxInfo* boxes, double* x, const double* p, double* r,
+                        const double* q, const double* num, const double* den,
+                        unsigned long long* normbits) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_xr, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, x, p, r, q, num,
+                     den, normbits, sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_p(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                       const BoxInfo* boxes, double* p, const double* z, const double* num,
+                       const double* den, int first) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_p, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, p, z, num, den,
+                     first, sh.tz);
   return hipGetLastError();
 }
 

@@ -101,15 +101,31 @@ template <typename T>
 hipError_t launch_zero_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                              const BoxInfo* boxes, T* v, int ng);
 
-// Deterministic sum of v (ng 1) over valid cells: one partial per tile into
-// partials[ntiles], then one work-group adds them in order into *sum.  Then
-// v -= *sum / ncell on valid cells.
+// Deterministic sum of v (layout ng 0 or 1) over valid cells: one partial per
+// tile into partials[ntiles], then one work-group adds them in order into
+// *sum.  Then v -= *sum / ncell on valid cells.
 hipError_t launch_sum_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
-                            const BoxInfo* boxes, const double* v, double* partials,
+                            const BoxInfo* boxes, const double* v, int ng, double* partials,
                             double* sum);
 hipError_t launch_shift_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
-                              const BoxInfo* boxes, double* v, const double* sum,
+                              const BoxInfo* boxes, double* v, int ng, const double* sum,
                               long long ncell);
+
+// Deterministic *out = sum over valid cells of a*b (layouts ang, bng in {0, 1}),
+// partials as in launch_sum_valid.
+hipError_t launch_dot(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                      const BoxInfo* boxes, const double* a, int ang, const double* b, int bng,
+                      double* partials, double* out);
+// Conjugate-gradient steps with device scalars: x (ng 1) += alpha p (ng 1),
+// r (ng 0) -= alpha q (ng 0), alpha = *num / *den, max |r| into *normbits;
+// and p (ng 1) = z (first) or z + (*num / *den) p.
+hipError_t launch_cg_xr(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                        const BoxInfo* boxes, double* x, const double* p, double* r,
+                        const double* q, const double* num, const double* den,
+                        unsigned long long* normbits);
+hipError_t launch_cg_p(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                       const BoxInfo* boxes, double* p, const double* z, const double* num,
+                       const double* den, int first);
 
 // Ghost exchange: every chunk copies FB_CHUNK cells of one tag, ncomp comps.
 template <typename T>

@@ -114,6 +114,7 @@ struct Level {
   FbChunk* d_chunks = nullptr;
   double *b64[3] = {nullptr, nullptr, nullptr}, *a64 = nullptr;
   double *e64 = nullptr, *rhs64 = nullptr, *r64 = nullptr;
+  double* p64 = nullptr;  // level 0, preconditioned CG: search direction (ng 1)
   float *b32[3] = {nullptr, nullptr, nullptr}, *a32 = nullptr;
   float *e32 = nullptr, *rhs32 = nullptr, *r32 = nullptr;
 };
@@ -143,6 +144,7 @@ struct mg_solver {
   float *bdiag32 = nullptr, *bcoef32 = nullptr, *bwork32 = nullptr;
   // scratch
   unsigned long long* d_norm = nullptr;  // [4]
+  double* d_cg = nullptr;                // [4] preconditioned CG scalars
   int* d_iters = nullptr;
   double* d_sum = nullptr;
   double* d_partials = nullptr;
@@ -491,10 +493,11 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     const bool bottom = l + 1 == nlev;
     if (l == 0) {
       lv.r64 = bump.take<double>(lv.n_g0);
-      if (s->composite) {
+      if (s->composite || s->opts.krylov) {
         lv.e64 = bump.take<double>(lv.n_g1);
         lv.rhs64 = bump.take<double>(lv.n_g0);
       }
+      if (s->opts.krylov) lv.p64 = bump.take<double>(lv.n_g1);
     } else if (!f32) {
       lv.e64 = bump.take<double>(lv.n_g1);
       lv.rhs64 = bump.take<double>(lv.n_g0);
@@ -530,6 +533,7 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     s->bwork64 = bump.take<double>(4 * (size_t)nb);
   }
   s->d_norm = bump.take<unsigned long long>(4);
+  s->d_cg = bump.take<double>(4);
   s->d_iters = bump.take<int>(4);
   s->d_sum = bump.take<double>(2);
   s->d_partials = bump.take<double>(std::max<size_t>(1, s->L[0].cap_cell));
@@ -759,10 +763,14 @@ int smooth_fused(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, cons
   return MG_OK;
 }
 
+// reverse: black before red in every sweep (the post-smoothing of the
+// symmetric V-cycle; always as half-sweeps).
 template <typename T>
 int smooth(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng,
-           int sweeps, bool zero_first, bool prof) {
-  if (lv.fused) return smooth_fused<T>(s, lv, op, phi, rhs, rhs_ng, sweeps, zero_first, prof);
+           int sweeps, bool zero_first, bool prof, bool reverse = false) {
+  if (lv.fused && !reverse)
+    return smooth_fused<T>(s, lv, op, phi, rhs, rhs_ng, sweeps, zero_first, prof);
+  const int c0 = reverse ? 1 : 0;
   int rc;
   for (int k = 0; k < sweeps; ++k) {
     const bool zg = zero_first && k == 0;
@@ -770,13 +778,13 @@ int smooth(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, const T* r
     {
       ProfScope ps(s, 0, prof);
       HIPTRY(launch_gsrb<T>(s->st, lv.d_gsrb, (int)lv.t_gsrb.size(), lv.s_gsrb, op, phi, rhs,
-                            rhs_ng, 0, zg ? 1 : 0));
+                            rhs_ng, c0, zg ? 1 : 0));
     }
     if ((rc = exchange<T>(s, lv, phi, prof))) return rc;
     {
       ProfScope ps(s, 0, prof);
       HIPTRY(launch_gsrb<T>(s->st, lv.d_gsrb, (int)lv.t_gsrb.size(), lv.s_gsrb, op, phi, rhs,
-                            rhs_ng, 1, 0));
+                            rhs_ng, 1 - c0, 0));
     }
   }
   return MG_OK;
@@ -830,7 +838,7 @@ int coarse_cycle(mg_solver* s, size_t l, bool f32) {
     HIPTRY(launch_prolong_add<T>(s->st, lv.d_cell, (int)lv.t_cell.size(), lv.s_cell, lv.d_info,
                                  cl.d_info, D.e, C.e));
   }
-  return smooth<T>(s, lv, op, D.e, D.rhs, 0, s->opts.nu2, false, prof);
+  return smooth<T>(s, lv, op, D.e, D.rhs, 0, s->opts.nu2, false, prof, s->opts.krylov != 0);
 }
 
 int capture_graphs(mg_solver* s) {
@@ -1591,6 +1599,7 @@ void mg_default_opts(mg_opts_t* o) {
   o->aggregate = 0;
   o->bottom_rel_tol = 1e-4;
   o->fused_min_edge = 0;
+  o->krylov = 0;
 }
 
 static int check_opts(const mg_opts_t* o) {
@@ -1602,6 +1611,9 @@ static int check_opts(const mg_opts_t* o) {
   if (o->tune < 0 || o->tune > 2) return fail(MG_ERR_ARG, "bad tune");
   if (!(o->bottom_rel_tol >= 0)) return fail(MG_ERR_ARG, "bad bottom_rel_tol");
   if (o->fused_min_edge < 0) return fail(MG_ERR_ARG, "fused_min_edge < 0");
+  if (o->krylov != 0 && o->krylov != 1) return fail(MG_ERR_ARG, "bad krylov");
+  if (o->krylov && o->precision != MG_PREC_F64)
+    return fail(MG_ERR_ARG, "the preconditioned CG solve runs in FP64 only");
   return MG_OK;
 }
 
@@ -1747,6 +1759,106 @@ int mg_set_coefficients_global(mg_solver_t* s, const void* acoef_global,
   return end_call(s);
 }
 
+// Preconditioned conjugate gradients on level 0 with one symmetric V-cycle
+// (zero guess, post-smoothing black then red) as the preconditioner: the
+// paper's Krylov CG with its multigrid inside.  x = P (ng 1) in place;
+// r = L0.rhs64 (the V-cycle's right-hand side), z = L0.e64 (its result),
+// p = L0.p64, q = A p in L0.r64 (free again once the V-cycle has returned).
+// The max-norm stop test runs on the recurrence residual and is confirmed on
+// the true one; if that is still above tol, r is replaced by it and the
+// recurrence restarts from p = M r.  Scalars stay on the device: d_cg[0..1]
+// hold rho = r.z of alternate iterations, d_cg[2] = p.q.
+int solve_pcg(mg_solver* s, double* P, const double* F, int rng, double tol, mg_info_t* inf,
+              double* resid_history) {
+  Level& l0 = s->L[0];
+  const StencilArgs<double> op = stencil_of<double>(s, l0, false);
+  const int nt = (int)l0.t_cell.size();
+  const Shape sh = l0.s_cell;
+  double* r = l0.rhs64;
+  double* z = l0.e64;
+  double* p = l0.p64;
+  double* q = l0.r64;
+  int rc;
+  // r = f - A x (into buf), mean taken out when singular; max |r| read back
+  auto true_residual = [&](double* buf, double* norm) -> int {
+    HIPTRY(launch_fill_u64(s->st, s->d_norm + 2, 1, 0ull));
+    if ((rc = exchange<double>(s, l0, P, false))) return rc;
+    {
+      ProfScope ps(s, 1, true);
+      HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, nt, sh, op, P, F, rng, buf,
+                                              s->singular ? nullptr : s->d_norm + 2, 0)));
+    }
+    if (s->singular) {
+      HIPTRY(launch_sum_valid(s->st, l0.d_cell, nt, sh, l0.d_info, buf, 0, s->d_partials,
+                              s->d_sum));
+      HIPTRY(launch_shift_valid(s->st, l0.d_cell, nt, sh, l0.d_info, buf, 0, s->d_sum, l0.ncell));
+      HIPTRY(launch_maxabs<double>(s->st, l0.d_cell, nt, sh, l0.d_info, buf, 0, s->d_norm + 2));
+    }
+    return read_norm(s, 2, norm);
+  };
+  double rn;
+  if ((rc = true_residual(r, &rn))) return rc;
+  int it = 0, status = MG_OK;
+  bool restart = true;
+  while (true) {
+    if (resid_history) resid_history[it] = rn;
+    if (s->opts.verbose) fprintf(stderr, "amrmg pcg %d  max|r| = %.6e\n", it, rn);
+    if (!std::isfinite(rn)) {
+      status = fail(MG_ERR_NAN, "residual norm is not finite");
+      break;
+    }
+    if (rn <= tol) {
+      double rt;
+      if ((rc = true_residual(q, &rt))) return rc;
+      if (rt <= tol) {
+        inf->converged = 1;
+        break;
+      }
+      HIPTRY(hipMemcpyAsync(r, q, sizeof(double) * l0.n_g0, hipMemcpyDeviceToDevice, s->st));
+      restart = true;
+    }
+    if (it == s->opts.max_iter) {
+      status = fail(MG_ERR_NOT_CONVERGED, "max_iter reached");
+      break;
+    }
+    // z = M r
+    if ((rc = coarse_cycle<double>(s, 0, false))) return rc;
+    if (s->singular) {
+      HIPTRY(launch_sum_valid(s->st, l0.d_cell, nt, sh, l0.d_info, z, 1, s->d_partials, s->d_sum));
+      HIPTRY(launch_shift_valid(s->st, l0.d_cell, nt, sh, l0.d_info, z, 1, s->d_sum, l0.ncell));
+    }
+    double* rho_new = s->d_cg + (it & 1);
+    double* rho_old = s->d_cg + ((it + 1) & 1);
+    HIPTRY(launch_dot(s->st, l0.d_cell, nt, sh, l0.d_info, r, 0, z, 1, s->d_partials, rho_new));
+    {
+      ProfScope ps(s, 6, true);
+      HIPTRY(launch_cg_p(s->st, l0.d_cell, nt, sh, l0.d_info, p, z, rho_new, rho_old,
+                         restart ? 1 : 0));
+    }
+    restart = false;
+    // q = A p, alpha = rho_new / p.q
+    if ((rc = exchange<double>(s, l0, p, true))) return rc;
+    {
+      ProfScope ps(s, 1, true);
+      HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, nt, sh, op, p, nullptr, 0, q,
+                                              nullptr, 1)));
+    }
+    HIPTRY(launch_dot(s->st, l0.d_cell, nt, sh, l0.d_info, p, 1, q, 0, s->d_partials,
+                      s->d_cg + 2));
+    HIPTRY(launch_fill_u64(s->st, s->d_norm + 2, 1, 0ull));
+    {
+      ProfScope ps(s, 6, true);
+      HIPTRY(launch_cg_xr(s->st, l0.d_cell, nt, sh, l0.d_info, P, p, r, q, rho_new, s->d_cg + 2,
+                          s->d_norm + 2));
+    }
+    ++it;
+    if ((rc = read_norm(s, 2, &rn))) return rc;
+  }
+  inf->iters = it;
+  inf->abs_resid = rn;
+  return status;
+}
+
 int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, double rel_tol,
              double abs_tol, mg_info_t* info, double* resid_history) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -1783,6 +1895,9 @@ int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, doubl
     HIPTRY(hipStreamSynchronize(s->st));
     inf.converged = 1;
     if (resid_history) resid_history[0] = 0.0;
+  } else if (s->opts.krylov) {
+    status = solve_pcg(s, P, F, rng, std::max(rel_tol * normf, abs_tol), &inf, resid_history);
+    inf.rel_resid = inf.abs_resid / normf;
   } else {
     const double tol = std::max(rel_tol * normf, abs_tol);
     int it = 0, rising = 0;
@@ -1838,9 +1953,9 @@ int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, doubl
     inf.rel_resid = rn / normf;
   }
   if (s->singular) {
-    HIPTRY(launch_sum_valid(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info, P,
+    HIPTRY(launch_sum_valid(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info, P, 1,
                             s->d_partials, s->d_sum));
-    HIPTRY(launch_shift_valid(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info, P,
+    HIPTRY(launch_shift_valid(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info, P, 1,
                               s->d_sum, l0.ncell));
   }
   HIPTRY(hipMemcpyAsync(s->h_iters, s->d_iters, sizeof(int), hipMemcpyDeviceToHost, s->st));
@@ -2001,6 +2116,7 @@ static int amr_plan(mg_solver* s, const mg_box_t* cboxes, int32_t ncb, const mg_
   if ((rc = check_opts(&s->opts))) return rc;
   if (s->opts.precision != MG_PREC_F64)
     return fail(MG_ERR_ARG, "the composite solve runs in FP64 only");
+  if (s->opts.krylov) return fail(MG_ERR_ARG, "the composite solve has no Krylov variant");
   if ((rc = check_geom(geom, nullptr, nullptr, s))) return rc;
   for (int d = 0; d < 3; ++d)
     if (s->periodic[d]) return fail(MG_ERR_ARG, "the composite solve needs Dirichlet walls");

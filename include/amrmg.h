@@ -119,9 +119,11 @@ typedef struct {
                                       gradients preconditioned by one symmetric
                                       V-cycle per iteration (post-smoothing black
                                       then red on every level; the paper's
-                                      Krylov CG, "Linear Solvers"); FP64 only,
-                                      not for the composite solve. iters then
-                                      counts CG iterations                    */
+                                      Krylov CG, "Linear Solvers"); with
+                                      MG_PREC_F32_REFINE the V-cycle runs in
+                                      FP32 on r rounded to FP32 and CG stays in
+                                      FP64.  Not for the composite solve; iters
+                                      then counts CG iterations               */
 } mg_opts_t;
 
 typedef struct {

@@ -517,24 +517,30 @@ def solve_refine(lev0, phi, f, rel_tol=1e-10, abs_tol=0.0, opts=None, inner_dtyp
 
 
 def vcycle_precond(levels, r, opts):
-    """z = M r: one V-cycle on A z = r from z = 0 (mean removed for a singular
-    all-periodic problem)."""
-    z = new_cell_data(levels[0])
-    vcycle(levels, 0, z, r, opts)
+    """z = M r: one V-cycle on A z = r from z = 0, in the precision of
+    ``levels`` (r rounded to it, z returned in float64); mean removed for a
+    singular all-periodic problem."""
+    dt = levels[0].dtype
+    z = new_cell_data(levels[0], dtype=dt)
+    vcycle(levels, 0, z, [x.astype(dt) for x in r], opts)
+    z = [x.astype(np.float64) for x in z]
     if is_singular(levels[0]):
-        m = levels[0].dtype(_mean([valid(v) for v in z]))
+        m = _mean([valid(v) for v in z])
         for v in z:
             valid(v)[...] -= m
     return z
 
 
-def pcg_solve(lev0, phi, f, rel_tol=1e-10, abs_tol=0.0, opts=None, levels=None, precond=None):
+def pcg_solve(lev0, phi, f, rel_tol=1e-10, abs_tol=0.0, opts=None, levels=None, precond=None,
+              inner_dtype=np.float64):
     """Preconditioned conjugate gradients on A phi = f (the paper's Krylov CG
     with its multigrid as preconditioner; "Linear Solvers").
 
     Default preconditioner: one symmetric V-cycle from a zero guess
-    (``opts.symmetric`` is forced on).  ``precond(r) -> z`` replaces it
-    (identity gives plain CG).  From r = f - A phi, z = M r, p = z, rho = r.z,
+    (``opts.symmetric`` is forced on), run in ``inner_dtype`` on a copy of the
+    hierarchy coarsened in float64 and then rounded (float32: the mixed
+    precision of ``solve_refine`` with CG as the outer loop).
+    ``precond(r) -> z`` replaces it (identity gives plain CG).  From r = f - A phi, z = M r, p = z, rho = r.z,
     each iteration: q = A p, alpha = rho / p.q, phi += alpha p, r -= alpha q;
     stop when max|r| <= tol (tol as in ``solve``), confirmed on the true
     residual f - A phi (if that is still above tol, r is replaced by it and the
@@ -549,8 +555,10 @@ def pcg_solve(lev0, phi, f, rel_tol=1e-10, abs_tol=0.0, opts=None, levels=None, 
     if levels is None:
         levels = build_levels(lev0, opts.min_bottom_edge, opts.aggregate)
     if precond is None:
+        inner = levels if inner_dtype == np.float64 else [cast_level(L, inner_dtype) for L in levels]
+
         def precond(r):
-            return vcycle_precond(levels, r, opts)
+            return vcycle_precond(inner, r, opts)
     singular = is_singular(lev0)
     normf = max_norm(f)
     info = {"history": [], "iters": 0, "converged": False, "nlevels": len(levels),

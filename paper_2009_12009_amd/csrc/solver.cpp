@@ -1612,8 +1612,6 @@ static int check_opts(const mg_opts_t* o) {
   if (!(o->bottom_rel_tol >= 0)) return fail(MG_ERR_ARG, "bad bottom_rel_tol");
   if (o->fused_min_edge < 0) return fail(MG_ERR_ARG, "fused_min_edge < 0");
   if (o->krylov != 0 && o->krylov != 1) return fail(MG_ERR_ARG, "bad krylov");
-  if (o->krylov && o->precision != MG_PREC_F64)
-    return fail(MG_ERR_ARG, "the preconditioned CG solve runs in FP64 only");
   return MG_OK;
 }
 
@@ -1821,8 +1819,15 @@ int solve_pcg(mg_solver* s, double* P, const double* F, int rng, double tol, mg_
       status = fail(MG_ERR_NOT_CONVERGED, "max_iter reached");
       break;
     }
-    // z = M r
-    if ((rc = coarse_cycle<double>(s, 0, false))) return rc;
+    // z = M r, the V-cycle in FP64, or in FP32 on r rounded to FP32 (the
+    // mixed-precision preconditioner; CG itself stays in FP64)
+    if (s->opts.precision == MG_PREC_F32_REFINE) {
+      HIPTRY((launch_convert<double, float>(s->st, r, l0.rhs32, l0.n_g0)));
+      if ((rc = coarse_cycle<float>(s, 0, true))) return rc;
+      HIPTRY((launch_convert<float, double>(s->st, l0.e32, z, l0.n_g1)));
+    } else {
+      if ((rc = coarse_cycle<double>(s, 0, false))) return rc;
+    }
     if (s->singular) {
       HIPTRY(launch_sum_valid(s->st, l0.d_cell, nt, sh, l0.d_info, z, 1, s->d_partials, s->d_sum));
       HIPTRY(launch_shift_valid(s->st, l0.d_cell, nt, sh, l0.d_info, z, 1, s->d_sum, l0.ncell));

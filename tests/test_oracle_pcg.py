@@ -75,15 +75,19 @@ def test_identity_preconditioner_is_scipy_cg():
         assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("periodic", [(False, False, False), (True, False, True)])
-def test_pcg_matches_dense_direct(periodic):
+@pytest.mark.parametrize("periodic,inner", [((False, False, False), np.float64),
+                                            ((True, False, True), np.float64),
+                                            ((False, False, False), np.float32)])
+def test_pcg_matches_dense_direct(periodic, inner):
+    """Also with a float32 V-cycle as the preconditioner: the float64 CG loop
+    still reaches the float64 solution."""
     n = 16
     lev, faces = _level(n, 8, periodic)
     A = assemble(n, faces, 1.0, 1.0, periodic)
     f = W.uniform_rhs(n, 16)
     phi = O.new_cell_data(lev)
     info = O.pcg_solve(lev, phi, W.scatter_cells(f, lev.boxes), 1e-13,
-                       opts=O.Opts(min_bottom_edge=2, bottom_tol=1e-12))
+                       opts=O.Opts(min_bottom_edge=2, bottom_tol=1e-12), inner_dtype=inner)
     assert info["converged"]
     ref = np.linalg.solve(A, f.ravel()).reshape(n, n, n)
     got = W.gather_cells(phi, lev.boxes, n, ng=1)

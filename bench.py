@@ -397,27 +397,31 @@ def bench_c4(args):
     rc = P.MultiFab.from_numpy(cb, W.scatter_cells(cfg["rhs"], cb), 0)
     rf = P.MultiFab.from_numpy(fb, amr.fine_rhs(fb, cfg["centres"], 2 * cfg["n"]), 0)
     log(f"c4 inputs ({len(fb)} fine boxes) in {time.perf_counter() - t0:.1f} s", args.quiet)
-    s = P.CompositeMLMG(cb, fb, W.domain_box(cfg["n"]), 1.0, 1.0, b_c=bcm, b_f=bfm,
-                        opts=dict(tune=2, aggregate=args.aggregate))
-    pc = s.coarse_mf(1, fill=0.0)
-    pf = s.fine_mf(1, fill=0.0)
-    times = []
-    for k in range(args.warmup + args.steps):
-        pc.data.zero_()
-        pf.data.zero_()
-        info = s.solve(pc, pf, rc, rf, 1e-10)
-        assert info["converged"], info
-        if k >= args.warmup:
-            times.append(info["solve_ms"])
+    res = {}
+    for name, prec in (("f64", 0), ("f32_refine", 1)):
+        s = P.CompositeMLMG(cb, fb, W.domain_box(cfg["n"]), 1.0, 1.0, b_c=bcm, b_f=bfm,
+                            opts=dict(tune=2, aggregate=args.aggregate, precision=prec))
+        pc = s.coarse_mf(1, fill=0.0)
+        pf = s.fine_mf(1, fill=0.0)
+        times = []
+        for k in range(args.warmup + args.steps):
+            pc.data.zero_()
+            pf.data.zero_()
+            info = s.solve(pc, pf, rc, rf, 1e-10)
+            assert info["converged"], info
+            if k >= args.warmup:
+                times.append(info["solve_ms"])
+        res[name] = dict(time_to_tol_ms=float(np.median(times)), cycles=info["iters"],
+                         rel_resid=info["rel_resid"], setup_ms=info["setup_ms"])
+        s.close()
     fine_cells = sum(int(np.prod([h - l + 1 for l, h in zip(*b)])) for b in fb)
     out = {"metric": "time to 1e-10 composite rel residual, two-level 256^3 + blob refinement",
            "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
-           "dtype": "f64", "value": float(np.median(times)),
+           "dtype": "f64", "value": res["f64"]["time_to_tol_ms"],
            "config": {"workload": "composite256", "fine_boxes": len(fb), "fine_cells": fine_cells,
                       "aggregate": args.aggregate},
-           "cycles": info["iters"], "rel_resid": info["rel_resid"], "setup_ms": info["setup_ms"]}
+           "variants": res}
     print(json.dumps(out), flush=True)
-    s.close()
     torch.cuda.synchronize()
 
 

@@ -155,8 +155,11 @@ void mg_default_opts(mg_opts_t* opts);
  * fine box covers; covered coarse cells hold the mean of their children.
  * Fine ghost cells no fine box supplies are interpolated from the coarse
  * level (central slopes, unlimited); an uncovered coarse cell's flux across
- * a coarse/fine face is the mean of the 4 fine fluxes.  a = 1; FP64 only.
+ * a coarse/fine face is the mean of the 4 fine fluxes.  a = 1.
  * Each outer step: 2*nu1 fine sweeps, one coarse V-cycle, 2*nu2 fine sweeps.
+ * The outer composite residual and the update are FP64; with precision
+ * MG_PREC_F32_REFINE the correction (sweeps, V-cycle, interpolation,
+ * refluxing) runs in FP32 on that residual rounded once.  krylov must be 0.
  * bcoef_c / bcoef_f: three face MultiFabs per level, or NULL for b = 1.
  * mg_solve_amr stops when the max-norm composite residual (fine cells and
  * uncovered coarse cells) is <= max(rel_tol * max|rhs| over the same cells,

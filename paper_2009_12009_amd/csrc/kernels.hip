@@ -1000,10 +1000,11 @@ __global__ void __launch_bounds__(1024)
 }
 
 // Coarse cells of coarsen(fine box): mean of the 8 children or zero.
+template <typename T>
 __global__ void __launch_bounds__(256)
     k_avgdown(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ fine,
-              const BoxInfo* __restrict__ coarse, const double* __restrict__ f, int fng,
-              double* __restrict__ c, int cng, int zero_only, int tz) {
+              const BoxInfo* __restrict__ coarse, const T* __restrict__ f, int fng,
+              T* __restrict__ c, int cng, int zero_only, int tz) {
   const Tile t = tiles[blockIdx.x];
   const BoxInfo F = fine[t.box];
   const BoxInfo C = coarse[F.parent];
@@ -1011,63 +1012,64 @@ __global__ void __launch_bounds__(256)
   const int I = t.x0 + threadIdx.x, J = t.y0 + threadIdx.y;
   if (I > fdiv2(F.hi[0]) || J > fdiv2(F.hi[1])) return;
   const int kend = min(t.z0 + tz - 1, fdiv2(F.hi[2]));
-  const double* R = zero_only ? nullptr : f + (fng ? F.off_g1 : F.off_g0);
-  double* Q = c + (cng ? C.off_g1 : C.off_g0);
+  const T* R = zero_only ? nullptr : f + (fng ? F.off_g1 : F.off_g0);
+  T* Q = c + (cng ? C.off_g1 : C.off_g0);
   const long long sy = df.nx + 2 * fng, sz = sy * (df.ny + 2 * fng);
   for (int K = t.z0; K <= kend; ++K) {
     const long long q = cidx(dc, cng, I - C.lo[0], J - C.lo[1], K - C.lo[2]);
     if (zero_only) {
-      Q[q] = 0.0;
+      Q[q] = T(0);
       continue;
     }
     const long long b = cidx(df, fng, 2 * I - F.lo[0], 2 * J - F.lo[1], 2 * K - F.lo[2]);
-    const double z0 = (R[b] + R[b + 1]) + (R[b + sy] + R[b + sy + 1]);
-    const double z1 = (R[b + sz] + R[b + sz + 1]) + (R[b + sz + sy] + R[b + sz + sy + 1]);
-    Q[q] = (z0 + z1) * 0.125;
+    const T z0 = (R[b] + R[b + 1]) + (R[b + sy] + R[b + sy + 1]);
+    const T z1 = (R[b + sz] + R[b + sz + 1]) + (R[b + sz + sy] + R[b + sz + sy + 1]);
+    Q[q] = (z0 + z1) * T(0.125);
   }
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256)
-    k_cf_ghost(const CfGhost* __restrict__ g, int n, const double* __restrict__ coarse,
-               double* __restrict__ fine) {
+    k_cf_ghost(const CfGhost* __restrict__ g, int n, const T* __restrict__ coarse,
+               T* __restrict__ fine) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const CfGhost e = g[i];
-  const double vc = coarse[e.c];
-  double acc = 0.0;
+  const T vc = coarse[e.c];
+  T acc = T(0);
   for (int d = 0; d < 3; ++d) {
-    const double lo = e.nb[2 * d] >= 0 ? coarse[e.nb[2 * d]] : -vc;
-    const double hi = e.nb[2 * d + 1] >= 0 ? coarse[e.nb[2 * d + 1]] : -vc;
-    const double s = 0.5 * (hi - lo);
+    const T lo = e.nb[2 * d] >= 0 ? coarse[e.nb[2 * d]] : -vc;
+    const T hi = e.nb[2 * d + 1] >= 0 ? coarse[e.nb[2 * d + 1]] : -vc;
+    const T s = T(0.5) * (hi - lo);
     acc = acc + (((e.sign >> d) & 1) ? s : -s);
   }
-  fine[e.dst] = vc + 0.25 * acc;
+  fine[e.dst] = vc + T(0.25) * acc;
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256)
     k_cf_reflux(const CfCell* __restrict__ cells, int ncell, const CfFace* __restrict__ faces,
-                const double* __restrict__ phic, const double* __restrict__ phif,
-                const double* __restrict__ bc0, const double* __restrict__ bc1,
-                const double* __restrict__ bc2, const double* __restrict__ bf0,
-                const double* __restrict__ bf1, const double* __restrict__ bf2, double beta,
-                double3 ihc, double3 ihf, double* __restrict__ r) {
+                const T* __restrict__ phic, const T* __restrict__ phif, const T* __restrict__ bc0,
+                const T* __restrict__ bc1, const T* __restrict__ bc2, const T* __restrict__ bf0,
+                const T* __restrict__ bf1, const T* __restrict__ bf2, T beta, T ihc0, T ihc1,
+                T ihc2, T ihf0, T ihf1, T ihf2, T* __restrict__ r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ncell) return;
   const CfCell cc = cells[i];
-  const double pI = phic[cc.phi_idx];
-  double acc = r[cc.r_idx];
+  const T pI = phic[cc.phi_idx];
+  T acc = r[cc.r_idx];
   for (int k = 0; k < cc.count; ++k) {
     const CfFace f = faces[cc.first + k];
-    const double* bc = f.d == 0 ? bc0 : (f.d == 1 ? bc1 : bc2);
-    const double* bf = f.d == 0 ? bf0 : (f.d == 1 ? bf1 : bf2);
-    const double ic = f.d == 0 ? ihc.x : (f.d == 1 ? ihc.y : ihc.z);
-    const double ifn = f.d == 0 ? ihf.x : (f.d == 1 ? ihf.y : ihf.z);
-    const double c = (beta * bc[f.cb_idx]) * ic;
-    const double term_c = c * (pI - phic[f.j_idx]);
-    double fl[4];
+    const T* bc = f.d == 0 ? bc0 : (f.d == 1 ? bc1 : bc2);
+    const T* bf = f.d == 0 ? bf0 : (f.d == 1 ? bf1 : bf2);
+    const T ic = f.d == 0 ? ihc0 : (f.d == 1 ? ihc1 : ihc2);
+    const T ifn = f.d == 0 ? ihf0 : (f.d == 1 ? ihf1 : ihf2);
+    const T c = (beta * bc[f.cb_idx]) * ic;
+    const T term_c = c * (pI - phic[f.j_idx]);
+    T fl[4];
     for (int q = 0; q < 4; ++q) fl[q] = beta * bf[f.fb[q]] * (phif[f.fg[q]] - phif[f.fv[q]]);
     // mean fine flux / h_c, ifn = 1 / (h_f h_c)
-    const double term_f = (((fl[0] + fl[1]) + (fl[2] + fl[3])) * 0.25) * ifn;
+    const T term_f = (((fl[0] + fl[1]) + (fl[2] + fl[3])) * T(0.25)) * ifn;
     acc = acc + (term_c - term_f);
   }
   r[cc.r_idx] = acc;
@@ -1464,31 +1466,32 @@ hipError_t launch_face_grad(hipStream_t st, const BoxInfo* boxes, int nbox, int 
   return hipGetLastError();
 }
 
+template <typename T>
 hipError_t launch_avgdown(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
-                          const BoxInfo* fine, const BoxInfo* coarse, const double* f, int fng,
-                          double* c, int cng, int zero_only) {
+                          const BoxInfo* fine, const BoxInfo* coarse, const T* f, int fng, T* c,
+                          int cng, int zero_only) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_avgdown, dim3(ntiles), block_of(sh), 0, st, tiles, fine, coarse, f, fng, c,
-                     cng, zero_only, sh.tz);
+  hipLaunchKernelGGL(k_avgdown<T>, dim3(ntiles), block_of(sh), 0, st, tiles, fine, coarse, f, fng,
+                     c, cng, zero_only, sh.tz);
   return hipGetLastError();
 }
 
-hipError_t launch_cf_ghost(hipStream_t st, const CfGhost* g, int n, const double* coarse,
-                           double* fine) {
+template <typename T>
+hipError_t launch_cf_ghost(hipStream_t st, const CfGhost* g, int n, const T* coarse, T* fine) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cf_ghost, dim3((n + 255) / 256), dim3(256), 0, st, g, n, coarse, fine);
+  hipLaunchKernelGGL(k_cf_ghost<T>, dim3((n + 255) / 256), dim3(256), 0, st, g, n, coarse, fine);
   return hipGetLastError();
 }
 
+template <typename T>
 hipError_t launch_cf_reflux(hipStream_t st, const CfCell* cells, int ncell, const CfFace* faces,
-                            const double* phic, const double* phif, const double* bc0,
-                            const double* bc1, const double* bc2, const double* bf0,
-                            const double* bf1, const double* bf2, double beta,
-                            const double ihc[3], const double ihf[3], double* r) {
+                            const T* phic, const T* phif, const T* bc0, const T* bc1,
+                            const T* bc2, const T* bf0, const T* bf1, const T* bf2, double beta,
+                            const double ihc[3], const double ihf[3], T* r) {
   if (ncell <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cf_reflux, dim3((ncell + 255) / 256), dim3(256), 0, st, cells, ncell,
-                     faces, phic, phif, bc0, bc1, bc2, bf0, bf1, bf2, beta,
-                     make_double3(ihc[0], ihc[1], ihc[2]), make_double3(ihf[0], ihf[1], ihf[2]), r);
+  hipLaunchKernelGGL(k_cf_reflux<T>, dim3((ncell + 255) / 256), dim3(256), 0, st, cells, ncell,
+                     faces, phic, phif, bc0, bc1, bc2, bf0, bf1, bf2, (T)beta, (T)ihc[0],
+                     (T)ihc[1], (T)ihc[2], (T)ihf[0], (T)ihf[1], (T)ihf[2], r);
   return hipGetLastError();
 }
 
@@ -1536,6 +1539,13 @@ hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* dia
                                       unsigned long long*);                                      \
   template hipError_t launch_rim<T>(hipStream_t, const RimTile*, int, const StencilArgs<T>&, T*, \
                                     const T*, int);                                              \
+  template hipError_t launch_avgdown<T>(hipStream_t, const Tile*, int, Shape, const BoxInfo*,    \
+                                        const BoxInfo*, const T*, int, T*, int, int);            \
+  template hipError_t launch_cf_ghost<T>(hipStream_t, const CfGhost*, int, const T*, T*);        \
+  template hipError_t launch_cf_reflux<T>(hipStream_t, const CfCell*, int, const CfFace*,        \
+                                          const T*, const T*, const T*, const T*, const T*,      \
+                                          const T*, const T*, const T*, double, const double*,   \
+                                          const double*, T*);                                    \
   template hipError_t launch_maxabs<T>(hipStream_t, const Tile*, int, Shape, const BoxInfo*,     \
                                        const T*, int, unsigned long long*);                      \
   template hipError_t launch_restrict<T>(hipStream_t, const Tile*, int, Shape, const BoxInfo*,   \

@@ -165,19 +165,20 @@ hipError_t launch_face_grad(hipStream_t st, const BoxInfo* boxes, int nbox, int 
 // Two-level composite pieces.
 // Covered coarse cells (ghost layer cng) = mean of their 8 fine children (fine
 // ghost layer fng), or 0 when zero_only; tiles = coarse cells of each fine box.
+template <typename T>
 hipError_t launch_avgdown(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
-                          const BoxInfo* fine, const BoxInfo* coarse, const double* f, int fng,
-                          double* c, int cng, int zero_only);
+                          const BoxInfo* fine, const BoxInfo* coarse, const T* f, int fng, T* c,
+                          int cng, int zero_only);
 // Fine ghosts from coarse values (one lane per CfGhost).
-hipError_t launch_cf_ghost(hipStream_t st, const CfGhost* g, int n, const double* coarse,
-                           double* fine);
+template <typename T>
+hipError_t launch_cf_ghost(hipStream_t st, const CfGhost* g, int n, const T* coarse, T* fine);
 // Coarse residual at coarse/fine faces: r += c (phi_I - phi_J) - mean fine flux / h_c,
 // ihc[d] = 1/h_c^2, ihf[d] = 1/(h_f h_c).
+template <typename T>
 hipError_t launch_cf_reflux(hipStream_t st, const CfCell* cells, int ncell, const CfFace* faces,
-                            const double* phic, const double* phif, const double* bc0,
-                            const double* bc1, const double* bc2, const double* bf0,
-                            const double* bf1, const double* bf2, double beta,
-                            const double ihc[3], const double ihf[3], double* r);
+                            const T* phic, const T* phif, const T* bc0, const T* bc1,
+                            const T* bc2, const T* bf0, const T* bf1, const T* bf2, double beta,
+                            const double ihc[3], const double ihf[3], T* r);
 // v += w on valid cells (both ghost layer 1).
 hipError_t launch_axpy_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                              const BoxInfo* boxes, double* v, const double* w);

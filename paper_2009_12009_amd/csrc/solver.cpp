@@ -176,6 +176,8 @@ struct mg_solver {
   CfCell* d_cfcell = nullptr;
   CfFace* d_cfface = nullptr;
   double *Rc = nullptr, *ef = nullptr, *Rf = nullptr, *rf2 = nullptr;
+  // FP32 correction of the composite solve (precision MG_PREC_F32_REFINE)
+  float *Rc32 = nullptr, *ef32 = nullptr, *Rf32 = nullptr, *rf2_32 = nullptr;
 };
 
 namespace {
@@ -1439,6 +1441,13 @@ int build_composite(mg_solver* s, const std::vector<IBox>& fboxes, Bump& bump) {
   s->ef = bump.take<double>(F.n_g1);
   s->Rf = bump.take<double>(F.n_g0);
   s->rf2 = bump.take<double>(F.n_g0);
+  if (s->opts.precision == MG_PREC_F32_REFINE) {
+    for (int d = 0; d < 3; ++d) F.b32[d] = bump.take<float>(F.n_f[d]);
+    s->Rc32 = bump.take<float>(L0.n_g0);
+    s->ef32 = bump.take<float>(F.n_g1);
+    s->Rf32 = bump.take<float>(F.n_g0);
+    s->rf2_32 = bump.take<float>(F.n_g0);
+  }
   s->ws_need = bump.off + 256;
   return MG_OK;
 }
@@ -1462,72 +1471,111 @@ int upload_composite(mg_solver* s) {
 
 // fine ghosts: other fine boxes, then coarse interpolation (covered coarse
 // cells must already hold the average of their children)
-int fine_ghosts(mg_solver* s, double* fine, const double* coarse) {
+template <typename T>
+int fine_ghosts(mg_solver* s, T* fine, const T* coarse) {
   int rc;
-  if ((rc = exchange<double>(s, s->F, fine, false))) return rc;
-  HIPTRY(launch_cf_ghost(s->st, s->d_ghost, (int)s->h_ghost.size(), coarse, fine));
+  if ((rc = exchange<T>(s, s->F, fine, false))) return rc;
+  HIPTRY(launch_cf_ghost<T>(s->st, s->d_ghost, (int)s->h_ghost.size(), coarse, fine));
   return MG_OK;
 }
 
-int avgdown(mg_solver* s, const double* f, int fng, double* c, int cng, int zero_only) {
-  HIPTRY(launch_avgdown(s->st, s->d_fcov, (int)s->t_fcov.size(), s->s_fcov, s->F.d_info,
-                        s->L[0].d_info, f, fng, c, cng, zero_only));
+template <typename T>
+int avgdown(mg_solver* s, const T* f, int fng, T* c, int cng, int zero_only) {
+  HIPTRY(launch_avgdown<T>(s->st, s->d_fcov, (int)s->t_fcov.size(), s->s_fcov, s->F.d_info,
+                           s->L[0].d_info, f, fng, c, cng, zero_only));
   return MG_OK;
 }
+
+template <typename T>
+const T* bcoef(const Level& lv, int d);
+template <>
+const double* bcoef<double>(const Level& lv, int d) { return lv.b64[d]; }
+template <>
+const float* bcoef<float>(const Level& lv, int d) { return lv.b32[d]; }
 
 // composite residual: Rf = ff - A_f phi_f, Rc = fc - A_c phi_c with refluxing,
 // covered Rc = 0 (or, with cover_from, the mean of cover_from's children).
 // Norms (when normbits != null) over fine cells and uncovered coarse cells.
-int composite_residual(mg_solver* s, double* phic, double* phif, const double* fc, int fc_ng,
-                       const double* ff, int ff_ng, double* Rc, double* Rf,
-                       unsigned long long* normbits, const double* cover_from) {
+template <typename T>
+int composite_residual(mg_solver* s, T* phic, T* phif, const T* fc, int fc_ng, const T* ff,
+                       int ff_ng, T* Rc, T* Rf, unsigned long long* normbits, const T* cover_from) {
   Level& L0 = s->L[0];
   Level& F = s->F;
+  const bool f32 = sizeof(T) == 4;
   int rc;
-  if ((rc = avgdown(s, phif, 1, phic, 1, 0))) return rc;
-  if ((rc = exchange<double>(s, L0, phic, false))) return rc;
-  if ((rc = fine_ghosts(s, phif, phic))) return rc;
-  const StencilArgs<double> opf = stencil_of<double>(s, F, false);
-  const StencilArgs<double> opc = stencil_of<double>(s, L0, false);
-  HIPTRY((launch_residual<double, double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, opf,
-                                          phif, ff, ff_ng, Rf, normbits, 0)));
-  HIPTRY((launch_residual<double, double>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, opc,
-                                          phic, fc, fc_ng, Rc, nullptr, 0)));
+  if ((rc = avgdown<T>(s, phif, 1, phic, 1, 0))) return rc;
+  if ((rc = exchange<T>(s, L0, phic, false))) return rc;
+  if ((rc = fine_ghosts<T>(s, phif, phic))) return rc;
+  const StencilArgs<T> opf = stencil_of<T>(s, F, f32);
+  const StencilArgs<T> opc = stencil_of<T>(s, L0, f32);
+  HIPTRY((launch_residual<T, T>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, opf, phif, ff,
+                                ff_ng, Rf, normbits, 0)));
+  HIPTRY((launch_residual<T, T>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, opc, phic, fc,
+                                fc_ng, Rc, nullptr, 0)));
   double ihc[3], ihf[3];
   for (int d = 0; d < 3; ++d) {
     ihc[d] = 1.0 / (L0.h[d] * L0.h[d]);
     ihf[d] = 1.0 / (F.h[d] * L0.h[d]);
   }
-  HIPTRY(launch_cf_reflux(s->st, s->d_cfcell, (int)s->h_cfcell.size(), s->d_cfface, phic, phif,
-                          L0.b64[0], L0.b64[1], L0.b64[2], F.b64[0], F.b64[1], F.b64[2], s->beta,
-                          ihc, ihf, Rc));
+  HIPTRY(launch_cf_reflux<T>(s->st, s->d_cfcell, (int)s->h_cfcell.size(), s->d_cfface, phic,
+                             phif, bcoef<T>(L0, 0), bcoef<T>(L0, 1), bcoef<T>(L0, 2),
+                             bcoef<T>(F, 0), bcoef<T>(F, 1), bcoef<T>(F, 2), s->beta, ihc, ihf,
+                             Rc));
   if (cover_from) {
-    if ((rc = avgdown(s, cover_from, 0, Rc, 0, 0))) return rc;
+    if ((rc = avgdown<T>(s, cover_from, 0, Rc, 0, 0))) return rc;
   } else {
-    if ((rc = avgdown(s, nullptr, 0, Rc, 0, 1))) return rc;
+    if ((rc = avgdown<T>(s, nullptr, 0, Rc, 0, 1))) return rc;
   }
   if (normbits)
-    HIPTRY(launch_maxabs<double>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, Rc,
-                                 0, normbits));
+    HIPTRY(launch_maxabs<T>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, Rc, 0,
+                            normbits));
   return MG_OK;
 }
 
-int fine_sweeps(mg_solver* s, double* ef, double* ec, const double* rhs, int sweeps) {
+template <typename T>
+int fine_sweeps(mg_solver* s, T* ef, T* ec, const T* rhs, int sweeps) {
   Level& F = s->F;
-  const StencilArgs<double> opf = stencil_of<double>(s, F, false);
+  const StencilArgs<T> opf = stencil_of<T>(s, F, sizeof(T) == 4);
   int rc;
   for (int k = 0; k < sweeps; ++k)
     for (int colour = 0; colour < 2; ++colour) {
-      if ((rc = avgdown(s, ef, 1, ec, 1, 0))) return rc;
-      if ((rc = fine_ghosts(s, ef, ec))) return rc;
-      HIPTRY(launch_gsrb<double>(s->st, F.d_gsrb, (int)F.t_gsrb.size(), F.s_gsrb, opf, ef, rhs, 0,
-                                 colour, 0));
+      if ((rc = avgdown<T>(s, ef, 1, ec, 1, 0))) return rc;
+      if ((rc = fine_ghosts<T>(s, ef, ec))) return rc;
+      HIPTRY(launch_gsrb<T>(s->st, F.d_gsrb, (int)F.t_gsrb.size(), F.s_gsrb, opf, ef, rhs, 0,
+                            colour, 0));
     }
   return MG_OK;
 }
 
+// The same correction computed in FP32 on (Rc, Rf) rounded once; phi is
+// updated in FP64.
+int composite_correction32(mg_solver* s, double* phic, double* phif) {
+  Level& L0 = s->L[0];
+  Level& F = s->F;
+  int rc;
+  HIPTRY((launch_convert<double, float>(s->st, s->Rc, s->Rc32, L0.n_g0)));
+  HIPTRY((launch_convert<double, float>(s->st, s->Rf, s->Rf32, F.n_g0)));
+  HIPTRY(launch_zero_valid<float>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info,
+                                  s->ef32, 1));
+  HIPTRY(launch_zero_valid<float>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info,
+                                  L0.e32, 1));
+  if ((rc = fine_sweeps<float>(s, s->ef32, L0.e32, s->Rf32, 2 * s->opts.nu1))) return rc;
+  if ((rc = composite_residual<float>(s, L0.e32, s->ef32, s->Rc32, 0, s->Rf32, 0, L0.rhs32,
+                                      s->rf2_32, nullptr, s->rf2_32)))
+    return rc;
+  if ((rc = coarse_cycle<float>(s, 0, true))) return rc;
+  HIPTRY(launch_prolong_add<float>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info,
+                                   L0.d_info, s->ef32, L0.e32));
+  if ((rc = fine_sweeps<float>(s, s->ef32, L0.e32, s->Rf32, 2 * s->opts.nu2))) return rc;
+  HIPTRY(launch_update(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, phif, s->ef32));
+  HIPTRY(launch_update(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, phic,
+                       L0.e32));
+  return avgdown<double>(s, phif, 1, phic, 1, 0);
+}
+
 // One two-level correction of the composite residual (Rc, Rf) applied to phi.
 int composite_correction(mg_solver* s, double* phic, double* phif) {
+  if (s->opts.precision == MG_PREC_F32_REFINE) return composite_correction32(s, phic, phif);
   Level& L0 = s->L[0];
   Level& F = s->F;
   int rc;
@@ -1538,21 +1586,21 @@ int composite_correction(mg_solver* s, double* phic, double* phif) {
   // the fine level gets twice the sweeps of the coarse V-cycle on each side: it
   // is a small share of the cells, and two sweeps leave its error decaying at
   // about 0.5 per correction against about 0.35 with four
-  if ((rc = fine_sweeps(s, s->ef, L0.e64, s->Rf, 2 * s->opts.nu1))) return rc;
+  if ((rc = fine_sweeps<double>(s, s->ef, L0.e64, s->Rf, 2 * s->opts.nu1))) return rc;
   // residual the fine correction leaves: fine part into rf2, coarse part into
   // L0.rhs64 with covered cells = mean of rf2's children
-  if ((rc = composite_residual(s, L0.e64, s->ef, s->Rc, 0, s->Rf, 0, L0.rhs64, s->rf2, nullptr,
-                               s->rf2)))
+  if ((rc = composite_residual<double>(s, L0.e64, s->ef, s->Rc, 0, s->Rf, 0, L0.rhs64, s->rf2,
+                                       nullptr, s->rf2)))
     return rc;
   // one coarse V-cycle from zero on the whole coarse level
   if ((rc = coarse_cycle<double>(s, 0, false))) return rc;
   HIPTRY(launch_prolong_add<double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info,
                                     L0.d_info, s->ef, L0.e64));
-  if ((rc = fine_sweeps(s, s->ef, L0.e64, s->Rf, 2 * s->opts.nu2))) return rc;
+  if ((rc = fine_sweeps<double>(s, s->ef, L0.e64, s->Rf, 2 * s->opts.nu2))) return rc;
   HIPTRY(launch_axpy_valid(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, phif, s->ef));
   HIPTRY(launch_axpy_valid(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, phic,
                            L0.e64));
-  return avgdown(s, phif, 1, phic, 1, 0);
+  return avgdown<double>(s, phif, 1, phic, 1, 0);
 }
 
 int check_mf_boxes(const std::vector<IBox>& boxes, const mg_multifab_t* mf, int ng_min, int ng_max,
@@ -2119,8 +2167,6 @@ static int amr_plan(mg_solver* s, const mg_box_t* cboxes, int32_t ncb, const mg_
     mg_default_opts(&s->opts);
   int rc;
   if ((rc = check_opts(&s->opts))) return rc;
-  if (s->opts.precision != MG_PREC_F64)
-    return fail(MG_ERR_ARG, "the composite solve runs in FP64 only");
   if (s->opts.krylov) return fail(MG_ERR_ARG, "the composite solve has no Krylov variant");
   if ((rc = check_geom(geom, nullptr, nullptr, s))) return rc;
   for (int d = 0; d < 3; ++d)
@@ -2191,9 +2237,12 @@ int mg_create_amr(const mg_box_t* cboxes, int32_t ncb, const mg_box_t* fboxes, i
   if ((rc = upload_tables(s.get()))) return rc;
   if ((rc = upload_composite(s.get()))) return rc;
   if ((rc = setup_coefficients(s.get(), nullptr, bcoef_c))) return rc;
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < 3; ++d) {
     HIPTRY(launch_scale_faces(s->st, bcoef_f ? (const double*)bcoef_f[d]->data : nullptr,
                               s->F.b64[d], s->F.n_f[d], 1.0));
+    if (s->F.b32[d])
+      HIPTRY((launch_convert<double, float>(s->st, s->F.b64[d], s->F.b32[d], s->F.n_f[d])));
+  }
   if ((rc = coarsen_all(s.get()))) return rc;
   if ((rc = autotune(s.get()))) return rc;
   if ((rc = capture_graphs(s.get()))) return rc;
@@ -2230,7 +2279,7 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
   HIPTRY(launch_fill_u64(s->st, s->d_norm, 4, 0ull));
   HIPTRY(launch_copy_valid(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, Fc,
                            rhs_c->ngrow, s->Rc, 0));
-  if ((rc = avgdown(s, nullptr, 0, s->Rc, 0, 1))) return rc;
+  if ((rc = avgdown<double>(s, nullptr, 0, s->Rc, 0, 1))) return rc;
   HIPTRY(launch_maxabs<double>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, s->Rc,
                                0, s->d_norm));
   HIPTRY(launch_maxabs<double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, Ff,
@@ -2255,8 +2304,8 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
     double rn = 0;
     while (true) {
       HIPTRY(launch_fill_u64(s->st, s->d_norm + 1, 1, 0ull));
-      if ((rc = composite_residual(s, Pc, Pf, Fc, rhs_c->ngrow, Ff, rhs_f->ngrow, s->Rc, s->Rf,
-                                   s->d_norm + 1, nullptr)))
+      if ((rc = composite_residual<double>(s, Pc, Pf, Fc, rhs_c->ngrow, Ff, rhs_f->ngrow, s->Rc,
+                                           s->Rf, s->d_norm + 1, nullptr)))
         return rc;
       if ((rc = read_norm(s, 1, &rn))) return rc;
       if (resid_history) resid_history[it] = rn;

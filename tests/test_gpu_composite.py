@@ -120,6 +120,40 @@ def test_composite_generated_boxes_converge_to_oracle():
 
 
 @pytest.mark.gpu
+def test_composite_float32_correction_reaches_fp64_oracle():
+    """FP32 correction inside the FP64 composite residual loop: converges to
+    1e-10 and to the FP64 oracle's composite solution within 1e-8 rel-L2."""
+    print("[composite] FP32 correction, generated boxes 32^3", flush=True)
+    P = lib()
+    nc = 32
+    fcg = amr.blob_rhs(nc, amr.blob_centres())
+    fboxes = amr.fine_boxes(fcg, block=2, coarse_box=16)
+    case = _case(nc, 16, fboxes)
+    f_f = amr.fine_rhs(fboxes, amr.blob_centres(), 2 * nc)
+    cb = case["cboxes"]
+    s = _gpu(case, dict(bottom_rel_tol=TIGHT, min_bottom_edge=2, precision=1))
+    pc = s.coarse_mf(1, fill=0.0)
+    pf = s.fine_mf(1, fill=0.0)
+    g = s.solve(pc, pf, P.MultiFab.from_numpy(cb, W.scatter_cells(fcg, cb), 0),
+                P.MultiFab.from_numpy(fboxes, f_f, 0), 1e-10, history=True)
+    torch.cuda.synchronize()
+    s.close()
+    comp = _oracle_comp(case)
+    opc = O.new_cell_data(comp.lc)
+    opf = O.new_cell_data(comp.lf)
+    o = OC.composite_solve(comp, opf, opc, f_f, W.scatter_cells(fcg, cb), 1e-10,
+                           opts=O.Opts(min_bottom_edge=2, bottom_tol=TIGHT))
+    print(f"  FP32 correction {g['iters']} steps, FP64 oracle {o['iters']}")
+    assert g["converged"] and abs(g["iters"] - o["iters"]) <= 2
+    gf = np.concatenate([x.ravel() for x in pf.valid_numpy()])
+    of = np.concatenate([O.valid(x).ravel() for x in opf])
+    gc = W.gather_cells(pc.valid_numpy(), cb, nc)
+    oc = W.gather_cells(opc, cb, nc, ng=1)
+    print(f"  rel-L2 vs FP64 oracle: fine {rel_l2(gf, of):.2e}, coarse {rel_l2(gc, oc):.2e}")
+    assert rel_l2(gf, of) <= 1e-8 and rel_l2(gc, oc) <= 1e-8
+
+
+@pytest.mark.gpu
 def test_c4_full_size_composite_residual():
     """256^3 coarse in 64 boxes, blob-tagged fine boxes: the oracle's composite
     operator recomputes the residual of the GPU solution on every composite cell."""

@@ -229,7 +229,9 @@ def main():
     }
     g64 = gs["f64"]
     kname = ("k_sweep<double> level 0, one fused red+black sweep (64 boxes of 64^3)"
-             if g64["fused"] else "k_gsrb<double> level 0, one half-sweep (64 boxes of 64^3)")
+             if g64["fused"] else
+             "k_gsrb<double> level 0, one half-sweep with face-ghost write-through "
+             "(64 boxes of 64^3)")
     traffic = None if g64["fused"] else measured_traffic("k_gsrb<double>",
                                                          g64["tile_shapes"]["smoother"])
     result["roofline"] = {

@@ -124,6 +124,14 @@ typedef struct {
                                       FP32 on r rounded to FP32 and CG stays in
                                       FP64.  Not for the composite solve; iters
                                       then counts CG iterations               */
+  int32_t ghost_write;         /* [1] on levels using half-sweeps (even extents
+                                      in periodic directions), each update of a
+                                      cell on a box's boundary layer is also
+                                      stored into the face ghosts that mirror it,
+                                      so only the first half-sweep after an
+                                      interpolation needs an exchange (same
+                                      result); 0 = exchange before every
+                                      half-sweep                               */
 } mg_opts_t;
 
 typedef struct {

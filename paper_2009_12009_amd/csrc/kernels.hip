@@ -152,6 +152,36 @@ __device__ __forceinline__ Cell<T> eval(const StencilArgs<T>& op, const Nbr<T>& 
   return {diag, off};
 }
 
+// Store a new value of a cell on its box's boundary layer into the face
+// ghosts of the boxes that see it (at most one entry per face in a uniform
+// box array, a few where faces are shared unevenly).  wb is the box's entry
+// range and ex[0..1] its x faces' entries, loaded once per work-group when a
+// face has exactly one (every row of a tile has x-face cells, so these must
+// not wait on dependent loads inside the loop).
+template <typename T>
+__device__ __forceinline__ void wt_store(const WtEntry& w, T* phi, int il, int jl, int kl, T v) {
+  if (il >= w.lo[0] && il <= w.hi[0] && jl >= w.lo[1] && jl <= w.hi[1] && kl >= w.lo[2] &&
+      kl <= w.hi[2])
+    phi[w.base + il + (long long)jl * w.sy + (long long)kl * w.sz] = v;
+}
+
+template <typename T>
+__device__ __forceinline__ void write_through(const WtBox& wb, const WtEntry* ex,
+                                              const WtEntry* __restrict__ wte, T* phi,
+                                              const Strides& s, int il, int jl, int kl, T v) {
+  const bool on[6] = {il == 0, il == s.nx - 1, jl == 0, jl == s.ny - 1, kl == 0, kl == s.nz - 1};
+  if (!(on[0] | on[1] | on[2] | on[3] | on[4] | on[5])) return;
+  for (int f = 0; f < 6; ++f) {
+    if (!on[f]) continue;
+    if (f < 2 && wb.count[f] == 1) {
+      wt_store<T>(ex[f], phi, il, jl, kl, v);
+      continue;
+    }
+    for (int e = wb.first[f]; e < wb.first[f] + wb.count[f]; ++e)
+      wt_store<T>(wte[e], phi, il, jl, kl, v);
+  }
+}
+
 // Red/black half-sweep.  Cells of one colour never read each other, so a lane
 // gathers the inputs of U planes first and then updates them: U independent
 // load groups in flight per lane instead of one.
@@ -159,10 +189,16 @@ __device__ __forceinline__ Cell<T> eval(const StencilArgs<T>& op, const Nbr<T>& 
 // read as an x-neighbour), so that every cache line is written whole instead
 // of one double in two.  No other lane writes that cell in a half-sweep, so
 // the result is the same either way.
-template <typename T, int U, bool ZG, bool WP>
+// WT: each new value is also written into the face ghosts of the boxes that
+// see the cell (wtb/wte), so the next half-sweep needs no exchange.  Only
+// cells of the active colour are written, into ghosts of that colour, and a
+// half-sweep reads only ghosts of the other colour (even periodic extents),
+// so no lane reads what another writes.
+template <typename T, int U, bool ZG, bool WP, bool WT>
 __global__ void __launch_bounds__(256)
     k_gsrb(const Tile* __restrict__ tiles, StencilArgs<T> op, T* __restrict__ phi,
-           const T* __restrict__ rhs, int rhs_ng, int colour, int tz) {
+           const T* __restrict__ rhs, int rhs_ng, int colour, int tz,
+           const WtBox* __restrict__ wtb, const WtEntry* __restrict__ wte) {
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = op.boxes[t.box];
   const int j = t.y0 + threadIdx.y;
@@ -177,6 +213,13 @@ __global__ void __launch_bounds__(256)
   const T* BZ = op.b2 + B.off_f[2];
   const T* A = op.a ? op.a + B.off_g0 : nullptr;
   const int m = B.bcmask;
+  WtBox wb;
+  WtEntry ex[2];
+  if (WT) {
+    wb = wtb[t.box];
+    for (int f = 0; f < 2; ++f)
+      if (wb.count[f] == 1) ex[f] = wte[wb.first[f]];
+  }
   for (int k0 = t.z0; k0 <= kend; k0 += U) {
     Nbr<T> v[U];
     int il[U], pc[U];
@@ -195,7 +238,9 @@ __global__ void __launch_bounds__(256)
     for (int u = 0; u < U; ++u) {
       if (!ok[u]) continue;
       const Cell<T> c = eval<T, !ZG>(op, v[u], A != nullptr, m, s, il[u], jl, k0 + u - B.lo[2]);
-      P[pc[u]] = ZG ? v[u].f / c.diag : (v[u].f + c.off) / c.diag;
+      const T nv = ZG ? v[u].f / c.diag : (v[u].f + c.off) / c.diag;
+      P[pc[u]] = nv;
+      if (WT) write_through<T>(wb, ex, wte, phi, s, il[u], jl, k0 + u - B.lo[2], nv);
       if (WP && !ZG) {
         // partner = the pair's other cell: x+1 when the active cell is the pair's first
         const bool first = ((il[u] + B.lo[0] - t.x0) & 1) == 0;
@@ -1203,21 +1248,26 @@ inline dim3 block_of(Shape sh) { return dim3(sh.lx, sh.ly, 1); }
 template <typename T>
 hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                        const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng, int colour,
-                       int zero_guess) {
+                       int zero_guess, const WtBox* wtb, const WtEntry* wte) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 g(ntiles), b = block_of(sh);
-#define GS(U, Z, W) \
-  hipLaunchKernelGGL((k_gsrb<T, U, Z, W>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng, colour, sh.tz)
-  if (zero_guess) {
-    if (sh.u >= 4) GS(4, true, false); else if (sh.u == 2) GS(2, true, false);
-    else GS(1, true, false);
-  } else if (sh.wp) {
-    if (sh.u >= 4) GS(4, false, true); else if (sh.u == 2) GS(2, false, true);
-    else GS(1, false, true);
+#define GS(U, Z, W, X)                                                                         \
+  hipLaunchKernelGGL((k_gsrb<T, U, Z, W, X>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng, colour, \
+                     sh.tz, wtb, wte)
+#define GSU(Z, W, X)                       \
+  if (sh.u >= 4) GS(4, Z, W, X);           \
+  else if (sh.u == 2) GS(2, Z, W, X);      \
+  else GS(1, Z, W, X);
+  if (wtb) {
+    if (zero_guess) { GSU(true, false, true) }
+    else if (sh.wp) { GSU(false, true, true) }
+    else { GSU(false, false, true) }
   } else {
-    if (sh.u >= 4) GS(4, false, false); else if (sh.u == 2) GS(2, false, false);
-    else GS(1, false, false);
+    if (zero_guess) { GSU(true, false, false) }
+    else if (sh.wp) { GSU(false, true, false) }
+    else { GSU(false, false, false) }
   }
+#undef GSU
 #undef GS
   return hipGetLastError();
 }
@@ -1533,7 +1583,8 @@ hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* dia
 
 #define INST(T)                                                                                  \
   template hipError_t launch_gsrb<T>(hipStream_t, const Tile*, int, Shape, const StencilArgs<T>&, \
-                                     T*, const T*, int, int, int);                               \
+                                     T*, const T*, int, int, int, const WtBox*,                  \
+                                     const WtEntry*);                                            \
   template hipError_t launch_sweep<T>(hipStream_t, const Tile*, int, Shape,                      \
                                       const StencilArgs<T>&, const T*, T*, const T*, int, int,   \
                                       unsigned long long*);                                      \

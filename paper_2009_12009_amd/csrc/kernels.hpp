@@ -32,11 +32,13 @@ struct Shape {
 // Red/black Gauss-Seidel half-sweep over every box: lane (x, y) of a block
 // updates the cell of colour `colour` among tile cells x0+2x, x0+2x+1 on row
 // y0+y, marching z over tz planes.  zero_guess: phi is taken as 0 (nothing
-// but rhs is read).  rhs_ng: 0 or 1.
+// but rhs is read).  rhs_ng: 0 or 1.  With wtb/wte (non-null) every update
+// is also written into the face ghosts that mirror the cell, so face ghosts
+// stay current across half-sweeps without an exchange.
 template <typename T>
 hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                        const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng, int colour,
-                       int zero_guess);
+                       int zero_guess, const WtBox* wtb = nullptr, const WtEntry* wte = nullptr);
 
 // One full red/black sweep, both colours in one pass, out of place: pout
 // receives the result of a red half-sweep followed by a black half-sweep of

@@ -105,6 +105,12 @@ struct Level {
   RimTile* d_rim = nullptr;
   double* alt64 = nullptr;  // second buffer of the smoothed array (ng 1)
   float* alt32 = nullptr;
+  // half-sweeps write updates straight into the face ghosts of other boxes
+  bool wt = false;
+  std::vector<WtEntry> h_wt;
+  std::vector<WtBox> h_wtbox;
+  WtEntry* d_wt = nullptr;
+  WtBox* d_wtbox = nullptr;
   std::vector<FbTag> tags;
   std::vector<FbChunk> chunks;
   // device
@@ -356,6 +362,57 @@ Shape fit_tz(const std::vector<BoxInfo>& info, Shape sh, int xmul, bool coarse) 
   return sh;
 }
 
+// Write-through tables of a level: for every copy tag of the one-layer
+// exchange, the part of its destination region on one of the destination
+// box's six face-ghost slabs (edges and corners are never read by the
+// 7-point kernels) becomes an entry of the source box's opposite face.
+bool make_wt_tables(Level& lv, const int periodic[3]) {
+  std::vector<CopyTag> tags = copy_tags(lv.boxes, lv.domain, periodic, 1);
+  std::vector<std::vector<WtEntry>> per(lv.nbox * 6);
+  for (const CopyTag& t : tags) {
+    const IBox& D = lv.boxes[t.dst];
+    const IBox& S = lv.boxes[t.src];
+    const BoxInfo& DI = lv.info[t.dst];
+    const long long dsy = ext(D, 0) + 2, dsz = dsy * (ext(D, 1) + 2);
+    for (int d = 0; d < 3; ++d)
+      for (int side = 0; side < 2; ++side) {
+        IBox slab = D;
+        slab.lo[d] = slab.hi[d] = side ? D.hi[d] + 1 : D.lo[d] - 1;
+        const IBox r = intersect(t.region, slab);
+        if (!ok(r)) continue;
+        WtEntry e;
+        for (int a = 0; a < 3; ++a) {
+          e.lo[a] = r.lo[a] - t.shift[a] - S.lo[a];
+          e.hi[a] = r.hi[a] - t.shift[a] - S.lo[a];
+        }
+        // the source cells sit on the source box's face opposite to the slab
+        const int sf = 2 * d + (side ? 0 : 1);
+        e.base = DI.off_g1 + (S.lo[0] + t.shift[0] - D.lo[0] + 1) +
+                 (S.lo[1] + t.shift[1] - D.lo[1] + 1) * dsy +
+                 (S.lo[2] + t.shift[2] - D.lo[2] + 1) * dsz;
+        e.sy = (int)dsy;
+        e.sz = (int)dsz;
+        // every target must be a face ghost of the destination's grown array
+        const long long first = e.base + e.lo[0] + e.lo[1] * dsy + e.lo[2] * dsz;
+        const long long last = e.base + e.hi[0] + e.hi[1] * dsy + e.hi[2] * dsz;
+        const long long end = DI.off_g1 + grown_volume(D, 1, -1);
+        const bool src_face = side ? (e.lo[d] == 0 && e.hi[d] == 0)
+                                   : (e.lo[d] == ext(S, d) - 1 && e.hi[d] == ext(S, d) - 1);
+        if (first < DI.off_g1 || last >= end || !src_face) return false;
+        per[t.src * 6 + sf].push_back(e);
+      }
+  }
+  lv.h_wt.clear();
+  lv.h_wtbox.assign(lv.nbox, WtBox{});
+  for (int b = 0; b < lv.nbox; ++b)
+    for (int f = 0; f < 6; ++f) {
+      lv.h_wtbox[b].first[f] = (int)lv.h_wt.size();
+      lv.h_wtbox[b].count[f] = (int)per[b * 6 + f].size();
+      for (const WtEntry& e : per[b * 6 + f]) lv.h_wt.push_back(e);
+    }
+  return true;
+}
+
 // Builds every host table; with a Bump in measure mode it also lays out the
 // workspace.  Returns 0 or an error code.
 int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
@@ -405,6 +462,14 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     // small boxes leave most cells to the rim pass; opts.fused_min_edge says
     // how small is too small
     lv.fused = s->opts.fused_min_edge > 0 && l + 1 < hb.size() && mn >= s->opts.fused_min_edge;
+    // write-through keeps the colours apart only if they alternate across
+    // every periodic wrap
+    bool even = true;
+    for (int d = 0; d < 3; ++d)
+      if (s->periodic[d] && ext(lv.domain, d) % 2) even = false;
+    lv.wt = s->opts.ghost_write && !lv.fused && l + 1 < hb.size() && even;
+    if (lv.wt && !make_wt_tables(lv, s->periodic))
+      return fail(MG_ERR_INVALID_BOXARRAY, "write-through table outside a box's ghost layer");
     if (lv.fused) {
       lv.s_sweep = shape_sweep(mx[0]);
       make_tiles(lv.info, lv.s_sweep, lv.s_sweep.lx, false, lv.t_sweep);
@@ -504,6 +569,10 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
       lv.e64 = bump.take<double>(lv.n_g1);
       lv.rhs64 = bump.take<double>(lv.n_g0);
       if (!bottom) lv.r64 = bump.take<double>(lv.n_g0);
+    }
+    if (lv.wt) {
+      lv.d_wt = bump.take<WtEntry>(std::max<size_t>(1, lv.h_wt.size()));
+      lv.d_wtbox = bump.take<WtBox>(lv.h_wtbox.size());
     }
     if (lv.fused) {
       lv.d_sweep = bump.take<Tile>(lv.cap_sweep);
@@ -766,27 +835,35 @@ int smooth_fused(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, cons
 }
 
 // reverse: black before red in every sweep (the post-smoothing of the
-// symmetric V-cycle; always as half-sweeps).
+// symmetric V-cycle; always as half-sweeps).  On a write-through level the
+// face ghosts stay current from half-sweep to half-sweep, so only the first
+// one needs them exchanged, and only when the caller's data may have stale
+// ghosts (ghosts_current false; a zero-guess start reads none).  On return
+// a write-through level's face ghosts are current.
 template <typename T>
 int smooth(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng,
-           int sweeps, bool zero_first, bool prof, bool reverse = false) {
+           int sweeps, bool zero_first, bool prof, bool reverse = false,
+           bool ghosts_current = false) {
   if (lv.fused && !reverse)
     return smooth_fused<T>(s, lv, op, phi, rhs, rhs_ng, sweeps, zero_first, prof);
   const int c0 = reverse ? 1 : 0;
+  const WtBox* wtb = lv.wt ? lv.d_wtbox : nullptr;
+  const WtEntry* wte = lv.wt ? lv.d_wt : nullptr;
   int rc;
   for (int k = 0; k < sweeps; ++k) {
     const bool zg = zero_first && k == 0;
-    if (!zg && (rc = exchange<T>(s, lv, phi, prof))) return rc;
+    const bool need = lv.wt ? (k == 0 && !zg && !ghosts_current) : !zg;
+    if (need && (rc = exchange<T>(s, lv, phi, prof))) return rc;
     {
       ProfScope ps(s, 0, prof);
       HIPTRY(launch_gsrb<T>(s->st, lv.d_gsrb, (int)lv.t_gsrb.size(), lv.s_gsrb, op, phi, rhs,
-                            rhs_ng, c0, zg ? 1 : 0));
+                            rhs_ng, c0, zg ? 1 : 0, wtb, wte));
     }
-    if ((rc = exchange<T>(s, lv, phi, prof))) return rc;
+    if (!lv.wt && (rc = exchange<T>(s, lv, phi, prof))) return rc;
     {
       ProfScope ps(s, 0, prof);
       HIPTRY(launch_gsrb<T>(s->st, lv.d_gsrb, (int)lv.t_gsrb.size(), lv.s_gsrb, op, phi, rhs,
-                            rhs_ng, 1 - c0, 0));
+                            rhs_ng, 1 - c0, 0, wtb, wte));
     }
   }
   return MG_OK;
@@ -814,7 +891,8 @@ int coarse_cycle(mg_solver* s, size_t l, bool f32) {
     HIPTRY(launch_zero_valid<T>(s->st, lv.d_cell, (int)lv.t_cell.size(), lv.s_cell, lv.d_info, D.e,
                                 1));
   if ((rc = smooth<T>(s, lv, op, D.e, D.rhs, 0, s->opts.nu1, s->opts.nu1 > 0, prof))) return rc;
-  if ((rc = exchange<T>(s, lv, D.e, prof))) return rc;
+  // write-through smoothing leaves the face ghosts current
+  if (!(lv.wt && s->opts.nu1 > 0) && (rc = exchange<T>(s, lv, D.e, prof))) return rc;
   {
     ProfScope ps(s, 1, prof);
     HIPTRY((launch_residual<T, T>(s->st, lv.d_cell, (int)lv.t_cell.size(), lv.s_cell, op, D.e,
@@ -884,8 +962,11 @@ int vcycle64(mg_solver* s, double* phi, const double* rhs, int rhs_ng) {
                                     s->d_iters));
     return MG_OK;
   }
-  if ((rc = smooth<double>(s, l0, op, phi, rhs, rhs_ng, s->opts.nu1, false, true))) return rc;
-  if ((rc = exchange<double>(s, l0, phi, true))) return rc;
+  // the caller's last exchange (or write-through smoothing) left phi's face
+  // ghosts current
+  if ((rc = smooth<double>(s, l0, op, phi, rhs, rhs_ng, s->opts.nu1, false, true, false, true)))
+    return rc;
+  if (!(l0.wt && s->opts.nu1 > 0) && (rc = exchange<double>(s, l0, phi, true))) return rc;
   {
     ProfScope ps(s, 1, true);
     HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, op,
@@ -1049,12 +1130,17 @@ int time_gsrb(mg_solver* s, Shape sh, T* phi, const T* rhs, const StencilArgs<T>
   if ((rc = apply_shape(s, sh, true))) return rc;
   hipEvent_t a = take_event(s), b = take_event(s);
   Level& l0 = s->L[0];
+  // with the level's write-through tables, as the solve launches it
+  const WtBox* wtb = l0.wt ? l0.d_wtbox : nullptr;
+  const WtEntry* wte = l0.wt ? l0.d_wt : nullptr;
   for (int w = 0; w < 2; ++w)
-    HIPTRY(launch_gsrb<T>(s->st, l0.d_gsrb, (int)l0.t_gsrb.size(), sh, op, phi, rhs, 0, w & 1, 0));
+    HIPTRY(launch_gsrb<T>(s->st, l0.d_gsrb, (int)l0.t_gsrb.size(), sh, op, phi, rhs, 0, w & 1, 0,
+                          wtb, wte));
   HIPTRY(hipEventRecord(a, s->st));
   const int reps = 6;
   for (int w = 0; w < reps; ++w)
-    HIPTRY(launch_gsrb<T>(s->st, l0.d_gsrb, (int)l0.t_gsrb.size(), sh, op, phi, rhs, 0, w & 1, 0));
+    HIPTRY(launch_gsrb<T>(s->st, l0.d_gsrb, (int)l0.t_gsrb.size(), sh, op, phi, rhs, 0, w & 1, 0,
+                          wtb, wte));
   HIPTRY(hipEventRecord(b, s->st));
   HIPTRY(hipEventSynchronize(b));
   float t;
@@ -1196,6 +1282,13 @@ int upload_tables(mg_solver* s) {
     if (!lv.t_rst.empty())
       HIPTRY(hipMemcpyAsync(lv.d_rst, lv.t_rst.data(), sizeof(Tile) * lv.t_rst.size(),
                             hipMemcpyHostToDevice, s->st));
+    if (lv.wt) {
+      if (!lv.h_wt.empty())
+        HIPTRY(hipMemcpyAsync(lv.d_wt, lv.h_wt.data(), sizeof(WtEntry) * lv.h_wt.size(),
+                              hipMemcpyHostToDevice, s->st));
+      HIPTRY(hipMemcpyAsync(lv.d_wtbox, lv.h_wtbox.data(), sizeof(WtBox) * lv.h_wtbox.size(),
+                            hipMemcpyHostToDevice, s->st));
+    }
     if (lv.fused) {
       HIPTRY(hipMemcpyAsync(lv.d_sweep, lv.t_sweep.data(), sizeof(Tile) * lv.t_sweep.size(),
                             hipMemcpyHostToDevice, s->st));
@@ -1648,6 +1741,7 @@ void mg_default_opts(mg_opts_t* o) {
   o->bottom_rel_tol = 1e-4;
   o->fused_min_edge = 0;
   o->krylov = 0;
+  o->ghost_write = 1;
 }
 
 static int check_opts(const mg_opts_t* o) {
@@ -1660,6 +1754,7 @@ static int check_opts(const mg_opts_t* o) {
   if (!(o->bottom_rel_tol >= 0)) return fail(MG_ERR_ARG, "bad bottom_rel_tol");
   if (o->fused_min_edge < 0) return fail(MG_ERR_ARG, "fused_min_edge < 0");
   if (o->krylov != 0 && o->krylov != 1) return fail(MG_ERR_ARG, "bad krylov");
+  if (o->ghost_write != 0 && o->ghost_write != 1) return fail(MG_ERR_ARG, "bad ghost_write");
   return MG_OK;
 }
 
@@ -1957,7 +2052,11 @@ int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, doubl
     double rn = 0, first = 0, prev = 0;
     while (true) {
       HIPTRY(launch_fill_u64(s->st, s->d_norm + 1, 1, 0ull));
-      if ((rc = exchange<double>(s, l0, P, false))) return rc;
+      // after an FP64 V-cycle whose post-smoothing wrote through, phi's face
+      // ghosts are current; the refinement update touches valid cells only
+      if ((f32 || it == 0 || !l0.wt || s->opts.nu2 == 0) &&
+          (rc = exchange<double>(s, l0, P, false)))
+        return rc;
       {
         ProfScope ps(s, 1, true);
         if (f32)

@@ -45,6 +45,23 @@ struct FbChunk {
 
 constexpr int FB_CHUNK = 256;
 
+// Write-through of a smoother update into other boxes' face ghosts: the
+// valid cells lo..hi (box-local, inclusive) of a source box are the face
+// ghosts of one destination box; local cell (i, j, k) goes to element
+// base + i + j*sy + k*sz of the level's array.
+struct WtEntry {
+  int lo[3], hi[3];
+  long long base;
+  int sy, sz;
+};
+
+// Per source box and face (xlo, xhi, ylo, yhi, zlo, zhi): the range of its
+// write-through entries.
+struct WtBox {
+  int first[6];
+  int count[6];
+};
+
 // A block of cells of one box (box-local offsets i0, j0, k0 from the box's
 // low corner, extents ni, nj, nk, at most 256 cells) on the box's boundary
 // layer, where the fused sweep leaves the second colour's update to a pass

@@ -36,9 +36,10 @@ def test_struct_sizes_match_header_layout():
     L = P._lib
     assert C.sizeof(L.MgBox) == 24
     assert C.sizeof(L.MgGeom) == 24 + 48 + 12 + 4  # trailing padding to 8
-    assert C.sizeof(L.MgOpts) == 10 * 4 + 8 + 4 + 4  # fused_min_edge, krylov
+    assert C.sizeof(L.MgOpts) == 10 * 4 + 8 + 3 * 4 + 4  # fused_min_edge, krylov, ghost_write, pad
     o = L.default_opts()
-    assert (o.nu1, o.nu2, o.fused_min_edge, o.krylov, o.bottom_rel_tol) == (2, 2, 0, 0, 1e-4)
+    assert (o.nu1, o.nu2, o.fused_min_edge, o.krylov, o.ghost_write, o.bottom_rel_tol) == \
+        (2, 2, 0, 0, 1, 1e-4)
     assert C.sizeof(L.MgCopyTag) == 8 + 24 + 12
 
 

@@ -178,6 +178,10 @@ def main():
                                 "fused_sweep": s.tile_shape(3)}
         s.profile(False)
 
+    # the level-0 FP64 half-sweep launched alone, without ghost write-through
+    ms_alone = solvers["f64"].time_smoother(phis["f64"], rhs, reps=20)
+    smoother_alone = {"mean_ms": ms_alone, "gbps": 6 * 8 * ncell / (ms_alone * 1e-3) / 1e9}
+
     # plain device copy as the achievable ceiling
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
@@ -226,6 +230,7 @@ def main():
         "time_by_family_ms": {k: g["families"] for k, g in gs.items()},
         "tile_shapes": {k: g["tile_shapes"] for k, g in gs.items()},
         "copy_kernel_gbps": copy_gbps,
+        "smoother_alone_f64": smoother_alone,
     }
     g64 = gs["f64"]
     kname = ("k_sweep<double> level 0, one fused red+black sweep (64 boxes of 64^3)"

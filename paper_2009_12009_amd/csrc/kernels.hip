@@ -165,6 +165,21 @@ __device__ __forceinline__ void wt_store(const WtEntry& w, T* phi, int il, int j
     phi[w.base + il + (long long)jl * w.sy + (long long)kl * w.sz] = v;
 }
 
+// y and z faces only (whole rows and planes of a tile); x faces go through
+// the work-group's end-of-tile pass.
+template <typename T>
+__device__ __forceinline__ void write_through_yz(const WtBox& wb, const WtEntry* __restrict__ wte,
+                                                 T* phi, const Strides& s, int il, int jl, int kl,
+                                                 T v) {
+  const bool on[6] = {false, false, jl == 0, jl == s.ny - 1, kl == 0, kl == s.nz - 1};
+  if (!(on[2] | on[3] | on[4] | on[5])) return;
+  for (int f = 2; f < 6; ++f) {
+    if (!on[f]) continue;
+    for (int e = wb.first[f]; e < wb.first[f] + wb.count[f]; ++e)
+      wt_store<T>(wte[e], phi, il, jl, kl, v);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void write_through(const WtBox& wb, const WtEntry* ex,
                                               const WtEntry* __restrict__ wte, T* phi,
@@ -193,7 +208,10 @@ __device__ __forceinline__ void write_through(const WtBox& wb, const WtEntry* ex
 // see the cell (wtb/wte), so the next half-sweep needs no exchange.  Only
 // cells of the active colour are written, into ghosts of that colour, and a
 // half-sweep reads only ghosts of the other colour (even periodic extents),
-// so no lane reads what another writes.
+// so no lane reads what another writes.  Rows of y/z-face cells write as
+// they go; x-face cells (one or two lanes per row) park their values in LDS
+// and the work-group stores them after its z-march, so the march itself
+// carries no per-row divergent stores.
 template <typename T, int U, bool ZG, bool WP, bool WT>
 __global__ void __launch_bounds__(256)
     k_gsrb(const Tile* __restrict__ tiles, StencilArgs<T> op, T* __restrict__ phi,
@@ -202,11 +220,15 @@ __global__ void __launch_bounds__(256)
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = op.boxes[t.box];
   const int j = t.y0 + threadIdx.y;
-  if (j > B.hi[1]) return;
+  if (!WT && j > B.hi[1]) return;  // with WT every lane reaches the barrier below
+  const bool row_ok = j <= B.hi[1];
   const Strides s = strides_of(B, rhs_ng);
   const int jl = j - B.lo[1];
   const int kend = min(t.z0 + tz - 1, B.hi[2]);
   T* P = phi + B.off_g1;
+  extern __shared__ double lds_gsrb[];
+  T* XS = reinterpret_cast<T*>(lds_gsrb);  // [2][ly][tz] x-face values (WT)
+  const int ly = blockDim.y;
   const T* R = rhs + (rhs_ng ? B.off_g1 : B.off_g0);
   const T* BX = op.b0 + B.off_f[0];
   const T* BY = op.b1 + B.off_f[1];
@@ -228,7 +250,7 @@ __global__ void __launch_bounds__(256)
     for (int u = 0; u < U; ++u) {
       const int k = k0 + u;
       const int i = t.x0 + 2 * (int)threadIdx.x + ((colour + t.x0 + j + k) & 1);
-      ok[u] = k <= kend && i <= B.hi[0];
+      ok[u] = row_ok && k <= kend && i <= B.hi[0];
       il[u] = i - B.lo[0];
       pc[u] = (il[u] + 1) + s.sy * (jl + 1) + s.sz * (k - B.lo[2] + 1);
       if (ok[u])
@@ -240,12 +262,47 @@ __global__ void __launch_bounds__(256)
       const Cell<T> c = eval<T, !ZG>(op, v[u], A != nullptr, m, s, il[u], jl, k0 + u - B.lo[2]);
       const T nv = ZG ? v[u].f / c.diag : (v[u].f + c.off) / c.diag;
       P[pc[u]] = nv;
-      if (WT) write_through<T>(wb, ex, wte, phi, s, il[u], jl, k0 + u - B.lo[2], nv);
+      if (WT) {
+        const int kk = k0 + u - t.z0;
+        if (il[u] == 0) XS[(0 * ly + threadIdx.y) * tz + kk] = nv;
+        if (il[u] == s.nx - 1) XS[(1 * ly + threadIdx.y) * tz + kk] = nv;
+        write_through_yz<T>(wb, wte, phi, s, il[u], jl, k0 + u - B.lo[2], nv);
+      }
       if (WP && !ZG) {
         // partner = the pair's other cell: x+1 when the active cell is the pair's first
         const bool first = ((il[u] + B.lo[0] - t.x0) & 1) == 0;
         const int pil = first ? il[u] + 1 : il[u] - 1;
         if (pil >= 0 && pil < s.nx) P[first ? pc[u] + 1 : pc[u] - 1] = first ? v[u].pxh : v[u].pxl;
+      }
+    }
+  }
+  if (WT) {
+    // x faces of this tile: cells of the active colour in column 0 (tile
+    // starts at the box's low x) and column nx-1 (tile reaches its high x)
+    const bool has_lo = t.x0 == B.lo[0] && wb.count[0] > 0;
+    const bool has_hi = B.hi[0] <= t.x0 + 2 * (int)blockDim.x - 1 && wb.count[1] > 0;
+    if (has_lo || has_hi) {
+      __syncthreads();
+      const int nz_t = kend - t.z0 + 1;
+      const int n = ly * nz_t;
+      const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        if (!(f ? has_hi : has_lo)) continue;
+        const int ilf = f ? s.nx - 1 : 0;
+        for (int q = tid; q < n; q += blockDim.x * blockDim.y) {
+          const int ty = q / nz_t, kk = q - ty * nz_t;
+          const int jj = t.y0 + ty, k = t.z0 + kk;
+          if (jj > B.hi[1] || ((B.lo[0] + ilf + jj + k) & 1) != colour) continue;
+          const T xv = XS[(f * ly + ty) * tz + kk];
+          const int jlf = jj - B.lo[1], klf = k - B.lo[2];
+          if (wb.count[f] == 1) {
+            wt_store<T>(ex[f], phi, ilf, jlf, klf, xv);
+          } else {
+            for (int e = wb.first[f]; e < wb.first[f] + wb.count[f]; ++e)
+              wt_store<T>(wte[e], phi, ilf, jlf, klf, xv);
+          }
+        }
       }
     }
   }
@@ -1251,8 +1308,9 @@ hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                        int zero_guess, const WtBox* wtb, const WtEntry* wte) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 g(ntiles), b = block_of(sh);
-#define GS(U, Z, W, X)                                                                         \
-  hipLaunchKernelGGL((k_gsrb<T, U, Z, W, X>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng, colour, \
+  const size_t lds = wtb ? 2 * (size_t)sh.ly * sh.tz * sizeof(T) : 0;
+#define GS(U, Z, W, X)                                                                           \
+  hipLaunchKernelGGL((k_gsrb<T, U, Z, W, X>), g, b, lds, st, tiles, op, phi, rhs, rhs_ng, colour, \
                      sh.tz, wtb, wte)
 #define GSU(Z, W, X)                       \
   if (sh.u >= 4) GS(4, Z, W, X);           \

@@ -510,19 +510,22 @@ __global__ void __launch_bounds__(256)
   P[pc] = (v.f + c.off) / c.diag;
 }
 
+__device__ double block_sum(double v, double* red, int& phase);
+
 // out = rhs - A phi (mode 0) or A phi (mode 1), one lane per cell, U planes
 // gathered at a time; optional NaN-propagating max |out|.
 template <typename T, typename TO, int U>
 __global__ void __launch_bounds__(256)
     k_residual(const Tile* __restrict__ tiles, StencilArgs<T> op, const T* __restrict__ phi,
                const T* __restrict__ rhs, int rhs_ng, TO* __restrict__ out,
-               unsigned long long* normbits, int tz, int mode) {
+               unsigned long long* normbits, int tz, int mode, double* __restrict__ dot_partials) {
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = op.boxes[t.box];
   const int i = t.x0 + threadIdx.x;
   const int j = t.y0 + threadIdx.y;
   const bool act = i <= B.hi[0] && j <= B.hi[1];
   unsigned long long mx = 0;
+  double dot = 0.0;
   if (act) {
     const Strides s = strides_of(B, rhs_ng);
     const int kend = min(t.z0 + tz - 1, B.hi[2]);
@@ -554,10 +557,17 @@ __global__ void __launch_bounds__(256)
         if (O) O[il + s.nx * (jl + s.ny * kl)] = (TO)r;
         const unsigned long long bits = absbits(r);
         mx = bits > mx ? bits : mx;
+        if (dot_partials) dot += (double)v[u].pc * (double)r;
       }
     }
   }
   if (normbits) block_max_u64(mx, normbits);
+  if (dot_partials) {
+    __shared__ double red[32];
+    int phase = 0;
+    dot = block_sum(dot, red, phase);
+    if (threadIdx.x == 0 && threadIdx.y == 0) dot_partials[blockIdx.x] = dot;
+  }
 }
 
 template <typename T>
@@ -744,7 +754,7 @@ __global__ void __launch_bounds__(256)
     k_cg_xr(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes, double* __restrict__ x,
             const double* __restrict__ p, double* __restrict__ r, const double* __restrict__ q,
             const double* __restrict__ num, const double* __restrict__ den,
-            unsigned long long* normbits, int tz) {
+            unsigned long long* normbits, float* __restrict__ r32, int tz) {
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = boxes[t.box];
   const BoxDims d = dims(B);
@@ -761,11 +771,40 @@ __global__ void __launch_bounds__(256)
       x[c1] = __dadd_rn(x[c1], __dmul_rn(alpha, p[c1]));
       const double rv = __dsub_rn(r[c0], __dmul_rn(alpha, q[c0]));
       r[c0] = rv;
+      if (r32) r32[c0] = (float)rv;
       const unsigned long long bits = absbits(rv);
       mx = bits > mx ? bits : mx;
     }
   }
   block_max_u64(mx, normbits);
+}
+
+// z (ng 1, FP64) = e (ng 1, FP32) on valid cells, and per tile the partial
+// of sum r*z (r ghost-free), for k_sum_final.
+__global__ void __launch_bounds__(256)
+    k_widen_dot(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+                const float* __restrict__ e, double* __restrict__ z, const double* __restrict__ r,
+                double* __restrict__ partials, int tz) {
+  __shared__ double red[32];
+  int phase = 0;
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  double s = 0.0;
+  if (i <= B.hi[0] && j <= B.hi[1]) {
+    const int kend = min(t.z0 + tz - 1, B.hi[2]);
+    const int il = i - B.lo[0], jl = j - B.lo[1];
+    for (int k = t.z0; k <= kend; ++k) {
+      const int kl = k - B.lo[2];
+      const long long c1 = B.off_g1 + cidx(d, 1, il, jl, kl);
+      const double zv = (double)e[c1];
+      z[c1] = zv;
+      s += r[B.off_g0 + cidx(d, 0, il, jl, kl)] * zv;
+    }
+  }
+  s = block_sum(s, red, phase);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.x] = s;
 }
 
 // p = z (first) or p = z + (*num / *den) p, both with one ghost layer.
@@ -1377,12 +1416,13 @@ hipError_t launch_rim(hipStream_t st, const RimTile* tiles, int ntiles, const St
 template <typename T, typename TO>
 hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                            const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
-                           TO* out, unsigned long long* normbits, int mode) {
+                           TO* out, unsigned long long* normbits, int mode,
+                           double* dot_partials) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 g(ntiles), b = block_of(sh);
 #define RS(U) \
   hipLaunchKernelGGL((k_residual<T, TO, U>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng, out, \
-                     normbits, sh.tz, mode)
+                     normbits, sh.tz, mode, dot_partials)
   if (sh.u >= 4) RS(4); else if (sh.u == 2) RS(2); else RS(1);
 #undef RS
   return hipGetLastError();
@@ -1472,10 +1512,26 @@ hipError_t launch_dot(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
 hipError_t launch_cg_xr(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                         const BoxInfo* boxes, double* x, const double* p, double* r,
                         const double* q, const double* num, const double* den,
-                        unsigned long long* normbits) {
+                        unsigned long long* normbits, float* r32) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_cg_xr, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, x, p, r, q, num,
-                     den, normbits, sh.tz);
+                     den, normbits, r32, sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_final(hipStream_t st, const double* partials, int n, double* out) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partials, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_widen_dot(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                            const BoxInfo* boxes, const float* e, double* z, const double* r,
+                            double* partials, double* out) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_widen_dot, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, e, z, r,
+                     partials, sh.tz);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partials, ntiles, out);
   return hipGetLastError();
 }
 
@@ -1679,15 +1735,15 @@ INST(float)
 template hipError_t launch_residual<double, double>(hipStream_t, const Tile*, int, Shape,
                                                     const StencilArgs<double>&, const double*,
                                                     const double*, int, double*,
-                                                    unsigned long long*, int);
+                                                    unsigned long long*, int, double*);
 template hipError_t launch_residual<double, float>(hipStream_t, const Tile*, int, Shape,
                                                    const StencilArgs<double>&, const double*,
                                                    const double*, int, float*,
-                                                   unsigned long long*, int);
+                                                   unsigned long long*, int, double*);
 template hipError_t launch_residual<float, float>(hipStream_t, const Tile*, int, Shape,
                                                   const StencilArgs<float>&, const float*,
                                                   const float*, int, float*,
-                                                  unsigned long long*, int);
+                                                  unsigned long long*, int, double*);
 template hipError_t launch_convert<double, float>(hipStream_t, const double*, float*, long long);
 template hipError_t launch_convert<float, double>(hipStream_t, const float*, double*, long long);
 

@@ -63,6 +63,8 @@ template <typename T>
 hipError_t launch_rim(hipStream_t st, const RimTile* tiles, int ntiles, const StencilArgs<T>& op,
                       T* phi, const T* rhs, int rhs_ng);
 
+// With dot_partials, partials[tile] = sum over the tile of phi * out (the
+// product computed before out is rounded to TO), for launch_sum_final.
 // out = rhs - A phi (mode 0) or out = A phi (mode 1) on every valid cell, one
 // lane per cell; out may be null (norm only).  When normbits is non-null the
 // max |out| is folded into *normbits as IEEE-754 bits (NaN-propagating).
@@ -71,7 +73,8 @@ hipError_t launch_rim(hipStream_t st, const RimTile* tiles, int ntiles, const St
 template <typename T, typename TO>
 hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                            const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
-                           TO* out, unsigned long long* normbits, int mode);
+                           TO* out, unsigned long long* normbits, int mode,
+                           double* dot_partials = nullptr);
 
 // max |v| over valid cells folded into *normbits (v: ng 0 or 1 layout).
 template <typename T>
@@ -121,10 +124,17 @@ hipError_t launch_dot(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
 // Conjugate-gradient steps with device scalars: x (ng 1) += alpha p (ng 1),
 // r (ng 0) -= alpha q (ng 0), alpha = *num / *den, max |r| into *normbits;
 // and p (ng 1) = z (first) or z + (*num / *den) p.
+// With r32 (non-null) the new r is also stored rounded to FP32 (ng 0).
 hipError_t launch_cg_xr(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                         const BoxInfo* boxes, double* x, const double* p, double* r,
                         const double* q, const double* num, const double* den,
-                        unsigned long long* normbits);
+                        unsigned long long* normbits, float* r32 = nullptr);
+// *out = partials[0] + ... + partials[n-1] in a fixed order (one work-group).
+hipError_t launch_sum_final(hipStream_t st, const double* partials, int n, double* out);
+// z (FP64, ng 1) = e (FP32, ng 1) on valid cells and *out = sum r*z (r ng 0).
+hipError_t launch_widen_dot(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                            const BoxInfo* boxes, const float* e, double* z, const double* r,
+                            double* partials, double* out);
 hipError_t launch_cg_p(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                        const BoxInfo* boxes, double* p, const double* z, const double* num,
                        const double* den, int first);

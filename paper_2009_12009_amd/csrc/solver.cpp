@@ -94,6 +94,12 @@ struct Level {
   // tile tables (host) and shapes
   std::vector<Tile> t_gsrb, t_cell, t_rst;
   Shape s_gsrb{32, 8, 16}, s_cell{64, 4, 16}, s_rst{64, 4, 16};
+  // level 0: deep tiles for streaming vector kernels (CG updates, dots): the
+  // residual's tuned tiles can be a few hundred cells, and a block reduction
+  // per tiny tile costs more than the data it covers
+  std::vector<Tile> t_vec;
+  Shape s_vec{64, 4, 16};
+  Tile* d_vec = nullptr;
   size_t cap_gsrb = 0, cap_cell = 0;  // tile slots reserved in the workspace
   // fused sweeps (both colours in one pass, out of place, rim pass after)
   bool fused = false;
@@ -447,6 +453,10 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     make_tiles(lv.info, lv.s_gsrb, 2 * lv.s_gsrb.lx, false, lv.t_gsrb);
     make_tiles(lv.info, lv.s_cell, lv.s_cell.lx, false, lv.t_cell);
     if (l + 1 < hb.size()) make_tiles(lv.info, lv.s_rst, lv.s_rst.lx, true, lv.t_rst);
+    if (l == 0) {
+      lv.s_vec = fit_tz(lv.info, shape_cell(mx[0], mx[1], mx[2]), 1, false);
+      make_tiles(lv.info, lv.s_vec, lv.s_vec.lx, false, lv.t_vec);
+    }
     build_fb(lv, s->periodic, 1);
     lv.cap_gsrb = lv.t_gsrb.size();
     lv.cap_cell = lv.t_cell.size();
@@ -570,6 +580,7 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
       lv.rhs64 = bump.take<double>(lv.n_g0);
       if (!bottom) lv.r64 = bump.take<double>(lv.n_g0);
     }
+    if (l == 0) lv.d_vec = bump.take<Tile>(lv.t_vec.size());
     if (lv.wt) {
       lv.d_wt = bump.take<WtEntry>(std::max<size_t>(1, lv.h_wt.size()));
       lv.d_wtbox = bump.take<WtBox>(lv.h_wtbox.size());
@@ -607,7 +618,8 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
   s->d_cg = bump.take<double>(4);
   s->d_iters = bump.take<int>(4);
   s->d_sum = bump.take<double>(2);
-  s->d_partials = bump.take<double>(std::max<size_t>(1, s->L[0].cap_cell));
+  s->d_partials =
+      bump.take<double>(std::max<size_t>({1, s->L[0].cap_cell, s->L[0].t_vec.size()}));
   if (s->opts.tune == 2) s->tune_scratch = bump.take<double>(s->L[0].n_g1);
   s->ws_need = bump.off + 256;
   return MG_OK;
@@ -1282,6 +1294,9 @@ int upload_tables(mg_solver* s) {
     if (!lv.t_rst.empty())
       HIPTRY(hipMemcpyAsync(lv.d_rst, lv.t_rst.data(), sizeof(Tile) * lv.t_rst.size(),
                             hipMemcpyHostToDevice, s->st));
+    if (!lv.t_vec.empty())
+      HIPTRY(hipMemcpyAsync(lv.d_vec, lv.t_vec.data(), sizeof(Tile) * lv.t_vec.size(),
+                            hipMemcpyHostToDevice, s->st));
     if (lv.wt) {
       if (!lv.h_wt.empty())
         HIPTRY(hipMemcpyAsync(lv.d_wt, lv.h_wt.data(), sizeof(WtEntry) * lv.h_wt.size(),
@@ -1915,6 +1930,10 @@ int solve_pcg(mg_solver* s, double* P, const double* F, int rng, double tol, mg_
   const StencilArgs<double> op = stencil_of<double>(s, l0, false);
   const int nt = (int)l0.t_cell.size();
   const Shape sh = l0.s_cell;
+  // vector kernels (dots, updates, shifts) on the deep tiles
+  const Tile* vt = l0.d_vec;
+  const int nv = (int)l0.t_vec.size();
+  const Shape sv = l0.s_vec;
   double* r = l0.rhs64;
   double* z = l0.e64;
   double* p = l0.p64;
@@ -1930,17 +1949,18 @@ int solve_pcg(mg_solver* s, double* P, const double* F, int rng, double tol, mg_
                                               s->singular ? nullptr : s->d_norm + 2, 0)));
     }
     if (s->singular) {
-      HIPTRY(launch_sum_valid(s->st, l0.d_cell, nt, sh, l0.d_info, buf, 0, s->d_partials,
-                              s->d_sum));
-      HIPTRY(launch_shift_valid(s->st, l0.d_cell, nt, sh, l0.d_info, buf, 0, s->d_sum, l0.ncell));
-      HIPTRY(launch_maxabs<double>(s->st, l0.d_cell, nt, sh, l0.d_info, buf, 0, s->d_norm + 2));
+      HIPTRY(launch_sum_valid(s->st, vt, nv, sv, l0.d_info, buf, 0, s->d_partials, s->d_sum));
+      HIPTRY(launch_shift_valid(s->st, vt, nv, sv, l0.d_info, buf, 0, s->d_sum, l0.ncell));
+      HIPTRY(launch_maxabs<double>(s->st, vt, nv, sv, l0.d_info, buf, 0, s->d_norm + 2));
     }
     return read_norm(s, 2, norm);
   };
+  const bool f32 = s->opts.precision == MG_PREC_F32_REFINE;
   double rn;
   if ((rc = true_residual(r, &rn))) return rc;
   int it = 0, status = MG_OK;
   bool restart = true;
+  bool r32_current = false;  // FP32 copy of r written by the last update
   while (true) {
     if (resid_history) resid_history[it] = rn;
     if (s->opts.verbose) fprintf(stderr, "amrmg pcg %d  max|r| = %.6e\n", it, rn);
@@ -1957,6 +1977,7 @@ int solve_pcg(mg_solver* s, double* P, const double* F, int rng, double tol, mg_
       }
       HIPTRY(hipMemcpyAsync(r, q, sizeof(double) * l0.n_g0, hipMemcpyDeviceToDevice, s->st));
       restart = true;
+      r32_current = false;
     }
     if (it == s->opts.max_iter) {
       status = fail(MG_ERR_NOT_CONVERGED, "max_iter reached");
@@ -1964,40 +1985,52 @@ int solve_pcg(mg_solver* s, double* P, const double* F, int rng, double tol, mg_
     }
     // z = M r, the V-cycle in FP64, or in FP32 on r rounded to FP32 (the
     // mixed-precision preconditioner; CG itself stays in FP64)
-    if (s->opts.precision == MG_PREC_F32_REFINE) {
-      HIPTRY((launch_convert<double, float>(s->st, r, l0.rhs32, l0.n_g0)));
+    double* rho_new = s->d_cg + (it & 1);
+    double* rho_old = s->d_cg + ((it + 1) & 1);
+    if (f32) {
+      if (!r32_current) HIPTRY((launch_convert<double, float>(s->st, r, l0.rhs32, l0.n_g0)));
       if ((rc = coarse_cycle<float>(s, 0, true))) return rc;
-      HIPTRY((launch_convert<float, double>(s->st, l0.e32, z, l0.n_g1)));
     } else {
       if ((rc = coarse_cycle<double>(s, 0, false))) return rc;
     }
-    if (s->singular) {
-      HIPTRY(launch_sum_valid(s->st, l0.d_cell, nt, sh, l0.d_info, z, 1, s->d_partials, s->d_sum));
-      HIPTRY(launch_shift_valid(s->st, l0.d_cell, nt, sh, l0.d_info, z, 1, s->d_sum, l0.ncell));
+    {
+      ProfScope ps_dot(s, 6, true);
+      if (s->singular) {
+        if (f32) HIPTRY((launch_convert<float, double>(s->st, l0.e32, z, l0.n_g1)));
+        HIPTRY(launch_sum_valid(s->st, vt, nv, sv, l0.d_info, z, 1, s->d_partials, s->d_sum));
+        HIPTRY(launch_shift_valid(s->st, vt, nv, sv, l0.d_info, z, 1, s->d_sum, l0.ncell));
+        HIPTRY(launch_dot(s->st, vt, nv, sv, l0.d_info, r, 0, z, 1, s->d_partials, rho_new));
+      } else if (f32) {
+        // z = FP64 of the FP32 V-cycle result and rho = r.z in one pass
+        HIPTRY(launch_widen_dot(s->st, vt, nv, sv, l0.d_info, l0.e32, z, r, s->d_partials,
+                                rho_new));
+      } else {
+        HIPTRY(launch_dot(s->st, vt, nv, sv, l0.d_info, r, 0, z, 1, s->d_partials, rho_new));
+      }
     }
-    double* rho_new = s->d_cg + (it & 1);
-    double* rho_old = s->d_cg + ((it + 1) & 1);
-    HIPTRY(launch_dot(s->st, l0.d_cell, nt, sh, l0.d_info, r, 0, z, 1, s->d_partials, rho_new));
     {
       ProfScope ps(s, 6, true);
-      HIPTRY(launch_cg_p(s->st, l0.d_cell, nt, sh, l0.d_info, p, z, rho_new, rho_old,
-                         restart ? 1 : 0));
+      HIPTRY(launch_cg_p(s->st, vt, nv, sv, l0.d_info, p, z, rho_new, rho_old, restart ? 1 : 0));
     }
     restart = false;
     // q = A p, alpha = rho_new / p.q
     if ((rc = exchange<double>(s, l0, p, true))) return rc;
     {
+      // q = A p with the per-tile partials of p.q from the same pass
       ProfScope ps(s, 1, true);
       HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, nt, sh, op, p, nullptr, 0, q,
-                                              nullptr, 1)));
+                                              nullptr, 1, s->d_partials)));
     }
-    HIPTRY(launch_dot(s->st, l0.d_cell, nt, sh, l0.d_info, p, 1, q, 0, s->d_partials,
-                      s->d_cg + 2));
+    {
+      ProfScope ps(s, 6, true);
+      HIPTRY(launch_sum_final(s->st, s->d_partials, nt, s->d_cg + 2));
+    }
     HIPTRY(launch_fill_u64(s->st, s->d_norm + 2, 1, 0ull));
     {
       ProfScope ps(s, 6, true);
-      HIPTRY(launch_cg_xr(s->st, l0.d_cell, nt, sh, l0.d_info, P, p, r, q, rho_new, s->d_cg + 2,
-                          s->d_norm + 2));
+      HIPTRY(launch_cg_xr(s->st, vt, nv, sv, l0.d_info, P, p, r, q, rho_new, s->d_cg + 2,
+                          s->d_norm + 2, f32 ? l0.rhs32 : nullptr));
+      r32_current = f32;
     }
     ++it;
     if ((rc = read_norm(s, 2, &rn))) return rc;

@@ -266,6 +266,65 @@ def _fine_sweep(comp, e_f, e_c, rhs_f, colour):
     gsrb_halfsweep(comp.lf, e_f, rhs_f, colour)
 
 
+def composite_precond(comp, Rf, Rc, opts, nf1, nf2):
+    """One two-level correction (e_f, e_c) of the composite residual (Rf, Rc)
+    from a zero guess: nf1 fine Gauss-Seidel sweeps with ghosts from a zero
+    coarse correction, the composite residual of that fine correction, its
+    fine part averaged onto covered coarse cells, one coarse V-cycle on the
+    whole coarse level, the coarse correction added to the fine cells under
+    it, nf2 fine sweeps with ghosts from the coarse correction.  Returns
+    per-box arrays with one ghost layer."""
+    e_f = new_cell_data(comp.lf)
+    e_c = new_cell_data(comp.lc)
+    for _ in range(nf1):
+        _fine_sweep(comp, e_f, e_c, Rf, 0)
+        _fine_sweep(comp, e_f, e_c, Rf, 1)
+    Af, Ac = composite_apply(comp, e_f, e_c)
+    rf = [r - a for r, a in zip(Rf, Af)]
+    rc = [r - a for r, a in zip(Rc, Ac)]
+    rcg = [np.pad(x, NG) for x in rc]
+    average_down(comp, rf, rcg, ng_f=0)
+    rc = [valid(x) for x in rcg]
+    ec = new_cell_data(comp.lc)
+    vcycle(comp.levels_c, 0, ec, rc, opts)
+    for ib, fb in enumerate(comp.lf.boxes):
+        cb = coarsen_box(fb)
+        p = comp.parent[ib]
+        plo = comp.lc.boxes[p][0]
+        E = ec[p][tuple(slice(cb[0][a] - plo[a] + NG, cb[1][a] - plo[a] + NG + 1)
+                         for a in range(3))]
+        valid(e_f[ib])[...] += np.repeat(np.repeat(np.repeat(E, 2, 0), 2, 1), 2, 2)
+    for _ in range(nf2):
+        _fine_sweep(comp, e_f, ec, Rf, 0)
+        _fine_sweep(comp, e_f, ec, Rf, 1)
+    return e_f, ec
+
+
+def _add_correction(comp, phi_f, phi_c, e_f, e_c, scale=1.0):
+    """phi_f += scale e_f; uncovered phi_c += scale e_c (covered cells are
+    set by the caller's average down)."""
+    for ib in range(len(phi_f)):
+        valid(phi_f[ib])[...] += scale * valid(e_f[ib])
+    for ib, (lo, hi) in enumerate(comp.lc.boxes):
+        m = ~comp.covered[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1]
+        valid(phi_c[ib])[m] += scale * valid(e_c[ib])[m]
+
+
+def _sweeps(opts, fine_sweeps):
+    nf1 = 2 * opts.nu1 if fine_sweeps is None else fine_sweeps
+    nf2 = 2 * opts.nu2 if fine_sweeps is None else fine_sweeps
+    return nf1, nf2
+
+
+def _normf(comp, f_f, f_c):
+    fz = []
+    for ib, (lo, hi) in enumerate(comp.lc.boxes):
+        x = f_c[ib].copy()
+        x[comp.covered[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1]] = 0.0
+        fz.append(x)
+    return max(max_norm(f_f) if f_f else 0.0, max_norm(fz))
+
+
 def composite_solve(comp, phi_f, phi_c, f_f, f_c, rel_tol=1e-10, abs_tol=0.0, opts=None,
                     fine_sweeps=None):
     """Outer iteration on the composite residual with two-level corrections.
@@ -276,16 +335,10 @@ def composite_solve(comp, phi_f, phi_c, f_f, f_c, rel_tol=1e-10, abs_tol=0.0, op
     2 nu2; the fine level is a small part of the cells and two sweeps per side
     leave its error decaying at about 0.5 per step, four at about 0.35)."""
     opts = opts or Opts()
-    nf1 = 2 * opts.nu1 if fine_sweeps is None else fine_sweeps
-    nf2 = 2 * opts.nu2 if fine_sweeps is None else fine_sweeps
+    nf1, nf2 = _sweeps(opts, fine_sweeps)
     if comp.levels_c is None:
         comp.levels_c = build_levels(comp.lc, opts.min_bottom_edge, opts.aggregate)
-    fz = []
-    for ib, (lo, hi) in enumerate(comp.lc.boxes):
-        x = f_c[ib].copy()
-        x[comp.covered[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1]] = 0.0
-        fz.append(x)
-    normf = max(max_norm(f_f) if f_f else 0.0, max_norm(fz))
+    normf = _normf(comp, f_f, f_c)
     tol = max(rel_tol * normf, abs_tol)
     info = {"history": [], "iters": 0, "converged": False, "normf": normf}
     it = 0
@@ -300,39 +353,107 @@ def composite_solve(comp, phi_f, phi_c, f_f, f_c, rel_tol=1e-10, abs_tol=0.0, op
             break
         if it == opts.max_iter:
             break
-        # fine pre-smoothing of the correction with ghosts from a zero coarse correction
-        e_f = new_cell_data(comp.lf)
-        e_c = new_cell_data(comp.lc)
-        for _ in range(nf1):
-            _fine_sweep(comp, e_f, e_c, Rf, 0)
-            _fine_sweep(comp, e_f, e_c, Rf, 1)
-        # composite residual left by that fine correction
-        Af, Ac = composite_apply(comp, e_f, e_c)
-        rf = [r - a for r, a in zip(Rf, Af)]
-        rc = [r - a for r, a in zip(Rc, Ac)]
-        # fine part onto covered coarse cells, then one coarse V-cycle
-        rcg = [np.pad(x, NG) for x in rc]
-        average_down(comp, rf, rcg, ng_f=0)
-        rc = [valid(x) for x in rcg]
-        ec = new_cell_data(comp.lc)
-        vcycle(comp.levels_c, 0, ec, rc, opts)
-        # coarse correction under the fine cells, fine post-smoothing
-        for ib, fb in enumerate(comp.lf.boxes):
-            cb = coarsen_box(fb)
-            p = comp.parent[ib]
-            plo = comp.lc.boxes[p][0]
-            E = ec[p][tuple(slice(cb[0][a] - plo[a] + NG, cb[1][a] - plo[a] + NG + 1)
-                             for a in range(3))]
-            valid(e_f[ib])[...] += np.repeat(np.repeat(np.repeat(E, 2, 0), 2, 1), 2, 2)
-        for _ in range(nf2):
-            _fine_sweep(comp, e_f, ec, Rf, 0)
-            _fine_sweep(comp, e_f, ec, Rf, 1)
-        for ib in range(len(phi_f)):
-            valid(phi_f[ib])[...] += valid(e_f[ib])
-        for ib, (lo, hi) in enumerate(comp.lc.boxes):
-            m = ~comp.covered[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1]
-            valid(phi_c[ib])[m] += valid(ec[ib])[m]
+        e_f, ec = composite_precond(comp, Rf, Rc, opts, nf1, nf2)
+        _add_correction(comp, phi_f, phi_c, e_f, ec)
         average_down(comp, phi_f, phi_c)
         it += 1
     info["iters"] = it
+    return info
+
+
+def _cdot(uf, uc, vf, vc):
+    """Dot product over fine cells and coarse cells of residual-shaped
+    (ghost-free) composite vectors (covered coarse entries are zero)."""
+    return float(sum(np.sum(a * b) for a, b in zip(uf, vf)) +
+                 sum(np.sum(a * b) for a, b in zip(uc, vc)))
+
+
+def composite_fgmres(comp, phi_f, phi_c, f_f, f_c, rel_tol=1e-10, abs_tol=0.0, opts=None,
+                     fine_sweeps=None, restart=20, precond=None):
+    """Flexible GMRES on the composite system, right-preconditioned by the
+    two-level correction (the paper's Krylov solvers with its multigrid as the
+    preconditioner; the composite operator is not symmetric, and the
+    correction's bottom CG makes the preconditioner vary a little, hence the
+    flexible form that keeps each z_j = M v_j).
+
+    Each cycle: R = f - A phi (true composite residual; its max norm is the
+    history entry and the stop test, as in composite_solve); beta = ||R||_2,
+    v_1 = R / beta; for j = 1.. restart: z_j = M v_j, w = A z_j, classical
+    Gram-Schmidt against v_1..v_j (coefficients from w before any
+    subtraction), h_{j+1,j} = ||w||_2, v_{j+1} = w / h_{j+1,j}, Givens
+    rotations on H and g = beta e_1; the cycle ends when |g_{j+1}| (the 2-norm
+    of the residual) <= tol * beta / max|R| (the residual's 2-norm to
+    max-norm ratio at the start of the cycle carried over to the target), at
+    restart, or when the iteration budget (opts.max_iter) is used up.  Then
+    y = H^{-1} g (triangular), phi += sum y_j z_j, average down.  Dot products
+    run over fine cells and uncovered coarse cells.  precond(Rf, Rc) ->
+    (e_f, e_c) (ghost layer 1) replaces the two-level correction.
+    Returns a dict: history (max |R| at the start of each cycle), iters
+    (preconditioner applications), cycles, converged."""
+    opts = opts or Opts()
+    nf1, nf2 = _sweeps(opts, fine_sweeps)
+    if comp.levels_c is None:
+        comp.levels_c = build_levels(comp.lc, opts.min_bottom_edge, opts.aggregate)
+    if precond is None:
+        def precond(Rf, Rc):
+            return composite_precond(comp, Rf, Rc, opts, nf1, nf2)
+    normf = _normf(comp, f_f, f_c)
+    tol = max(rel_tol * normf, abs_tol)
+    info = {"history": [], "iters": 0, "cycles": 0, "converged": False, "normf": normf}
+    total = 0
+    while True:
+        Rf, Rc = composite_residual(comp, phi_f, phi_c, f_f, f_c)
+        rn = composite_norm(comp, Rf, Rc)
+        info["history"].append(rn)
+        if not np.isfinite(rn):
+            break
+        if rn <= tol:
+            info["converged"] = True
+            break
+        if total >= opts.max_iter:
+            break
+        beta = np.sqrt(_cdot(Rf, Rc, Rf, Rc))
+        target = tol * beta / rn
+        Vf, Vc = [[x / beta for x in Rf]], [[x / beta for x in Rc]]
+        Z = []
+        m = restart
+        H = np.zeros((m + 1, m))
+        g = np.zeros(m + 1)
+        g[0] = beta
+        cs, sn = np.zeros(m), np.zeros(m)
+        k = 0
+        for j in range(m):
+            zf, zc = precond(Vf[j], Vc[j])
+            Z.append((zf, zc))
+            wf, wc = composite_apply(comp, zf, zc)
+            h = [_cdot(wf, wc, Vf[i], Vc[i]) for i in range(j + 1)]
+            for i in range(j + 1):
+                wf = [a - h[i] * b for a, b in zip(wf, Vf[i])]
+                wc = [a - h[i] * b for a, b in zip(wc, Vc[i])]
+            hn = np.sqrt(_cdot(wf, wc, wf, wc))
+            H[:j + 1, j] = h
+            H[j + 1, j] = hn
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            r = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / r, H[j + 1, j] / r
+            H[j, j], H[j + 1, j] = r, 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            total += 1
+            k = j + 1
+            if hn == 0.0 or abs(g[j + 1]) <= target or total >= opts.max_iter:
+                break
+            Vf.append([x / hn for x in wf])
+            Vc.append([x / hn for x in wc])
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):
+            y[i] = (g[i] - np.dot(H[i, i + 1:k], y[i + 1:k])) / H[i, i]
+        for i in range(k):
+            _add_correction(comp, phi_f, phi_c, Z[i][0], Z[i][1], y[i])
+        average_down(comp, phi_f, phi_c)
+        info["cycles"] += 1
+    info["iters"] = total
     return info

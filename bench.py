@@ -405,9 +405,11 @@ def bench_c4(args):
     rf = P.MultiFab.from_numpy(fb, amr.fine_rhs(fb, cfg["centres"], 2 * cfg["n"]), 0)
     log(f"c4 inputs ({len(fb)} fine boxes) in {time.perf_counter() - t0:.1f} s", args.quiet)
     res = {}
-    for name, prec in (("f64", 0), ("f32_refine", 1)):
+    for name, prec, kry in (("f64", 0, 0), ("f32_refine", 1, 0), ("f64_fgmres", 0, 1),
+                            ("f32_fgmres", 1, 1)):
         s = P.CompositeMLMG(cb, fb, W.domain_box(cfg["n"]), 1.0, 1.0, b_c=bcm, b_f=bfm,
-                            opts=dict(tune=2, aggregate=args.aggregate, precision=prec))
+                            opts=dict(tune=2, aggregate=args.aggregate, precision=prec,
+                                      krylov=kry))
         pc = s.coarse_mf(1, fill=0.0)
         pf = s.fine_mf(1, fill=0.0)
         times = []

@@ -122,8 +122,9 @@ typedef struct {
                                       Krylov CG, "Linear Solvers"); with
                                       MG_PREC_F32_REFINE the V-cycle runs in
                                       FP32 on r rounded to FP32 and CG stays in
-                                      FP64.  Not for the composite solve; iters
-                                      then counts CG iterations               */
+                                      FP64; iters then counts CG iterations.
+                                      The composite solve uses flexible GMRES
+                                      instead (see mg_create_amr)              */
   int32_t ghost_write;         /* [1] on levels using half-sweeps (even extents
                                       in periodic directions), each update of a
                                       cell on a box's boundary layer is also
@@ -167,7 +168,13 @@ void mg_default_opts(mg_opts_t* opts);
  * Each outer step: 2*nu1 fine sweeps, one coarse V-cycle, 2*nu2 fine sweeps.
  * The outer composite residual and the update are FP64; with precision
  * MG_PREC_F32_REFINE the correction (sweeps, V-cycle, interpolation,
- * refluxing) runs in FP32 on that residual rounded once.  krylov must be 0.
+ * refluxing) runs in FP32 on that residual rounded once.  With krylov = 1
+ * the correction instead preconditions flexible GMRES (restart 20) on the
+ * composite system: each cycle starts from the true composite residual and
+ * ends when the Krylov estimate of its 2-norm reaches tol scaled by the
+ * cycle's starting 2-norm / max-norm ratio; iters counts corrections, the
+ * residual history has one entry per cycle.  The workspace then also holds
+ * 21 + 20 composite vectors.
  * bcoef_c / bcoef_f: three face MultiFabs per level, or NULL for b = 1.
  * mg_solve_amr stops when the max-norm composite residual (fine cells and
  * uncovered coarse cells) is <= max(rel_tol * max|rhs| over the same cells,

@@ -807,6 +807,99 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.x] = s;
 }
 
+// Krylov-basis kernels over one level's valid cells (vectors ghost-free,
+// basis vector i at V + i*vstride).  Partials of every product go to
+// partials[i*pstride + poff + tile], so a level's tiles can follow another
+// level's in the same row and one ordered sum per i covers both.
+__global__ void __launch_bounds__(256)
+    k_mdot(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+           const double* __restrict__ w, const double* __restrict__ V, long long vstride, int n,
+           double* __restrict__ partials, int pstride, int poff, int tz) {
+  __shared__ double red[32];
+  int phase = 0;
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  const bool act = i <= B.hi[0] && j <= B.hi[1];
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  for (int q = 0; q < n; ++q) {
+    double s = 0.0;
+    if (act)
+      for (int k = t.z0; k <= kend; ++k) {
+        const long long c = B.off_g0 + cidx(d, 0, i - B.lo[0], j - B.lo[1], k - B.lo[2]);
+        s += w[c] * V[q * vstride + c];
+      }
+    s = block_sum(s, red, phase);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partials[q * pstride + poff + blockIdx.x] = s;
+  }
+}
+
+// out = sign*w - sum_q h_q V_q with h_q = sign * dots[q] (subtractions in q
+// order, products rounded separately), and the partial of sum out^2.
+__global__ void __launch_bounds__(256)
+    k_maxpy(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+            const double* __restrict__ w, const double* __restrict__ V, long long vstride, int n,
+            const double* __restrict__ dots, double sign, double* __restrict__ out,
+            double* __restrict__ partials, int poff, int tz) {
+  __shared__ double red[32];
+  int phase = 0;
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  double s = 0.0;
+  if (i <= B.hi[0] && j <= B.hi[1]) {
+    const int kend = min(t.z0 + tz - 1, B.hi[2]);
+    for (int k = t.z0; k <= kend; ++k) {
+      const long long c = B.off_g0 + cidx(d, 0, i - B.lo[0], j - B.lo[1], k - B.lo[2]);
+      double v = sign * w[c];
+      for (int q = 0; q < n; ++q) v = __dsub_rn(v, __dmul_rn(sign * dots[q], V[q * vstride + c]));
+      out[c] = v;
+      s += v * v;
+    }
+  }
+  s = block_sum(s, red, phase);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[poff + blockIdx.x] = s;
+}
+
+// v = w / sqrt(*ss) on valid cells (ghost-free).
+__global__ void __launch_bounds__(256)
+    k_vnormalise(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+                 const double* __restrict__ w, double* __restrict__ v, const double* __restrict__ ss,
+                 int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  if (i > B.hi[0] || j > B.hi[1]) return;
+  const double hn = sqrt(*ss);
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  for (int k = t.z0; k <= kend; ++k) {
+    const long long c = B.off_g0 + cidx(d, 0, i - B.lo[0], j - B.lo[1], k - B.lo[2]);
+    v[c] = w[c] / hn;
+  }
+}
+
+// phi (ng 1) += sum_q y[q] Z_q (ng 1, Z_q at Z + q*zstride), in q order.
+__global__ void __launch_bounds__(256)
+    k_zaxpy(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
+            double* __restrict__ phi, const double* __restrict__ Z, long long zstride, int n,
+            const double* __restrict__ y, int tz) {
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = boxes[t.box];
+  const BoxDims d = dims(B);
+  const int i = t.x0 + threadIdx.x, j = t.y0 + threadIdx.y;
+  if (i > B.hi[0] || j > B.hi[1]) return;
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  for (int k = t.z0; k <= kend; ++k) {
+    const long long c = B.off_g1 + cidx(d, 1, i - B.lo[0], j - B.lo[1], k - B.lo[2]);
+    double v = phi[c];
+    for (int q = 0; q < n; ++q) v = __dadd_rn(v, __dmul_rn(y[q], Z[q * zstride + c]));
+    phi[c] = v;
+  }
+}
+
 // p = z (first) or p = z + (*num / *den) p, both with one ghost layer.
 __global__ void __launch_bounds__(256)
     k_cg_p(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes, double* __restrict__ p,
@@ -1522,6 +1615,60 @@ hipError_t launch_cg_xr(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
 hipError_t launch_sum_final(hipStream_t st, const double* partials, int n, double* out) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partials, n, out);
+  return hipGetLastError();
+}
+
+// One ordered sum per row: out[q] = sum of partials[q*n .. q*n + n - 1].
+__global__ void __launch_bounds__(256) k_sum_rows(const double* __restrict__ partials, int n,
+                                                  double* __restrict__ out) {
+  __shared__ double red[32];
+  int phase = 0;
+  double s = 0.0;
+  const double* row = partials + (long long)blockIdx.x * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += row[i];
+  s = block_sum(s, red, phase);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+hipError_t launch_mdot(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                       const BoxInfo* boxes, const double* w, const double* V, long long vstride,
+                       int n, double* partials, int pstride, int poff) {
+  if (ntiles <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mdot, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, w, V, vstride, n,
+                     partials, pstride, poff, sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_rows(hipStream_t st, const double* partials, int rows, int n, double* out) {
+  if (rows <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_rows, dim3(rows), dim3(256), 0, st, partials, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxpy(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                        const BoxInfo* boxes, const double* w, const double* V, long long vstride,
+                        int n, const double* dots, double sign, double* out, double* partials,
+                        int poff) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_maxpy, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, w, V, vstride, n,
+                     dots, sign, out, partials, poff, sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_vnormalise(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                             const BoxInfo* boxes, const double* w, double* v, const double* ss) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vnormalise, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, w, v, ss,
+                     sh.tz);
+  return hipGetLastError();
+}
+
+hipError_t launch_zaxpy(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                        const BoxInfo* boxes, double* phi, const double* Z, long long zstride,
+                        int n, const double* y) {
+  if (ntiles <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zaxpy, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, phi, Z, zstride, n,
+                     y, sh.tz);
   return hipGetLastError();
 }
 

@@ -129,6 +129,24 @@ hipError_t launch_cg_xr(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                         const BoxInfo* boxes, double* x, const double* p, double* r,
                         const double* q, const double* num, const double* den,
                         unsigned long long* normbits, float* r32 = nullptr);
+// Krylov basis on one level (ghost-free vectors; vector q at V + q*vstride):
+// partials[q*pstride + poff + tile] = tile part of w.V_q for q < n;
+// out[q] = ordered sum of row q (n partials per row);
+// out = sign*w - sum_q (sign*dots[q]) V_q with partials[poff + tile] of out.out;
+// v = w / sqrt(*ss); phi (ng 1) += sum_q y[q] Z_q (ng 1, stride zstride).
+hipError_t launch_mdot(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                       const BoxInfo* boxes, const double* w, const double* V, long long vstride,
+                       int n, double* partials, int pstride, int poff);
+hipError_t launch_sum_rows(hipStream_t st, const double* partials, int rows, int n, double* out);
+hipError_t launch_maxpy(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                        const BoxInfo* boxes, const double* w, const double* V, long long vstride,
+                        int n, const double* dots, double sign, double* out, double* partials,
+                        int poff);
+hipError_t launch_vnormalise(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                             const BoxInfo* boxes, const double* w, double* v, const double* ss);
+hipError_t launch_zaxpy(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                        const BoxInfo* boxes, double* phi, const double* Z, long long zstride,
+                        int n, const double* y);
 // *out = partials[0] + ... + partials[n-1] in a fixed order (one work-group).
 hipError_t launch_sum_final(hipStream_t st, const double* partials, int n, double* out);
 // z (FP64, ng 1) = e (FP32, ng 1) on valid cells and *out = sum r*z (r ng 0).

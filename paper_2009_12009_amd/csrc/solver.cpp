@@ -190,6 +190,13 @@ struct mg_solver {
   double *Rc = nullptr, *ef = nullptr, *Rf = nullptr, *rf2 = nullptr;
   // FP32 correction of the composite solve (precision MG_PREC_F32_REFINE)
   float *Rc32 = nullptr, *ef32 = nullptr, *Rf32 = nullptr, *rf2_32 = nullptr;
+  // flexible GMRES of the composite solve (krylov = 1): restart length,
+  // basis (m+1 ghost-free pairs), preconditioned directions (m pairs, ng 1),
+  // W = -A z, zero right-hand sides, partial sums, device and pinned scalars
+  int gm_m = 20;
+  double *gm_Vf = nullptr, *gm_Vc = nullptr, *gm_Zf = nullptr, *gm_Zc = nullptr;
+  double *gm_Wf = nullptr, *gm_Wc = nullptr, *gm_zero_f = nullptr, *gm_zero_c = nullptr;
+  double *gm_part = nullptr, *d_gm = nullptr, *h_gm = nullptr;
 };
 
 namespace {
@@ -1549,6 +1556,19 @@ int build_composite(mg_solver* s, const std::vector<IBox>& fboxes, Bump& bump) {
   s->ef = bump.take<double>(F.n_g1);
   s->Rf = bump.take<double>(F.n_g0);
   s->rf2 = bump.take<double>(F.n_g0);
+  if (s->opts.krylov) {
+    const int m = s->gm_m;
+    s->gm_Vf = bump.take<double>((size_t)(m + 1) * F.n_g0);
+    s->gm_Vc = bump.take<double>((size_t)(m + 1) * L0.n_g0);
+    s->gm_Zf = bump.take<double>((size_t)m * F.n_g1);
+    s->gm_Zc = bump.take<double>((size_t)m * L0.n_g1);
+    s->gm_Wf = bump.take<double>(F.n_g0);
+    s->gm_Wc = bump.take<double>(L0.n_g0);
+    s->gm_zero_f = bump.take<double>(F.n_g0);
+    s->gm_zero_c = bump.take<double>(L0.n_g0);
+    s->gm_part = bump.take<double>((size_t)(m + 1) * (F.t_cell.size() + L0.t_vec.size()));
+    s->d_gm = bump.take<double>(m + 2);
+  }
   if (s->opts.precision == MG_PREC_F32_REFINE) {
     for (int d = 0; d < 3; ++d) F.b32[d] = bump.take<float>(F.n_f[d]);
     s->Rc32 = bump.take<float>(L0.n_g0);
@@ -1655,14 +1675,14 @@ int fine_sweeps(mg_solver* s, T* ef, T* ec, const T* rhs, int sweeps) {
   return MG_OK;
 }
 
-// The same correction computed in FP32 on (Rc, Rf) rounded once; phi is
-// updated in FP64.
-int composite_correction32(mg_solver* s, double* phic, double* phif) {
+// The two-level correction of a composite residual (vc, vf) from zero, in
+// FP32 on (vc, vf) rounded once: result in ef32 (fine) and L0.e32 (coarse).
+int correction_core32(mg_solver* s, const double* vc, const double* vf) {
   Level& L0 = s->L[0];
   Level& F = s->F;
   int rc;
-  HIPTRY((launch_convert<double, float>(s->st, s->Rc, s->Rc32, L0.n_g0)));
-  HIPTRY((launch_convert<double, float>(s->st, s->Rf, s->Rf32, F.n_g0)));
+  HIPTRY((launch_convert<double, float>(s->st, vc, s->Rc32, L0.n_g0)));
+  HIPTRY((launch_convert<double, float>(s->st, vf, s->Rf32, F.n_g0)));
   HIPTRY(launch_zero_valid<float>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info,
                                   s->ef32, 1));
   HIPTRY(launch_zero_valid<float>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info,
@@ -1674,41 +1694,195 @@ int composite_correction32(mg_solver* s, double* phic, double* phif) {
   if ((rc = coarse_cycle<float>(s, 0, true))) return rc;
   HIPTRY(launch_prolong_add<float>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info,
                                    L0.d_info, s->ef32, L0.e32));
-  if ((rc = fine_sweeps<float>(s, s->ef32, L0.e32, s->Rf32, 2 * s->opts.nu2))) return rc;
-  HIPTRY(launch_update(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, phif, s->ef32));
-  HIPTRY(launch_update(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, phic,
-                       L0.e32));
-  return avgdown<double>(s, phif, 1, phic, 1, 0);
+  return fine_sweeps<float>(s, s->ef32, L0.e32, s->Rf32, 2 * s->opts.nu2);
 }
 
-// One two-level correction of the composite residual (Rc, Rf) applied to phi.
-int composite_correction(mg_solver* s, double* phic, double* phif) {
-  if (s->opts.precision == MG_PREC_F32_REFINE) return composite_correction32(s, phic, phif);
+// The same in FP64: result in ef (fine, ng 1) and L0.e64 (coarse).
+int correction_core64(mg_solver* s, const double* vc, const double* vf, double* ef) {
   Level& L0 = s->L[0];
   Level& F = s->F;
   int rc;
-  HIPTRY(launch_zero_valid<double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, s->ef,
+  HIPTRY(launch_zero_valid<double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, ef,
                                    1));
   HIPTRY(launch_zero_valid<double>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info,
                                    L0.e64, 1));
   // the fine level gets twice the sweeps of the coarse V-cycle on each side: it
   // is a small share of the cells, and two sweeps leave its error decaying at
   // about 0.5 per correction against about 0.35 with four
-  if ((rc = fine_sweeps<double>(s, s->ef, L0.e64, s->Rf, 2 * s->opts.nu1))) return rc;
+  if ((rc = fine_sweeps<double>(s, ef, L0.e64, vf, 2 * s->opts.nu1))) return rc;
   // residual the fine correction leaves: fine part into rf2, coarse part into
   // L0.rhs64 with covered cells = mean of rf2's children
-  if ((rc = composite_residual<double>(s, L0.e64, s->ef, s->Rc, 0, s->Rf, 0, L0.rhs64, s->rf2,
-                                       nullptr, s->rf2)))
+  if ((rc = composite_residual<double>(s, L0.e64, ef, vc, 0, vf, 0, L0.rhs64, s->rf2, nullptr,
+                                       s->rf2)))
     return rc;
   // one coarse V-cycle from zero on the whole coarse level
   if ((rc = coarse_cycle<double>(s, 0, false))) return rc;
   HIPTRY(launch_prolong_add<double>(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info,
-                                    L0.d_info, s->ef, L0.e64));
-  if ((rc = fine_sweeps<double>(s, s->ef, L0.e64, s->Rf, 2 * s->opts.nu2))) return rc;
-  HIPTRY(launch_axpy_valid(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, phif, s->ef));
-  HIPTRY(launch_axpy_valid(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, phic,
-                           L0.e64));
+                                    L0.d_info, ef, L0.e64));
+  return fine_sweeps<double>(s, ef, L0.e64, vf, 2 * s->opts.nu2);
+}
+
+// One two-level correction of the composite residual (Rc, Rf) applied to phi
+// (FP32 correction: phi updated in FP64).
+int composite_correction(mg_solver* s, double* phic, double* phif) {
+  Level& L0 = s->L[0];
+  Level& F = s->F;
+  int rc;
+  if (s->opts.precision == MG_PREC_F32_REFINE) {
+    if ((rc = correction_core32(s, s->Rc, s->Rf))) return rc;
+    HIPTRY(launch_update(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, phif,
+                         s->ef32));
+    HIPTRY(launch_update(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, phic,
+                         L0.e32));
+  } else {
+    if ((rc = correction_core64(s, s->Rc, s->Rf, s->ef))) return rc;
+    HIPTRY(launch_axpy_valid(s->st, F.d_cell, (int)F.t_cell.size(), F.s_cell, F.d_info, phif,
+                             s->ef));
+    HIPTRY(launch_axpy_valid(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, phic,
+                             L0.e64));
+  }
   return avgdown<double>(s, phif, 1, phic, 1, 0);
+}
+
+// Flexible GMRES on the composite system, right-preconditioned by the
+// two-level correction (z_j = M v_j kept, as the correction's bottom CG makes
+// M vary slightly).  Basis vectors are ghost-free pairs (fine, coarse) with
+// covered coarse entries zero; dot products run over fine cells and coarse
+// cells.  Each cycle starts from the true composite residual (its max norm
+// is the stop test and the history entry) and ends when the Givens estimate
+// of the residual's 2-norm reaches tol times the cycle's starting 2-norm /
+// max-norm ratio, at the restart length or when max_iter corrections are
+// used; then phi += sum y_j z_j and covered coarse cells are averaged down.
+int solve_amr_fgmres(mg_solver* s, double* Pc, double* Pf, const double* Fc, int fc_ng,
+                     const double* Ff, int ff_ng, double tol, mg_info_t* inf,
+                     double* resid_history) {
+  Level& L0 = s->L[0];
+  Level& F = s->F;
+  const int m = s->gm_m;
+  const bool f32 = s->opts.precision == MG_PREC_F32_REFINE;
+  const int ntf = (int)F.t_cell.size(), ntc = (int)L0.t_vec.size(), np = ntf + ntc;
+  const long long sf = F.n_g0, sc = L0.n_g0, zf = F.n_g1, zc = L0.n_g1;
+  int rc;
+  int total = 0, hist = 0, status = MG_OK;
+  double rn = 0;
+  std::vector<double> H((m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
+  auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  // dots of w (fine wf, coarse wc) with basis vectors 0..n-1 -> s->d_gm[0..n)
+  auto mdot = [&](const double* wf, const double* wc, const double* Vf, const double* Vc,
+                  int n) -> int {
+    HIPTRY(launch_mdot(s->st, F.d_cell, ntf, F.s_cell, F.d_info, wf, Vf, sf, n, s->gm_part, np,
+                       0));
+    HIPTRY(launch_mdot(s->st, L0.d_vec, ntc, L0.s_vec, L0.d_info, wc, Vc, sc, n, s->gm_part, np,
+                       ntf));
+    HIPTRY(launch_sum_rows(s->st, s->gm_part, n, np, s->d_gm));
+    return MG_OK;
+  };
+  auto readback = [&](int n) -> int {
+    HIPTRY(hipMemcpyAsync(s->h_gm, s->d_gm, sizeof(double) * n, hipMemcpyDeviceToHost, s->st));
+    HIPTRY(hipStreamSynchronize(s->st));
+    return MG_OK;
+  };
+  while (true) {
+    HIPTRY(launch_fill_u64(s->st, s->d_norm + 1, 1, 0ull));
+    if ((rc = composite_residual<double>(s, Pc, Pf, Fc, fc_ng, Ff, ff_ng, s->Rc, s->Rf,
+                                         s->d_norm + 1, nullptr)))
+      return rc;
+    if ((rc = read_norm(s, 1, &rn))) return rc;
+    if (resid_history) resid_history[hist] = rn;
+    ++hist;
+    if (s->opts.verbose) fprintf(stderr, "amrmg composite fgmres %d  max|R| = %.6e\n", total, rn);
+    if (!std::isfinite(rn)) {
+      status = fail(MG_ERR_NAN, "residual norm is not finite");
+      break;
+    }
+    if (rn <= tol) {
+      inf->converged = 1;
+      break;
+    }
+    if (total >= s->opts.max_iter) {
+      status = fail(MG_ERR_NOT_CONVERGED, "max_iter reached");
+      break;
+    }
+    // v_0 = R / ||R||
+    if ((rc = mdot(s->Rf, s->Rc, s->Rf, s->Rc, 1))) return rc;
+    HIPTRY(launch_vnormalise(s->st, F.d_cell, ntf, F.s_cell, F.d_info, s->Rf, s->gm_Vf, s->d_gm));
+    HIPTRY(launch_vnormalise(s->st, L0.d_vec, ntc, L0.s_vec, L0.d_info, s->Rc, s->gm_Vc, s->d_gm));
+    if ((rc = readback(1))) return rc;
+    const double beta = std::sqrt(s->h_gm[0]);
+    const double target = tol * beta / rn;
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double* Zfj = s->gm_Zf + j * zf;
+      double* Zcj = s->gm_Zc + j * zc;
+      const double* Vfj = s->gm_Vf + j * sf;
+      const double* Vcj = s->gm_Vc + j * sc;
+      // z_j = M v_j
+      if (f32) {
+        if ((rc = correction_core32(s, Vcj, Vfj))) return rc;
+        HIPTRY((launch_convert<float, double>(s->st, s->ef32, Zfj, F.n_g1)));
+        HIPTRY((launch_convert<float, double>(s->st, L0.e32, Zcj, L0.n_g1)));
+      } else {
+        if ((rc = correction_core64(s, Vcj, Vfj, Zfj))) return rc;
+        HIPTRY(hipMemcpyAsync(Zcj, L0.e64, sizeof(double) * L0.n_g1, hipMemcpyDeviceToDevice,
+                              s->st));
+      }
+      // W = 0 - A z_j (covered coarse entries zero), then classical
+      // Gram-Schmidt of A z_j = -W against v_0..v_j into slot j+1
+      if ((rc = composite_residual<double>(s, Zcj, Zfj, s->gm_zero_c, 0, s->gm_zero_f, 0,
+                                           s->gm_Wc, s->gm_Wf, nullptr, nullptr)))
+        return rc;
+      if ((rc = mdot(s->gm_Wf, s->gm_Wc, s->gm_Vf, s->gm_Vc, j + 1))) return rc;
+      double* Vf1 = s->gm_Vf + (j + 1) * sf;
+      double* Vc1 = s->gm_Vc + (j + 1) * sc;
+      HIPTRY(launch_maxpy(s->st, F.d_cell, ntf, F.s_cell, F.d_info, s->gm_Wf, s->gm_Vf, sf, j + 1,
+                          s->d_gm, -1.0, Vf1, s->gm_part, 0));
+      HIPTRY(launch_maxpy(s->st, L0.d_vec, ntc, L0.s_vec, L0.d_info, s->gm_Wc, s->gm_Vc, sc, j + 1,
+                          s->d_gm, -1.0, Vc1, s->gm_part, ntf));
+      HIPTRY(launch_sum_rows(s->st, s->gm_part, 1, np, s->d_gm + m + 1));
+      HIPTRY(hipMemcpyAsync(s->h_gm, s->d_gm, sizeof(double) * (m + 2), hipMemcpyDeviceToHost,
+                            s->st));
+      HIPTRY(hipStreamSynchronize(s->st));
+      const double hn = std::sqrt(s->h_gm[m + 1]);
+      for (int i = 0; i <= j; ++i) Hij(i, j) = -s->h_gm[i];
+      Hij(j + 1, j) = hn;
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+        Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+        Hij(i, j) = t;
+      }
+      const double r = std::hypot(Hij(j, j), Hij(j + 1, j));
+      cs[j] = Hij(j, j) / r;
+      sn[j] = Hij(j + 1, j) / r;
+      Hij(j, j) = r;
+      Hij(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      k = j + 1;
+      if (hn == 0.0 || std::fabs(g[j + 1]) <= target || total >= s->opts.max_iter) break;
+      HIPTRY(launch_vnormalise(s->st, F.d_cell, ntf, F.s_cell, F.d_info, Vf1, Vf1,
+                               s->d_gm + m + 1));
+      HIPTRY(launch_vnormalise(s->st, L0.d_vec, ntc, L0.s_vec, L0.d_info, Vc1, Vc1,
+                               s->d_gm + m + 1));
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int l = i + 1; l < k; ++l) acc -= Hij(i, l) * y[l];
+      y[i] = acc / Hij(i, i);
+    }
+    std::memcpy(s->h_gm, y.data(), sizeof(double) * k);
+    HIPTRY(hipMemcpyAsync(s->d_gm, s->h_gm, sizeof(double) * k, hipMemcpyHostToDevice, s->st));
+    HIPTRY(launch_zaxpy(s->st, F.d_cell, ntf, F.s_cell, F.d_info, Pf, s->gm_Zf, zf, k, s->d_gm));
+    HIPTRY(launch_zaxpy(s->st, L0.d_vec, ntc, L0.s_vec, L0.d_info, Pc, s->gm_Zc, zc, k, s->d_gm));
+    if ((rc = avgdown<double>(s, Pf, 1, Pc, 1, 0))) return rc;
+    HIPTRY(hipStreamSynchronize(s->st));  // h_gm is reused by the next cycle
+  }
+  inf->iters = total;
+  inf->abs_resid = rn;
+  return status;
 }
 
 int check_mf_boxes(const std::vector<IBox>& boxes, const mg_multifab_t* mf, int ng_min, int ng_max,
@@ -2234,6 +2408,7 @@ void mg_destroy(mg_solver_t* s) {
   if (s->ev_in) hipEventDestroy(s->ev_in);
   if (s->ev_out) hipEventDestroy(s->ev_out);
   if (s->h_norm) hipHostFree(s->h_norm);
+  if (s->h_gm) hipHostFree(s->h_gm);
   if (s->st) hipStreamDestroy(s->st);
   delete s;
 }
@@ -2299,7 +2474,6 @@ static int amr_plan(mg_solver* s, const mg_box_t* cboxes, int32_t ncb, const mg_
     mg_default_opts(&s->opts);
   int rc;
   if ((rc = check_opts(&s->opts))) return rc;
-  if (s->opts.krylov) return fail(MG_ERR_ARG, "the composite solve has no Krylov variant");
   if ((rc = check_geom(geom, nullptr, nullptr, s))) return rc;
   for (int d = 0; d < 3; ++d)
     if (s->periodic[d]) return fail(MG_ERR_ARG, "the composite solve needs Dirichlet walls");
@@ -2368,6 +2542,11 @@ int mg_create_amr(const mg_box_t* cboxes, int32_t ncb, const mg_box_t* fboxes, i
   if ((rc = begin_call(s.get()))) return rc;
   if ((rc = upload_tables(s.get()))) return rc;
   if ((rc = upload_composite(s.get()))) return rc;
+  if (s->opts.krylov) {
+    HIPTRY(hipHostMalloc((void**)&s->h_gm, sizeof(double) * (s->gm_m + 2), hipHostMallocDefault));
+    HIPTRY(hipMemsetAsync(s->gm_zero_f, 0, sizeof(double) * s->F.n_g0, s->st));
+    HIPTRY(hipMemsetAsync(s->gm_zero_c, 0, sizeof(double) * s->L[0].n_g0, s->st));
+  }
   if ((rc = setup_coefficients(s.get(), nullptr, bcoef_c))) return rc;
   for (int d = 0; d < 3; ++d) {
     HIPTRY(launch_scale_faces(s->st, bcoef_f ? (const double*)bcoef_f[d]->data : nullptr,
@@ -2430,6 +2609,10 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
                                      1));
     inf.converged = 1;
     if (resid_history) resid_history[0] = 0.0;
+  } else if (s->opts.krylov) {
+    status = solve_amr_fgmres(s, Pc, Pf, Fc, rhs_c->ngrow, Ff, rhs_f->ngrow,
+                              std::max(rel_tol * normf, abs_tol), &inf, resid_history);
+    inf.rel_resid = inf.abs_resid / normf;
   } else {
     const double tol = std::max(rel_tol * normf, abs_tol);
     int it = 0;

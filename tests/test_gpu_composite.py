@@ -154,16 +154,55 @@ def test_composite_float32_correction_reaches_fp64_oracle():
 
 
 @pytest.mark.gpu
-def test_c4_full_size_composite_residual():
+@pytest.mark.parametrize("prec", [0, 1])
+def test_composite_fgmres_matches_oracle(prec):
+    """Flexible GMRES preconditioned by the two-level correction (krylov = 1)
+    against the oracle's composite_fgmres (FP64 correction): corrections
+    within one, solutions to 1e-9 rel-L2 (FP32 correction: 1e-8)."""
+    print(f"[composite] FGMRES precision {prec}, generated boxes 32^3", flush=True)
+    P = lib()
+    nc = 32
+    fcg = amr.blob_rhs(nc, amr.blob_centres())
+    fboxes = amr.fine_boxes(fcg, block=2, coarse_box=16)
+    case = _case(nc, 16, fboxes)
+    f_f = amr.fine_rhs(fboxes, amr.blob_centres(), 2 * nc)
+    cb = case["cboxes"]
+    s = _gpu(case, dict(bottom_rel_tol=TIGHT, min_bottom_edge=2, krylov=1, precision=prec))
+    pc = s.coarse_mf(1, fill=0.0)
+    pf = s.fine_mf(1, fill=0.0)
+    g = s.solve(pc, pf, P.MultiFab.from_numpy(cb, W.scatter_cells(fcg, cb), 0),
+                P.MultiFab.from_numpy(fboxes, f_f, 0), 1e-10, history=True)
+    torch.cuda.synchronize()
+    s.close()
+    comp = _oracle_comp(case)
+    opc = O.new_cell_data(comp.lc)
+    opf = O.new_cell_data(comp.lf)
+    o = OC.composite_fgmres(comp, opf, opc, f_f, W.scatter_cells(fcg, cb), 1e-10,
+                            opts=O.Opts(min_bottom_edge=2, bottom_tol=TIGHT))
+    print(f"  GPU {g['iters']} corrections, oracle {o['iters']} ({o['cycles']} cycles)")
+    assert g["converged"] and o["converged"] and abs(g["iters"] - o["iters"]) <= 1
+    gf = np.concatenate([x.ravel() for x in pf.valid_numpy()])
+    of = np.concatenate([O.valid(x).ravel() for x in opf])
+    gc = W.gather_cells(pc.valid_numpy(), cb, nc)
+    oc = W.gather_cells(opc, cb, nc, ng=1)
+    bound = 1e-9 if prec == 0 else 1e-8
+    print(f"  rel-L2 vs oracle: fine {rel_l2(gf, of):.2e}, coarse {rel_l2(gc, oc):.2e}")
+    assert rel_l2(gf, of) <= bound and rel_l2(gc, oc) <= bound
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("krylov", [0, 1])
+def test_c4_full_size_composite_residual(krylov):
     """256^3 coarse in 64 boxes, blob-tagged fine boxes: the oracle's composite
-    operator recomputes the residual of the GPU solution on every composite cell."""
-    print("[composite] C4 256^3", flush=True)
+    operator recomputes the residual of the GPU solution on every composite cell
+    (stationary iteration and flexible GMRES)."""
+    print(f"[composite] C4 256^3 krylov={krylov}", flush=True)
     P = lib()
     cfg = amr.config_c4()
     fboxes = cfg["fine_boxes"]
     case = dict(nc=256, cboxes=cfg["boxes"], fboxes=fboxes, bc=cfg["bcell"], cf=cfg["faces"],
                 ffaces=[amr.fine_faces(cfg["bcell"], cfg["faces"], fboxes, d) for d in range(3)])
-    s = _gpu(case, dict(aggregate=1))
+    s = _gpu(case, dict(aggregate=1, krylov=krylov))
     cb = cfg["boxes"]
     fc_boxes = W.scatter_cells(cfg["rhs"], cb)
     f_f = amr.fine_rhs(fboxes, cfg["centres"], 512)

@@ -33,6 +33,9 @@ def parse():
     p.add_argument("--fused-min-edge", type=int, default=0,
                    help="fused red/black sweeps on levels whose boxes are all this large (0 = off)")
     p.add_argument("--cpu-cycles", type=int, default=1, help="oracle V-cycles in the CPU sample")
+    p.add_argument("--smoother-shape", default=None,
+                   help="lx,ly,tz,unroll[,whole_pairs]: level-0 half-sweep tile shape applied "
+                        "after tuning (counter runs per shape)")
     p.add_argument("--quiet", action="store_true")
     p.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"],
                    help="c1: the headline 256^3 line; c2: 512^3 uneven boxes, four variants; "
@@ -56,26 +59,28 @@ def kernel_source_sha256():
 def measured_traffic(kernel, shape):
     """HBM bytes per launch of the level-0 half-sweep from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
-    None when the summary is missing, was taken on other kernel sources, or for
-    another kernel or tile shape than the one this run uses."""
+    None when the summary is missing, was taken on other kernel sources, or holds
+    no block for this kernel and tile shape."""
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
-    block = text.split("```")[1] if text.count("```") >= 2 else ""
-    kv = {}
-    for line in block.splitlines():
-        if ":" in line:
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
-    try:
-        if (kv.get("source_sha256") != kernel_source_sha256() or kv.get("kernel") != kernel
-                or tuple(int(x) for x in kv["shape"].split()) != tuple(shape)):
-            return None
-        return (float(kv["fetch_kib_per_dispatch"]) * 1024 * float(kv["fetch_scale"])
-                + float(kv["write_kib_per_dispatch"]) * 1024 * float(kv["write_scale"]))
-    except (KeyError, ValueError):
-        return None
+    # fenced blocks alternate with prose: the odd pieces are the blocks
+    for block in text.split("```")[1::2]:
+        kv = {}
+        for line in block.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        try:
+            if (kv.get("source_sha256") != kernel_source_sha256() or kv.get("kernel") != kernel
+                    or tuple(int(x) for x in kv["shape"].split()) != tuple(shape)):
+                continue
+            return (float(kv["fetch_kib_per_dispatch"]) * 1024 * float(kv["fetch_scale"])
+                    + float(kv["write_kib_per_dispatch"]) * 1024 * float(kv["write_scale"]))
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def log(msg, quiet=False):
@@ -129,6 +134,11 @@ def main():
         "f32_mgpcg": P.MLMG(boxes, dom, cfg["periodic"], 1.0, 1.0, b=bmf,
                             opts=dict(precision=1, krylov=1, **common)),
     }
+    if args.smoother_shape:
+        v = [int(x) for x in args.smoother_shape.split(",")]
+        kern = 2 if len(v) == 5 and v[4] else 0
+        for s in solvers.values():
+            s.set_tile_shape(kern, *v[:4])
     phis = {k: s.cell_mf(1, fill=0.0) for k, s in solvers.items()}
     setup_ms = {k: s.solve(phis[k], rhs, 1e-10)["setup_ms"] for k, s in solvers.items()}
 

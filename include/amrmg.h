@@ -133,6 +133,15 @@ typedef struct {
                                       interpolation needs an exchange (same
                                       result); 0 = exchange before every
                                       half-sweep                               */
+  int32_t interp_fold;         /* [1] where a level and the next coarser one
+                                      both write through (and the coarser one
+                                      is smoothed, not the bottom), the
+                                      interpolation of the correction is done
+                                      by the first post-smoothing half-sweep,
+                                      which adds the correction to each value
+                                      it reads, instead of a pass of its own
+                                      and an exchange (same result); 0 = a
+                                      separate interpolation pass             */
 } mg_opts_t;
 
 typedef struct {

@@ -62,6 +62,9 @@ __device__ void block_max_u64(unsigned long long v, unsigned long long* dst) {
   }
 }
 
+// floor(a / 2) for any sign: the coarse index of fine index a.
+__device__ __forceinline__ int fdiv2(int a) { return a >= 0 ? a / 2 : -((-a + 1) / 2); }
+
 // The stencil at one valid cell.  Returns diag and the neighbour sum.
 template <typename T>
 struct Cell {
@@ -212,11 +215,22 @@ __device__ __forceinline__ void write_through(const WtBox& wb, const WtEntry* ex
 // they go; x-face cells (one or two lanes per row) park their values in LDS
 // and the work-group stores them after its z-march, so the march itself
 // carries no per-row divergent stores.
-template <typename T, int U, bool ZG, bool WP, bool WT>
+// PE: interpolation folded in.  The half-sweep first in line after the
+// coarse correction ec (cell data of the next coarser level, boxes cinfo)
+// would have been added to every cell: it reads only the other colour, so
+// each neighbour value it loads gets its coarse parent's correction added
+// (the same single addition), and the other colour is never stored, since
+// the next half-sweep overwrites it without reading it (hence never WP,
+// whose partner store would race with the lanes adding the correction to
+// that cell).  Neighbours on the box's ghost layer take the correction from
+// the coarse box's ghost layer, which the caller keeps current.
+template <typename T, int U, bool ZG, bool WP, bool WT, bool PE>
 __global__ void __launch_bounds__(256)
     k_gsrb(const Tile* __restrict__ tiles, StencilArgs<T> op, T* __restrict__ phi,
            const T* __restrict__ rhs, int rhs_ng, int colour, int tz,
-           const WtBox* __restrict__ wtb, const WtEntry* __restrict__ wte) {
+           const WtBox* __restrict__ wtb, const WtEntry* __restrict__ wte,
+           const BoxInfo* __restrict__ cinfo, const T* __restrict__ ec) {
+  static_assert(!(PE && (WP || ZG || !WT)), "folded interpolation: write-through half-sweeps only");
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = op.boxes[t.box];
   const int j = t.y0 + threadIdx.y;
@@ -242,8 +256,19 @@ __global__ void __launch_bounds__(256)
     for (int f = 0; f < 2; ++f)
       if (wb.count[f] == 1) ex[f] = wte[wb.first[f]];
   }
+  // PE: the coarse parent box (ghost layer 1) and this row's parent index
+  const T* EC = nullptr;
+  int csy = 0, csz = 0, cbase = 0;
+  if (PE) {
+    const BoxInfo C = cinfo[B.parent];
+    csy = C.hi[0] - C.lo[0] + 3;
+    csz = csy * (C.hi[1] - C.lo[1] + 3);
+    EC = ec + C.off_g1;
+    cbase = (1 - C.lo[0]) + csy * (fdiv2(j) - C.lo[1] + 1) + csz * (1 - C.lo[2]);
+  }
   for (int k0 = t.z0; k0 <= kend; k0 += U) {
     Nbr<T> v[U];
+    T ev[U][PE ? 4 : 1];
     int il[U], pc[U];
     bool ok[U];
 #pragma unroll
@@ -253,12 +278,31 @@ __global__ void __launch_bounds__(256)
       ok[u] = row_ok && k <= kend && i <= B.hi[0];
       il[u] = i - B.lo[0];
       pc[u] = (il[u] + 1) + s.sy * (jl + 1) + s.sz * (k - B.lo[2] + 1);
-      if (ok[u])
+      if (ok[u]) {
         gather<T, !ZG, false>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il[u], jl, k - B.lo[2], pc[u]);
+        if (PE) {
+          // the parent of (i, j, k) and, per axis, the parent of the
+          // neighbour that lies in the next coarse cell
+          const int cc = cbase + fdiv2(i) + csz * fdiv2(k);
+          ev[u][0] = EC[cc];
+          ev[u][1] = EC[cc + ((i & 1) ? 1 : -1)];
+          ev[u][2] = EC[cc + ((j & 1) ? csy : -csy)];
+          ev[u][3] = EC[cc + ((k & 1) ? csz : -csz)];
+        }
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (!ok[u]) continue;
+      if (PE) {
+        const bool ox = (il[u] + B.lo[0]) & 1, oy = j & 1, oz = (k0 + u) & 1;
+        v[u].pxl = v[u].pxl + (ox ? ev[u][0] : ev[u][1]);
+        v[u].pxh = v[u].pxh + (ox ? ev[u][1] : ev[u][0]);
+        v[u].pyl = v[u].pyl + (oy ? ev[u][0] : ev[u][2]);
+        v[u].pyh = v[u].pyh + (oy ? ev[u][2] : ev[u][0]);
+        v[u].pzl = v[u].pzl + (oz ? ev[u][0] : ev[u][3]);
+        v[u].pzh = v[u].pzh + (oz ? ev[u][3] : ev[u][0]);
+      }
       const Cell<T> c = eval<T, !ZG>(op, v[u], A != nullptr, m, s, il[u], jl, k0 + u - B.lo[2]);
       const T nv = ZG ? v[u].f / c.diag : (v[u].f + c.off) / c.diag;
       P[pc[u]] = nv;
@@ -590,8 +634,6 @@ __global__ void __launch_bounds__(256)
   }
   block_max_u64(mx, normbits);
 }
-
-__device__ __forceinline__ int fdiv2(int a) { return a >= 0 ? a / 2 : -((-a + 1) / 2); }
 
 // Tiles index coarse cells of coarsen(fine box t.box).
 template <typename T>
@@ -1437,25 +1479,31 @@ inline dim3 block_of(Shape sh) { return dim3(sh.lx, sh.ly, 1); }
 template <typename T>
 hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                        const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng, int colour,
-                       int zero_guess, const WtBox* wtb, const WtEntry* wte) {
+                       int zero_guess, const WtBox* wtb, const WtEntry* wte,
+                       const BoxInfo* cinfo, const T* ec) {
   if (ntiles <= 0) return hipSuccess;
+  if (ec && (!wtb || zero_guess || !cinfo)) return hipErrorInvalidValue;
   const dim3 g(ntiles), b = block_of(sh);
   const size_t lds = wtb ? 2 * (size_t)sh.ly * sh.tz * sizeof(T) : 0;
-#define GS(U, Z, W, X)                                                                           \
-  hipLaunchKernelGGL((k_gsrb<T, U, Z, W, X>), g, b, lds, st, tiles, op, phi, rhs, rhs_ng, colour, \
-                     sh.tz, wtb, wte)
-#define GSU(Z, W, X)                       \
-  if (sh.u >= 4) GS(4, Z, W, X);           \
-  else if (sh.u == 2) GS(2, Z, W, X);      \
-  else GS(1, Z, W, X);
-  if (wtb) {
-    if (zero_guess) { GSU(true, false, true) }
-    else if (sh.wp) { GSU(false, true, true) }
-    else { GSU(false, false, true) }
+#define GS(U, Z, W, X, E)                                                                        \
+  hipLaunchKernelGGL((k_gsrb<T, U, Z, W, X, E>), g, b, lds, st, tiles, op, phi, rhs, rhs_ng,     \
+                     colour, sh.tz, wtb, wte, cinfo, ec)
+#define GSU(Z, W, X, E)                    \
+  if (sh.u >= 4) GS(4, Z, W, X, E);        \
+  else if (sh.u == 2) GS(2, Z, W, X, E);   \
+  else GS(1, Z, W, X, E);
+  if (ec) {
+    // never whole pairs: the other cell of a pair would be stored with its
+    // correction while other lanes still read it and add the correction
+    GSU(false, false, true, true)
+  } else if (wtb) {
+    if (zero_guess) { GSU(true, false, true, false) }
+    else if (sh.wp) { GSU(false, true, true, false) }
+    else { GSU(false, false, true, false) }
   } else {
-    if (zero_guess) { GSU(true, false, false) }
-    else if (sh.wp) { GSU(false, true, false) }
-    else { GSU(false, false, false) }
+    if (zero_guess) { GSU(true, false, false, false) }
+    else if (sh.wp) { GSU(false, true, false, false) }
+    else { GSU(false, false, false, false) }
   }
 #undef GSU
 #undef GS
@@ -1845,7 +1893,7 @@ hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* dia
 #define INST(T)                                                                                  \
   template hipError_t launch_gsrb<T>(hipStream_t, const Tile*, int, Shape, const StencilArgs<T>&, \
                                      T*, const T*, int, int, int, const WtBox*,                  \
-                                     const WtEntry*);                                            \
+                                     const WtEntry*, const BoxInfo*, const T*);                  \
   template hipError_t launch_sweep<T>(hipStream_t, const Tile*, int, Shape,                      \
                                       const StencilArgs<T>&, const T*, T*, const T*, int, int,   \
                                       unsigned long long*);                                      \

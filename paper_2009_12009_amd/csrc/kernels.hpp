@@ -34,11 +34,19 @@ struct Shape {
 // y0+y, marching z over tz planes.  zero_guess: phi is taken as 0 (nothing
 // but rhs is read).  rhs_ng: 0 or 1.  With wtb/wte (non-null) every update
 // is also written into the face ghosts that mirror the cell, so face ghosts
-// stay current across half-sweeps without an exchange.
+// stay current across half-sweeps without an exchange.  With ec (non-null;
+// needs wtb, no zero guess) the half-sweep also performs the interpolation
+// phi += P ec of the coarse correction ec (cell data with 1 ghost of the
+// boxes cinfo, every phi box's parent): each other-colour value read gets
+// its parent's correction added; only cells of `colour` are stored, so the
+// other colour is left without the correction and must be overwritten (the
+// next half-sweep) before anything reads it.  phi's face ghosts must be
+// current without the correction, ec's face ghosts current.
 template <typename T>
 hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                        const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng, int colour,
-                       int zero_guess, const WtBox* wtb = nullptr, const WtEntry* wte = nullptr);
+                       int zero_guess, const WtBox* wtb = nullptr, const WtEntry* wte = nullptr,
+                       const BoxInfo* cinfo = nullptr, const T* ec = nullptr);
 
 // One full red/black sweep, both colours in one pass, out of place: pout
 // receives the result of a red half-sweep followed by a black half-sweep of

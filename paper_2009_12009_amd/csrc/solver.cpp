@@ -859,21 +859,34 @@ int smooth_fused(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, cons
 // one needs them exchanged, and only when the caller's data may have stale
 // ghosts (ghosts_current false; a zero-guess start reads none).  On return
 // a write-through level's face ghosts are current.
+//
+// With a coarse correction ec (cinfo: the coarse level's box table) the
+// first half-sweep also adds P ec to phi (interpolation folded in; see
+// launch_gsrb): phi's face ghosts must be current without the correction
+// and ec's face ghosts current (fold_interp says when the V-cycle has that).
 template <typename T>
 int smooth(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng,
            int sweeps, bool zero_first, bool prof, bool reverse = false,
-           bool ghosts_current = false) {
+           bool ghosts_current = false, const BoxInfo* cinfo = nullptr, const T* ec = nullptr) {
+  if (ec && (!lv.wt || lv.fused || zero_first || sweeps < 1))
+    return fail(MG_ERR_ARG, "folded interpolation on a level without write-through");
   if (lv.fused && !reverse)
     return smooth_fused<T>(s, lv, op, phi, rhs, rhs_ng, sweeps, zero_first, prof);
   const int c0 = reverse ? 1 : 0;
   const WtBox* wtb = lv.wt ? lv.d_wtbox : nullptr;
   const WtEntry* wte = lv.wt ? lv.d_wt : nullptr;
+  if (ec) ghosts_current = true;
   int rc;
   for (int k = 0; k < sweeps; ++k) {
     const bool zg = zero_first && k == 0;
     const bool need = lv.wt ? (k == 0 && !zg && !ghosts_current) : !zg;
     if (need && (rc = exchange<T>(s, lv, phi, prof))) return rc;
-    {
+    if (k == 0 && ec) {
+      // counted as interpolation, which it replaces
+      ProfScope ps(s, 4, prof);
+      HIPTRY(launch_gsrb<T>(s->st, lv.d_gsrb, (int)lv.t_gsrb.size(), lv.s_gsrb, op, phi, rhs,
+                            rhs_ng, c0, 0, wtb, wte, cinfo, ec));
+    } else {
       ProfScope ps(s, 0, prof);
       HIPTRY(launch_gsrb<T>(s->st, lv.d_gsrb, (int)lv.t_gsrb.size(), lv.s_gsrb, op, phi, rhs,
                             rhs_ng, c0, zg ? 1 : 0, wtb, wte));
@@ -886,6 +899,18 @@ int smooth(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, const T* r
     }
   }
   return MG_OK;
+}
+
+// Whether level l's interpolation from level l+1 folds into its first
+// post-smoothing half-sweep: both levels write through (so phi's face ghosts
+// are current before the interpolation and level l+1's, which is smoothed
+// and not the bottom, are current after its post-smoothing), and there is a
+// half-sweep to fold into.
+bool fold_interp(const mg_solver* s, size_t l) {
+  if (!s->opts.interp_fold || s->opts.nu2 < 1 || l + 1 >= s->L.size()) return false;
+  const Level& f = s->L[l];
+  const Level& c = s->L[l + 1];
+  return f.wt && c.wt && !f.fused && !c.fused;
 }
 
 // Coarse levels l >= lstart in correction form (zero initial guess).
@@ -932,6 +957,9 @@ int coarse_cycle(mg_solver* s, size_t l, bool f32) {
     ProfScope ps(s, 5, l == 0);
     if ((rc = coarse_cycle<T>(s, l + 1, f32))) return rc;
   }
+  if (fold_interp(s, l))
+    return smooth<T>(s, lv, op, D.e, D.rhs, 0, s->opts.nu2, false, prof, s->opts.krylov != 0,
+                     true, cl.d_info, C.e);
   {
     ProfScope ps(s, 4, prof);
     HIPTRY(launch_prolong_add<T>(s->st, lv.d_cell, (int)lv.t_cell.size(), lv.s_cell, lv.d_info,
@@ -1004,6 +1032,9 @@ int vcycle64(mg_solver* s, double* phi, const double* rhs, int rhs_ng) {
     ProfScope ps(s, 5, true);
     if ((rc = coarse_cycle<double>(s, 1, false))) return rc;
   }
+  if (fold_interp(s, 0))
+    return smooth<double>(s, l0, op, phi, rhs, rhs_ng, s->opts.nu2, false, true, false, true,
+                          l1.d_info, l1.e64);
   {
     ProfScope ps(s, 4, true);
     HIPTRY(launch_prolong_add<double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell,
@@ -1931,6 +1962,7 @@ void mg_default_opts(mg_opts_t* o) {
   o->fused_min_edge = 0;
   o->krylov = 0;
   o->ghost_write = 1;
+  o->interp_fold = 1;
 }
 
 static int check_opts(const mg_opts_t* o) {
@@ -1944,6 +1976,7 @@ static int check_opts(const mg_opts_t* o) {
   if (o->fused_min_edge < 0) return fail(MG_ERR_ARG, "fused_min_edge < 0");
   if (o->krylov != 0 && o->krylov != 1) return fail(MG_ERR_ARG, "bad krylov");
   if (o->ghost_write != 0 && o->ghost_write != 1) return fail(MG_ERR_ARG, "bad ghost_write");
+  if (o->interp_fold != 0 && o->interp_fold != 1) return fail(MG_ERR_ARG, "bad interp_fold");
   return MG_OK;
 }
 

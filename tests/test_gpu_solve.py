@@ -287,26 +287,35 @@ WT_CASES = [
 @pytest.mark.parametrize("name,make,boxes,extra", WT_CASES, ids=[c[0] for c in WT_CASES])
 def test_ghost_write_through_bitwise_equal_exchanges(name, make, boxes, extra):
     """Half-sweeps that store boundary updates straight into the neighbours'
-    face ghosts (no exchange between half-sweeps) give the same bits as an
-    exchange before every half-sweep."""
+    face ghosts (no exchange between half-sweeps), with and without the
+    interpolation folded into the first post-smoothing half-sweep, give the
+    same bits as a separate interpolation pass and an exchange before every
+    half-sweep."""
     print(f"[solve] ghost write-through vs exchanges {name}", flush=True)
     P = lib()
     cfg = make()
     boxes = boxes or cfg["boxes"]
     f = cfg["rhs"] - (cfg["rhs"].mean() if all(cfg["periodic"]) else 0.0)
     rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(f, boxes), 0)
-    outs, hist = [], []
-    for gw in (1, 0):
-        s = gpu_solver(cfg, boxes=boxes, opts=dict(max_iter=3, tune=0, ghost_write=gw, **extra))
+    outs, hist, interp = [], [], []
+    for gw, fold in ((1, 1), (1, 0), (0, 1)):
+        s = gpu_solver(cfg, boxes=boxes, opts=dict(max_iter=3, tune=0, ghost_write=gw,
+                                                   interp_fold=fold, **extra))
         phi = s.cell_mf(1, fill=0.0)
+        s.profile(True)
         info = s.solve(phi, rhs, 1e-10, raise_on_fail=False, history=True)
         torch.cuda.synchronize()
+        interp.append(s.kernel_stats(P._lib.FAM_PROLONG)[1])
+        s.profile(False)
         outs.append(to_global(phi, boxes, cfg["n"]))
         hist.append(list(info["history"]))
         s.close()
     assert np.all(np.isfinite(outs[0]))
-    assert np.array_equal(outs[0], outs[1])
-    assert hist[0] == hist[1]
+    for o, h in zip(outs[1:], hist[1:]):
+        assert np.array_equal(outs[0], o)
+        assert hist[0] == h
+    # one level-0 interpolation per V-cycle either way (folded or a pass)
+    assert interp[0] == interp[1] == interp[2] > 0
 
 
 @pytest.mark.gpu

@@ -36,10 +36,11 @@ def test_struct_sizes_match_header_layout():
     L = P._lib
     assert C.sizeof(L.MgBox) == 24
     assert C.sizeof(L.MgGeom) == 24 + 48 + 12 + 4  # trailing padding to 8
-    assert C.sizeof(L.MgOpts) == 10 * 4 + 8 + 3 * 4 + 4  # fused_min_edge, krylov, ghost_write, pad
+    # fused_min_edge, krylov, ghost_write, interp_fold
+    assert C.sizeof(L.MgOpts) == 10 * 4 + 8 + 4 * 4
     o = L.default_opts()
-    assert (o.nu1, o.nu2, o.fused_min_edge, o.krylov, o.ghost_write, o.bottom_rel_tol) == \
-        (2, 2, 0, 0, 1, 1e-4)
+    assert (o.nu1, o.nu2, o.fused_min_edge, o.krylov, o.ghost_write, o.interp_fold,
+            o.bottom_rel_tol) == (2, 2, 0, 0, 1, 1, 1e-4)
     assert C.sizeof(L.MgCopyTag) == 8 + 24 + 12
 
 
@@ -105,6 +106,13 @@ def test_workspace_too_small_rejected_before_any_device_call():
     code = L.lib.mg_create(bx, len(boxes), C.byref(g), bc, bc, 1.0, 1.0, None, None,
                            C.byref(opts), C.c_void_p(4100), 1 << 40, None, C.byref(h))
     assert code == L.MG_ERR_WORKSPACE  # misaligned
+    for field, bad in (("interp_fold", 2), ("ghost_write", -1), ("krylov", 2)):
+        o2 = L.default_opts()
+        setattr(o2, field, bad)
+        size = C.c_size_t(0)
+        code = L.lib.mg_query_workspace(bx, len(boxes), C.byref(g), C.byref(o2), 0, C.byref(size))
+        assert code == L.MG_ERR_ARG, field
+        assert field.encode() in L.lib.mg_last_error()
     bad_bc = (C.c_int32 * 3)(0, 1, 1)  # periodic bc in a non-periodic direction
     code = L.lib.mg_create(bx, len(boxes), C.byref(g), bad_bc, bad_bc, 1.0, 1.0, None, None,
                            C.byref(opts), C.c_void_p(4096), 1 << 40, None, C.byref(h))

@@ -121,6 +121,75 @@ __device__ __forceinline__ void gather(Nbr<T>& v, const Strides& s, const T* P, 
   }
 }
 
+// Buffer descriptors of one box's arrays (phi with one ghost layer, rhs,
+// face coefficients, cell coefficient): a load through them takes the base
+// from SGPRs and a 32-bit byte offset per lane, and loads of the read-once
+// arrays carry the non-temporal hint.  Offsets past a descriptor's size
+// read 0 (none occur: the indexing is the same as gather's).
+struct BoxBufs {
+  __amdgpu_buffer_rsrc_t p, r, x, y, z, a;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* base, long long elems,
+                                                          int word) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0,
+                                           (int)(unsigned)(elems * word), 0x00020000);
+}
+
+// aux 2: non-temporal
+template <typename T, int AUX>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int idx) {
+  if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)((unsigned)idx * 8u),
+                                                                      0, AUX));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)((unsigned)idx * 4u),
+                                                                      0, AUX));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ BoxBufs bufs_of(const StencilArgs<T>& op, const BoxInfo& B,
+                                           const Strides& s, const T* P, const T* R, int rhs_ng,
+                                           const T* BX, const T* BY, const T* BZ, const T* A) {
+  BoxBufs b;
+  const int w = (int)sizeof(T);
+  const long long ncell = (long long)s.nx * s.ny * s.nz;
+  b.p = rsrc_of(P, (long long)s.sz * (s.nz + 2), w);
+  b.r = rsrc_of(R, (long long)s.rsz * (s.nz + 2 * rhs_ng), w);
+  b.x = rsrc_of(BX, ncell + (long long)s.ny * s.nz, w);
+  b.y = rsrc_of(BY, ncell + (long long)s.nx * s.nz, w);
+  b.z = rsrc_of(BZ, ncell + (long long)s.nx * s.ny, w);
+  b.a = rsrc_of(A ? A : P, A ? ncell : 0, w);
+  return b;
+}
+
+// gather through buffer descriptors (same indices, same values)
+template <typename T, bool READ_PHI>
+__device__ __forceinline__ void gather_buf(Nbr<T>& v, const Strides& s, const BoxBufs& b,
+                                           int rhs_ng, bool has_a, int il, int jl, int kl,
+                                           int pc) {
+  v.f = bload<T, 2>(b.r, (il + rhs_ng) + s.rsy * (jl + rhs_ng) + s.rsz * (kl + rhs_ng));
+  const int fx = il + (s.nx + 1) * (jl + s.ny * kl);
+  const int fy = il + s.nx * (jl + (s.ny + 1) * kl);
+  const int fz = il + s.nx * (jl + s.ny * kl);
+  v.bxl = bload<T, 2>(b.x, fx);
+  v.bxh = bload<T, 2>(b.x, fx + 1);
+  v.byl = bload<T, 2>(b.y, fy);
+  v.byh = bload<T, 2>(b.y, fy + s.nx);
+  v.bzl = bload<T, 2>(b.z, fz);
+  v.bzh = bload<T, 2>(b.z, fz + s.nx * s.ny);
+  if (has_a) v.a = bload<T, 2>(b.a, fz);
+  if (READ_PHI) {
+    v.pxl = bload<T, 0>(b.p, pc - 1);
+    v.pxh = bload<T, 0>(b.p, pc + 1);
+    v.pyl = bload<T, 0>(b.p, pc - s.sy);
+    v.pyh = bload<T, 0>(b.p, pc + s.sy);
+    v.pzl = bload<T, 0>(b.p, pc - s.sz);
+    v.pzh = bload<T, 0>(b.p, pc + s.sz);
+  }
+}
+
 // diag and neighbour sum from gathered values.  Every kernel that applies
 // the operator goes through this one function, so all of them compute the
 // same numbers for a cell.
@@ -224,7 +293,10 @@ __device__ __forceinline__ void write_through(const WtBox& wb, const WtEntry* ex
 // whose partner store would race with the lanes adding the correction to
 // that cell).  Neighbours on the box's ghost layer take the correction from
 // the coarse box's ghost layer, which the caller keeps current.
-template <typename T, int U, bool ZG, bool WP, bool WT, bool PE>
+// BUF: loads through buffer descriptors (gather_buf), for levels whose
+// arrays fit 32-bit offsets and are too large to stay in the last-level
+// cache between sweeps (the non-temporal hint would cost re-reads there).
+template <typename T, int U, bool ZG, bool WP, bool WT, bool PE, bool BUF>
 __global__ void __launch_bounds__(256)
     k_gsrb(const Tile* __restrict__ tiles, StencilArgs<T> op, T* __restrict__ phi,
            const T* __restrict__ rhs, int rhs_ng, int colour, int tz,
@@ -249,6 +321,8 @@ __global__ void __launch_bounds__(256)
   const T* BZ = op.b2 + B.off_f[2];
   const T* A = op.a ? op.a + B.off_g0 : nullptr;
   const int m = B.bcmask;
+  BoxBufs bb;
+  if (BUF) bb = bufs_of<T>(op, B, s, P, R, rhs_ng, BX, BY, BZ, A);
   WtBox wb;
   WtEntry ex[2];
   if (WT) {
@@ -279,7 +353,11 @@ __global__ void __launch_bounds__(256)
       il[u] = i - B.lo[0];
       pc[u] = (il[u] + 1) + s.sy * (jl + 1) + s.sz * (k - B.lo[2] + 1);
       if (ok[u]) {
-        gather<T, !ZG, false>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il[u], jl, k - B.lo[2], pc[u]);
+        if (BUF)
+          gather_buf<T, !ZG>(v[u], s, bb, rhs_ng, A != nullptr, il[u], jl, k - B.lo[2], pc[u]);
+        else
+          gather<T, !ZG, false>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il[u], jl, k - B.lo[2],
+                                pc[u]);
         if (PE) {
           // the parent of (i, j, k) and, per axis, the parent of the
           // neighbour that lies in the next coarse cell
@@ -1485,25 +1563,30 @@ hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
   if (ec && (!wtb || zero_guess || !cinfo)) return hipErrorInvalidValue;
   const dim3 g(ntiles), b = block_of(sh);
   const size_t lds = wtb ? 2 * (size_t)sh.ly * sh.tz * sizeof(T) : 0;
-#define GS(U, Z, W, X, E)                                                                        \
-  hipLaunchKernelGGL((k_gsrb<T, U, Z, W, X, E>), g, b, lds, st, tiles, op, phi, rhs, rhs_ng,     \
+#define GS(U, Z, W, X, E, F)                                                                     \
+  hipLaunchKernelGGL((k_gsrb<T, U, Z, W, X, E, F>), g, b, lds, st, tiles, op, phi, rhs, rhs_ng,  \
                      colour, sh.tz, wtb, wte, cinfo, ec)
-#define GSU(Z, W, X, E)                    \
-  if (sh.u >= 4) GS(4, Z, W, X, E);        \
-  else if (sh.u == 2) GS(2, Z, W, X, E);   \
-  else GS(1, Z, W, X, E);
+#define GSU(Z, W, X, E, F)                    \
+  if (sh.u >= 4) GS(4, Z, W, X, E, F);        \
+  else if (sh.u == 2) GS(2, Z, W, X, E, F);   \
+  else GS(1, Z, W, X, E, F);
+  // buffer loads on the write-through paths the solve runs most, where the
+  // level streams (op.buf)
+  const bool buf = op.buf != 0;
   if (ec) {
     // never whole pairs: the other cell of a pair would be stored with its
     // correction while other lanes still read it and add the correction
-    GSU(false, false, true, true)
+    // (measured: buffer loads made this variant slower)
+    GSU(false, false, true, true, false)
   } else if (wtb) {
-    if (zero_guess) { GSU(true, false, true, false) }
-    else if (sh.wp) { GSU(false, true, true, false) }
-    else { GSU(false, false, true, false) }
+    if (zero_guess) { GSU(true, false, true, false, false) }
+    else if (sh.wp) { GSU(false, true, true, false, false) }
+    else if (buf) { GSU(false, false, true, false, true) }
+    else { GSU(false, false, true, false, false) }
   } else {
-    if (zero_guess) { GSU(true, false, false, false) }
-    else if (sh.wp) { GSU(false, true, false, false) }
-    else { GSU(false, false, false, false) }
+    if (zero_guess) { GSU(true, false, false, false, false) }
+    else if (sh.wp) { GSU(false, true, false, false, false) }
+    else { GSU(false, false, false, false, false) }
   }
 #undef GSU
 #undef GS

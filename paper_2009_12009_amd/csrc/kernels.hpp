@@ -19,6 +19,10 @@ struct StencilArgs {
   const T* b2;
   T alpha, beta;
   T ih0, ih1, ih2;  // 1 / h_d^2
+  // every array of every box of the level spans < 4 GiB (buffer
+  // descriptors with 32-bit offsets work) and a half-sweep's arrays exceed
+  // the last-level cache (read-once loads may carry the non-temporal hint)
+  int buf = 0;
 };
 
 // Launch shape of a tiled kernel: block (lx, ly), each block marching tz

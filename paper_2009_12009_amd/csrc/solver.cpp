@@ -86,6 +86,7 @@ struct Level {
   std::vector<IBox> boxes;
   IBox domain;
   bool merged = false;
+  bool buf = false;  // every box array < 4 GiB (32-bit buffer offsets)
   int nbox = 0;
   double h[3];
   int64_t ncell = 0, n_g1 = 0, n_g0 = 0, n_f[3] = {0, 0, 0};
@@ -485,6 +486,11 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     for (int d = 0; d < 3; ++d)
       if (s->periodic[d] && ext(lv.domain, d) % 2) even = false;
     lv.wt = s->opts.ghost_write && !lv.fused && l + 1 < hb.size() && even;
+    // largest array of a box: cells with one ghost layer, FP64
+    long long big = 0;
+    for (const IBox& b : lv.boxes)
+      big = std::max(big, (long long)(ext(b, 0) + 2) * (ext(b, 1) + 2) * (ext(b, 2) + 2));
+    lv.buf = big * 8 < (1ll << 32);
     if (lv.wt && !make_wt_tables(lv, s->periodic))
       return fail(MG_ERR_INVALID_BOXARRAY, "write-through table outside a box's ghost layer");
     if (lv.fused) {
@@ -678,6 +684,9 @@ StencilArgs<T> stencil_of(const mg_solver* s, const Level& lv, bool f32) {
   op.ih0 = (T)(1.0 / (lv.h[0] * lv.h[0]));
   op.ih1 = (T)(1.0 / (lv.h[1] * lv.h[1]));
   op.ih2 = (T)(1.0 / (lv.h[2] * lv.h[2]));
+  // phi (read and written), f and three face arrays against the 256 MiB
+  // last-level cache
+  op.buf = lv.buf && 6.0 * sizeof(T) * (double)lv.n_g0 > 256.0 * (1 << 20) ? 1 : 0;
   return op;
 }
 

@@ -280,6 +280,9 @@ WT_CASES = [
      [((0, 0, 0), (15, 31, 31)), ((16, 0, 0), (31, 15, 31)), ((16, 16, 0), (31, 31, 15)),
       ((16, 16, 16), (31, 31, 31))], {}),
     ("uneven96", lambda: W.config_lognormal(96, None, boxes=_uneven_boxes_96()), None, {}),
+    # 192^3: a half-sweep's arrays (340 MB) exceed the last-level cache, so the
+    # write-through path loads through buffer descriptors
+    ("lognormal192_27boxes_buffer_loads", lambda: W.config_lognormal(192, 64), None, {}),
 ]
 
 

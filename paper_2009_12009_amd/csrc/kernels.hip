@@ -40,12 +40,14 @@ __device__ __forceinline__ unsigned long long absbits(double v) {
 }
 __device__ __forceinline__ unsigned long long absbits(float v) { return absbits((double)v); }
 
-// Fold a per-lane value into *dst as an unsigned max over the block.  The
-// block's atomic is skipped when *dst already holds at least its value: *dst
-// only grows, so a value read at any time that is >= m makes the atomic a
-// no-op.  With tens of thousands of blocks this avoids queueing one atomic
-// per block on the single L2 channel that holds *dst.
+// Fold a per-lane value into the norm slot at dst as an unsigned max over
+// the block, into the block's way of the slot (kNormWays words on separate
+// cache lines, so the blocks of a launch do not all meet on one line).  The
+// block's atomic is skipped when its way already holds at least its value:
+// a way only grows, so a value read at any time that is >= m makes the
+// atomic a no-op.
 __device__ void block_max_u64(unsigned long long v, unsigned long long* dst) {
+  dst += kNormStride * (blockIdx.x % kNormWays);
   __shared__ unsigned long long red[16];
   for (int o = 32; o > 0; o >>= 1) {
     unsigned long long w = (unsigned long long)__shfl_xor((long long)v, o);
@@ -156,7 +158,7 @@ __device__ __forceinline__ BoxBufs bufs_of(const StencilArgs<T>& op, const BoxIn
   const int w = (int)sizeof(T);
   const long long ncell = (long long)s.nx * s.ny * s.nz;
   b.p = rsrc_of(P, (long long)s.sz * (s.nz + 2), w);
-  b.r = rsrc_of(R, (long long)s.rsz * (s.nz + 2 * rhs_ng), w);
+  b.r = rsrc_of(R ? R : P, R ? (long long)s.rsz * (s.nz + 2 * rhs_ng) : 0, w);
   b.x = rsrc_of(BX, ncell + (long long)s.ny * s.nz, w);
   b.y = rsrc_of(BY, ncell + (long long)s.nx * s.nz, w);
   b.z = rsrc_of(BZ, ncell + (long long)s.nx * s.ny, w);
@@ -165,11 +167,12 @@ __device__ __forceinline__ BoxBufs bufs_of(const StencilArgs<T>& op, const BoxIn
 }
 
 // gather through buffer descriptors (same indices, same values)
-template <typename T, bool READ_PHI>
+template <typename T, bool READ_PHI, bool READ_CENTRE>
 __device__ __forceinline__ void gather_buf(Nbr<T>& v, const Strides& s, const BoxBufs& b,
-                                           int rhs_ng, bool has_a, int il, int jl, int kl,
-                                           int pc) {
-  v.f = bload<T, 2>(b.r, (il + rhs_ng) + s.rsy * (jl + rhs_ng) + s.rsz * (kl + rhs_ng));
+                                           int rhs_ng, bool has_r, bool has_a, int il, int jl,
+                                           int kl, int pc) {
+  if (has_r)
+    v.f = bload<T, 2>(b.r, (il + rhs_ng) + s.rsy * (jl + rhs_ng) + s.rsz * (kl + rhs_ng));
   const int fx = il + (s.nx + 1) * (jl + s.ny * kl);
   const int fy = il + s.nx * (jl + (s.ny + 1) * kl);
   const int fz = il + s.nx * (jl + s.ny * kl);
@@ -180,6 +183,7 @@ __device__ __forceinline__ void gather_buf(Nbr<T>& v, const Strides& s, const Bo
   v.bzl = bload<T, 2>(b.z, fz);
   v.bzh = bload<T, 2>(b.z, fz + s.nx * s.ny);
   if (has_a) v.a = bload<T, 2>(b.a, fz);
+  if (READ_CENTRE) v.pc = bload<T, 0>(b.p, pc);
   if (READ_PHI) {
     v.pxl = bload<T, 0>(b.p, pc - 1);
     v.pxh = bload<T, 0>(b.p, pc + 1);
@@ -354,7 +358,8 @@ __global__ void __launch_bounds__(256)
       pc[u] = (il[u] + 1) + s.sy * (jl + 1) + s.sz * (k - B.lo[2] + 1);
       if (ok[u]) {
         if (BUF)
-          gather_buf<T, !ZG>(v[u], s, bb, rhs_ng, A != nullptr, il[u], jl, k - B.lo[2], pc[u]);
+          gather_buf<T, !ZG, false>(v[u], s, bb, rhs_ng, true, A != nullptr, il[u], jl,
+                                    k - B.lo[2], pc[u]);
         else
           gather<T, !ZG, false>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il[u], jl, k - B.lo[2],
                                 pc[u]);
@@ -636,7 +641,7 @@ __device__ double block_sum(double v, double* red, int& phase);
 
 // out = rhs - A phi (mode 0) or A phi (mode 1), one lane per cell, U planes
 // gathered at a time; optional NaN-propagating max |out|.
-template <typename T, typename TO, int U>
+template <typename T, typename TO, int U, bool BUF>
 __global__ void __launch_bounds__(256)
     k_residual(const Tile* __restrict__ tiles, StencilArgs<T> op, const T* __restrict__ phi,
                const T* __restrict__ rhs, int rhs_ng, TO* __restrict__ out,
@@ -660,14 +665,20 @@ __global__ void __launch_bounds__(256)
     TO* O = out ? out + B.off_g0 : nullptr;
     const int il = i - B.lo[0], jl = j - B.lo[1];
     const int m = B.bcmask;
+    BoxBufs bb;
+    if (BUF) bb = bufs_of<T>(op, B, s, P, R, rhs_ng, BX, BY, BZ, A);
     for (int k0 = t.z0; k0 <= kend; k0 += U) {
       Nbr<T> v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int kl = k0 + u - B.lo[2];
-        if (k0 + u <= kend)
-          gather<T, true, true>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il, jl, kl,
-                                (il + 1) + s.sy * (jl + 1) + s.sz * (kl + 1));
+        const int pc = (il + 1) + s.sy * (jl + 1) + s.sz * (kl + 1);
+        if (k0 + u > kend) continue;
+        if (BUF)
+          gather_buf<T, true, true>(v[u], s, bb, rhs_ng, R != nullptr, A != nullptr, il, jl, kl,
+                                    pc);
+        else
+          gather<T, true, true>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il, jl, kl, pc);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -1644,10 +1655,15 @@ hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape 
                            double* dot_partials) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 g(ntiles), b = block_of(sh);
-#define RS(U) \
-  hipLaunchKernelGGL((k_residual<T, TO, U>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng, out, \
+#define RS(U, F)                                                                           \
+  hipLaunchKernelGGL((k_residual<T, TO, U, F>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng, out, \
                      normbits, sh.tz, mode, dot_partials)
-  if (sh.u >= 4) RS(4); else if (sh.u == 2) RS(2); else RS(1);
+  // buffer loads where the level streams (op.buf)
+  if (op.buf) {
+    if (sh.u >= 4) RS(4, true); else if (sh.u == 2) RS(2, true); else RS(1, true);
+  } else {
+    if (sh.u >= 4) RS(4, false); else if (sh.u == 2) RS(2, false); else RS(1, false);
+  }
 #undef RS
   return hipGetLastError();
 }

@@ -25,6 +25,13 @@ struct StencilArgs {
   int buf = 0;
 };
 
+// A max-norm slot: kNormWays words kNormStride apart (one per 128-byte line);
+// work-group b folds its maximum into way b % kNormWays, and the slot's norm
+// is the largest of its ways.  Clearing a slot clears all kNormSlot words.
+constexpr int kNormWays = 64;
+constexpr int kNormStride = 16;
+constexpr int kNormSlot = kNormWays * kNormStride;
+
 // Launch shape of a tiled kernel: block (lx, ly), each block marching tz
 // planes, u planes gathered per step (smoother and residual only).
 struct Shape {

@@ -156,7 +156,7 @@ struct mg_solver {
   double *bdiag64 = nullptr, *bcoef64 = nullptr, *bwork64 = nullptr;
   float *bdiag32 = nullptr, *bcoef32 = nullptr, *bwork32 = nullptr;
   // scratch
-  unsigned long long* d_norm = nullptr;  // [4]
+  unsigned long long* d_norm = nullptr;  // 4 norm slots of kNormSlot words
   double* d_cg = nullptr;                // [4] preconditioned CG scalars
   int* d_iters = nullptr;
   double* d_sum = nullptr;
@@ -199,6 +199,11 @@ struct mg_solver {
   double *gm_Wf = nullptr, *gm_Wc = nullptr, *gm_zero_f = nullptr, *gm_zero_c = nullptr;
   double *gm_part = nullptr, *d_gm = nullptr, *h_gm = nullptr;
 };
+
+// Norm slot k (kNormSlot words) of the solver's norm scratch.
+inline unsigned long long* norm_slot(mg_solver* s, int k) {
+  return s->d_norm + (size_t)k * kNormSlot;
+}
 
 namespace {
 
@@ -627,7 +632,7 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     s->bcoef64 = bump.take<double>(6 * (size_t)nb);
     s->bwork64 = bump.take<double>(4 * (size_t)nb);
   }
-  s->d_norm = bump.take<unsigned long long>(4);
+  s->d_norm = bump.take<unsigned long long>(4 * kNormSlot);
   s->d_cg = bump.take<double>(4);
   s->d_iters = bump.take<int>(4);
   s->d_sum = bump.take<double>(2);
@@ -1052,12 +1057,16 @@ int vcycle64(mg_solver* s, double* phi, const double* rhs, int rhs_ng) {
   return smooth<double>(s, l0, op, phi, rhs, rhs_ng, s->opts.nu2, false, true);
 }
 
+// The norm of a slot: the largest of its ways (bit patterns of |x|, so the
+// unsigned maximum is the maximum of the values, NaN included).
 int read_norm(mg_solver* s, int slot, double* out) {
-  HIPTRY(hipMemcpyAsync(s->h_norm, s->d_norm + slot, sizeof(unsigned long long),
+  HIPTRY(hipMemcpyAsync(s->h_norm, norm_slot(s, slot), sizeof(unsigned long long) * kNormSlot,
                         hipMemcpyDeviceToHost, s->st));
   HIPTRY(hipStreamSynchronize(s->st));
+  unsigned long long m = 0;
+  for (int w = 0; w < kNormWays; ++w) m = std::max(m, s->h_norm[w * kNormStride]);
   double v;
-  std::memcpy(&v, s->h_norm, sizeof(double));
+  std::memcpy(&v, &m, sizeof(double));
   *out = v;
   return MG_OK;
 }
@@ -1823,9 +1832,9 @@ int solve_amr_fgmres(mg_solver* s, double* Pc, double* Pf, const double* Fc, int
     return MG_OK;
   };
   while (true) {
-    HIPTRY(launch_fill_u64(s->st, s->d_norm + 1, 1, 0ull));
+    HIPTRY(launch_fill_u64(s->st, norm_slot(s, 1), kNormSlot, 0ull));
     if ((rc = composite_residual<double>(s, Pc, Pf, Fc, fc_ng, Ff, ff_ng, s->Rc, s->Rf,
-                                         s->d_norm + 1, nullptr)))
+                                         norm_slot(s, 1), nullptr)))
       return rc;
     if ((rc = read_norm(s, 1, &rn))) return rc;
     if (resid_history) resid_history[hist] = rn;
@@ -2075,8 +2084,9 @@ int mg_create(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom, const 
   HIPTRY(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
   HIPTRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
   HIPTRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
-  HIPTRY(hipHostMalloc((void**)&s->h_norm, 64, hipHostMallocDefault));
-  s->h_iters = reinterpret_cast<int*>(s->h_norm + 4);
+  HIPTRY(hipHostMalloc((void**)&s->h_norm, sizeof(unsigned long long) * (kNormSlot + 8),
+                       hipHostMallocDefault));
+  s->h_iters = reinterpret_cast<int*>(s->h_norm + kNormSlot);
   if ((rc = begin_call(s.get()))) return rc;
   if ((rc = upload_tables(s.get()))) return rc;
   if ((rc = setup_coefficients(s.get(), acoef, bcoef))) return rc;
@@ -2157,17 +2167,17 @@ int solve_pcg(mg_solver* s, double* P, const double* F, int rng, double tol, mg_
   int rc;
   // r = f - A x (into buf), mean taken out when singular; max |r| read back
   auto true_residual = [&](double* buf, double* norm) -> int {
-    HIPTRY(launch_fill_u64(s->st, s->d_norm + 2, 1, 0ull));
+    HIPTRY(launch_fill_u64(s->st, norm_slot(s, 2), kNormSlot, 0ull));
     if ((rc = exchange<double>(s, l0, P, false))) return rc;
     {
       ProfScope ps(s, 1, true);
       HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, nt, sh, op, P, F, rng, buf,
-                                              s->singular ? nullptr : s->d_norm + 2, 0)));
+                                              s->singular ? nullptr : norm_slot(s, 2), 0)));
     }
     if (s->singular) {
       HIPTRY(launch_sum_valid(s->st, vt, nv, sv, l0.d_info, buf, 0, s->d_partials, s->d_sum));
       HIPTRY(launch_shift_valid(s->st, vt, nv, sv, l0.d_info, buf, 0, s->d_sum, l0.ncell));
-      HIPTRY(launch_maxabs<double>(s->st, vt, nv, sv, l0.d_info, buf, 0, s->d_norm + 2));
+      HIPTRY(launch_maxabs<double>(s->st, vt, nv, sv, l0.d_info, buf, 0, norm_slot(s, 2)));
     }
     return read_norm(s, 2, norm);
   };
@@ -2241,11 +2251,11 @@ int solve_pcg(mg_solver* s, double* P, const double* F, int rng, double tol, mg_
       ProfScope ps(s, 6, true);
       HIPTRY(launch_sum_final(s->st, s->d_partials, nt, s->d_cg + 2));
     }
-    HIPTRY(launch_fill_u64(s->st, s->d_norm + 2, 1, 0ull));
+    HIPTRY(launch_fill_u64(s->st, norm_slot(s, 2), kNormSlot, 0ull));
     {
       ProfScope ps(s, 6, true);
       HIPTRY(launch_cg_xr(s->st, vt, nv, sv, l0.d_info, P, p, r, q, rho_new, s->d_cg + 2,
-                          s->d_norm + 2, f32 ? l0.rhs32 : nullptr));
+                          norm_slot(s, 2), f32 ? l0.rhs32 : nullptr));
       r32_current = f32;
     }
     ++it;
@@ -2276,7 +2286,7 @@ int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, doubl
   inf.nlevels = (int)s->L.size();
   inf.setup_ms = s->setup_ms;
 
-  HIPTRY(launch_fill_u64(s->st, s->d_norm, 4, 0ull));
+  HIPTRY(launch_fill_u64(s->st, s->d_norm, 4 * kNormSlot, 0ull));
   HIPTRY(launch_maxabs<double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info, F,
                                rng, s->d_norm));
   double normf;
@@ -2300,7 +2310,7 @@ int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, doubl
     int it = 0, rising = 0;
     double rn = 0, first = 0, prev = 0;
     while (true) {
-      HIPTRY(launch_fill_u64(s->st, s->d_norm + 1, 1, 0ull));
+      HIPTRY(launch_fill_u64(s->st, norm_slot(s, 1), kNormSlot, 0ull));
       // after an FP64 V-cycle whose post-smoothing wrote through, phi's face
       // ghosts are current; the refinement update touches valid cells only
       if ((f32 || it == 0 || !l0.wt || s->opts.nu2 == 0) &&
@@ -2310,12 +2320,12 @@ int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, doubl
         ProfScope ps(s, 1, true);
         if (f32)
           HIPTRY((launch_residual<double, float>(s->st, l0.d_cell, (int)l0.t_cell.size(),
-                                                 l0.s_cell, op, P, F, rng, l0.rhs32, s->d_norm + 1,
+                                                 l0.s_cell, op, P, F, rng, l0.rhs32, norm_slot(s, 1),
                                                  0)));
         else
           HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(),
                                                   l0.s_cell, op, P, F, rng, nullptr,
-                                                  s->d_norm + 1, 0)));
+                                                  norm_slot(s, 1), 0)));
       }
       if ((rc = read_norm(s, 1, &rn))) return rc;
       if (resid_history) resid_history[it] = rn;
@@ -2579,8 +2589,9 @@ int mg_create_amr(const mg_box_t* cboxes, int32_t ncb, const mg_box_t* fboxes, i
   HIPTRY(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
   HIPTRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
   HIPTRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
-  HIPTRY(hipHostMalloc((void**)&s->h_norm, 64, hipHostMallocDefault));
-  s->h_iters = reinterpret_cast<int*>(s->h_norm + 4);
+  HIPTRY(hipHostMalloc((void**)&s->h_norm, sizeof(unsigned long long) * (kNormSlot + 8),
+                       hipHostMallocDefault));
+  s->h_iters = reinterpret_cast<int*>(s->h_norm + kNormSlot);
   if ((rc = begin_call(s.get()))) return rc;
   if ((rc = upload_tables(s.get()))) return rc;
   if ((rc = upload_composite(s.get()))) return rc;
@@ -2629,7 +2640,7 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
   std::memset(&inf, 0, sizeof(inf));
   inf.nlevels = (int)s->L.size() + 1;
   inf.setup_ms = s->setup_ms;
-  HIPTRY(launch_fill_u64(s->st, s->d_norm, 4, 0ull));
+  HIPTRY(launch_fill_u64(s->st, s->d_norm, 4 * kNormSlot, 0ull));
   HIPTRY(launch_copy_valid(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, Fc,
                            rhs_c->ngrow, s->Rc, 0));
   if ((rc = avgdown<double>(s, nullptr, 0, s->Rc, 0, 1))) return rc;
@@ -2660,9 +2671,9 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
     int it = 0;
     double rn = 0;
     while (true) {
-      HIPTRY(launch_fill_u64(s->st, s->d_norm + 1, 1, 0ull));
+      HIPTRY(launch_fill_u64(s->st, norm_slot(s, 1), kNormSlot, 0ull));
       if ((rc = composite_residual<double>(s, Pc, Pf, Fc, rhs_c->ngrow, Ff, rhs_f->ngrow, s->Rc,
-                                           s->Rf, s->d_norm + 1, nullptr)))
+                                           s->Rf, norm_slot(s, 1), nullptr)))
         return rc;
       if ((rc = read_norm(s, 1, &rn))) return rc;
       if (resid_history) resid_history[it] = rn;

@@ -51,6 +51,7 @@ from .mlmg import (  # noqa: F401
     restrict,
     prolong_add,
     cg_bottom,
+    bicgstab_bottom,
     vcycle,
     solve,
     solve_refine,

@@ -25,7 +25,8 @@ along d (indices lo_d .. hi_d+1).  Readings taken where the paper is silent:
   (the averaging and interpolation of "Operations between levels");
 * coefficients coarsened by averaging (a: 8 cells, b: the 4 fine faces on a
   coarse face) and the operator re-discretised at h_c = 2h;
-* bottom = unpreconditioned CG from a zero guess, stopped on the 2-norm;
+* bottom = unpreconditioned CG from a zero guess, stopped on the 2-norm
+  (or BiCGStab, the paper's other native Krylov solver, with the same stop);
 * outer stop test on the max norm relative to max|f|.
 """
 
@@ -368,6 +369,95 @@ def cg_bottom(lev, rhs, tol=1e-4, max_iter=None, singular=None):
     return x, it
 
 
+def bicgstab_bottom(lev, rhs, tol=1e-4, max_iter=None, singular=None):
+    """Unpreconditioned BiCGStab on ``A x = rhs`` from x = 0: the bi-conjugate
+    gradient member of the paper's native Krylov solvers ("CG and BiCG",
+    "Linear Solvers"), used as the bottom solve.
+
+    Stabilised BiCG with the shadow residual fixed at r^ = r_0.  Iteration i
+    (rho_0 = alpha = omega = 1, p = v = 0 before the first):
+
+        rho_i = (r^, r);   p = r + (rho_i / rho_{i-1}) (alpha / omega) (p - omega v)
+        v = A p;           alpha = rho_i / (r^, v);   s = r - alpha v
+        t = A s;           omega = (t, s) / (t, t)
+        x = x + alpha p + omega s;   r = s - omega t
+
+    Stops when ||r||_2 <= tol * ||rhs||_2, or earlier in an iteration when
+    ||s||_2 is already there (x += alpha p), or after ``max_iter`` iterations
+    (default: number of cells).  A zero rho_i or (r^, v) ends the solve with x
+    as it stands; a zero (t, t) takes x += alpha p, r = s and ends it.  For a
+    singular all-periodic problem the mean of rhs is removed first and the
+    mean of x at the end (A maps onto mean-free fields there, so r, s, v and t
+    stay mean-free).  Dot products accumulate in float64; vectors and the
+    scalars applied to them are in the level's precision.  Returns (x with
+    ghosts, iterations).
+    """
+    dt = lev.dtype
+    if singular is None:
+        singular = is_singular(lev)
+    ncell = sum(int(np.prod(box_shape(b))) for b in lev.boxes)
+    if max_iter is None:
+        max_iter = ncell
+    x = new_cell_data(lev)
+    r = [np.array(v, dtype=dt, copy=True) for v in rhs]
+    if singular:
+        m = dt(_mean(r))
+        r = [(v - m).astype(dt) for v in r]
+    bnorm = math.sqrt(_dot(r, r))
+    if bnorm == 0.0:
+        return x, 0
+    rh = [v.copy() for v in r]
+    p = new_cell_data(lev)
+    s = new_cell_data(lev)
+    v = [np.zeros_like(w) for w in r]
+    rho_prev, alpha, omega = 1.0, 1.0, 1.0
+    it = 0
+    while it < max_iter:
+        rho = _dot(rh, r)
+        if rho == 0.0:
+            break
+        beta = (rho / rho_prev) * (alpha / omega)
+        for ib in range(len(p)):
+            P = valid(p[ib])
+            P[...] = r[ib] + dt(beta) * (P - dt(omega) * v[ib])
+        v = apply_op(lev, p)
+        rv = _dot(rh, v)
+        if rv == 0.0:
+            break
+        alpha = rho / rv
+        for ib in range(len(s)):
+            valid(s[ib])[...] = r[ib] - dt(alpha) * v[ib]
+        it += 1
+        if not math.sqrt(_dot([valid(w) for w in s], [valid(w) for w in s])) > tol * bnorm:
+            for ib in range(len(x)):
+                valid(x[ib])[...] += dt(alpha) * valid(p[ib])
+            break
+        t = apply_op(lev, s)
+        tt = _dot(t, t)
+        if tt == 0.0:
+            for ib in range(len(x)):
+                valid(x[ib])[...] += dt(alpha) * valid(p[ib])
+            break
+        omega = _dot(t, [valid(w) for w in s]) / tt
+        for ib in range(len(x)):
+            X = valid(x[ib])
+            X[...] = (X + dt(alpha) * valid(p[ib])) + dt(omega) * valid(s[ib])
+            r[ib] = valid(s[ib]) - dt(omega) * t[ib]
+        if not math.sqrt(_dot(r, r)) > tol * bnorm:
+            break
+        if omega == 0.0:
+            break
+        rho_prev = rho
+    if singular:
+        m = dt(_mean([valid(w) for w in x]))
+        for w in x:
+            valid(w)[...] -= m
+    return x, it
+
+
+BOTTOM_SOLVERS = {"cg": cg_bottom, "bicgstab": bicgstab_bottom}
+
+
 @dataclass
 class Opts:
     nu1: int = 2
@@ -375,6 +465,8 @@ class Opts:
     max_iter: int = 100
     bottom_tol: float = 1e-4
     bottom_max_iter: int = None
+    # "cg" or "bicgstab"
+    bottom_solver: str = "cg"
     min_bottom_edge: int = 4
     aggregate: bool = False
     # post-smoothing in black-then-red order on every level, which makes the
@@ -386,11 +478,11 @@ class Opts:
 def vcycle(levels, l, phi, f, opts, stats=None):
     """V(l, phi, f): nu1 pre-smoothing sweeps, residual, restrict, recurse on a zero
     coarse guess, add the interpolated correction, nu2 post-smoothing sweeps; the
-    bottom level is solved by CG on its residual equation."""
+    bottom level is solved by CG (or BiCGStab) on its residual equation."""
     lev = levels[l]
     if l == len(levels) - 1:
         r = residual(lev, phi, f)
-        e, its = cg_bottom(lev, r, opts.bottom_tol, opts.bottom_max_iter)
+        e, its = BOTTOM_SOLVERS[opts.bottom_solver](lev, r, opts.bottom_tol, opts.bottom_max_iter)
         for ib in range(len(phi)):
             valid(phi[ib])[...] += valid(e[ib])
         if stats is not None:

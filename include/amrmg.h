@@ -142,6 +142,11 @@ typedef struct {
                                       it reads, instead of a pass of its own
                                       and an exchange (same result); 0 = a
                                       separate interpolation pass             */
+  int32_t bottom_solver;       /* [0] bottom solve on its residual equation,
+                                      from zero, to bottom_rel_tol in the
+                                      2-norm: 0 = CG, 1 = BiCGStab (the
+                                      paper's native "CG and BiCG" Krylov
+                                      solvers, "Linear Solvers")              */
 } mg_opts_t;
 
 typedef struct {

@@ -1364,6 +1364,138 @@ __global__ void __launch_bounds__(1024)
   if (tid == 0) *iters_out = it;
 }
 
+// One work-group of 1024 lanes runs the whole BiCGStab (stabilised
+// bi-conjugate gradients, shadow residual r^ = r_0, from x = 0); lane l owns
+// cells l, l+1024, ...  Iteration: p = r + beta (p - omega v), v = A p,
+// alpha = rho / (r^, v), s = r - alpha v, t = A s, omega = (t, s) / (t, t),
+// x = (x + alpha p) + omega s, r = s - omega t, rho = (r^, r).  Stops on
+// ||r||_2 <= tol ||r_0||_2, on ||s||_2 there (x += alpha p), or on a
+// breakdown (rho or (r^, v) zero; (t, t) zero takes x += alpha p).  The
+// seven vectors live in the workspace (L2-resident at bottom sizes); p and
+// s, which other lanes read in the products, are separated from their
+// writes by barriers.  Dots accumulate in double.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_bottom_bicgstab(BottomTables bt, const T* __restrict__ diag, const T* __restrict__ coef,
+                      const T* __restrict__ rhs, T* __restrict__ out, int accumulate, T* work,
+                      double tol, int maxiter, int singular, int* iters_out) {
+  __shared__ double red[32];
+  int phase = 0;
+  const int n = bt.n;
+  T* x = work;
+  T* r = work + n;
+  T* rh = work + 2 * (long long)n;
+  T* p = work + 3 * (long long)n;
+  T* v = work + 4 * (long long)n;
+  T* sv = work + 5 * (long long)n;
+  T* tv = work + 6 * (long long)n;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  auto apply = [&](const T* u, int c) {
+    T off = T(0);
+    for (int f = 0; f < 6; ++f) {
+      const int nb = bt.nbr[f * n + c];
+      off = off + (nb < 0 ? T(0) : coef[f * n + c] * u[nb]);
+    }
+    return diag[c] * u[c] - off;
+  };
+  double s = 0.0;
+  for (int c = tid; c < n; c += nt) {
+    const T val = rhs[bt.map_rhs[c]];
+    r[c] = val;
+    x[c] = T(0);
+    s += (double)val;
+  }
+  if (singular) {
+    s = block_sum(s, red, phase);
+    const T m = (T)(s / n);
+    for (int c = tid; c < n; c += nt) r[c] = r[c] - m;
+  }
+  s = 0.0;
+  for (int c = tid; c < n; c += nt) {
+    rh[c] = r[c];
+    p[c] = T(0);
+    v[c] = T(0);
+    s += (double)r[c] * (double)r[c];
+  }
+  double rho = block_sum(s, red, phase);
+  const double bnorm = sqrt(rho);
+  int it = 0;
+  if (bnorm > 0.0) {
+    double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+    while (it < maxiter) {
+      if (rho == 0.0) break;
+      const T btT = (T)((rho / rho_prev) * (alpha / omega));
+      const T omT = (T)omega;
+      for (int c = tid; c < n; c += nt) p[c] = r[c] + btT * (p[c] - omT * v[c]);
+      __syncthreads();
+      s = 0.0;
+      for (int c = tid; c < n; c += nt) {
+        const T q = apply(p, c);
+        v[c] = q;
+        s += (double)rh[c] * (double)q;
+      }
+      const double rv = block_sum(s, red, phase);
+      if (rv == 0.0) break;
+      alpha = rho / rv;
+      const T alT = (T)alpha;
+      s = 0.0;
+      for (int c = tid; c < n; c += nt) {
+        const T q = r[c] - alT * v[c];
+        sv[c] = q;
+        s += (double)q * (double)q;
+      }
+      ++it;
+      const double ss = block_sum(s, red, phase);
+      if (!(sqrt(ss) > tol * bnorm)) {
+        for (int c = tid; c < n; c += nt) x[c] = x[c] + alT * p[c];
+        break;
+      }
+      double ts = 0.0;
+      s = 0.0;
+      for (int c = tid; c < n; c += nt) {
+        const T q = apply(sv, c);
+        tv[c] = q;
+        ts += (double)q * (double)sv[c];
+        s += (double)q * (double)q;
+      }
+      const double tt = block_sum(s, red, phase);
+      ts = block_sum(ts, red, phase);
+      if (tt == 0.0) {
+        for (int c = tid; c < n; c += nt) x[c] = x[c] + alT * p[c];
+        break;
+      }
+      omega = ts / tt;
+      const T om2 = (T)omega;
+      double rr = 0.0, rhr = 0.0;
+      for (int c = tid; c < n; c += nt) {
+        x[c] = (x[c] + alT * p[c]) + om2 * sv[c];
+        const T q = sv[c] - om2 * tv[c];
+        r[c] = q;
+        rr += (double)q * (double)q;
+        rhr += (double)rh[c] * (double)q;
+      }
+      rr = block_sum(rr, red, phase);
+      rhr = block_sum(rhr, red, phase);
+      if (!(sqrt(rr) > tol * bnorm)) break;
+      if (omega == 0.0) break;
+      rho_prev = rho;
+      rho = rhr;
+    }
+  }
+  if (singular) {
+    s = 0.0;
+    for (int c = tid; c < n; c += nt) s += (double)x[c];
+    s = block_sum(s, red, phase);
+    const T m = (T)(s / n);
+    for (int c = tid; c < n; c += nt) x[c] = x[c] - m;
+  }
+  for (int c = tid; c < n; c += nt) {
+    const long long o = bt.map_out[c];
+    out[o] = accumulate ? out[o] + x[c] : x[c];
+  }
+  if (tid == 0) *iters_out = it;
+}
+
 // Coarse cells of coarsen(fine box): mean of the 8 children or zero.
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -1989,6 +2121,16 @@ hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* dia
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_bottom_bicgstab(hipStream_t st, const BottomTables& bt, const T* diag,
+                                  const T* coef, const T* rhs, T* out, int accumulate, T* work,
+                                  double tol, int maxiter, int singular, int* iters_out) {
+  if (bt.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bottom_bicgstab<T>, dim3(1), dim3(1024), 0, st, bt, diag, coef, rhs, out,
+                     accumulate, work, tol, maxiter, singular, iters_out);
+  return hipGetLastError();
+}
+
 #define INST(T)                                                                                  \
   template hipError_t launch_gsrb<T>(hipStream_t, const Tile*, int, Shape, const StencilArgs<T>&, \
                                      T*, const T*, int, int, int, const WtBox*,                  \
@@ -2020,7 +2162,10 @@ hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* dia
   template hipError_t launch_bottom_setup<T>(hipStream_t, const BottomTables&,                   \
                                              const StencilArgs<T>&, T*, T*);                     \
   template hipError_t launch_bottom_cg<T>(hipStream_t, const BottomTables&, const T*, const T*,  \
-                                          const T*, T*, int, T*, double, int, int, int*);
+                                          const T*, T*, int, T*, double, int, int, int*);      \
+  template hipError_t launch_bottom_bicgstab<T>(hipStream_t, const BottomTables&, const T*,      \
+                                                const T*, const T*, T*, int, T*, double, int,    \
+                                                int, int*);
 
 INST(double)
 INST(float)

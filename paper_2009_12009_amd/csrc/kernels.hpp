@@ -248,5 +248,10 @@ template <typename T>
 hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* diag, const T* coef,
                             const T* rhs, T* out, int accumulate, T* work, double tol,
                             int maxiter, int singular, int* iters_out);
+// BiCGStab instead of CG (same arguments; work holds 7 n values).
+template <typename T>
+hipError_t launch_bottom_bicgstab(hipStream_t st, const BottomTables& bt, const T* diag,
+                                  const T* coef, const T* rhs, T* out, int accumulate, T* work,
+                                  double tol, int maxiter, int singular, int* iters_out);
 
 }  // namespace amrmg

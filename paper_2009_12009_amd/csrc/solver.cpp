@@ -626,11 +626,11 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
   if (f32) {
     s->bdiag32 = bump.take<float>(nb);
     s->bcoef32 = bump.take<float>(6 * (size_t)nb);
-    s->bwork32 = bump.take<float>(4 * (size_t)nb);
+    s->bwork32 = bump.take<float>(7 * (size_t)nb);  // CG 4 n, BiCGStab 7 n
   } else {
     s->bdiag64 = bump.take<double>(nb);
     s->bcoef64 = bump.take<double>(6 * (size_t)nb);
-    s->bwork64 = bump.take<double>(4 * (size_t)nb);
+    s->bwork64 = bump.take<double>(7 * (size_t)nb);  // CG 4 n, BiCGStab 7 n
   }
   s->d_norm = bump.take<unsigned long long>(4 * kNormSlot);
   s->d_cg = bump.take<double>(4);
@@ -941,8 +941,13 @@ int coarse_cycle(mg_solver* s, size_t l, bool f32) {
     const T* coef = f32 ? (const T*)s->bcoef32 : (const T*)s->bcoef64;
     T* work = f32 ? (T*)s->bwork32 : (T*)s->bwork64;
     const int maxit = s->opts.bottom_max_iter > 0 ? s->opts.bottom_max_iter : s->nb;
-    HIPTRY(launch_bottom_cg<T>(s->st, bt, diag, coef, D.rhs, D.e, 0, work,
-                               s->opts.bottom_rel_tol, maxit, s->singular ? 1 : 0, s->d_iters));
+    if (s->opts.bottom_solver == 1)
+      HIPTRY(launch_bottom_bicgstab<T>(s->st, bt, diag, coef, D.rhs, D.e, 0, work,
+                                       s->opts.bottom_rel_tol, maxit, s->singular ? 1 : 0,
+                                       s->d_iters));
+    else
+      HIPTRY(launch_bottom_cg<T>(s->st, bt, diag, coef, D.rhs, D.e, 0, work,
+                                 s->opts.bottom_rel_tol, maxit, s->singular ? 1 : 0, s->d_iters));
     return MG_OK;
   }
   if (s->opts.nu1 == 0)
@@ -1018,9 +1023,14 @@ int vcycle64(mg_solver* s, double* phi, const double* rhs, int rhs_ng) {
     HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, op,
                                             phi, rhs, rhs_ng, l0.r64, nullptr, 0)));
     const int maxit = s->opts.bottom_max_iter > 0 ? s->opts.bottom_max_iter : s->nb;
-    HIPTRY(launch_bottom_cg<double>(s->st, bottom_tables(s), s->bdiag64, s->bcoef64, l0.r64, phi, 1,
-                                    s->bwork64, s->opts.bottom_rel_tol, maxit, s->singular ? 1 : 0,
-                                    s->d_iters));
+    if (s->opts.bottom_solver == 1)
+      HIPTRY(launch_bottom_bicgstab<double>(s->st, bottom_tables(s), s->bdiag64, s->bcoef64, l0.r64,
+                                            phi, 1, s->bwork64, s->opts.bottom_rel_tol, maxit,
+                                            s->singular ? 1 : 0, s->d_iters));
+    else
+      HIPTRY(launch_bottom_cg<double>(s->st, bottom_tables(s), s->bdiag64, s->bcoef64, l0.r64,
+                                      phi, 1, s->bwork64, s->opts.bottom_rel_tol, maxit,
+                                      s->singular ? 1 : 0, s->d_iters));
     return MG_OK;
   }
   // the caller's last exchange (or write-through smoothing) left phi's face
@@ -1981,6 +1991,7 @@ void mg_default_opts(mg_opts_t* o) {
   o->krylov = 0;
   o->ghost_write = 1;
   o->interp_fold = 1;
+  o->bottom_solver = 0;
 }
 
 static int check_opts(const mg_opts_t* o) {
@@ -1995,6 +2006,7 @@ static int check_opts(const mg_opts_t* o) {
   if (o->krylov != 0 && o->krylov != 1) return fail(MG_ERR_ARG, "bad krylov");
   if (o->ghost_write != 0 && o->ghost_write != 1) return fail(MG_ERR_ARG, "bad ghost_write");
   if (o->interp_fold != 0 && o->interp_fold != 1) return fail(MG_ERR_ARG, "bad interp_fold");
+  if (o->bottom_solver != 0 && o->bottom_solver != 1) return fail(MG_ERR_ARG, "bad bottom_solver");
   return MG_OK;
 }
 

@@ -19,7 +19,7 @@ TIGHT = 1e-12  # bottom CG tolerance for parity: roundoff cannot move its stoppi
 
 
 def _run_pair(cfg, opts=None, rel_tol=1e-10, max_iter=100, a_cells=None, min_edge=4,
-              aggregate=0):
+              aggregate=0, oracle_opts=None):
     P = lib()
     n, boxes = cfg["n"], cfg["boxes"]
     gopts = dict(bottom_rel_tol=TIGHT, max_iter=max_iter, min_bottom_edge=min_edge,
@@ -36,7 +36,7 @@ def _run_pair(cfg, opts=None, rel_tol=1e-10, max_iter=100, a_cells=None, min_edg
     ophi = O.new_cell_data(lev)
     oinfo = O.solve(lev, ophi, f_boxes, rel_tol,
                     opts=O.Opts(bottom_tol=TIGHT, max_iter=max_iter, min_bottom_edge=min_edge,
-                                aggregate=bool(aggregate)))
+                                aggregate=bool(aggregate), **(oracle_opts or {})))
     s.close()
     return ginfo, gphi, oinfo, W.gather_cells(ophi, boxes, n, ng=1)
 

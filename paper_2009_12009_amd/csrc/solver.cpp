@@ -1228,27 +1228,66 @@ int time_gsrb(mg_solver* s, Shape sh, T* phi, const T* rhs, const StencilArgs<T>
   return MG_OK;
 }
 
+// A residual that writes r, and with_norm a norm-only residual (into the
+// spare norm slot 3) after it: the two ways an FP64 solve runs the kernel
+// (the FP32 V-cycle only writes r; its norms come from FP64 residuals).
 template <typename T>
 int time_resid(mg_solver* s, Shape sh, const T* phi, const T* rhs, const StencilArgs<T>& op,
-               T* out, float* ms) {
+               T* out, bool with_norm, float* ms) {
   int rc;
   if ((rc = apply_shape(s, sh, false))) return rc;
   hipEvent_t a = take_event(s), b = take_event(s);
   Level& l0 = s->L[0];
-  for (int w = 0; w < 2; ++w)
-    HIPTRY((launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi, rhs, 0,
-                                  out, nullptr, 0)));
+  unsigned long long* nb = norm_slot(s, 3);
+  auto pair = [&]() -> hipError_t {
+    hipError_t e = launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi,
+                                         rhs, 0, out, nullptr, 0);
+    if (e != hipSuccess || !with_norm) return e;
+    return launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi, rhs, 0,
+                                 (T*)nullptr, nb, 0);
+  };
+  HIPTRY(launch_fill_u64(s->st, nb, kNormSlot, 0ull));
+  for (int w = 0; w < 2; ++w) HIPTRY(pair());
   HIPTRY(hipEventRecord(a, s->st));
-  const int reps = 6;
-  for (int w = 0; w < reps; ++w)
-    HIPTRY((launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi, rhs, 0,
-                                  out, nullptr, 0)));
+  const int reps = with_norm ? 3 : 6;
+  for (int w = 0; w < reps; ++w) HIPTRY(pair());
   HIPTRY(hipEventRecord(b, s->st));
   HIPTRY(hipEventSynchronize(b));
   float t;
   HIPTRY(hipEventElapsedTime(&t, a, b));
   *ms = t / reps;
   s->ev_used -= 2;
+  return MG_OK;
+}
+
+// Second pass of a shape search: the best few shapes of the first pass are
+// timed again, several times and interleaved, and the lowest median wins
+// (single short timings of shapes within a few per cent pick by noise).
+template <typename F>
+int pick_finalist(std::vector<std::pair<float, Shape>>& first, F&& time_one, Shape* best,
+                  float* best_ms) {
+  std::stable_sort(first.begin(), first.end(),
+                   [](const std::pair<float, Shape>& x, const std::pair<float, Shape>& y) {
+                     return x.first < y.first;
+                   });
+  const size_t k = std::min<size_t>(4, first.size());
+  std::vector<std::vector<float>> t(k);
+  for (int round = 0; round < 3; ++round)
+    for (size_t c = 0; c < k; ++c) {
+      float ms;
+      int rc = time_one(first[c].second, &ms);
+      if (rc) return rc;
+      t[c].push_back(ms);
+    }
+  float bm = 1e30f;
+  for (size_t c = 0; c < k; ++c) {
+    std::sort(t[c].begin(), t[c].end());
+    if (t[c][1] < bm) {
+      bm = t[c][1];
+      *best = first[c].second;
+    }
+  }
+  *best_ms = bm;
   return MG_OK;
 }
 
@@ -1298,14 +1337,23 @@ int autotune(mg_solver* s) {
         if ((rc = time_sweep<float>(s, sh, phi, l0.rhs32, op, &t))) return rc;
         if (t < tw) { tw = t; best_w = sh; }
       }
+    std::vector<std::pair<float, Shape>> fg, fr;
     for (Shape sh : gsrb_candidates()) {
       if ((rc = time_gsrb<float>(s, sh, phi, l0.rhs32, op, &t))) return rc;
-      if (t < tg) { tg = t; best_g = sh; }
+      fg.push_back({t, sh});
     }
+    if ((rc = pick_finalist(fg, [&](Shape sh, float* ms) {
+           return time_gsrb<float>(s, sh, phi, l0.rhs32, op, ms);
+         }, &best_g, &tg)))
+      return rc;
     for (Shape sh : cell_candidates()) {
-      if ((rc = time_resid<float>(s, sh, phi, l0.rhs32, op, l0.r32, &t))) return rc;
-      if (t < tr) { tr = t; best_c = sh; }
+      if ((rc = time_resid<float>(s, sh, phi, l0.rhs32, op, l0.r32, false, &t))) return rc;
+      fr.push_back({t, sh});
     }
+    if ((rc = pick_finalist(fr, [&](Shape sh, float* ms) {
+           return time_resid<float>(s, sh, phi, l0.rhs32, op, l0.r32, false, ms);
+         }, &best_c, &tr)))
+      return rc;
   } else {
     double* phi = s->tune_scratch;
     HIPTRY(hipMemsetAsync(phi, 0, sizeof(double) * l0.n_g1, s->st));
@@ -1315,14 +1363,23 @@ int autotune(mg_solver* s) {
         if ((rc = time_sweep<double>(s, sh, phi, l0.r64, op, &t))) return rc;
         if (t < tw) { tw = t; best_w = sh; }
       }
+    std::vector<std::pair<float, Shape>> fg, fr;
     for (Shape sh : gsrb_candidates()) {
       if ((rc = time_gsrb<double>(s, sh, phi, l0.r64, op, &t))) return rc;
-      if (t < tg) { tg = t; best_g = sh; }
+      fg.push_back({t, sh});
     }
+    if ((rc = pick_finalist(fg, [&](Shape sh, float* ms) {
+           return time_gsrb<double>(s, sh, phi, l0.r64, op, ms);
+         }, &best_g, &tg)))
+      return rc;
     for (Shape sh : cell_candidates()) {
-      if ((rc = time_resid<double>(s, sh, phi, l0.r64, op, l0.r64, &t))) return rc;
-      if (t < tr) { tr = t; best_c = sh; }
+      if ((rc = time_resid<double>(s, sh, phi, l0.r64, op, l0.r64, true, &t))) return rc;
+      fr.push_back({t, sh});
     }
+    if ((rc = pick_finalist(fr, [&](Shape sh, float* ms) {
+           return time_resid<double>(s, sh, phi, l0.r64, op, l0.r64, true, ms);
+         }, &best_c, &tr)))
+      return rc;
   }
   if ((rc = apply_shape(s, best_g, true))) return rc;
   if ((rc = apply_shape(s, best_c, false))) return rc;

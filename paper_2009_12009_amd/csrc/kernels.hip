@@ -166,8 +166,11 @@ __device__ __forceinline__ BoxBufs bufs_of(const StencilArgs<T>& op, const BoxIn
   return b;
 }
 
-// gather through buffer descriptors (same indices, same values)
-template <typename T, bool READ_PHI, bool READ_CENTRE>
+// gather through buffer descriptors (same indices, same values).  HI: aux
+// of the high-side y and z face loads, the rows and planes that the next
+// tile along y or z reads again as its low side (measured: the half-sweep
+// is fastest with them cached, 0; the residual with them non-temporal, 2).
+template <typename T, bool READ_PHI, bool READ_CENTRE, int HI>
 __device__ __forceinline__ void gather_buf(Nbr<T>& v, const Strides& s, const BoxBufs& b,
                                            int rhs_ng, bool has_r, bool has_a, int il, int jl,
                                            int kl, int pc) {
@@ -179,9 +182,9 @@ __device__ __forceinline__ void gather_buf(Nbr<T>& v, const Strides& s, const Bo
   v.bxl = bload<T, 2>(b.x, fx);
   v.bxh = bload<T, 2>(b.x, fx + 1);
   v.byl = bload<T, 2>(b.y, fy);
-  v.byh = bload<T, 2>(b.y, fy + s.nx);
+  v.byh = bload<T, HI>(b.y, fy + s.nx);
   v.bzl = bload<T, 2>(b.z, fz);
-  v.bzh = bload<T, 2>(b.z, fz + s.nx * s.ny);
+  v.bzh = bload<T, HI>(b.z, fz + s.nx * s.ny);
   if (has_a) v.a = bload<T, 2>(b.a, fz);
   if (READ_CENTRE) v.pc = bload<T, 0>(b.p, pc);
   if (READ_PHI) {
@@ -358,8 +361,8 @@ __global__ void __launch_bounds__(256)
       pc[u] = (il[u] + 1) + s.sy * (jl + 1) + s.sz * (k - B.lo[2] + 1);
       if (ok[u]) {
         if (BUF)
-          gather_buf<T, !ZG, false>(v[u], s, bb, rhs_ng, true, A != nullptr, il[u], jl,
-                                    k - B.lo[2], pc[u]);
+          gather_buf<T, !ZG, false, 0>(v[u], s, bb, rhs_ng, true, A != nullptr, il[u], jl,
+                                       k - B.lo[2], pc[u]);
         else
           gather<T, !ZG, false>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il[u], jl, k - B.lo[2],
                                 pc[u]);
@@ -675,8 +678,8 @@ __global__ void __launch_bounds__(256)
         const int pc = (il + 1) + s.sy * (jl + 1) + s.sz * (kl + 1);
         if (k0 + u > kend) continue;
         if (BUF)
-          gather_buf<T, true, true>(v[u], s, bb, rhs_ng, R != nullptr, A != nullptr, il, jl, kl,
-                                    pc);
+          gather_buf<T, true, true, 2>(v[u], s, bb, rhs_ng, R != nullptr, A != nullptr, il, jl,
+                                       kl, pc);
         else
           gather<T, true, true>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il, jl, kl, pc);
       }

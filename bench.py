@@ -27,6 +27,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--profile-steps", type=int, default=2,
+                   help="extra solves after the timed ones with per-kernel HIP events")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--tune", type=int, default=2, help="0 default tiles, 1 cache, 2 search")
     p.add_argument("--aggregate", type=int, default=1)
@@ -155,8 +157,6 @@ def main():
 
     for _ in range(args.warmup):
         step(None)
-    for s in solvers.values():
-        s.profile(True)
     rec = {k: [] for k in solvers}
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -166,7 +166,16 @@ def main():
     wall = (time.perf_counter() - t1) * 1e3
     ms_step = wall / args.steps
 
-    # level-0 smoother: mean launch duration over the timed steps (HIP events)
+    # kernel durations: HIP events around every level-0 launch, recorded in
+    # extra solves after the timed region (the event records add gaps, so the
+    # timed solves run without them)
+    for s in solvers.values():
+        s.profile(True)
+    for _ in range(args.profile_steps):
+        step(None)
+    torch.cuda.synchronize()
+
+    # level-0 smoother: mean launch duration over the profiled solves
     ncell = n ** 3
     gs = {}
     for k, s in solvers.items():
@@ -180,7 +189,8 @@ def main():
         for name, fid in (("smooth", 0), ("residual", 1), ("exchange", 2), ("restrict", 3),
                           ("prolong", 4), ("coarse_levels", 5), ("update", 6), ("rim", 7)):
             t, c = s.kernel_stats(fid)
-            fam[name] = dict(ms_per_solve=t / args.steps, launches_per_solve=c / args.steps)
+            fam[name] = dict(ms_per_solve=t / args.profile_steps,
+                             launches_per_solve=c / args.profile_steps)
         gs[k]["families"] = fam
         # rim launches only come with fused sweeps (the tuner may have kept half-sweeps)
         gs[k]["fused"] = fam["rim"]["launches_per_solve"] > 0
@@ -236,6 +246,7 @@ def main():
         "cycles": {k: rec[k][0]["iters"] for k in rec},
         "final_rel_resid": {k: rec[k][-1]["rel_resid"] for k in rec},
         "setup_ms": setup_ms,
+        "profiled_solves": args.profile_steps,
         "smoother": {k: {kk: v for kk, v in g.items() if kk != "families"} for k, g in gs.items()},
         "time_by_family_ms": {k: g["families"] for k, g in gs.items()},
         "tile_shapes": {k: g["tile_shapes"] for k, g in gs.items()},

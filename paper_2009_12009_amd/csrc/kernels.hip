@@ -1367,9 +1367,9 @@ __global__ void __launch_bounds__(1024)
   if (tid == 0) *iters_out = it;
 }
 
-// One work-group of 1024 lanes runs the whole BiCGStab (stabilised
-// bi-conjugate gradients, shadow residual r^ = r_0, from x = 0); lane l owns
-// cells l, l+1024, ...  Iteration: p = r + beta (p - omega v), v = A p,
+// One work-group (whole wavefronts, up to 1024 lanes) runs the whole
+// BiCGStab (stabilised bi-conjugate gradients, shadow residual r^ = r_0,
+// from x = 0); lane l owns cells l, l+nt, ...  Iteration: p = r + beta (p - omega v), v = A p,
 // alpha = rho / (r^, v), s = r - alpha v, t = A s, omega = (t, s) / (t, t),
 // x = (x + alpha p) + omega s, r = s - omega t, rho = (r^, r).  Stops on
 // ||r||_2 <= tol ||r_0||_2, on ||s||_2 there (x += alpha p), or on a
@@ -1591,9 +1591,11 @@ __global__ void __launch_bounds__(256)
 }
 
 // The same CG with the search direction p held in LDS and each lane's x, r, q
-// in registers (CPT cells per lane, lane l owns l, l+1024, ...): only the
-// stencil tables are read from memory inside the loop.  Same arithmetic and
-// reduction order as k_bottom_cg.
+// in registers (CPT cells per lane, lane l owns l, l+nt, ...), and for up to
+// two cells per lane also their stencil (diagonal, six coefficients and
+// neighbours): an iteration then reads nothing but LDS.  The work-group is sized to the bottom level (one wavefront for 64
+// cells), so its reductions cross few wavefronts.  Same arithmetic per cell
+// as k_bottom_cg.
 template <typename T, int CPT>
 __global__ void __launch_bounds__(1024)
     k_bottom_cg_lds(BottomTables bt, const T* __restrict__ diag, const T* __restrict__ coef,
@@ -1605,7 +1607,11 @@ __global__ void __launch_bounds__(1024)
   int phase = 0;
   const int n = bt.n;
   const int tid = threadIdx.x, nt = blockDim.x;
-  T x[CPT], r[CPT], q[CPT];
+  // stencil in registers up to two cells per lane (more would spill)
+  constexpr bool REG = CPT <= 2;
+  constexpr int RC = REG ? CPT : 1;
+  T x[CPT], r[CPT], q[CPT], dg[RC], cf[RC][6];
+  int nb[RC][6];
   double s = 0.0;
 #pragma unroll
   for (int m = 0; m < CPT; ++m) {
@@ -1615,6 +1621,13 @@ __global__ void __launch_bounds__(1024)
     if (c < n) {
       r[m] = rhs[bt.map_rhs[c]];
       s += (double)r[m];
+    }
+    if (REG) {
+      dg[m % RC] = c < n ? diag[c] : T(1);
+      for (int f = 0; f < 6; ++f) {
+        nb[m % RC][f] = c < n ? bt.nbr[f * n + c] : -1;
+        cf[m % RC][f] = c < n ? coef[f * n + c] : T(0);
+      }
     }
   }
   if (singular) {
@@ -1643,11 +1656,18 @@ __global__ void __launch_bounds__(1024)
         q[m] = T(0);
         if (c < n) {
           T off = T(0);
-          for (int f = 0; f < 6; ++f) {
-            const int nb = bt.nbr[f * n + c];
-            off = off + (nb < 0 ? T(0) : coef[f * n + c] * p[nb]);
+          if (REG) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+              off = off + (nb[m % RC][f] < 0 ? T(0) : cf[m % RC][f] * p[nb[m % RC][f]]);
+            q[m] = dg[m % RC] * p[c] - off;
+          } else {
+            for (int f = 0; f < 6; ++f) {
+              const int k = bt.nbr[f * n + c];
+              off = off + (k < 0 ? T(0) : coef[f * n + c] * p[k]);
+            }
+            q[m] = diag[c] * p[c] - off;
           }
-          q[m] = diag[c] * p[c] - off;
           s += (double)p[c] * (double)q[m];
         }
       }
@@ -2111,8 +2131,10 @@ hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* dia
   if (bt.n <= 0) return hipSuccess;
   const size_t lds = sizeof(T) * (size_t)bt.n;
   if (lds <= 61440 && bt.n <= 8 * 1024) {  // stays under 64 KiB with the reduction scratch
+    // up to 1024 cells one per lane in whole wavefronts, then 1024 lanes
+    const int nt = bt.n <= 1024 ? (bt.n + 63) / 64 * 64 : 1024;
 #define CGL(C) \
-  hipLaunchKernelGGL((k_bottom_cg_lds<T, C>), dim3(1), dim3(1024), lds, st, bt, diag, coef, rhs, \
+  hipLaunchKernelGGL((k_bottom_cg_lds<T, C>), dim3(1), dim3(nt), lds, st, bt, diag, coef, rhs, \
                      out, accumulate, tol, maxiter, singular, iters_out)
     if (bt.n <= 1024) CGL(1); else if (bt.n <= 2048) CGL(2); else if (bt.n <= 4096) CGL(4);
     else CGL(8);
@@ -2129,7 +2151,8 @@ hipError_t launch_bottom_bicgstab(hipStream_t st, const BottomTables& bt, const 
                                   const T* coef, const T* rhs, T* out, int accumulate, T* work,
                                   double tol, int maxiter, int singular, int* iters_out) {
   if (bt.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bottom_bicgstab<T>, dim3(1), dim3(1024), 0, st, bt, diag, coef, rhs, out,
+  const int nt = bt.n <= 1024 ? (bt.n + 63) / 64 * 64 : 1024;  // whole wavefronts
+  hipLaunchKernelGGL(k_bottom_bicgstab<T>, dim3(1), dim3(nt), 0, st, bt, diag, coef, rhs, out,
                      accumulate, work, tol, maxiter, singular, iters_out);
   return hipGetLastError();
 }

@@ -1369,9 +1369,10 @@ __global__ void __launch_bounds__(1024)
 
 // One work-group (whole wavefronts, up to 1024 lanes) runs the whole
 // BiCGStab (stabilised bi-conjugate gradients, shadow residual r^ = r_0,
-// from x = 0); lane l owns cells l, l+nt, ...  Iteration: p = r + beta (p - omega v), v = A p,
-// alpha = rho / (r^, v), s = r - alpha v, t = A s, omega = (t, s) / (t, t),
-// x = (x + alpha p) + omega s, r = s - omega t, rho = (r^, r).  Stops on
+// from x = 0); lane l owns cells l, l+nt, ...  Iteration:
+// p = r + beta (p - omega v), v = A p, alpha = rho / (r^, v), s = r - alpha v,
+// t = A s, omega = (t, s) / (t, t), x = (x + alpha p) + omega s,
+// r = s - omega t, rho = (r^, r).  Stops on
 // ||r||_2 <= tol ||r_0||_2, on ||s||_2 there (x += alpha p), or on a
 // breakdown (rho or (r^, v) zero; (t, t) zero takes x += alpha p).  The
 // seven vectors live in the workspace (L2-resident at bottom sizes); p and
@@ -1593,9 +1594,9 @@ __global__ void __launch_bounds__(256)
 // The same CG with the search direction p held in LDS and each lane's x, r, q
 // in registers (CPT cells per lane, lane l owns l, l+nt, ...), and for up to
 // two cells per lane also their stencil (diagonal, six coefficients and
-// neighbours): an iteration then reads nothing but LDS.  The work-group is sized to the bottom level (one wavefront for 64
-// cells), so its reductions cross few wavefronts.  Same arithmetic per cell
-// as k_bottom_cg.
+// neighbours): an iteration then reads nothing but LDS.  The work-group is
+// sized to the bottom level (one wavefront for 64 cells), so its reductions
+// cross few wavefronts.  Same arithmetic per cell as k_bottom_cg.
 template <typename T, int CPT>
 __global__ void __launch_bounds__(1024)
     k_bottom_cg_lds(BottomTables bt, const T* __restrict__ diag, const T* __restrict__ coef,

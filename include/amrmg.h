@@ -307,9 +307,10 @@ int mg_num_levels(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
  * mg_kernel_stats returns the summed duration and launch count since the last
  * reset.  family: 0 smoother (a half-sweep, or the fused pass of a whole
  * sweep when the level uses fused sweeps), 1 residual, 2 ghost exchange,
- * 3 restriction, 4 interpolation, 5 coarse levels (one graph or launch
- * sequence per cycle), 6 refinement update, 7 the rim pass that ends a fused
- * sweep. */
+ * 3 restriction, 4 interpolation (a separate pass, or the first
+ * post-smoothing half-sweep that carries it when interp_fold applies),
+ * 5 coarse levels (one graph or launch sequence per cycle), 6 refinement
+ * update and Krylov vector work, 7 the rim pass that ends a fused sweep. */
 int mg_profile(mg_solver_t* s, int32_t enable);
 int mg_kernel_stats(mg_solver_t* s, int32_t family, double* total_ms, int64_t* launches);
 

@@ -103,7 +103,10 @@ typedef struct {
   int32_t precision;           /* [MG_PREC_F64] or MG_PREC_F32_REFINE           */
   int32_t use_graph;           /* [1] replay the coarse levels as a HIP graph   */
   int32_t tune;                /* [1] 0 default tiles, 1 use tune cache,
-                                      2 time the candidates now (and store)     */
+                                      2 time the candidates now (and store);
+                                      tiles of the level-0 and level-1 smoother
+                                      and residual, cached by arch, kernel,
+                                      precision, box shape and box count       */
   int32_t verbose;             /* [0] per-cycle log on stderr                   */
   int32_t aggregate;           /* [0] merge boxes once they stop coarsening and
                                       keep coarsening the merged box            */

@@ -473,7 +473,7 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     build_fb(lv, s->periodic, 1);
     lv.cap_gsrb = lv.t_gsrb.size();
     lv.cap_cell = lv.t_cell.size();
-    if (l == 0) {
+    if (l <= 1) {
       for (Shape c : gsrb_candidates())
         lv.cap_gsrb = std::max(lv.cap_gsrb, tile_count(lv.info, c, 2 * c.lx));
       for (Shape c : cell_candidates())
@@ -1095,8 +1095,8 @@ int end_call(mg_solver* s) {
 // ---------------------------------------------------------------------------
 // Tile-shape tuning of the level-0 smoother and residual.
 
-std::string tune_key(const mg_solver* s, const char* kern, bool f32) {
-  const Level& l0 = s->L[0];
+std::string tune_key(const mg_solver* s, const char* kern, bool f32, size_t lev = 0) {
+  const Level& l0 = s->L[lev];
   int mx[3] = {0, 0, 0};
   for (const IBox& b : l0.boxes)
     for (int d = 0; d < 3; ++d) mx[d] = std::max(mx[d], ext(b, d));
@@ -1136,8 +1136,8 @@ void write_cache(const std::map<std::string, Shape>& m) {
         << kv.second.u << " " << kv.second.wp << "\n";
 }
 
-int apply_shape(mg_solver* s, Shape sh, bool gsrb) {
-  Level& l0 = s->L[0];
+int apply_shape(mg_solver* s, Shape sh, bool gsrb, size_t lev = 0) {
+  Level& l0 = s->L[lev];
   if (gsrb) {
     std::vector<Tile> t;
     make_tiles(l0.info, sh, 2 * sh.lx, false, t);
@@ -1203,11 +1203,12 @@ int time_sweep(mg_solver* s, Shape sh, T* phi, const T* rhs, const StencilArgs<T
 }
 
 template <typename T>
-int time_gsrb(mg_solver* s, Shape sh, T* phi, const T* rhs, const StencilArgs<T>& op, float* ms) {
+int time_gsrb(mg_solver* s, Shape sh, T* phi, const T* rhs, const StencilArgs<T>& op, float* ms,
+              size_t lev = 0) {
   int rc;
-  if ((rc = apply_shape(s, sh, true))) return rc;
+  if ((rc = apply_shape(s, sh, true, lev))) return rc;
   hipEvent_t a = take_event(s), b = take_event(s);
-  Level& l0 = s->L[0];
+  Level& l0 = s->L[lev];
   // with the level's write-through tables, as the solve launches it
   const WtBox* wtb = l0.wt ? l0.d_wtbox : nullptr;
   const WtEntry* wte = l0.wt ? l0.d_wt : nullptr;
@@ -1215,7 +1216,7 @@ int time_gsrb(mg_solver* s, Shape sh, T* phi, const T* rhs, const StencilArgs<T>
     HIPTRY(launch_gsrb<T>(s->st, l0.d_gsrb, (int)l0.t_gsrb.size(), sh, op, phi, rhs, 0, w & 1, 0,
                           wtb, wte));
   HIPTRY(hipEventRecord(a, s->st));
-  const int reps = 6;
+  const int reps = lev ? 24 : 6;
   for (int w = 0; w < reps; ++w)
     HIPTRY(launch_gsrb<T>(s->st, l0.d_gsrb, (int)l0.t_gsrb.size(), sh, op, phi, rhs, 0, w & 1, 0,
                           wtb, wte));
@@ -1233,11 +1234,11 @@ int time_gsrb(mg_solver* s, Shape sh, T* phi, const T* rhs, const StencilArgs<T>
 // (the FP32 V-cycle only writes r; its norms come from FP64 residuals).
 template <typename T>
 int time_resid(mg_solver* s, Shape sh, const T* phi, const T* rhs, const StencilArgs<T>& op,
-               T* out, bool with_norm, float* ms) {
+               T* out, bool with_norm, float* ms, size_t lev = 0) {
   int rc;
-  if ((rc = apply_shape(s, sh, false))) return rc;
+  if ((rc = apply_shape(s, sh, false, lev))) return rc;
   hipEvent_t a = take_event(s), b = take_event(s);
-  Level& l0 = s->L[0];
+  Level& l0 = s->L[lev];
   unsigned long long* nb = norm_slot(s, 3);
   auto pair = [&]() -> hipError_t {
     hipError_t e = launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi,
@@ -1249,7 +1250,7 @@ int time_resid(mg_solver* s, Shape sh, const T* phi, const T* rhs, const Stencil
   HIPTRY(launch_fill_u64(s->st, nb, kNormSlot, 0ull));
   for (int w = 0; w < 2; ++w) HIPTRY(pair());
   HIPTRY(hipEventRecord(a, s->st));
-  const int reps = with_norm ? 3 : 6;
+  const int reps = lev ? 24 : with_norm ? 3 : 6;
   for (int w = 0; w < reps; ++w) HIPTRY(pair());
   HIPTRY(hipEventRecord(b, s->st));
   HIPTRY(hipEventSynchronize(b));
@@ -1291,14 +1292,63 @@ int pick_finalist(std::vector<std::pair<float, Shape>>& first, F&& time_one, Sha
   return MG_OK;
 }
 
+// Level 1, one eighth of the cells, runs from the last-level cache rather
+// than from HBM, so its best shapes differ from level 0's: its smoother and
+// residual are timed on its own boxes (the residual writes r only; the norm
+// is taken on level 0).  Levels below it are a few microseconds per launch.
+bool tune_level1_ok(const mg_solver* s) { return s->L.size() >= 3 && !s->L[1].fused; }
+
+template <typename T>
+int tune_level1(mg_solver* s, bool f32, T* phi, Shape* best_g, Shape* best_c, float* tg,
+                float* tr) {
+  Level& l1 = s->L[1];
+  const LevelData<T> D = ldata<T>(l1, f32);
+  const StencilArgs<T> op = stencil_of<T>(s, l1, f32);
+  HIPTRY(hipMemsetAsync(phi, 0, sizeof(T) * l1.n_g1, s->st));
+  HIPTRY(hipMemsetAsync(D.rhs, 0, sizeof(T) * l1.n_g0, s->st));
+  int rc;
+  float t;
+  std::vector<std::pair<float, Shape>> fg, fr;
+  for (Shape sh : gsrb_candidates()) {
+    if ((rc = time_gsrb<T>(s, sh, phi, D.rhs, op, &t, 1))) return rc;
+    fg.push_back({t, sh});
+  }
+  if ((rc = pick_finalist(fg, [&](Shape sh, float* ms) {
+         return time_gsrb<T>(s, sh, phi, D.rhs, op, ms, 1);
+       }, best_g, tg)))
+    return rc;
+  for (Shape sh : cell_candidates()) {
+    if ((rc = time_resid<T>(s, sh, phi, D.rhs, op, D.r, false, &t, 1))) return rc;
+    fr.push_back({t, sh});
+  }
+  if ((rc = pick_finalist(fr, [&](Shape sh, float* ms) {
+         return time_resid<T>(s, sh, phi, D.rhs, op, D.r, false, ms, 1);
+       }, best_c, tr)))
+    return rc;
+  if ((rc = apply_shape(s, *best_g, true, 1))) return rc;
+  return apply_shape(s, *best_c, false, 1);
+}
+
 int autotune(mg_solver* s) {
   const bool f32 = s->opts.precision == MG_PREC_F32_REFINE;
   Level& l0 = s->L[0];
   auto cache = read_cache();
   const std::string kg = tune_key(s, "gsrb", f32), kr = tune_key(s, "resid", f32);
   const std::string ks = tune_key(s, "sweep", f32);
+  const bool t1 = tune_level1_ok(s);
+  const std::string kg1 = t1 ? tune_key(s, "gsrb", f32, 1) : "", kr1 = t1 ? tune_key(s, "resid", f32, 1) : "";
   int rc;
   if (s->opts.tune == 1) {
+    // level 1 entries (keyed by the level's own box shape and count)
+    for (int g = 0; t1 && g < 2; ++g) {
+      auto it = cache.find(g ? kg1 : kr1);
+      if (it == cache.end() || !shape_ok(it->second)) continue;
+      std::vector<Tile> t;
+      make_tiles(s->L[1].info, it->second, g ? 2 * it->second.lx : it->second.lx, false, t);
+      if (t.size() <= (g ? s->L[1].cap_gsrb : s->L[1].cap_cell) &&
+          (rc = apply_shape(s, it->second, g == 1, 1)))
+        return rc;
+    }
     // sweep entry: the fused shape, u = 1 when it beat two half-sweeps
     auto is = cache.find(ks);
     if (l0.fused && is != cache.end()) {
@@ -1383,6 +1433,15 @@ int autotune(mg_solver* s) {
   }
   if ((rc = apply_shape(s, best_g, true))) return rc;
   if ((rc = apply_shape(s, best_c, false))) return rc;
+  Shape g1 = t1 ? s->L[1].s_gsrb : Shape{}, c1 = t1 ? s->L[1].s_cell : Shape{};
+  float tg1 = 0, tr1 = 0;
+  if (t1) {
+    rc = f32 ? tune_level1<float>(s, true, (float*)s->tune_scratch, &g1, &c1, &tg1, &tr1)
+             : tune_level1<double>(s, false, s->tune_scratch, &g1, &c1, &tg1, &tr1);
+    if (rc) return rc;
+    cache[kg1] = g1;
+    cache[kr1] = c1;
+  }
   if (l0.fused) {
     if ((rc = apply_sweep_shape(s, best_w))) return rc;
     // a fused sweep also saves nothing on exchanges, so it must beat the two
@@ -1398,6 +1457,9 @@ int autotune(mg_solver* s) {
             best_g.lx, best_g.ly, best_g.tz, best_g.u, best_g.wp, tg, best_c.lx, best_c.ly,
             best_c.tz, best_c.u, tr, best_w.lx, best_w.ly, best_w.tz, tw,
             l0.fused ? "fused" : "half-sweeps");
+  if (s->opts.verbose && t1)
+    fprintf(stderr, "amrmg tune level 1: gsrb %dx%dx%d u%d wp%d %.4f ms, resid %dx%dx%d u%d %.4f ms\n",
+            g1.lx, g1.ly, g1.tz, g1.u, g1.wp, tg1, c1.lx, c1.ly, c1.tz, c1.u, tr1);
   cache[kg] = best_g;
   cache[kr] = best_c;
   write_cache(cache);

@@ -230,6 +230,38 @@ def test_tile_shapes_and_graph_bitwise_identical():
         assert np.array_equal(o, ref)
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tuned_shapes_bitwise_identical(precision, tmp_path, monkeypatch):
+    """The tuner picks level-0 and level-1 tile shapes (search, then the cached
+    entries): the solution keeps the bits of the default tiling."""
+    print(f"[solve] tuned shapes 64^3 precision={precision}", flush=True)
+    P = lib()
+    cfg = W.config_lognormal(64, 32)
+    boxes = cfg["boxes"]
+    rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(cfg["rhs"], boxes), 0)
+    cache = tmp_path / "tiles.txt"
+    monkeypatch.setenv("AMRMG_TUNE_CACHE", str(cache))
+    outs = []
+    for tune in (0, 2, 1):
+        s = gpu_solver(cfg, opts=dict(max_iter=3, tune=tune, precision=precision))
+        phi = s.cell_mf(1, fill=0.0)
+        s.solve(phi, rhs, 1e-10, raise_on_fail=False)
+        torch.cuda.synchronize()
+        outs.append(to_global(phi, boxes, 64))
+        s.close()
+    lines = cache.read_text().split("\n")
+    tag = "f32" if precision else "f64"
+    # level 0 boxes and level 1 boxes (half their edges) each have entries
+    keys = [ln.split()[0] for ln in lines if ln.strip()]
+    for kern in ("gsrb", "resid"):
+        dims = sorted({k.split("|")[-2] for k in keys if f"|{kern}|{tag}|" in k})
+        assert len(dims) == 2, keys
+    assert np.all(np.isfinite(outs[0]))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 FUSED_CASES = [
     # (name, cfg, boxes or None, fused_min_edge, precision)
     ("lognormal64_32boxes_f64", lambda: W.config_lognormal(64, 32), None, 32, 0),

@@ -147,9 +147,19 @@ typedef struct {
                                       separate interpolation pass             */
   int32_t bottom_solver;       /* [0] bottom solve on its residual equation,
                                       from zero, to bottom_rel_tol in the
-                                      2-norm: 0 = CG, 1 = BiCGStab (the
-                                      paper's native "CG and BiCG" Krylov
-                                      solvers, "Linear Solvers")              */
+                                      2-norm: 0 = CG, 1 = BiCGStab (the two
+                                      Krylov bottom solvers of the paper's
+                                      section on linear solvers)              */
+  int32_t restrict_fold;       /* [1] where a coarse level is smoothed from
+                                      zero and its boxes are the finer boxes
+                                      coarsened one to one, the restriction of
+                                      the finer residual is done by that
+                                      level's first half-sweep (which reads
+                                      only its own cell's right-hand side),
+                                      not by a pass of its own (same result):
+                                      1 = on levels >= 2, and on level 1 where
+                                      tune measured it faster; 2 = on every
+                                      such level; 0 = separate passes         */
 } mg_opts_t;
 
 typedef struct {
@@ -310,9 +320,11 @@ int mg_num_levels(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
  * mg_kernel_stats returns the summed duration and launch count since the last
  * reset.  family: 0 smoother (a half-sweep, or the fused pass of a whole
  * sweep when the level uses fused sweeps), 1 residual, 2 ghost exchange,
- * 3 restriction, 4 interpolation (a separate pass, or the first
+ * 3 restriction (kept for numbering; the restriction into level 1 now
+ * opens the coarse levels), 4 interpolation (a separate pass, or the first
  * post-smoothing half-sweep that carries it when interp_fold applies),
- * 5 coarse levels (one graph or launch sequence per cycle), 6 refinement
+ * 5 coarse levels (one graph or launch sequence per cycle, from the
+ * restriction of the level-0 residual to level 1's corrections), 6 refinement
  * update and Krylov vector work, 7 the rim pass that ends a fused sweep. */
 int mg_profile(mg_solver_t* s, int32_t enable);
 int mg_kernel_stats(mg_solver_t* s, int32_t family, double* total_ms, int64_t* launches);

@@ -303,13 +303,15 @@ __device__ __forceinline__ void write_through(const WtBox& wb, const WtEntry* ex
 // BUF: loads through buffer descriptors (gather_buf), for levels whose
 // arrays fit 32-bit offsets and are too large to stay in the last-level
 // cache between sweeps (the non-temporal hint would cost re-reads there).
-template <typename T, int U, bool ZG, bool WP, bool WT, bool PE, bool BUF>
+template <typename T, int U, bool ZG, bool WP, bool WT, bool PE, bool BUF, bool RS>
 __global__ void __launch_bounds__(256)
     k_gsrb(const Tile* __restrict__ tiles, StencilArgs<T> op, T* __restrict__ phi,
            const T* __restrict__ rhs, int rhs_ng, int colour, int tz,
            const WtBox* __restrict__ wtb, const WtEntry* __restrict__ wte,
-           const BoxInfo* __restrict__ cinfo, const T* __restrict__ ec) {
+           const BoxInfo* __restrict__ cinfo, const T* __restrict__ ec,
+           const BoxInfo* __restrict__ finfo, const T* __restrict__ rf, T* __restrict__ rout) {
   static_assert(!(PE && (WP || ZG || !WT)), "folded interpolation: write-through half-sweeps only");
+  static_assert(!(RS && (!ZG || WP || PE || BUF)), "folded restriction: zero-guess half-sweeps only");
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = op.boxes[t.box];
   const int j = t.y0 + threadIdx.y;
@@ -347,9 +349,23 @@ __global__ void __launch_bounds__(256)
     EC = ec + C.off_g1;
     cbase = (1 - C.lo[0]) + csy * (fdiv2(j) - C.lo[1] + 1) + csz * (1 - C.lo[2]);
   }
+  // RS: box b of this level is the coarsening of box b of the finer level
+  // (finfo), whose residual rf this half-sweep restricts into rout (ng 0)
+  BoxInfo F;
+  const T* RF = nullptr;
+  T* RO = nullptr;
+  long long fsy = 0, fsz = 0;
+  if (RS) {
+    F = finfo[t.box];
+    RF = rf + F.off_g0;
+    RO = rout + B.off_g0;
+    fsy = F.hi[0] - F.lo[0] + 1;
+    fsz = fsy * (F.hi[1] - F.lo[1] + 1);
+  }
   for (int k0 = t.z0; k0 <= kend; k0 += U) {
     Nbr<T> v[U];
     T ev[U][PE ? 4 : 1];
+    T rv[U][RS ? 2 : 1];
     int il[U], pc[U];
     bool ok[U];
 #pragma unroll
@@ -359,13 +375,36 @@ __global__ void __launch_bounds__(256)
       ok[u] = row_ok && k <= kend && i <= B.hi[0];
       il[u] = i - B.lo[0];
       pc[u] = (il[u] + 1) + s.sy * (jl + 1) + s.sz * (k - B.lo[2] + 1);
+      if (RS && row_ok && k <= kend) {
+        // the average of the 2x2x2 fine children of both cells of the
+        // lane's x-pair (either colour), summed in the restriction's order;
+        // a child pair along x is one aligned two-element load (fine boxes
+        // have even extents and start at even offsets, so b is even)
+        using V2 = T __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int ic = t.x0 + 2 * (int)threadIdx.x + c;
+          if (ic > B.hi[0]) continue;
+          const long long b =
+              (2 * ic - F.lo[0]) + fsy * (2 * j - F.lo[1]) + fsz * (2 * k - F.lo[2]);
+          const V2 q00 = *reinterpret_cast<const V2*>(RF + b);
+          const V2 q01 = *reinterpret_cast<const V2*>(RF + b + fsy);
+          const V2 q10 = *reinterpret_cast<const V2*>(RF + b + fsz);
+          const V2 q11 = *reinterpret_cast<const V2*>(RF + b + fsz + fsy);
+          const T z0 = (q00.x + q00.y) + (q01.x + q01.y);
+          const T z1 = (q10.x + q10.y) + (q11.x + q11.y);
+          rv[u][c] = (z0 + z1) * T(0.125);
+          RO[(ic - B.lo[0]) + s.rsy * jl + s.rsz * (k - B.lo[2])] = rv[u][c];
+        }
+      }
       if (ok[u]) {
         if (BUF)
           gather_buf<T, !ZG, false, 0>(v[u], s, bb, rhs_ng, true, A != nullptr, il[u], jl,
                                        k - B.lo[2], pc[u]);
         else
-          gather<T, !ZG, false>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il[u], jl, k - B.lo[2],
-                                pc[u]);
+          gather<T, !ZG, false>(v[u], s, P, RS ? nullptr : R, rhs_ng, BX, BY, BZ, A, il[u], jl,
+                                k - B.lo[2], pc[u]);
+        if (RS) v[u].f = rv[u][(i - t.x0) & 1];
         if (PE) {
           // the parent of (i, j, k) and, per axis, the parent of the
           // neighbour that lies in the next coarse cell
@@ -1725,22 +1764,33 @@ template <typename T>
 hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                        const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng, int colour,
                        int zero_guess, const WtBox* wtb, const WtEntry* wte,
-                       const BoxInfo* cinfo, const T* ec) {
+                       const BoxInfo* cinfo, const T* ec, const BoxInfo* finfo, const T* rf,
+                       T* rout) {
   if (ntiles <= 0) return hipSuccess;
   if (ec && (!wtb || zero_guess || !cinfo)) return hipErrorInvalidValue;
+  if (rf && (!zero_guess || ec || !finfo || !rout || rhs_ng != 0)) return hipErrorInvalidValue;
   const dim3 g(ntiles), b = block_of(sh);
   const size_t lds = wtb ? 2 * (size_t)sh.ly * sh.tz * sizeof(T) : 0;
-#define GS(U, Z, W, X, E, F)                                                                     \
-  hipLaunchKernelGGL((k_gsrb<T, U, Z, W, X, E, F>), g, b, lds, st, tiles, op, phi, rhs, rhs_ng,  \
-                     colour, sh.tz, wtb, wte, cinfo, ec)
-#define GSU(Z, W, X, E, F)                    \
-  if (sh.u >= 4) GS(4, Z, W, X, E, F);        \
-  else if (sh.u == 2) GS(2, Z, W, X, E, F);   \
-  else GS(1, Z, W, X, E, F);
+#define GS(U, Z, W, X, E, F, RS)                                                                 \
+  hipLaunchKernelGGL((k_gsrb<T, U, Z, W, X, E, F, RS>), g, b, lds, st, tiles, op, phi, rhs,      \
+                     rhs_ng, colour, sh.tz, wtb, wte, cinfo, ec, finfo, rf, rout)
+#define GSU(Z, W, X, E, F)                       \
+  if (sh.u >= 4) GS(4, Z, W, X, E, F, false);    \
+  else if (sh.u == 2) GS(2, Z, W, X, E, F, false); \
+  else GS(1, Z, W, X, E, F, false);
+#define GSR(X)                                  \
+  if (sh.u >= 4) GS(4, true, false, X, false, false, true); \
+  else if (sh.u == 2) GS(2, true, false, X, false, false, true); \
+  else GS(1, true, false, X, false, false, true);
   // buffer loads on the write-through paths the solve runs most, where the
   // level streams (op.buf)
   const bool buf = op.buf != 0;
-  if (ec) {
+  if (rf) {
+    // the restriction into this level's rhs folded into its zero-guess
+    // first half-sweep (global loads, as on every cached level)
+    if (wtb) { GSR(true) }
+    else { GSR(false) }
+  } else if (ec) {
     // never whole pairs: the other cell of a pair would be stored with its
     // correction while other lanes still read it and add the correction
     // (measured: buffer loads made this variant slower)
@@ -1755,6 +1805,7 @@ hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
     else if (sh.wp) { GSU(false, true, false, false, false) }
     else { GSU(false, false, false, false, false) }
   }
+#undef GSR
 #undef GSU
 #undef GS
   return hipGetLastError();
@@ -2161,7 +2212,8 @@ hipError_t launch_bottom_bicgstab(hipStream_t st, const BottomTables& bt, const 
 #define INST(T)                                                                                  \
   template hipError_t launch_gsrb<T>(hipStream_t, const Tile*, int, Shape, const StencilArgs<T>&, \
                                      T*, const T*, int, int, int, const WtBox*,                  \
-                                     const WtEntry*, const BoxInfo*, const T*);                  \
+                                     const WtEntry*, const BoxInfo*, const T*, const BoxInfo*,   \
+                                     const T*, T*);                                              \
   template hipError_t launch_sweep<T>(hipStream_t, const Tile*, int, Shape,                      \
                                       const StencilArgs<T>&, const T*, T*, const T*, int, int,   \
                                       unsigned long long*);                                      \

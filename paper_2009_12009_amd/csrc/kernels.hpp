@@ -53,11 +53,17 @@ struct Shape {
 // other colour is left without the correction and must be overwritten (the
 // next half-sweep) before anything reads it.  phi's face ghosts must be
 // current without the correction, ec's face ghosts current.
+// With rf (zero_guess only, rhs_ng 0): the level's right-hand side is first
+// restricted here, rout = R rf, from the finer level's residual rf (no
+// ghosts) on boxes finfo, box b of this level being the coarsening of finer
+// box b; each lane stores both cells of its x-pair and smooths with the
+// active one.  rhs is then not read.
 template <typename T>
 hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                        const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng, int colour,
                        int zero_guess, const WtBox* wtb = nullptr, const WtEntry* wte = nullptr,
-                       const BoxInfo* cinfo = nullptr, const T* ec = nullptr);
+                       const BoxInfo* cinfo = nullptr, const T* ec = nullptr,
+                       const BoxInfo* finfo = nullptr, const T* rf = nullptr, T* rout = nullptr);
 
 // One full red/black sweep, both colours in one pass, out of place: pout
 // receives the result of a red half-sweep followed by a black half-sweep of

@@ -87,6 +87,11 @@ struct Level {
   IBox domain;
   bool merged = false;
   bool buf = false;  // every box array < 4 GiB (32-bit buffer offsets)
+  // box b is the coarsening of box b of the next finer level (level >= 1)
+  bool coarsened_1to1 = false;
+  // the restriction into this level may fold into its first half-sweep
+  // (level 1: only where the tuner measured the folded kernel faster)
+  bool fold_rs = true;
   int nbox = 0;
   double h[3];
   int64_t ncell = 0, n_g1 = 0, n_g0 = 0, n_f[3] = {0, 0, 0};
@@ -512,6 +517,21 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
   // parent links: box b of level l -> box of level l+1 holding coarsen(b)
   for (size_t l = 0; l + 1 < s->L.size(); ++l)
     for (int b = 0; b < s->L[l].nbox; ++b) s->L[l].info[b].parent = s->L[l + 1].merged ? 0 : b;
+  for (size_t l = 1; l < s->L.size(); ++l) {
+    const Level& f = s->L[l - 1];
+    Level& c = s->L[l];
+    bool one = !c.merged && c.nbox == f.nbox;
+    for (int b = 0; one && b < c.nbox; ++b)
+      for (int d = 0; d < 3; ++d)
+        one = one && f.info[b].parent == b && f.info[b].lo[d] % 2 == 0 &&
+              f.info[b].hi[d] % 2 != 0 && c.info[b].lo[d] * 2 == f.info[b].lo[d] &&
+              c.info[b].hi[d] * 2 + 1 == f.info[b].hi[d];
+    c.coarsened_1to1 = one;
+    // level 1 restricts the finest residual, read from HBM: there the folded
+    // kernel costs about what the two passes cost together (FP64 a few per
+    // cent more), so it runs only where the tuner measured it faster
+    c.fold_rs = l >= 2;
+  }
 
   // bottom tables: cells of the bottom level enumerated box by box, x fastest
   Level& bl = s->L.back();
@@ -881,9 +901,12 @@ int smooth_fused(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, cons
 template <typename T>
 int smooth(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, const T* rhs, int rhs_ng,
            int sweeps, bool zero_first, bool prof, bool reverse = false,
-           bool ghosts_current = false, const BoxInfo* cinfo = nullptr, const T* ec = nullptr) {
+           bool ghosts_current = false, const BoxInfo* cinfo = nullptr, const T* ec = nullptr,
+           const BoxInfo* finfo = nullptr, const T* rf = nullptr, T* rout = nullptr) {
   if (ec && (!lv.wt || lv.fused || zero_first || sweeps < 1))
     return fail(MG_ERR_ARG, "folded interpolation on a level without write-through");
+  if (rf && (!zero_first || lv.fused || reverse || sweeps < 1 || rhs_ng != 0 || rout != rhs))
+    return fail(MG_ERR_ARG, "folded restriction outside a zero-guess smoothing");
   if (lv.fused && !reverse)
     return smooth_fused<T>(s, lv, op, phi, rhs, rhs_ng, sweeps, zero_first, prof);
   const int c0 = reverse ? 1 : 0;
@@ -903,7 +926,8 @@ int smooth(mg_solver* s, Level& lv, const StencilArgs<T>& op, T* phi, const T* r
     } else {
       ProfScope ps(s, 0, prof);
       HIPTRY(launch_gsrb<T>(s->st, lv.d_gsrb, (int)lv.t_gsrb.size(), lv.s_gsrb, op, phi, rhs,
-                            rhs_ng, c0, zg ? 1 : 0, wtb, wte));
+                            rhs_ng, c0, zg ? 1 : 0, wtb, wte, nullptr, nullptr,
+                            zg ? finfo : nullptr, zg ? rf : nullptr, zg ? rout : nullptr));
     }
     if (!lv.wt && (rc = exchange<T>(s, lv, phi, prof))) return rc;
     {
@@ -927,14 +951,32 @@ bool fold_interp(const mg_solver* s, size_t l) {
   return f.wt && c.wt && !f.fused && !c.fused;
 }
 
-// Coarse levels l >= lstart in correction form (zero initial guess).
+// Whether the restriction into level l (>= 1) folds into level l's first
+// pre-smoothing half-sweep, which with a zero initial guess reads only the
+// right-hand side at its own cell: the level is smoothed (not the bottom)
+// by half-sweeps from zero, and its boxes are the finer boxes coarsened one
+// to one.
+bool fold_restrict(const mg_solver* s, size_t l) {
+  if (!s->opts.restrict_fold || l == 0 || l + 1 >= s->L.size() || s->opts.nu1 < 1) return false;
+  const Level& c = s->L[l];
+  return c.coarsened_1to1 && (c.fold_rs || s->opts.restrict_fold == 2) && !c.fused;
+}
+
+// Coarse levels l >= lstart in correction form (zero initial guess).  rf:
+// the finer level's residual, restricted here into this level's rhs.
 template <typename T>
-int coarse_cycle(mg_solver* s, size_t l, bool f32) {
+int coarse_cycle(mg_solver* s, size_t l, bool f32, const T* rf = nullptr) {
   Level& lv = s->L[l];
   LevelData<T> D = ldata<T>(lv, f32);
   const StencilArgs<T> op = stencil_of<T>(s, lv, f32);
   const bool prof = l == 0;
   int rc;
+  const bool rs = rf && fold_restrict(s, l);
+  if (rf && !rs) {
+    const Level& fl = s->L[l - 1];
+    HIPTRY(launch_restrict<T>(s->st, fl.d_rst, (int)fl.t_rst.size(), fl.s_rst, fl.d_info,
+                              lv.d_info, rf, D.rhs));
+  }
   if (l + 1 == s->L.size()) {
     const BottomTables bt = bottom_tables(s);
     const T* diag = f32 ? (const T*)s->bdiag32 : (const T*)s->bdiag64;
@@ -953,7 +995,10 @@ int coarse_cycle(mg_solver* s, size_t l, bool f32) {
   if (s->opts.nu1 == 0)
     HIPTRY(launch_zero_valid<T>(s->st, lv.d_cell, (int)lv.t_cell.size(), lv.s_cell, lv.d_info, D.e,
                                 1));
-  if ((rc = smooth<T>(s, lv, op, D.e, D.rhs, 0, s->opts.nu1, s->opts.nu1 > 0, prof))) return rc;
+  if ((rc = smooth<T>(s, lv, op, D.e, D.rhs, 0, s->opts.nu1, s->opts.nu1 > 0, prof, false, false,
+                      nullptr, nullptr, rs ? s->L[l - 1].d_info : nullptr, rs ? rf : nullptr,
+                      rs ? D.rhs : nullptr)))
+    return rc;
   // write-through smoothing leaves the face ghosts current
   if (!(lv.wt && s->opts.nu1 > 0) && (rc = exchange<T>(s, lv, D.e, prof))) return rc;
   {
@@ -963,18 +1008,14 @@ int coarse_cycle(mg_solver* s, size_t l, bool f32) {
   }
   Level& cl = s->L[l + 1];
   LevelData<T> C = ldata<T>(cl, f32);
-  {
-    ProfScope ps(s, 3, prof);
-    HIPTRY(launch_restrict<T>(s->st, lv.d_rst, (int)lv.t_rst.size(), lv.s_rst, lv.d_info,
-                              cl.d_info, D.r, C.rhs));
-  }
+  // the coarser levels, starting with the restriction of D.r
   if (l == 0 && s->opts.use_graph) {
     hipGraphExec_t g = f32 ? s->graph32 : s->graph64;
     ProfScope ps(s, 5, true);
     HIPTRY(hipGraphLaunch(g, s->st));
   } else {
     ProfScope ps(s, 5, l == 0);
-    if ((rc = coarse_cycle<T>(s, l + 1, f32))) return rc;
+    if ((rc = coarse_cycle<T>(s, l + 1, f32, D.r))) return rc;
   }
   if (fold_interp(s, l))
     return smooth<T>(s, lv, op, D.e, D.rhs, 0, s->opts.nu2, false, prof, s->opts.krylov != 0,
@@ -997,7 +1038,8 @@ int capture_graphs(mg_solver* s) {
   HIPTRY(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
   const bool saved = s->profile;
   s->profile = false;
-  int rc = f32 ? coarse_cycle<float>(s, 1, true) : coarse_cycle<double>(s, 1, false);
+  int rc = f32 ? coarse_cycle<float>(s, 1, true, s->L[0].r32)
+               : coarse_cycle<double>(s, 1, false, s->L[0].r64);
   s->profile = saved;
   hipError_t e = hipStreamEndCapture(s->st, &g);
   if (rc) return rc;
@@ -1044,17 +1086,13 @@ int vcycle64(mg_solver* s, double* phi, const double* rhs, int rhs_ng) {
                                             phi, rhs, rhs_ng, l0.r64, nullptr, 0)));
   }
   Level& l1 = s->L[1];
-  {
-    ProfScope ps(s, 3, true);
-    HIPTRY(launch_restrict<double>(s->st, l0.d_rst, (int)l0.t_rst.size(), l0.s_rst, l0.d_info,
-                                   l1.d_info, l0.r64, l1.rhs64));
-  }
+  // the coarser levels, starting with the restriction of the residual
   if (s->opts.use_graph) {
     ProfScope ps(s, 5, true);
     HIPTRY(hipGraphLaunch(s->graph64, s->st));
   } else {
     ProfScope ps(s, 5, true);
-    if ((rc = coarse_cycle<double>(s, 1, false))) return rc;
+    if ((rc = coarse_cycle<double>(s, 1, false, l0.r64))) return rc;
   }
   if (fold_interp(s, 0))
     return smooth<double>(s, l0, op, phi, rhs, rhs_ng, s->opts.nu2, false, true, false, true,
@@ -1329,6 +1367,40 @@ int tune_level1(mg_solver* s, bool f32, T* phi, Shape* best_g, Shape* best_c, fl
   return apply_shape(s, *best_c, false, 1);
 }
 
+// Restriction into level 1 plus its zero-guess half-sweep: two passes, or
+// the half-sweep that restricts as it goes (mean time of one pair / one).
+template <typename T>
+int time_rfold(mg_solver* s, bool f32, bool fold, T* phi, float* ms) {
+  Level& fl = s->L[0];
+  Level& cl = s->L[1];
+  const LevelData<T> F = ldata<T>(fl, f32), C = ldata<T>(cl, f32);
+  const StencilArgs<T> op = stencil_of<T>(s, cl, f32);
+  const WtBox* wtb = cl.wt ? cl.d_wtbox : nullptr;
+  const WtEntry* wte = cl.wt ? cl.d_wt : nullptr;
+  const int nt = (int)cl.t_gsrb.size();
+  auto one = [&]() -> hipError_t {
+    if (fold)
+      return launch_gsrb<T>(s->st, cl.d_gsrb, nt, cl.s_gsrb, op, phi, C.rhs, 0, 0, 1, wtb, wte,
+                            nullptr, nullptr, fl.d_info, F.r, C.rhs);
+    hipError_t e = launch_restrict<T>(s->st, fl.d_rst, (int)fl.t_rst.size(), fl.s_rst, fl.d_info,
+                                      cl.d_info, F.r, C.rhs);
+    if (e != hipSuccess) return e;
+    return launch_gsrb<T>(s->st, cl.d_gsrb, nt, cl.s_gsrb, op, phi, C.rhs, 0, 0, 1, wtb, wte);
+  };
+  hipEvent_t a = take_event(s), b = take_event(s);
+  for (int w = 0; w < 2; ++w) HIPTRY(one());
+  HIPTRY(hipEventRecord(a, s->st));
+  const int reps = 24;
+  for (int w = 0; w < reps; ++w) HIPTRY(one());
+  HIPTRY(hipEventRecord(b, s->st));
+  HIPTRY(hipEventSynchronize(b));
+  float t;
+  HIPTRY(hipEventElapsedTime(&t, a, b));
+  *ms = t / reps;
+  s->ev_used -= 2;
+  return MG_OK;
+}
+
 int autotune(mg_solver* s) {
   const bool f32 = s->opts.precision == MG_PREC_F32_REFINE;
   Level& l0 = s->L[0];
@@ -1337,8 +1409,13 @@ int autotune(mg_solver* s) {
   const std::string ks = tune_key(s, "sweep", f32);
   const bool t1 = tune_level1_ok(s);
   const std::string kg1 = t1 ? tune_key(s, "gsrb", f32, 1) : "", kr1 = t1 ? tune_key(s, "resid", f32, 1) : "";
+  // whether the restriction into level 1 folds (entry u = 1)
+  const bool tf = t1 && s->L[1].coarsened_1to1 && s->opts.restrict_fold == 1 && s->opts.nu1 >= 1;
+  const std::string kf = tf ? tune_key(s, "rfold", f32, 1) : "";
   int rc;
   if (s->opts.tune == 1) {
+    auto itf = tf ? cache.find(kf) : cache.end();
+    if (itf != cache.end()) s->L[1].fold_rs = itf->second.u == 1;
     // level 1 entries (keyed by the level's own box shape and count)
     for (int g = 0; t1 && g < 2; ++g) {
       auto it = cache.find(g ? kg1 : kr1);
@@ -1442,6 +1519,25 @@ int autotune(mg_solver* s) {
     cache[kg1] = g1;
     cache[kr1] = c1;
   }
+  float tsep = 0, tfold = 0;
+  if (tf) {
+    // with level 1's tiles as chosen above; best of three interleaved
+    float a = 1e30f, b = 1e30f, t;
+    for (int r = 0; r < 3; ++r) {
+      rc = f32 ? time_rfold<float>(s, true, false, (float*)s->tune_scratch, &t)
+               : time_rfold<double>(s, false, false, s->tune_scratch, &t);
+      if (rc) return rc;
+      a = std::min(a, t);
+      rc = f32 ? time_rfold<float>(s, true, true, (float*)s->tune_scratch, &t)
+               : time_rfold<double>(s, false, true, s->tune_scratch, &t);
+      if (rc) return rc;
+      b = std::min(b, t);
+    }
+    tsep = a;
+    tfold = b;
+    s->L[1].fold_rs = tfold < tsep;
+    cache[kf] = Shape{1, 1, 1, s->L[1].fold_rs ? 1 : 0, 0};
+  }
   if (l0.fused) {
     if ((rc = apply_sweep_shape(s, best_w))) return rc;
     // a fused sweep also saves nothing on exchanges, so it must beat the two
@@ -1458,8 +1554,10 @@ int autotune(mg_solver* s) {
             best_c.tz, best_c.u, tr, best_w.lx, best_w.ly, best_w.tz, tw,
             l0.fused ? "fused" : "half-sweeps");
   if (s->opts.verbose && t1)
-    fprintf(stderr, "amrmg tune level 1: gsrb %dx%dx%d u%d wp%d %.4f ms, resid %dx%dx%d u%d %.4f ms\n",
-            g1.lx, g1.ly, g1.tz, g1.u, g1.wp, tg1, c1.lx, c1.ly, c1.tz, c1.u, tr1);
+    fprintf(stderr,
+            "amrmg tune level 1: gsrb %dx%dx%d u%d wp%d %.4f ms, resid %dx%dx%d u%d %.4f ms, "
+            "restriction + first half-sweep %.4f ms, folded %.4f ms\n",
+            g1.lx, g1.ly, g1.tz, g1.u, g1.wp, tg1, c1.lx, c1.ly, c1.tz, c1.u, tr1, tsep, tfold);
   cache[kg] = best_g;
   cache[kr] = best_c;
   write_cache(cache);
@@ -2111,6 +2209,7 @@ void mg_default_opts(mg_opts_t* o) {
   o->ghost_write = 1;
   o->interp_fold = 1;
   o->bottom_solver = 0;
+  o->restrict_fold = 1;
 }
 
 static int check_opts(const mg_opts_t* o) {
@@ -2126,6 +2225,7 @@ static int check_opts(const mg_opts_t* o) {
   if (o->ghost_write != 0 && o->ghost_write != 1) return fail(MG_ERR_ARG, "bad ghost_write");
   if (o->interp_fold != 0 && o->interp_fold != 1) return fail(MG_ERR_ARG, "bad interp_fold");
   if (o->bottom_solver != 0 && o->bottom_solver != 1) return fail(MG_ERR_ARG, "bad bottom_solver");
+  if (o->restrict_fold < 0 || o->restrict_fold > 2) return fail(MG_ERR_ARG, "bad restrict_fold");
   return MG_OK;
 }
 

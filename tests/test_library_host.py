@@ -36,11 +36,11 @@ def test_struct_sizes_match_header_layout():
     L = P._lib
     assert C.sizeof(L.MgBox) == 24
     assert C.sizeof(L.MgGeom) == 24 + 48 + 12 + 4  # trailing padding to 8
-    # fused_min_edge, krylov, ghost_write, interp_fold, bottom_solver, pad
-    assert C.sizeof(L.MgOpts) == 10 * 4 + 8 + 5 * 4 + 4
+    # fused_min_edge, krylov, ghost_write, interp_fold, bottom_solver, restrict_fold
+    assert C.sizeof(L.MgOpts) == 10 * 4 + 8 + 6 * 4
     o = L.default_opts()
     assert (o.nu1, o.nu2, o.fused_min_edge, o.krylov, o.ghost_write, o.interp_fold,
-            o.bottom_solver, o.bottom_rel_tol) == (2, 2, 0, 0, 1, 1, 0, 1e-4)
+            o.bottom_solver, o.restrict_fold, o.bottom_rel_tol) == (2, 2, 0, 0, 1, 1, 0, 1, 1e-4)
     assert C.sizeof(L.MgCopyTag) == 8 + 24 + 12
 
 
@@ -107,7 +107,7 @@ def test_workspace_too_small_rejected_before_any_device_call():
                            C.byref(opts), C.c_void_p(4100), 1 << 40, None, C.byref(h))
     assert code == L.MG_ERR_WORKSPACE  # misaligned
     for field, bad in (("interp_fold", 2), ("ghost_write", -1), ("krylov", 2),
-                       ("bottom_solver", 2)):
+                       ("bottom_solver", 2), ("restrict_fold", 3)):
         o2 = L.default_opts()
         setattr(o2, field, bad)
         size = C.c_size_t(0)

@@ -315,6 +315,10 @@ WT_CASES = [
     # 192^3: a half-sweep's arrays (340 MB) exceed the last-level cache, so the
     # write-through path loads through buffer descriptors
     ("lognormal192_27boxes_buffer_loads", lambda: W.config_lognormal(192, 64), None, {}),
+    # 256^3 FP32: the FP32 arrays stream too, and the folded half-sweep then
+    # also loads the coarse correction through a buffer descriptor
+    ("lognormal256_64boxes_f32_buffer_loads", lambda: W.config_lognormal(256, 64), None,
+     dict(precision=1)),
 ]
 
 

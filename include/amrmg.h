@@ -347,7 +347,9 @@ int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rh
  * fused sweep of level 0 (lx x ly x tz cells per work-group of lx/2*ly lanes;
  * (lx, ly) in {(64,4), (64,8), (32,8), (32,16)}, tz in {4,8,16,32}; unroll
  * ignored; MG_ERR_ARG when level 0 does not use fused sweeps).  Every
- * shape gives bitwise-identical results. */
+ * shape gives bitwise-identical V-cycle solves; with krylov = 1 the dot
+ * p.q is summed per tile of kernel 1, whose shape then changes the last
+ * bits of the result. */
 int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, int32_t tz,
                       int32_t unroll);
 

@@ -360,6 +360,50 @@ def test_ghost_write_through_bitwise_equal_exchanges(name, make, boxes, extra):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("variant", ["f64", "f32_refine", "f64_mgpcg"])
+def test_c1_bench_configuration(variant, monkeypatch):
+    """256^3 in the benchmark's launch configuration (aggregated hierarchy,
+    tiles searched at set-up, coarse levels replayed from the graph, folded
+    restriction chosen by the tuner): the oracle's operator recomputes
+    f - A phi on every cell.  V-cycle solves keep the bits of the default
+    tiling; MG-PCG sums p.q per residual tile, so there the residual's tile
+    shape moves the last bits and both solutions are checked instead."""
+    print(f"[solve] C1 256^3 bench configuration {variant}", flush=True)
+    monkeypatch.delenv("AMRMG_TUNE_CACHE", raising=False)
+    P = lib()
+    cfg = W.config_c1()
+    n, boxes = cfg["n"], cfg["boxes"]
+    f_boxes = W.scatter_cells(cfg["rhs"], boxes)
+    rhs = P.MultiFab.from_numpy(boxes, f_boxes, 0)
+    opts = dict(aggregate=1, precision=1 if variant == "f32_refine" else 0,
+                krylov=1 if variant.endswith("mgpcg") else 0)
+    sols, infos = [], []
+    for tune in (2, 0):
+        s = gpu_solver(cfg, opts=dict(opts, tune=tune))
+        phi = s.cell_mf(1, fill=0.0)
+        info = s.solve(phi, rhs, 1e-10)
+        torch.cuda.synchronize()
+        assert info["converged"] and info["nlevels"] == 7
+        infos.append(info)
+        sols.append(phi.to_numpy())
+        s.close()
+        del phi
+    print(f"C1 {variant}: {infos[0]['iters']} iterations, {infos[0]['solve_ms']:.1f} ms")
+    assert infos[0]["iters"] == infos[1]["iters"]
+    pcg = variant.endswith("mgpcg")
+    if not pcg:
+        assert all(np.array_equal(a[1:-1, 1:-1, 1:-1], b[1:-1, 1:-1, 1:-1])
+                   for a, b in zip(sols[0], sols[1]))
+    lev = oracle_level(cfg)
+    normf = max(float(np.max(np.abs(x))) for x in f_boxes)
+    for sol in sols[:2 if pcg else 1]:
+        oA = O.apply_op(lev, sol)
+        r = max(float(np.max(np.abs(fb - a))) for fb, a in zip(f_boxes, oA))
+        assert r <= 1e-10 * normf * (1 + 1e-3)
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.gpu
 def test_error_paths():
     print("[solve] error paths", flush=True)
     P = lib()

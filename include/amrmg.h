@@ -329,6 +329,13 @@ int mg_num_levels(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
 int mg_profile(mg_solver_t* s, int32_t enable);
 int mg_kernel_stats(mg_solver_t* s, int32_t family, double* total_ms, int64_t* launches);
 
+/* dst = src over `bytes` bytes with the library's own streaming kernel (one
+ * 16-byte load and store per lane, no solver state): the achievable HBM rate
+ * beside the kernels' rooflines, and the reference copy of known size for
+ * the HBM traffic counters.  Device pointers, 16-byte aligned, bytes a
+ * multiple of 16 (else MG_ERR_ARG).  Asynchronous on hip_stream. */
+int mg_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
 /* Time one level-0 smoother half-sweep launched alone `reps` times on the
  * solver's stream (colour alternating) and return the mean duration; uses
  * phi/rhs as the data.  For roofline measurements. */

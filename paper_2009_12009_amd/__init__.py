@@ -15,6 +15,7 @@ from .solver import (  # noqa: F401
     fill_boundary,
     num_levels,
     release_caches,
+    stream_copy,
     workspace_bytes,
 )
 from .autograd import MGSolve, mg_solve  # noqa: F401

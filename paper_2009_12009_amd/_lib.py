@@ -99,6 +99,7 @@ SIGNATURES = {
     "mg_kernel_stats": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_int64)]),
     "mg_time_smoother": (C.c_int, [C.c_void_p, P(MgMultiFab), P(MgMultiFab), C.c_int32,
                                    P(C.c_double)]),
+    "mg_stream_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "mg_get_tile_shape": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32)]),
     "mg_set_tile_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                     C.c_int32]),

@@ -1153,6 +1153,14 @@ __global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
   if (i < n) p[i] = v;
 }
 
+// Plain device copy, one 16-byte element per lane (the achievable streaming
+// rate and the reference for the HBM traffic counters).
+__global__ void __launch_bounds__(256)
+    k_stream_copy(const uint4* __restrict__ in, uint4* __restrict__ out, long long n) {
+  const long long i = blockIdx.x * 256ll + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
 template <typename TI, typename TO>
 __global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -2086,6 +2094,15 @@ template <typename TI, typename TO>
 hipError_t launch_convert(hipStream_t st, const TI* in, TO* out, long long n) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_convert<TI, TO>), dim3(grid_for(n)), dim3(256), 0, st, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(hipStream_t st, const void* in, void* out, long long n16) {
+  if (n16 <= 0) return hipSuccess;
+  const long long blocks = (n16 + 255) / 256;
+  if (blocks > 0x7fffffffll) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<const uint4*>(in), static_cast<uint4*>(out), n16);
   return hipGetLastError();
 }
 

@@ -191,6 +191,8 @@ hipError_t launch_fill_boundary(hipStream_t st, const FbTag* tags, const FbChunk
 hipError_t launch_fill_u64(hipStream_t st, unsigned long long* p, int n, unsigned long long v);
 template <typename TI, typename TO>
 hipError_t launch_convert(hipStream_t st, const TI* in, TO* out, long long n);
+// out = in over n16 16-byte elements (both 16-byte aligned), one per lane.
+hipError_t launch_stream_copy(hipStream_t st, const void* in, void* out, long long n16);
 hipError_t launch_scale_faces(hipStream_t st, const double* in, double* out, long long n,
                               double v_if_null);
 

@@ -1130,6 +1130,36 @@ int end_call(mg_solver* s) {
   return MG_OK;
 }
 
+// One entry-point call: the solver stream waits for the caller's stream on
+// entry, and on every exit (error returns included) the caller's stream waits
+// for everything the call enqueued, so memory the caller frees or reuses
+// after an error is not still being written by the call's kernels.  On an
+// error exit the ordering is best effort and keeps the message of the failure
+// that caused the exit.
+class CallScope {
+ public:
+  explicit CallScope(mg_solver* s) : s_(s), rc_(begin_call(s)) {
+    if (rc_ != MG_OK) s_ = nullptr;
+  }
+  ~CallScope() {
+    if (s_ && hipEventRecord(s_->ev_out, s_->st) == hipSuccess)
+      (void)hipStreamWaitEvent(s_->user, s_->ev_out, 0);
+  }
+  CallScope(const CallScope&) = delete;
+  CallScope& operator=(const CallScope&) = delete;
+  int rc() const { return rc_; }
+  // The normal exit: the ordering's own errors are reported.
+  int finish() {
+    mg_solver* s = s_;
+    s_ = nullptr;
+    return s ? end_call(s) : MG_OK;
+  }
+
+ private:
+  mg_solver* s_;
+  int rc_;
+};
+
 // ---------------------------------------------------------------------------
 // Tile-shape tuning of the level-0 smoother and residual.
 
@@ -2318,14 +2348,17 @@ int mg_create(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom, const 
   HIPTRY(hipHostMalloc((void**)&s->h_norm, sizeof(unsigned long long) * (kNormSlot + 8),
                        hipHostMallocDefault));
   s->h_iters = reinterpret_cast<int*>(s->h_norm + kNormSlot);
-  if ((rc = begin_call(s.get()))) return rc;
-  if ((rc = upload_tables(s.get()))) return rc;
-  if ((rc = setup_coefficients(s.get(), acoef, bcoef))) return rc;
-  if ((rc = coarsen_all(s.get()))) return rc;
-  if ((rc = autotune(s.get()))) return rc;
-  if ((rc = capture_graphs(s.get()))) return rc;
-  HIPTRY(hipStreamSynchronize(s->st));
-  if ((rc = end_call(s.get()))) return rc;
+  {
+    CallScope call(s.get());
+    if ((rc = call.rc())) return rc;
+    if ((rc = upload_tables(s.get()))) return rc;
+    if ((rc = setup_coefficients(s.get(), acoef, bcoef))) return rc;
+    if ((rc = coarsen_all(s.get()))) return rc;
+    if ((rc = autotune(s.get()))) return rc;
+    if ((rc = capture_graphs(s.get()))) return rc;
+    HIPTRY(hipStreamSynchronize(s->st));
+    if ((rc = call.finish())) return rc;
+  }
   s->setup_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = s.release();
@@ -2342,10 +2375,11 @@ int mg_set_coefficients(mg_solver_t* s, const mg_multifab_t* acoef,
   if (bcoef)
     for (int d = 0; d < 3; ++d)
       if ((rc = check_mf(s, bcoef[d], MG_F64, 0, 0, d, "bcoef"))) return rc;
-  if ((rc = begin_call(s))) return rc;
+  CallScope call(s);
+  if ((rc = call.rc())) return rc;
   if ((rc = setup_coefficients(s, acoef, bcoef))) return rc;
   if ((rc = coarsen_all(s))) return rc;
-  return end_call(s);
+  return call.finish();
 }
 
 int mg_set_coefficients_global(mg_solver_t* s, const void* acoef_global,
@@ -2354,13 +2388,15 @@ int mg_set_coefficients_global(mg_solver_t* s, const void* acoef_global,
   if ((acoef_global != nullptr) != s->has_a)
     return fail(MG_ERR_ARG, "acoef presence must match mg_create");
   if (!bface_global) return fail(MG_ERR_ARG, "bface_global is null");
+  for (int d = 0; d < 3; ++d)
+    if (!bface_global[d]) return fail(MG_ERR_ARG, "bface_global entry is null");
   int rc;
-  if ((rc = begin_call(s))) return rc;
+  CallScope call(s);
+  if ((rc = call.rc())) return rc;
   Level& l0 = s->L[0];
   const int dlo[3] = {s->domain.lo[0], s->domain.lo[1], s->domain.lo[2]};
   const int dn[3] = {ext(s->domain, 0), ext(s->domain, 1), ext(s->domain, 2)};
   for (int d = 0; d < 3; ++d) {
-    if (!bface_global[d]) return fail(MG_ERR_ARG, "bface_global entry is null");
     HIPTRY(launch_scatter_faces(s->st, l0.d_info, l0.nbox, d, dlo, dn,
                                 (const double*)bface_global[d], l0.b64[d], is_log ? 1 : 0,
                                 l0.max_faces));
@@ -2369,7 +2405,7 @@ int mg_set_coefficients_global(mg_solver_t* s, const void* acoef_global,
     HIPTRY(launch_scatter_cells(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info, dlo,
                                 dn, (const double*)acoef_global, l0.a64));
   if ((rc = coarsen_all(s))) return rc;
-  return end_call(s);
+  return call.finish();
 }
 
 // Preconditioned conjugate gradients on level 0 with one symmetric V-cycle
@@ -2505,7 +2541,8 @@ int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, doubl
   if ((rc = check_mf(s, phi, MG_F64, 1, 1, -1, "phi"))) return rc;
   if ((rc = check_mf(s, rhs, MG_F64, 0, 1, -1, "rhs"))) return rc;
   if (!(rel_tol >= 0) || !(abs_tol >= 0)) return fail(MG_ERR_ARG, "negative tolerance");
-  if ((rc = begin_call(s))) return rc;
+  CallScope call(s);
+  if ((rc = call.rc())) return rc;
   Level& l0 = s->L[0];
   double* P = static_cast<double*>(phi->data);
   const double* F = static_cast<const double*>(rhs->data);
@@ -2523,10 +2560,7 @@ int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, doubl
   double normf;
   if ((rc = read_norm(s, 0, &normf))) return rc;
   int status = MG_OK;
-  if (!std::isfinite(normf)) {
-    end_call(s);
-    return fail(MG_ERR_NAN, "rhs holds a non-finite value");
-  }
+  if (!std::isfinite(normf)) return fail(MG_ERR_NAN, "rhs holds a non-finite value");
   if (normf == 0.0) {
     HIPTRY(launch_zero_valid<double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info,
                                      P, 1));
@@ -2603,7 +2637,7 @@ int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, doubl
   HIPTRY(hipMemcpyAsync(s->h_iters, s->d_iters, sizeof(int), hipMemcpyDeviceToHost, s->st));
   HIPTRY(hipStreamSynchronize(s->st));
   inf.bottom_iters = *s->h_iters;
-  if ((rc = end_call(s))) return rc;
+  if ((rc = call.finish())) return rc;
   inf.solve_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = inf;
@@ -2615,24 +2649,37 @@ int mg_apply(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* out) {
   int rc;
   if ((rc = check_mf(s, phi, MG_F64, 1, 1, -1, "phi"))) return rc;
   if ((rc = check_mf(s, out, MG_F64, 0, 0, -1, "out"))) return rc;
-  if ((rc = begin_call(s))) return rc;
+  CallScope call(s);
+  if ((rc = call.rc())) return rc;
   Level& l0 = s->L[0];
   if ((rc = exchange<double>(s, l0, (double*)phi->data, false))) return rc;
   HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell,
                                           stencil_of<double>(s, l0, false),
                                           (const double*)phi->data, nullptr, 0,
                                           (double*)out->data, nullptr, 1)));
-  return end_call(s);
+  return call.finish();
 }
 
-static int face_grad_common(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam) {
+static int face_grad_check(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam) {
   int rc;
   if ((rc = check_mf(s, phi, MG_F64, 1, 1, -1, "phi"))) return rc;
   if ((rc = check_mf(s, lam, MG_F64, 1, 1, -1, "lam"))) return rc;
-  if ((rc = begin_call(s))) return rc;
+  return MG_OK;
+}
+
+// Ghost exchange of phi and lambda, then the face-gradient launches.
+static int face_grad_run(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam, void* const* out,
+                         int mode) {
+  int rc;
   Level& l0 = s->L[0];
   if ((rc = exchange<double>(s, l0, (double*)phi->data, false))) return rc;
   if ((rc = exchange<double>(s, l0, (double*)lam->data, false))) return rc;
+  const int dlo[3] = {s->domain.lo[0], s->domain.lo[1], s->domain.lo[2]};
+  const int dn[3] = {ext(s->domain, 0), ext(s->domain, 1), ext(s->domain, 2)};
+  for (int d = 0; d < 3; ++d)
+    HIPTRY(launch_face_grad(s->st, l0.d_info, l0.nbox, d, stencil_of<double>(s, l0, false),
+                            (const double*)phi->data, (const double*)lam->data, (double*)out[d],
+                            mode, dlo, dn, s->periodic[d], l0.max_faces));
   return MG_OK;
 }
 
@@ -2642,15 +2689,12 @@ int mg_face_grad_logb(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam,
   int rc;
   for (int d = 0; d < 3; ++d)
     if ((rc = check_mf(s, grad[d], MG_F64, 0, 0, d, "grad"))) return rc;
-  if ((rc = face_grad_common(s, phi, lam))) return rc;
-  Level& l0 = s->L[0];
-  const int dlo[3] = {s->domain.lo[0], s->domain.lo[1], s->domain.lo[2]};
-  const int dn[3] = {ext(s->domain, 0), ext(s->domain, 1), ext(s->domain, 2)};
-  for (int d = 0; d < 3; ++d)
-    HIPTRY(launch_face_grad(s->st, l0.d_info, l0.nbox, d, stencil_of<double>(s, l0, false),
-                            (const double*)phi->data, (const double*)lam->data,
-                            (double*)grad[d]->data, 0, dlo, dn, s->periodic[d], l0.max_faces));
-  return end_call(s);
+  if ((rc = face_grad_check(s, phi, lam))) return rc;
+  void* out[3] = {grad[0]->data, grad[1]->data, grad[2]->data};
+  CallScope call(s);
+  if ((rc = call.rc())) return rc;
+  if ((rc = face_grad_run(s, phi, lam, out, 0))) return rc;
+  return call.finish();
 }
 
 int mg_face_grad_logb_global(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam,
@@ -2659,15 +2703,11 @@ int mg_face_grad_logb_global(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* 
   for (int d = 0; d < 3; ++d)
     if (!grad_global[d]) return fail(MG_ERR_ARG, "null gradient array");
   int rc;
-  if ((rc = face_grad_common(s, phi, lam))) return rc;
-  Level& l0 = s->L[0];
-  const int dlo[3] = {s->domain.lo[0], s->domain.lo[1], s->domain.lo[2]};
-  const int dn[3] = {ext(s->domain, 0), ext(s->domain, 1), ext(s->domain, 2)};
-  for (int d = 0; d < 3; ++d)
-    HIPTRY(launch_face_grad(s->st, l0.d_info, l0.nbox, d, stencil_of<double>(s, l0, false),
-                            (const double*)phi->data, (const double*)lam->data,
-                            (double*)grad_global[d], 1, dlo, dn, s->periodic[d], l0.max_faces));
-  return end_call(s);
+  if ((rc = face_grad_check(s, phi, lam))) return rc;
+  CallScope call(s);
+  if ((rc = call.rc())) return rc;
+  if ((rc = face_grad_run(s, phi, lam, grad_global, 1))) return rc;
+  return call.finish();
 }
 
 int mg_copy_valid(mg_solver_t* s, const mg_multifab_t* src, mg_multifab_t* dst) {
@@ -2675,11 +2715,12 @@ int mg_copy_valid(mg_solver_t* s, const mg_multifab_t* src, mg_multifab_t* dst) 
   int rc;
   if ((rc = check_mf(s, src, MG_F64, 0, 1, -1, "src"))) return rc;
   if ((rc = check_mf(s, dst, MG_F64, 0, 1, -1, "dst"))) return rc;
-  if ((rc = begin_call(s))) return rc;
+  CallScope call(s);
+  if ((rc = call.rc())) return rc;
   Level& l0 = s->L[0];
   HIPTRY(launch_copy_valid(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, l0.d_info,
                            (const double*)src->data, src->ngrow, (double*)dst->data, dst->ngrow));
-  return end_call(s);
+  return call.finish();
 }
 
 void mg_destroy(mg_solver_t* s) {
@@ -2722,13 +2763,23 @@ int mg_kernel_stats(mg_solver_t* s, int32_t family, double* total_ms, int64_t* l
   return MG_OK;
 }
 
+int mg_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (!dst || !src || bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 ||
+      reinterpret_cast<uintptr_t>(src) % 16)
+    return fail(MG_ERR_ARG, "mg_stream_copy: null pointer, or size or address not 16-byte aligned");
+  HIPTRY(launch_stream_copy(static_cast<hipStream_t>(hip_stream), src, dst,
+                            static_cast<long long>(bytes / 16)));
+  return MG_OK;
+}
+
 int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, int32_t reps,
                      double* mean_ms) {
   if (!s || !mean_ms || reps <= 0) return fail(MG_ERR_ARG, "bad argument");
   int rc;
   if ((rc = check_mf(s, phi, MG_F64, 1, 1, -1, "phi"))) return rc;
   if ((rc = check_mf(s, rhs, MG_F64, 0, 1, -1, "rhs"))) return rc;
-  if ((rc = begin_call(s))) return rc;
+  CallScope call(s);
+  if ((rc = call.rc())) return rc;
   Level& l0 = s->L[0];
   const StencilArgs<double> op = stencil_of<double>(s, l0, false);
   hipEvent_t a, b;
@@ -2745,7 +2796,7 @@ int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rh
   hipEventDestroy(a);
   hipEventDestroy(b);
   *mean_ms = ms / reps;
-  return end_call(s);
+  return call.finish();
 }
 
 static int amr_plan(mg_solver* s, const mg_box_t* cboxes, int32_t ncb, const mg_box_t* fboxes,
@@ -2823,26 +2874,29 @@ int mg_create_amr(const mg_box_t* cboxes, int32_t ncb, const mg_box_t* fboxes, i
   HIPTRY(hipHostMalloc((void**)&s->h_norm, sizeof(unsigned long long) * (kNormSlot + 8),
                        hipHostMallocDefault));
   s->h_iters = reinterpret_cast<int*>(s->h_norm + kNormSlot);
-  if ((rc = begin_call(s.get()))) return rc;
-  if ((rc = upload_tables(s.get()))) return rc;
-  if ((rc = upload_composite(s.get()))) return rc;
-  if (s->opts.krylov) {
-    HIPTRY(hipHostMalloc((void**)&s->h_gm, sizeof(double) * (s->gm_m + 2), hipHostMallocDefault));
-    HIPTRY(hipMemsetAsync(s->gm_zero_f, 0, sizeof(double) * s->F.n_g0, s->st));
-    HIPTRY(hipMemsetAsync(s->gm_zero_c, 0, sizeof(double) * s->L[0].n_g0, s->st));
+  {
+    CallScope call(s.get());
+    if ((rc = call.rc())) return rc;
+    if ((rc = upload_tables(s.get()))) return rc;
+    if ((rc = upload_composite(s.get()))) return rc;
+    if (s->opts.krylov) {
+      HIPTRY(hipHostMalloc((void**)&s->h_gm, sizeof(double) * (s->gm_m + 2), hipHostMallocDefault));
+      HIPTRY(hipMemsetAsync(s->gm_zero_f, 0, sizeof(double) * s->F.n_g0, s->st));
+      HIPTRY(hipMemsetAsync(s->gm_zero_c, 0, sizeof(double) * s->L[0].n_g0, s->st));
+    }
+    if ((rc = setup_coefficients(s.get(), nullptr, bcoef_c))) return rc;
+    for (int d = 0; d < 3; ++d) {
+      HIPTRY(launch_scale_faces(s->st, bcoef_f ? (const double*)bcoef_f[d]->data : nullptr,
+                                s->F.b64[d], s->F.n_f[d], 1.0));
+      if (s->F.b32[d])
+        HIPTRY((launch_convert<double, float>(s->st, s->F.b64[d], s->F.b32[d], s->F.n_f[d])));
+    }
+    if ((rc = coarsen_all(s.get()))) return rc;
+    if ((rc = autotune(s.get()))) return rc;
+    if ((rc = capture_graphs(s.get()))) return rc;
+    HIPTRY(hipStreamSynchronize(s->st));
+    if ((rc = call.finish())) return rc;
   }
-  if ((rc = setup_coefficients(s.get(), nullptr, bcoef_c))) return rc;
-  for (int d = 0; d < 3; ++d) {
-    HIPTRY(launch_scale_faces(s->st, bcoef_f ? (const double*)bcoef_f[d]->data : nullptr,
-                              s->F.b64[d], s->F.n_f[d], 1.0));
-    if (s->F.b32[d])
-      HIPTRY((launch_convert<double, float>(s->st, s->F.b64[d], s->F.b32[d], s->F.n_f[d])));
-  }
-  if ((rc = coarsen_all(s.get()))) return rc;
-  if ((rc = autotune(s.get()))) return rc;
-  if ((rc = capture_graphs(s.get()))) return rc;
-  HIPTRY(hipStreamSynchronize(s->st));
-  if ((rc = end_call(s.get()))) return rc;
   s->setup_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = s.release();
@@ -2860,7 +2914,8 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
   if ((rc = check_mf_boxes(s->F.boxes, phi_f, 1, 1, -1, "phi_f"))) return rc;
   if ((rc = check_mf_boxes(s->F.boxes, rhs_f, 0, 1, -1, "rhs_f"))) return rc;
   if (!(rel_tol >= 0) || !(abs_tol >= 0)) return fail(MG_ERR_ARG, "negative tolerance");
-  if ((rc = begin_call(s))) return rc;
+  CallScope call(s);
+  if ((rc = call.rc())) return rc;
   Level& L0 = s->L[0];
   Level& F = s->F;
   double* Pc = (double*)phi_c->data;
@@ -2882,10 +2937,7 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
   double normf;
   if ((rc = read_norm(s, 0, &normf))) return rc;
   int status = MG_OK;
-  if (!std::isfinite(normf)) {
-    end_call(s);
-    return fail(MG_ERR_NAN, "rhs holds a non-finite value");
-  }
+  if (!std::isfinite(normf)) return fail(MG_ERR_NAN, "rhs holds a non-finite value");
   if (normf == 0.0) {
     HIPTRY(launch_zero_valid<double>(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info,
                                      Pc, 1));
@@ -2931,7 +2983,7 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
   HIPTRY(hipMemcpyAsync(s->h_iters, s->d_iters, sizeof(int), hipMemcpyDeviceToHost, s->st));
   HIPTRY(hipStreamSynchronize(s->st));
   inf.bottom_iters = *s->h_iters;
-  if ((rc = end_call(s))) return rc;
+  if ((rc = call.finish())) return rc;
   inf.solve_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = inf;

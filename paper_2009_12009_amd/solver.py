@@ -63,6 +63,15 @@ def fill_boundary(mf, domain, periodic, stream=None):
     L.check(L.lib.fill_boundary(C.byref(m), C.byref(g), _stream_handle(stream)), "fill_boundary")
 
 
+def stream_copy(dst, src, stream=None):
+    """dst.copy_(src) with the library's streaming kernel (contiguous device
+    tensors of equal byte size, 16-byte aligned)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes and src.is_contiguous() and dst.is_contiguous()
+    L.check(L.lib.mg_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes,
+                                 _stream_handle(stream)), "mg_stream_copy")
+
+
 class MLMG:
     """Multigrid solver of alpha*a*phi - beta*div(b grad phi) = f on one level.
 

@@ -19,11 +19,13 @@ def _problem(n, m, sigma=0.5):
     return cfg
 
 
-def _gpu_setup(cfg):
+def _gpu_setup(cfg, precision=0):
+    """Solver handle (precision 0: FP64 V-cycles; 1: FP32 V-cycle inside FP64
+    refinement) and device tensors f, log b, log b_target."""
     P = lib()
     n, boxes = cfg["n"], cfg["boxes"]
     s = P.MLMG(boxes, W.domain_box(n), cfg["periodic"], cfg["alpha"], cfg["beta"],
-               opts=dict(bottom_rel_tol=TIGHT))
+               opts=dict(bottom_rel_tol=TIGHT, precision=precision))
     f = torch.from_numpy(np.concatenate([x.ravel(order="F") for x in
                                          W.scatter_cells(cfg["rhs"], boxes)])).cuda()
     logb = [torch.from_numpy(P.global_to_xfast(np.log(cfg["faces"][d]))).cuda() for d in range(3)]
@@ -33,12 +35,15 @@ def _gpu_setup(cfg):
 
 
 @pytest.mark.gpu
-def test_adjoint_gradient_vs_oracle():
-    print("[adjoint] 32^3, 8 boxes of 16^3", flush=True)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_adjoint_gradient_vs_oracle(precision):
+    """Forward and adjoint solves in FP64, or with the FP32 V-cycle inside FP64
+    refinement: dL/df and dL/dlog b against the FP64 oracle's gradient."""
+    print(f"[adjoint] 32^3, 8 boxes of 16^3, precision={precision}", flush=True)
     P = lib()
     cfg = _problem(32, 16)
     n, boxes = cfg["n"], cfg["boxes"]
-    s, f, logb, logbt = _gpu_setup(cfg)
+    s, f, logb, logbt = _gpu_setup(cfg, precision)
     with torch.no_grad():
         phi_t = P.mg_solve(f, *logbt, s, 1e-13)
     fr = f.clone().requires_grad_(True)
@@ -66,7 +71,9 @@ def test_adjoint_gradient_vs_oracle():
     gphi = W.gather_cells(P.MultiFab(boxes, 0, data=phi.detach()).valid_numpy(), boxes, n)
     assert rel_l2(gphi, Pg) <= 1e-10
     gf = W.gather_cells(P.MultiFab(boxes, 0, data=fr.grad).valid_numpy(), boxes, n)
-    assert rel_l2(gf, lam_ref) <= 1e-8
+    e = rel_l2(gf, lam_ref)
+    print(f"dL/df rel-L2 vs oracle: {e:.2e}")
+    assert e <= 1e-8
     for d in range(3):
         got = P.xfast_to_global(lb[d].grad)
         e = rel_l2(got, g_ref[d])
@@ -98,16 +105,45 @@ def test_face_gradient_per_box_matches_global():
     s.close()
 
 
+def _fd_picks(grads, rng, n_top, n_mid, n_rand):
+    """Sample positions (d, idx) over three face tensors: the n_top largest
+    |g|, n_mid drawn among faces with |g| in [1e-3, 1e-1] of the largest, and
+    n_rand uniform (which mostly land far below the largest entry)."""
+    flat = np.concatenate([g.ravel() for g in grads])
+    offs = np.cumsum([0] + [g.size for g in grads])
+    a = np.abs(flat)
+    gmax = float(a.max())
+    top = np.argpartition(-a, n_top)[:n_top]
+    mid_pool = np.flatnonzero((a >= 1e-3 * gmax) & (a <= 1e-1 * gmax))
+    mid = rng.choice(mid_pool, size=n_mid, replace=False)
+    rnd = rng.integers(flat.size, size=n_rand)
+    out = []
+    for q in list(top) + list(mid) + list(rnd):
+        d = int(np.searchsorted(offs, q, side="right") - 1)
+        out.append((d, tuple(int(x) for x in np.unravel_index(q - offs[d], grads[d].shape))))
+    return out
+
+
 @pytest.mark.gpu
-def test_c3_finite_differences():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c3_finite_differences(precision):
     """128^3, 8 boxes of 64^3, sigma 0.5: central differences (eps 1e-6) of L in
-    log b on 32 seeded faces and in f on 32 seeded cells, from warm-started
-    solves and solution differences."""
-    print("[adjoint] C3 128^3 finite differences", flush=True)
+    log b and in f, from warm-started solves and solution differences, against
+    the adjoint gradient; both computed with the solver handle of the given
+    precision (FP64, or the FP32 V-cycle inside FP64 refinement).
+
+    Faces: the 12 largest |dL/dlog b|, 12 with |g| between 1e-3 and 1e-1 of the
+    largest, and 8 uniform draws; cells likewise.  ΔL carries the solves'
+    roundoff, an absolute error floor under every entry: measured up to
+    2.0e-6 (FP64) and 4.6e-6 (FP32+refine) of the largest entry.  Each entry
+    must agree to 1e-4 |g| + 1e-5 max|g|, every sampled error must stay
+    under that 1e-5 floor, and at least 12 of each 32 samples lie where the
+    relative term is the larger (|g| >= 0.1 max|g|)."""
+    print(f"[adjoint] C3 128^3 finite differences precision={precision}", flush=True)
     P = lib()
     cfg = W.config_c3()
     n, boxes = cfg["n"], cfg["boxes"]
-    s, f, logb, logbt = _gpu_setup(cfg)
+    s, f, logb, logbt = _gpu_setup(cfg, precision)
     with torch.no_grad():
         phi_t = P.mg_solve(f, *logbt, s, 1e-12)
     fr = f.clone().requires_grad_(True)
@@ -128,30 +164,44 @@ def test_c3_finite_differences():
 
     rng = np.random.default_rng(W.SEED_FD)
     eps = 1e-6
-    gmax = max(float(x.grad.abs().max()) for x in lb)
-    worst = 0.0
-    for _ in range(32):
-        d = int(rng.integers(3))
-        shp = s.global_face_shape(d)
-        idx = tuple(int(rng.integers(x)) for x in shp)
+    floor_rel = 1e-5
+    gfaces = [x.grad.detach().cpu().numpy() for x in lb]
+    gmax = max(float(np.abs(g).max()) for g in gfaces)
+    rel_side, worst_rel, worst_abs = 0, 0.0, 0.0
+    for d, idx in _fd_picks(gfaces, rng, 12, 12, 8):
         lp = [x.detach().clone() for x in lb]
         lm = [x.detach().clone() for x in lb]
         lp[d][idx] += eps
         lm[d][idx] -= eps
         fd = dL(solve_with(f, lp), solve_with(f, lm)) / (2 * eps)
-        g = float(lb[d].grad[idx])
-        worst = max(worst, abs(fd - g) / (abs(g) + 1e-5 * gmax))
-        # solve roundoff gives dL an absolute floor: 1e-5 of the largest entry
-        assert abs(fd - g) <= 1e-4 * abs(g) + 1e-5 * gmax, (d, idx, fd, g)
-    gfmax = float(fr.grad.abs().max())
-    for _ in range(32):
-        c = int(rng.integers(f.numel()))
+        g = float(gfaces[d][idx])
+        rel = abs(fd - g) / abs(g) if g != 0 else float("inf")
+        print(f"  face d={d} {idx}: g {g:+.6e} fd {fd:+.6e} |g|/max {abs(g) / gmax:.1e} "
+              f"rel err {rel:.1e} abs err/max {abs(fd - g) / gmax:.1e}")
+        worst_abs = max(worst_abs, abs(fd - g) / gmax)
+        if abs(g) >= 0.1 * gmax:
+            rel_side += 1
+            worst_rel = max(worst_rel, rel)
+        assert abs(fd - g) <= 1e-4 * abs(g) + floor_rel * gmax, (d, idx, fd, g)
+    assert rel_side >= 12, rel_side
+    gcell = fr.grad.detach().cpu().numpy()
+    gfmax = float(np.abs(gcell).max())
+    rel_side_c, worst_abs_c = 0, 0.0
+    for (_, (c,)) in _fd_picks([gcell], rng, 12, 12, 8):
         fp = f.clone()
         fm = f.clone()
         fp[c] += eps
         fm[c] -= eps
         fd = dL(solve_with(fp, logb), solve_with(fm, logb)) / (2 * eps)
-        g = float(fr.grad[c])
-        assert abs(fd - g) <= 1e-4 * abs(g) + 1e-5 * gfmax, (c, fd, g)
-    print(f"C3 FD: worst relative face error {worst:.2e}")
+        g = float(gcell[c])
+        worst_abs_c = max(worst_abs_c, abs(fd - g) / gfmax)
+        if abs(g) >= 0.1 * gfmax:
+            rel_side_c += 1
+            worst_rel = max(worst_rel, abs(fd - g) / abs(g))
+        assert abs(fd - g) <= 1e-4 * abs(g) + floor_rel * gfmax, (c, fd, g)
+    assert rel_side_c >= 12, rel_side_c
+    assert worst_abs < floor_rel and worst_abs_c < floor_rel
+    print(f"C3 FD precision={precision}: worst relative error where |g| >= 0.1 max {worst_rel:.2e} "
+          f"({rel_side} faces, {rel_side_c} cells); worst absolute error / max: faces "
+          f"{worst_abs:.2e}, cells {worst_abs_c:.2e}")
     s.close()

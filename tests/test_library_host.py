@@ -23,7 +23,7 @@ def _lib():
 def test_exports_every_declared_symbol():
     P = _lib()
     text = open(os.path.join(ROOT, "include", "amrmg.h")).read()
-    names = re.findall(r"^(?:int|void|const char\*)\s+(\w+)\(", text, flags=re.M)
+    names = re.findall(r"^(?:int|void|size_t|const char\*)\s+(\w+)\(", text, flags=re.M)
     assert len(names) >= 20
     lib = C.CDLL(P._lib.LIB_PATH)
     for n in names:

@@ -404,8 +404,9 @@ def bench_c3(args):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     nf = 3 * (n + 1) * n * n
-    # per face: b, grad out, and the two cells' phi and lambda (cells read ~once per direction)
-    alg = nf * 8 * 2 + 3 * 2 * n ** 3 * 8
+    # what the method must move: per face b in and the gradient out, per cell phi and lambda
+    # once (one pass over all three directions)
+    alg = nf * 8 * 2 + 2 * n ** 3 * 8
     out = {"metric": "adjoint gradient, 128^3 (8 boxes of 64^3)", "unit": "ms", "n_gpus": 1,
            "higher_is_better": False, "data": "synthetic",
            "config": {"workload": "adjoint128", "sigma": 0.5, "rel_tol": 1e-10},

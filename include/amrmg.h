@@ -160,6 +160,15 @@ typedef struct {
                                       1 = on levels >= 2, and on level 1 where
                                       tune measured it faster; 2 = on every
                                       such level; 0 = separate passes         */
+  int32_t stop_fold;           /* [1] FP64 V-cycle solves (krylov 0, more than
+                                      one level, nu1 >= 1, level 0 not fused):
+                                      the stop test's residual pass also does
+                                      the next cycle's first red half-sweep,
+                                      into a second level-0 array, and the
+                                      cycle goes on there (the stop decision
+                                      is read while it runs); same iterates,
+                                      norms and result; 0 = a residual pass of
+                                      its own before each cycle               */
 } mg_opts_t;
 
 typedef struct {

@@ -57,7 +57,8 @@ class MgOpts(C.Structure):
                 ("verbose", C.c_int32), ("aggregate", C.c_int32), ("bottom_rel_tol", C.c_double),
                 ("fused_min_edge", C.c_int32), ("krylov", C.c_int32),
                 ("ghost_write", C.c_int32), ("interp_fold", C.c_int32),
-                ("bottom_solver", C.c_int32), ("restrict_fold", C.c_int32)]
+                ("bottom_solver", C.c_int32), ("restrict_fold", C.c_int32),
+                ("stop_fold", C.c_int32)]
 
 
 class MgInfo(C.Structure):

@@ -14,6 +14,8 @@
 // access is x-contiguous across the lanes of a wavefront.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace amrmg {
@@ -696,11 +698,16 @@ __device__ double block_sum(double v, double* red, int& phase);
 
 // out = rhs - A phi (mode 0) or A phi (mode 1), one lane per cell, U planes
 // gathered at a time; optional NaN-propagating max |out|.
-template <typename T, typename TO, int U, bool BUF>
+// NX (mode 0): also write phi after a red half-sweep into pnext (same ghost
+// layout as phi, valid cells only): a red cell gets (f + off) / diag from
+// the same gathered values, the same expression as the half-sweep, and a
+// black cell its old value.  The residual is that of phi, before the update.
+template <typename T, typename TO, int U, bool BUF, bool NX>
 __global__ void __launch_bounds__(256)
     k_residual(const Tile* __restrict__ tiles, StencilArgs<T> op, const T* __restrict__ phi,
                const T* __restrict__ rhs, int rhs_ng, TO* __restrict__ out,
-               unsigned long long* normbits, int tz, int mode, double* __restrict__ dot_partials) {
+               unsigned long long* normbits, int tz, int mode, double* __restrict__ dot_partials,
+               T* __restrict__ pnext) {
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = op.boxes[t.box];
   const int i = t.x0 + threadIdx.x;
@@ -743,6 +750,11 @@ __global__ void __launch_bounds__(256)
         const T Aphi = c.diag * v[u].pc - c.off;
         const T r = mode == 0 ? v[u].f - Aphi : Aphi;
         if (O) O[il + s.nx * (jl + s.ny * kl)] = (TO)r;
+        if (NX) {
+          const bool red = ((i + j + k0 + u) & 1) == 0;
+          pnext[B.off_g1 + (il + 1) + s.sy * (jl + 1) + s.sz * (kl + 1)] =
+              red ? (v[u].f + c.off) / c.diag : v[u].pc;
+        }
         const unsigned long long bits = absbits(r);
         mx = bits > mx ? bits : mx;
         if (dot_partials) dot += (double)v[u].pc * (double)r;
@@ -1269,60 +1281,141 @@ __global__ void __launch_bounds__(256)
         g[(i - dlo.x) + (long long)dn.x * ((j - dlo.y) + (long long)dn.y * (k - dlo.z))];
 }
 
-// Adjoint gradient on the d-faces of one box (grid.y = box).  mode 0: every
-// face of the box into its face array; mode 1: global array, the box writes
-// its low faces and, on the domain's high side, its high face as well.
+// Adjoint gradient on every face of one box in one pass (grid.y = box).  A
+// 64 x 4 block takes 64 x 4 cells of a column of tz planes; a lane computes
+// the low x, y and z faces of its cell, and the box's high face along d
+// where its cell is the last along d.  The cell below (z) stays in
+// registers from the previous plane, the x and y neighbours come through
+// the caches; offsets are 32-bit inside a box (face arrays of a box < 2^31
+// elements, checked on the host).  MODE 0: per-box face arrays (every face of the box); MODE 1:
+// global face arrays: a box writes its low faces, its high faces on the
+// domain's high side, and along a periodic direction the face at index 0
+// also at index n (the same face).
+template <int MODE>
 __global__ void __launch_bounds__(256)
-    k_face_grad(StencilArgs<double> op, int d, const double* __restrict__ phi,
-                const double* __restrict__ lam, double* __restrict__ out, int mode, int3 dlo,
-                int3 dn, int periodic_d) {
+    k_face_grad3(StencilArgs<double> op, const double* __restrict__ phi,
+                 const double* __restrict__ lam, double* __restrict__ g0,
+                 double* __restrict__ g1, double* __restrict__ g2, int3 dlo, int3 dn,
+                 int perbits, int ntx, int nty, int tz) {
   const BoxInfo B = op.boxes[blockIdx.y];
-  const BoxDims bd = dims(B);
-  int fx, fy, fz;
-  face_dims(bd, d, fx, fy, fz);
-  const long long total = (long long)fx * fy * fz;
-  const double* bf = d == 0 ? op.b0 : (d == 1 ? op.b1 : op.b2);
-  const double ih = d == 0 ? op.ih0 : (d == 1 ? op.ih1 : op.ih2);
-  const int nd = d == 0 ? bd.nx : (d == 1 ? bd.ny : bd.nz);
-  const int dom_n = d == 0 ? dn.x : (d == 1 ? dn.y : dn.z);
-  const int dom_lo = d == 0 ? dlo.x : (d == 1 ? dlo.y : dlo.z);
-  const int lo_d = B.lo[d];
-  const bool wall_lo = (B.bcmask >> (2 * d)) & 1, wall_hi = (B.bcmask >> (2 * d + 1)) & 1;
-  const long long sy = bd.nx + 2, sz = (long long)(bd.nx + 2) * (bd.ny + 2);
-  const long long step = d == 0 ? 1 : (d == 1 ? sy : sz);
-  const double* P = phi + B.off_g1;
-  const double* L = lam + B.off_g1;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    int f[3];
-    f[0] = e % fx;
-    f[1] = (e / fx) % fy;
-    f[2] = e / ((long long)fx * fy);
-    const int fl = f[d];  // face index along d, 0..nd
-    if (mode == 1 && fl == nd && !(lo_d + nd - dom_lo == dom_n)) continue;
-    // cell on the high side of the face (local), possibly the ghost at nd
-    const long long ph = (f[0] + 1) + sy * (f[1] + 1) + sz * (f[2] + 1);
-    const long long pl = ph - step;
-    const double c = (op.beta * bf[B.off_f[d] + e]) * ih;
-    double g;
-    if (fl == 0 && wall_lo) {
-      g = -2.0 * c * P[ph] * L[ph];
-    } else if (fl == nd && wall_hi) {
-      g = -2.0 * c * P[pl] * L[pl];
-    } else {
-      g = -c * (P[ph] - P[pl]) * (L[ph] - L[pl]);
-    }
-    if (mode == 0) {
-      out[B.off_f[d] + e] = g;
-    } else {
-      int gi[3] = {B.lo[0] - dlo.x + f[0], B.lo[1] - dlo.y + f[1], B.lo[2] - dlo.z + f[2]};
-      const long long gx = dn.x + (d == 0), gy = dn.y + (d == 1);
-      out[gi[0] + gx * (gi[1] + gy * (long long)gi[2])] = g;
-      if (periodic_d && gi[d] == 0) {
-        gi[d] = dom_n;
-        out[gi[0] + gx * (gi[1] + gy * (long long)gi[2])] = g;
+  const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
+  int t = blockIdx.x;
+  const int tx = t % ntx;
+  t /= ntx;
+  const int ty = t % nty;
+  const int tzb = t / nty;
+  const int i = tx * 64 + threadIdx.x, j = ty * 4 + threadIdx.y, k0 = tzb * tz;
+  if (i >= nx || j >= ny || k0 >= nz) return;
+  const int k1 = min(k0 + tz, nz);
+  const int sy = nx + 2, sz = sy * (ny + 2);
+  const double* __restrict__ P = phi + B.off_g1;
+  const double* __restrict__ L = lam + B.off_g1;
+  const double* __restrict__ bx = op.b0 + B.off_f[0];
+  const double* __restrict__ by = op.b1 + B.off_f[1];
+  const double* __restrict__ bz = op.b2 + B.off_f[2];
+  const int m = B.bcmask;
+  const bool xlo = i == 0, xhi = i == nx - 1, ylo = j == 0, yhi = j == ny - 1;
+  // high faces of the box: written in mode 0, or on the domain's high side
+  const bool dhx = MODE == 0 || B.hi[0] + 1 - dlo.x == dn.x;
+  const bool dhy = MODE == 0 || B.hi[1] + 1 - dlo.y == dn.y;
+  const bool dhz = MODE == 0 || B.hi[2] + 1 - dlo.z == dn.z;
+  const double beta = op.beta, ih0 = op.ih0, ih1 = op.ih1, ih2 = op.ih2;
+  // face-array offsets of face (i, j, k0) in the box's x, y and z face arrays
+  int fxo = i + (nx + 1) * (j + ny * k0);
+  int fyo = i + nx * (j + (ny + 1) * k0);
+  int fzo = i + nx * (j + ny * k0);
+  const int fxs = (nx + 1) * ny, fys = nx * (ny + 1), fzs = nx * ny;
+  // output offsets of the same faces (box arrays, or the global arrays)
+  long long ox, oy, oz, oxs, oys, ozs;
+  long long gx0 = 0, gy0 = 0, gz0 = 0;  // global index along d of this lane's low face
+  if (MODE == 0) {
+    ox = B.off_f[0] + fxo;
+    oy = B.off_f[1] + fyo;
+    oz = B.off_f[2] + fzo;
+    oxs = fxs;
+    oys = fys;
+    ozs = fzs;
+  } else {
+    const long long I = B.lo[0] - dlo.x + i, J = B.lo[1] - dlo.y + j, K = B.lo[2] - dlo.z + k0;
+    ox = I + (dn.x + 1ll) * (J + (long long)dn.y * K);
+    oy = I + (long long)dn.x * (J + (dn.y + 1ll) * K);
+    oz = I + (long long)dn.x * (J + (long long)dn.y * K);
+    oxs = (dn.x + 1ll) * dn.y;
+    oys = (long long)dn.x * (dn.y + 1);
+    ozs = (long long)dn.x * dn.y;
+    gx0 = I;
+    gy0 = J;
+    gz0 = K;
+  }
+  int p = (i + 1) + sy * (j + 1) + sz * (k0 + 1);
+  double pb = P[p - sz], lb = L[p - sz];
+  for (int k = k0; k < k1; ++k, p += sz, fxo += fxs, fyo += fys, fzo += fzs, ox += oxs,
+           oy += oys, oz += ozs) {
+    const double pc = P[p], lc = L[p];
+    const double pw = P[p - 1], lw = L[p - 1];
+    const double ps = P[p - sy], ls = L[p - sy];
+    // x faces
+    {
+      const double c = (beta * bx[fxo]) * ih0;
+      const double g = (xlo && (m & 1)) ? -2.0 * c * pc * lc : -c * (pc - pw) * (lc - lw);
+      if (MODE == 0) {
+        g0[ox] = g;
+      } else {
+        g0[ox] = g;
+        if ((perbits & 1) && gx0 == 0) g0[ox + dn.x] = g;
+      }
+      if (xhi && dhx) {
+        const double ch = (beta * bx[fxo + 1]) * ih0;
+        double gh;
+        if (m & 2) {
+          gh = -2.0 * ch * pc * lc;
+        } else {
+          const double pe = P[p + 1], le = L[p + 1];
+          gh = -ch * (pe - pc) * (le - lc);
+        }
+        g0[ox + 1] = gh;
       }
     }
+    // y faces
+    {
+      const double c = (beta * by[fyo]) * ih1;
+      const double g = (ylo && (m & 4)) ? -2.0 * c * pc * lc : -c * (pc - ps) * (lc - ls);
+      g1[oy] = g;
+      if (MODE == 1 && (perbits & 2) && gy0 == 0) g1[oy + (long long)dn.x * dn.y] = g;
+      if (yhi && dhy) {
+        const double ch = (beta * by[fyo + nx]) * ih1;
+        double gh;
+        if (m & 8) {
+          gh = -2.0 * ch * pc * lc;
+        } else {
+          const double pn = P[p + sy], ln = L[p + sy];
+          gh = -ch * (pn - pc) * (ln - lc);
+        }
+        g1[oy + (MODE == 0 ? nx : dn.x)] = gh;
+      }
+    }
+    // z faces
+    {
+      const double c = (beta * bz[fzo]) * ih2;
+      const bool zlo = k == 0;
+      const double g = (zlo && (m & 16)) ? -2.0 * c * pc * lc : -c * (pc - pb) * (lc - lb);
+      g2[oz] = g;
+      if (MODE == 1 && (perbits & 4) && gz0 + (k - k0) == 0)
+        g2[oz + (long long)dn.x * dn.y * dn.z] = g;
+      if (k == nz - 1 && dhz) {
+        const double ch = (beta * bz[fzo + fzs]) * ih2;
+        double gh;
+        if (m & 32) {
+          gh = -2.0 * ch * pc * lc;
+        } else {
+          const double pu = P[p + sz], lu = L[p + sz];
+          gh = -ch * (pu - pc) * (lu - lc);
+        }
+        g2[oz + ozs] = gh;
+      }
+    }
+    pb = pc;
+    lb = lc;
   }
 }
 
@@ -1882,18 +1975,26 @@ template <typename T, typename TO>
 hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                            const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
                            TO* out, unsigned long long* normbits, int mode,
-                           double* dot_partials) {
+                           double* dot_partials, T* pnext) {
   if (ntiles <= 0) return hipSuccess;
+  if (pnext && (mode != 0 || !rhs || pnext == phi)) return hipErrorInvalidValue;
   const dim3 g(ntiles), b = block_of(sh);
-#define RS(U, F)                                                                           \
-  hipLaunchKernelGGL((k_residual<T, TO, U, F>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng, out, \
-                     normbits, sh.tz, mode, dot_partials)
+#define RS(U, F, N)                                                                           \
+  hipLaunchKernelGGL((k_residual<T, TO, U, F, N>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng,    \
+                     out, normbits, sh.tz, mode, dot_partials, pnext)
+#define RSU(F, N) \
+  if (sh.u >= 4) RS(4, F, N); else if (sh.u == 2) RS(2, F, N); else RS(1, F, N);
   // buffer loads where the level streams (op.buf)
-  if (op.buf) {
-    if (sh.u >= 4) RS(4, true); else if (sh.u == 2) RS(2, true); else RS(1, true);
+  if (pnext) {
+    if constexpr (std::is_same<T, TO>::value) {
+      if (op.buf) { RSU(true, true) } else { RSU(false, true) }
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else {
-    if (sh.u >= 4) RS(4, false); else if (sh.u == 2) RS(2, false); else RS(1, false);
+    if (op.buf) { RSU(true, false) } else { RSU(false, false) }
   }
+#undef RSU
 #undef RS
   return hipGetLastError();
 }
@@ -2151,15 +2252,24 @@ hipError_t launch_scatter_cells(hipStream_t st, const Tile* tiles, int ntiles, S
   return hipGetLastError();
 }
 
-hipError_t launch_face_grad(hipStream_t st, const BoxInfo* boxes, int nbox, int d,
-                            const StencilArgs<double>& op, const double* phi, const double* lam,
-                            double* out, int mode, const int dom_lo[3], const int dom_n[3],
-                            int periodic_d, int max_faces_per_box) {
+hipError_t launch_face_grad(hipStream_t st, int nbox, const StencilArgs<double>& op,
+                            const double* phi, const double* lam, double* const out[3], int mode,
+                            const int dom_lo[3], const int dom_n[3], int perbits,
+                            const int max_n[3]) {
   if (nbox <= 0) return hipSuccess;
-  (void)boxes;
-  hipLaunchKernelGGL(k_face_grad, dim3(grid_for(max_faces_per_box), nbox), dim3(256), 0, st, op, d,
-                     phi, lam, out, mode, make_int3(dom_lo[0], dom_lo[1], dom_lo[2]),
-                     make_int3(dom_n[0], dom_n[1], dom_n[2]), periodic_d);
+  const int tz = 8;
+  const int ntx = (max_n[0] + 63) / 64, nty = (max_n[1] + 3) / 4, ntz = (max_n[2] + tz - 1) / tz;
+  const long long nblk = (long long)ntx * nty * ntz;
+  if (nblk > 0x7fffffffll || nbox > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nblk, nbox), block(64, 4);
+  const int3 lo = make_int3(dom_lo[0], dom_lo[1], dom_lo[2]);
+  const int3 n = make_int3(dom_n[0], dom_n[1], dom_n[2]);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_face_grad3<0>, grid, block, 0, st, op, phi, lam, out[0], out[1], out[2],
+                       lo, n, perbits, ntx, nty, tz);
+  else
+    hipLaunchKernelGGL(k_face_grad3<1>, grid, block, 0, st, op, phi, lam, out[0], out[1], out[2],
+                       lo, n, perbits, ntx, nty, tz);
   return hipGetLastError();
 }
 
@@ -2285,15 +2395,15 @@ INST(float)
 template hipError_t launch_residual<double, double>(hipStream_t, const Tile*, int, Shape,
                                                     const StencilArgs<double>&, const double*,
                                                     const double*, int, double*,
-                                                    unsigned long long*, int, double*);
+                                                    unsigned long long*, int, double*, double*);
 template hipError_t launch_residual<double, float>(hipStream_t, const Tile*, int, Shape,
                                                    const StencilArgs<double>&, const double*,
                                                    const double*, int, float*,
-                                                   unsigned long long*, int, double*);
+                                                   unsigned long long*, int, double*, double*);
 template hipError_t launch_residual<float, float>(hipStream_t, const Tile*, int, Shape,
                                                   const StencilArgs<float>&, const float*,
                                                   const float*, int, float*,
-                                                  unsigned long long*, int, double*);
+                                                  unsigned long long*, int, double*, float*);
 template hipError_t launch_convert<double, float>(hipStream_t, const double*, float*, long long);
 template hipError_t launch_convert<float, double>(hipStream_t, const float*, double*, long long);
 

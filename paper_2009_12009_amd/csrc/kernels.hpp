@@ -94,12 +94,16 @@ hipError_t launch_rim(hipStream_t st, const RimTile* tiles, int ntiles, const St
 // lane per cell; out may be null (norm only).  When normbits is non-null the
 // max |out| is folded into *normbits as IEEE-754 bits (NaN-propagating).
 // out uses the ghost-free layout; TO may be narrower than T (the value is
-// computed in T and rounded once).
+// computed in T and rounded once).  With pnext (mode 0, TO = T, pnext !=
+// phi) the launch also writes phi after a red half-sweep into pnext's valid
+// cells (red cells updated with the half-sweep's expression, black cells
+// copied), so that a stop test's residual and the next cycle's first
+// half-sweep share one pass over the level; pnext's ghosts are not written.
 template <typename T, typename TO>
 hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                            const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
                            TO* out, unsigned long long* normbits, int mode,
-                           double* dot_partials = nullptr);
+                           double* dot_partials = nullptr, T* pnext = nullptr);
 
 // max |v| over valid cells folded into *normbits (v: ng 0 or 1 layout).
 template <typename T>
@@ -214,10 +218,10 @@ hipError_t launch_scatter_cells(hipStream_t st, const Tile* tiles, int ntiles, S
 
 // Adjoint face gradient: per box face array (mode 0) or global face array
 // (mode 1, each physical face once).
-hipError_t launch_face_grad(hipStream_t st, const BoxInfo* boxes, int nbox, int d,
-                            const StencilArgs<double>& op, const double* phi, const double* lam,
-                            double* out, int mode, const int dom_lo[3], const int dom_n[3],
-                            int periodic_d, int max_faces_per_box);
+hipError_t launch_face_grad(hipStream_t st, int nbox, const StencilArgs<double>& op,
+                            const double* phi, const double* lam, double* const out[3], int mode,
+                            const int dom_lo[3], const int dom_n[3], int perbits,
+                            const int max_n[3]);
 
 // Two-level composite pieces.
 // Covered coarse cells (ghost layer cng) = mean of their 8 fine children (fine

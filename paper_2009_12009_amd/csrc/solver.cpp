@@ -24,6 +24,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/amrmg.h"
@@ -133,6 +134,7 @@ struct Level {
   double *b64[3] = {nullptr, nullptr, nullptr}, *a64 = nullptr;
   double *e64 = nullptr, *rhs64 = nullptr, *r64 = nullptr;
   double* p64 = nullptr;  // level 0, preconditioned CG: search direction (ng 1)
+  double* next64 = nullptr;  // level 0, folded stop test: the other iterate (ng 1)
   float *b32[3] = {nullptr, nullptr, nullptr}, *a32 = nullptr;
   float *e32 = nullptr, *rhs32 = nullptr, *r32 = nullptr;
 };
@@ -173,8 +175,11 @@ struct mg_solver {
   hipStream_t user = nullptr;
   hipStream_t st = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_norm[2] = {nullptr, nullptr};  // folded stop test: norm copies landed
   hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
-  unsigned long long* h_norm = nullptr;  // pinned
+  // pinned: [0, kNormSlot) read_norm; two more slots for the folded stop
+  // test's copies in flight; then h_iters
+  unsigned long long* h_norm = nullptr;
   int* h_iters = nullptr;
   bool profile = false;
   std::vector<ProfRec> prof;
@@ -439,6 +444,13 @@ bool make_wt_tables(Level& lv, const int periodic[3]) {
 
 // Builds every host table; with a Bump in measure mode it also lays out the
 // workspace.  Returns 0 or an error code.
+// Whether FP64 V-cycle solves fold the stop test's residual into the next
+// cycle's first half-sweep (needs the level hierarchy: call after it is set).
+bool stop_fold_on(const mg_solver* s) {
+  return s->opts.stop_fold && s->opts.precision == MG_PREC_F64 && !s->opts.krylov &&
+         !s->composite && s->opts.nu1 >= 1 && s->L.size() > 1 && !s->L[0].fused;
+}
+
 int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
   std::string err;
   if (!validate_boxes(boxes, s->domain, true, &err)) return fail(MG_ERR_INVALID_BOXARRAY, err);
@@ -613,6 +625,7 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
         lv.rhs64 = bump.take<double>(lv.n_g0);
       }
       if (s->opts.krylov) lv.p64 = bump.take<double>(lv.n_g1);
+      if (stop_fold_on(s)) lv.next64 = bump.take<double>(lv.n_g1);
     } else if (!f32) {
       lv.e64 = bump.take<double>(lv.n_g1);
       lv.rhs64 = bump.take<double>(lv.n_g0);
@@ -1055,8 +1068,10 @@ int capture_graphs(mg_solver* s) {
   return MG_OK;
 }
 
-// Level-0 V-cycle on the caller's phi (direct form, FP64).
-int vcycle64(mg_solver* s, double* phi, const double* rhs, int rhs_ng) {
+// Level-0 V-cycle on the caller's phi (direct form, FP64).  red_done: the
+// first pre-smoothing half-sweep (red) has already been applied to phi's
+// valid cells (by the stop test's residual pass) and phi's ghosts exchanged.
+int vcycle64(mg_solver* s, double* phi, const double* rhs, int rhs_ng, bool red_done = false) {
   Level& l0 = s->L[0];
   const StencilArgs<double> op = stencil_of<double>(s, l0, false);
   int rc;
@@ -1077,8 +1092,21 @@ int vcycle64(mg_solver* s, double* phi, const double* rhs, int rhs_ng) {
   }
   // the caller's last exchange (or write-through smoothing) left phi's face
   // ghosts current
-  if ((rc = smooth<double>(s, l0, op, phi, rhs, rhs_ng, s->opts.nu1, false, true, false, true)))
+  if (red_done) {
+    if (s->opts.nu1 < 1) return fail(MG_ERR_ARG, "folded red half-sweep without pre-smoothing");
+    {
+      ProfScope ps(s, 0, true);
+      HIPTRY(launch_gsrb<double>(s->st, l0.d_gsrb, (int)l0.t_gsrb.size(), l0.s_gsrb, op, phi, rhs,
+                                 rhs_ng, 1, 0, l0.wt ? l0.d_wtbox : nullptr,
+                                 l0.wt ? l0.d_wt : nullptr));
+    }
+    if ((rc = smooth<double>(s, l0, op, phi, rhs, rhs_ng, s->opts.nu1 - 1, false, true, false,
+                             true)))
+      return rc;
+  } else if ((rc = smooth<double>(s, l0, op, phi, rhs, rhs_ng, s->opts.nu1, false, true, false,
+                                  true))) {
     return rc;
+  }
   if (!(l0.wt && s->opts.nu1 > 0) && (rc = exchange<double>(s, l0, phi, true))) return rc;
   {
     ProfScope ps(s, 1, true);
@@ -1300,6 +1328,8 @@ int time_gsrb(mg_solver* s, Shape sh, T* phi, const T* rhs, const StencilArgs<T>
 // A residual that writes r, and with_norm a norm-only residual (into the
 // spare norm slot 3) after it: the two ways an FP64 solve runs the kernel
 // (the FP32 V-cycle only writes r; its norms come from FP64 residuals).
+// Where the FP64 solve folds its stop test into the next half-sweep, the
+// norm launch also writes the next iterate, as the solve runs it.
 template <typename T>
 int time_resid(mg_solver* s, Shape sh, const T* phi, const T* rhs, const StencilArgs<T>& op,
                T* out, bool with_norm, float* ms, size_t lev = 0) {
@@ -1312,8 +1342,10 @@ int time_resid(mg_solver* s, Shape sh, const T* phi, const T* rhs, const Stencil
     hipError_t e = launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi,
                                          rhs, 0, out, nullptr, 0);
     if (e != hipSuccess || !with_norm) return e;
+    T* nx = nullptr;
+    if constexpr (std::is_same<T, double>::value) nx = lev == 0 ? l0.next64 : nullptr;
     return launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi, rhs, 0,
-                                 (T*)nullptr, nb, 0);
+                                 (T*)nullptr, nb, 0, nullptr, nx);
   };
   HIPTRY(launch_fill_u64(s->st, nb, kNormSlot, 0ull));
   for (int w = 0; w < 2; ++w) HIPTRY(pair());
@@ -2240,6 +2272,7 @@ void mg_default_opts(mg_opts_t* o) {
   o->interp_fold = 1;
   o->bottom_solver = 0;
   o->restrict_fold = 1;
+  o->stop_fold = 1;
 }
 
 static int check_opts(const mg_opts_t* o) {
@@ -2256,6 +2289,7 @@ static int check_opts(const mg_opts_t* o) {
   if (o->interp_fold != 0 && o->interp_fold != 1) return fail(MG_ERR_ARG, "bad interp_fold");
   if (o->bottom_solver != 0 && o->bottom_solver != 1) return fail(MG_ERR_ARG, "bad bottom_solver");
   if (o->restrict_fold < 0 || o->restrict_fold > 2) return fail(MG_ERR_ARG, "bad restrict_fold");
+  if (o->stop_fold != 0 && o->stop_fold != 1) return fail(MG_ERR_ARG, "bad stop_fold");
   return MG_OK;
 }
 
@@ -2345,9 +2379,10 @@ int mg_create(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom, const 
   HIPTRY(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
   HIPTRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
   HIPTRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
-  HIPTRY(hipHostMalloc((void**)&s->h_norm, sizeof(unsigned long long) * (kNormSlot + 8),
+  for (hipEvent_t& e : s->ev_norm) HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIPTRY(hipHostMalloc((void**)&s->h_norm, sizeof(unsigned long long) * (3 * kNormSlot + 8),
                        hipHostMallocDefault));
-  s->h_iters = reinterpret_cast<int*>(s->h_norm + kNormSlot);
+  s->h_iters = reinterpret_cast<int*>(s->h_norm + 3 * kNormSlot);
   {
     CallScope call(s.get());
     if ((rc = call.rc())) return rc;
@@ -2533,6 +2568,100 @@ int solve_pcg(mg_solver* s, double* P, const double* F, int rng, double tol, mg_
   return status;
 }
 
+// FP64 V-cycles with the stop test's residual folded into the next cycle's
+// first half-sweep: one pass computes max|f - A phi| of the current iterate
+// and writes that iterate after a red half-sweep into the other level-0
+// array, where the cycle goes on, so the iterates alternate between the
+// caller's phi and next64.  The norm is copied to the host while the rest
+// of the cycle runs and read before the next pass (which overwrites the
+// iterate it was taken of); while the norms' geometric trend puts the next
+// one well above the tolerance the cycle is queued before the norm is read,
+// else after (a converged solve would otherwise run one cycle for nothing).
+// Same iterates, norms, decisions and result as the plain loop.
+int solve_folded(mg_solver* s, double* P, const double* F, int rng, double tol, mg_info_t* inf,
+                 double* hist, int* status) {
+  Level& l0 = s->L[0];
+  const StencilArgs<double> op = stencil_of<double>(s, l0, false);
+  double* cur = P;
+  double* nxt = l0.next64;
+  int rc;
+  int it = 0, rising = 0;
+  double rn = 0, first = 0, prev = 0, prev2 = 0;
+  *status = MG_OK;
+  // 1 = stop, 0 = go on
+  auto decide = [&]() -> int {
+    if (hipEventSynchronize(s->ev_norm[it & 1]) != hipSuccess) return -1;
+    const unsigned long long* h = s->h_norm + (size_t)(1 + (it & 1)) * kNormSlot;
+    unsigned long long m = 0;
+    for (int w = 0; w < kNormWays; ++w) m = std::max(m, h[w * kNormStride]);
+    std::memcpy(&rn, &m, sizeof(double));
+    if (hist) hist[it] = rn;
+    if (s->opts.verbose) fprintf(stderr, "amrmg cycle %d  max|r| = %.6e\n", it, rn);
+    if (!std::isfinite(rn)) {
+      *status = fail(MG_ERR_NAN, "residual norm is not finite");
+      return 1;
+    }
+    if (it == 0) first = rn;
+    if (rn <= tol) {
+      inf->converged = 1;
+      return 1;
+    }
+    if (it == s->opts.max_iter) {
+      *status = fail(MG_ERR_NOT_CONVERGED, "max_iter reached");
+      return 1;
+    }
+    if (it > 0) rising = rn > prev ? rising + 1 : 0;
+    if (rising >= 3 && rn > first) {
+      *status = fail(MG_ERR_DIVERGED, "residual grew for 3 cycles");
+      return 1;
+    }
+    prev2 = prev;
+    prev = rn;
+    return 0;
+  };
+  while (true) {
+    // the caller's ghosts may be stale; after a cycle they are current where
+    // its post-smoothing wrote through
+    if ((it == 0 || !l0.wt || s->opts.nu2 == 0) && (rc = exchange<double>(s, l0, cur, false)))
+      return rc;
+    const int slot = 1 + (it & 1);
+    HIPTRY(launch_fill_u64(s->st, norm_slot(s, slot), kNormSlot, 0ull));
+    {
+      ProfScope ps(s, 1, true);
+      HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell,
+                                              op, cur, F, rng, nullptr, norm_slot(s, slot), 0,
+                                              nullptr, nxt)));
+    }
+    HIPTRY(hipMemcpyAsync(s->h_norm + (size_t)slot * kNormSlot, norm_slot(s, slot),
+                          sizeof(unsigned long long) * kNormSlot, hipMemcpyDeviceToHost, s->st));
+    HIPTRY(hipEventRecord(s->ev_norm[it & 1], s->st));
+    bool wait = it < 2 || it >= s->opts.max_iter;
+    if (!wait) {
+      const double pred = prev * (prev / prev2);
+      wait = !(pred > 8.0 * tol);
+    }
+    if (wait) {
+      const int d = decide();
+      if (d < 0) return fail(MG_ERR_HIP, "norm read-back failed");
+      if (d) break;
+    }
+    if ((rc = exchange<double>(s, l0, nxt, false))) return rc;
+    if ((rc = vcycle64(s, nxt, F, rng, true))) return rc;
+    if (!wait) {
+      const int d = decide();
+      if (d < 0) return fail(MG_ERR_HIP, "norm read-back failed");
+      if (d) break;
+    }
+    std::swap(cur, nxt);
+    ++it;
+  }
+  if (cur != P)
+    HIPTRY(hipMemcpyAsync(P, cur, sizeof(double) * l0.n_g1, hipMemcpyDeviceToDevice, s->st));
+  inf->iters = it;
+  inf->abs_resid = rn;
+  return MG_OK;
+}
+
 int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, double rel_tol,
              double abs_tol, mg_info_t* info, double* resid_history) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -2569,6 +2698,11 @@ int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, doubl
     if (resid_history) resid_history[0] = 0.0;
   } else if (s->opts.krylov) {
     status = solve_pcg(s, P, F, rng, std::max(rel_tol * normf, abs_tol), &inf, resid_history);
+    inf.rel_resid = inf.abs_resid / normf;
+  } else if (l0.next64) {
+    if ((rc = solve_folded(s, P, F, rng, std::max(rel_tol * normf, abs_tol), &inf, resid_history,
+                           &status)))
+      return rc;
     inf.rel_resid = inf.abs_resid / normf;
   } else {
     const double tol = std::max(rel_tol * normf, abs_tol);
@@ -2676,10 +2810,18 @@ static int face_grad_run(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam,
   if ((rc = exchange<double>(s, l0, (double*)lam->data, false))) return rc;
   const int dlo[3] = {s->domain.lo[0], s->domain.lo[1], s->domain.lo[2]};
   const int dn[3] = {ext(s->domain, 0), ext(s->domain, 1), ext(s->domain, 2)};
-  for (int d = 0; d < 3; ++d)
-    HIPTRY(launch_face_grad(s->st, l0.d_info, l0.nbox, d, stencil_of<double>(s, l0, false),
-                            (const double*)phi->data, (const double*)lam->data, (double*)out[d],
-                            mode, dlo, dn, s->periodic[d], l0.max_faces));
+  int max_n[3] = {0, 0, 0};
+  for (const IBox& b : l0.boxes)
+    for (int d = 0; d < 3; ++d) max_n[d] = std::max(max_n[d], ext(b, d));
+  // 32-bit offsets inside a box's face arrays
+  if ((int64_t)(max_n[0] + 1) * (max_n[1] + 1) * (max_n[2] + 1) >= (int64_t(1) << 31))
+    return fail(MG_ERR_ARG, "face gradient: a box is too large for 32-bit face offsets");
+  const int perbits = (s->periodic[0] ? 1 : 0) | (s->periodic[1] ? 2 : 0) |
+                      (s->periodic[2] ? 4 : 0);
+  double* const o[3] = {(double*)out[0], (double*)out[1], (double*)out[2]};
+  HIPTRY(launch_face_grad(s->st, l0.nbox, stencil_of<double>(s, l0, false),
+                          (const double*)phi->data, (const double*)lam->data, o, mode, dlo, dn,
+                          perbits, max_n));
   return MG_OK;
 }
 
@@ -2731,6 +2873,8 @@ void mg_destroy(mg_solver_t* s) {
   for (hipEvent_t e : s->ev_pool) hipEventDestroy(e);
   if (s->ev_in) hipEventDestroy(s->ev_in);
   if (s->ev_out) hipEventDestroy(s->ev_out);
+  for (hipEvent_t e : s->ev_norm)
+    if (e) hipEventDestroy(e);
   if (s->h_norm) hipHostFree(s->h_norm);
   if (s->h_gm) hipHostFree(s->h_gm);
   if (s->st) hipStreamDestroy(s->st);
@@ -2871,9 +3015,9 @@ int mg_create_amr(const mg_box_t* cboxes, int32_t ncb, const mg_box_t* fboxes, i
   HIPTRY(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
   HIPTRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
   HIPTRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
-  HIPTRY(hipHostMalloc((void**)&s->h_norm, sizeof(unsigned long long) * (kNormSlot + 8),
+  HIPTRY(hipHostMalloc((void**)&s->h_norm, sizeof(unsigned long long) * (3 * kNormSlot + 8),
                        hipHostMallocDefault));
-  s->h_iters = reinterpret_cast<int*>(s->h_norm + kNormSlot);
+  s->h_iters = reinterpret_cast<int*>(s->h_norm + 3 * kNormSlot);
   {
     CallScope call(s.get());
     if ((rc = call.rc())) return rc;

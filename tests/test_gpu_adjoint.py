@@ -82,16 +82,67 @@ def test_adjoint_gradient_vs_oracle(precision):
     s.close()
 
 
+FACE_CASES = [
+    # (name, n, boxes, periodic)
+    ("dirichlet16_8boxes", 16, W.uniform_boxes(16, 8), (False, False, False)),
+    ("uneven32_periodic_y", 32, [((0, 0, 0), (15, 31, 31)), ((16, 0, 0), (31, 15, 31)),
+                                 ((16, 16, 0), (31, 31, 15)), ((16, 16, 16), (31, 31, 31))],
+     (False, True, False)),
+    ("periodic24_one_box", 24, [((0, 0, 0), (23, 23, 23))], (True, True, True)),
+    # x extent 96: two 64-lane x tiles per row, the second one ragged
+    ("wide96_periodic_xz", 96, [((0, 0, 0), (95, 47, 95)), ((0, 48, 0), (95, 95, 95))],
+     (True, False, True)),
+]
+
+
+def _face_case(n, boxes, periodic, seed):
+    cfg = W.config_lognormal(n, None, 0.5, boxes=boxes)
+    cfg["periodic"] = periodic
+    cfg["faces"] = W.harmonic_faces(W.lognormal_cells(n, 0.5, W.SEED_B), periodic)
+    rng = np.random.default_rng(seed)
+    return cfg, rng.standard_normal((n,) * 3), rng.standard_normal((n,) * 3)
+
+
 @pytest.mark.gpu
-def test_face_gradient_per_box_matches_global():
+@pytest.mark.parametrize("name,n,boxes,periodic", FACE_CASES, ids=[c[0] for c in FACE_CASES])
+def test_face_gradient_kernel_vs_oracle(name, n, boxes, periodic):
+    """The one-pass face-gradient kernel (all three directions, global face
+    arrays) on given phi and lambda against the oracle's dL/dlog b, on every
+    face: walls, periodic wrap faces (written at both ends), uneven boxes and
+    rows wider than one 64-lane tile."""
+    print(f"[adjoint] face gradient vs oracle {name}", flush=True)
     P = lib()
-    cfg = _problem(16, 8)
-    n, boxes = cfg["n"], cfg["boxes"]
-    s, f, logb, _ = _gpu_setup(cfg)
+    cfg, Pg, Lg = _face_case(n, boxes, periodic, 5)
+    s = P.MLMG(boxes, W.domain_box(n), periodic, 1.0, 1.0, opts=dict(tune=0))
+    logb = [torch.from_numpy(P.global_to_xfast(np.log(cfg["faces"][d]))).cuda() for d in range(3)]
     s.set_coefficients_global(logb, is_log=True)
-    rng = np.random.default_rng(3)
-    phi = P.MultiFab.from_numpy(boxes, W.scatter_cells(rng.standard_normal((n,) * 3), boxes, 1), 1)
-    lam = P.MultiFab.from_numpy(boxes, W.scatter_cells(rng.standard_normal((n,) * 3), boxes, 1), 1)
+    phi = P.MultiFab.from_numpy(boxes, W.scatter_cells(Pg, boxes, 1, fill=np.nan), 1)
+    lam = P.MultiFab.from_numpy(boxes, W.scatter_cells(Lg, boxes, 1, fill=np.nan), 1)
+    glob = s.face_grad_logb_global(phi, lam)
+    torch.cuda.synchronize()
+    lev = O.make_level(boxes, W.domain_box(n), periodic, 1.0, 1.0, None,
+                       [W.scatter_faces(cfg["faces"][d], boxes, d) for d in range(3)])
+    ref = O.grad_logb(lev, W.scatter_cells(Pg, boxes, 1), W.scatter_cells(Lg, boxes, 1))
+    for d in range(3):
+        got = P.xfast_to_global(glob[d])
+        assert got.shape == ref[d].shape
+        scale = np.abs(ref[d]).max()
+        err = np.abs(got - ref[d]).max()
+        print(f"  d={d}: max |gpu - oracle| = {err:.2e} of max {scale:.2e}")
+        assert err <= 1e-13 * scale
+    s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,n,boxes,periodic", FACE_CASES, ids=[c[0] for c in FACE_CASES])
+def test_face_gradient_per_box_matches_global(name, n, boxes, periodic):
+    P = lib()
+    cfg, Pg, Lg = _face_case(n, boxes, periodic, 3)
+    s = P.MLMG(boxes, W.domain_box(n), periodic, 1.0, 1.0, opts=dict(tune=0))
+    logb = [torch.from_numpy(P.global_to_xfast(np.log(cfg["faces"][d]))).cuda() for d in range(3)]
+    s.set_coefficients_global(logb, is_log=True)
+    phi = P.MultiFab.from_numpy(boxes, W.scatter_cells(Pg, boxes, 1), 1)
+    lam = P.MultiFab.from_numpy(boxes, W.scatter_cells(Lg, boxes, 1), 1)
     glob = s.face_grad_logb_global(phi, lam)
     per = [s.face_mf(d) for d in range(3)]
     s.face_grad_logb(phi, lam, per)

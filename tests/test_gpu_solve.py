@@ -359,6 +359,60 @@ def test_ghost_write_through_bitwise_equal_exchanges(name, make, boxes, extra):
     assert interp[0] > 0 and all(x == interp[0] for x in interp)
 
 
+STOP_FOLD_CASES = [
+    # (name, cfg maker, boxes or None, opts, rel_tol)
+    ("lognormal64_32boxes_converged", lambda: W.config_lognormal(64, 32), None, {}, 1e-10),
+    ("lognormal64_32boxes_max_iter", lambda: W.config_lognormal(64, 32), None,
+     dict(max_iter=3), 1e-10),
+    ("lognormal64_16boxes_no_graph_no_write_through", lambda: W.config_lognormal(64, 16), None,
+     dict(use_graph=0, ghost_write=0), 1e-10),
+    ("lognormal64_16boxes_nu1_nu2_1", lambda: W.config_lognormal(64, 16), None,
+     dict(nu1=1, nu2=1), 1e-9),
+    ("lognormal64_16boxes_nu2_0", lambda: W.config_lognormal(64, 16), None,
+     dict(nu1=3, nu2=0), 1e-8),
+    ("poisson32_periodic_singular", W.config_c0, None, {}, 1e-10),
+    ("uneven_periodic_y", lambda: dict(W.config_c0(), periodic=(False, True, False)),
+     [((0, 0, 0), (15, 31, 31)), ((16, 0, 0), (31, 15, 31)), ((16, 16, 0), (31, 31, 15)),
+      ((16, 16, 16), (31, 31, 31))], {}, 1e-10),
+    ("lognormal192_27boxes_buffer_loads", lambda: W.config_lognormal(192, 64), None, {}, 1e-10),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,make,boxes,extra,tol", STOP_FOLD_CASES,
+                         ids=[c[0] for c in STOP_FOLD_CASES])
+def test_stop_fold_bitwise_equal_plain_loop(name, make, boxes, extra, tol):
+    """The stop test's residual pass that also performs the next cycle's red
+    half-sweep into the second level-0 array (iterates alternating between
+    the two, norms read one pass behind) gives the same norms, cycle count,
+    status and solution bits as a norm-only residual pass before each cycle."""
+    print(f"[solve] folded stop test vs plain loop {name}", flush=True)
+    P = lib()
+    cfg = make()
+    boxes = boxes or cfg["boxes"]
+    f = cfg["rhs"] - (cfg["rhs"].mean() if all(cfg["periodic"]) else 0.0)
+    rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(f, boxes), 0)
+    outs, infos = [], []
+    for sf in (1, 0):
+        s = gpu_solver(cfg, boxes=boxes, opts=dict(tune=0, bottom_rel_tol=TIGHT, stop_fold=sf,
+                                                   **extra))
+        phi = s.cell_mf(1, fill=0.0)
+        info = s.solve(phi, rhs, tol, raise_on_fail=False, history=True)
+        torch.cuda.synchronize()
+        outs.append(to_global(phi, boxes, cfg["n"]))
+        infos.append(info)
+        s.close()
+    assert np.all(np.isfinite(outs[0]))
+    assert np.array_equal(outs[0], outs[1])
+    assert infos[0]["iters"] == infos[1]["iters"]
+    assert infos[0]["converged"] == infos[1]["converged"]
+    assert list(infos[0]["history"]) == list(infos[1]["history"])
+    if "max_iter" in extra:
+        assert not infos[0]["converged"] and infos[0]["iters"] == extra["max_iter"]
+    else:
+        assert infos[0]["converged"]
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("variant", ["f64", "f32_refine", "f64_mgpcg"])
 def test_c1_bench_configuration(variant, monkeypatch):

@@ -19,7 +19,10 @@ Block-Structured Adaptive Mesh Refinement for Multiphysics Applications"):
   scalar alpha/beta, ``a`` per cell and ``b`` per face;
 * a geometric multigrid V-cycle with a CG bottom solve ("Linear Solvers"),
   with averaging restriction and piecewise-constant interpolation ("Operations
-  between levels").
+  between levels");
+* the nodal solver of the same section (``oracle.nodal``): the trilinear
+  finite-element operator of -div(sigma grad phi) built from the cells' moment
+  integrals, Galerkin coarse operators, Jacobi smoothing, CG bottom.
 
 The paper does not fix the smoother, the transfer operators, the coefficient
 coarsening, the boundary stencil, the bottom tolerance or the stopping norm;

@@ -313,6 +313,20 @@ void mg_destroy(mg_solver_t* s);
 int fill_boundary(mg_multifab_t* mf, const mg_geom_t* geom, void* hip_stream);
 int mg_fill_boundary(mg_multifab_t* mf, const mg_geom_t* geom, void* hip_stream);
 
+/* fill_boundary for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as fill_boundary, bit for bit, and it
+ * calls no hipMalloc/hipFree: the exchange plan (64 bytes per copy tag plus
+ * 8 bytes per 256 ghost cells of a tag) is copied on hip_stream into a
+ * static device array of 4 MiB that the library holds on each device it
+ * runs on until the process ends.  A plan larger than that returns
+ * MG_ERR_WORKSPACE without launching anything (fill_boundary then serves the
+ * layout).  Every call on one device shares that array: calls that overlap
+ * on one device (other streams or threads) race and must be ordered by the
+ * caller.  The host side of the plan is built with ordinary host memory
+ * and cached like fill_boundary's.  Asynchronous on hip_stream. */
+int mg_fill_boundary_noalloc(mg_multifab_t* mf, const mg_geom_t* geom, void* hip_stream);
+
 /* The copy tags fill_boundary applies, in canonical order (dst, src, shift,
  * region lo), built by hash intersection ("Communication").  Host only.
  * Writes up to cap tags to out (out may be NULL when cap = 0) and the total

@@ -13,6 +13,7 @@ from .solver import (  # noqa: F401
     CompositeMLMG,
     copy_tags,
     fill_boundary,
+    fill_boundary_noalloc,
     num_levels,
     release_caches,
     stream_copy,

@@ -93,6 +93,7 @@ SIGNATURES = {
     "mg_destroy": (None, [C.c_void_p]),
     "fill_boundary": (C.c_int, [P(MgMultiFab), P(MgGeom), C.c_void_p]),
     "mg_fill_boundary": (C.c_int, [P(MgMultiFab), P(MgGeom), C.c_void_p]),
+    "mg_fill_boundary_noalloc": (C.c_int, [P(MgMultiFab), P(MgGeom), C.c_void_p]),
     "mg_copy_tags": (C.c_int, [P(MgBox), C.c_int32, P(MgGeom), C.c_int32, P(MgCopyTag),
                                C.c_int32, P(C.c_int32)]),
     "mg_num_levels": (C.c_int, [P(MgBox), C.c_int32, P(MgGeom), P(MgOpts), P(C.c_int32)]),

@@ -81,29 +81,39 @@ int mg_copy_tags(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom, int
   return MG_OK;
 }
 
-int fill_boundary(mg_multifab_t* mf, const mg_geom_t* geom, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by both exchanges; *skip = nothing to exchange.
+int check_fb_args(const mg_multifab_t* mf, const mg_geom_t* geom, const char* who, bool* skip) {
+  *skip = false;
   if (!mf || !geom || !mf->boxes || !mf->offsets || mf->nbox <= 0) {
-    set_error("fill_boundary: bad argument");
+    set_error(std::string(who) + ": bad argument");
     return MG_ERR_ARG;
   }
   if (mf->ixtype[0] || mf->ixtype[1] || mf->ixtype[2]) {
-    set_error("fill_boundary: only cell-centred MultiFabs are supported");
+    set_error(std::string(who) + ": only cell-centred MultiFabs are supported");
     return MG_ERR_ARG;
   }
   if (mf->ngrow < 0 || mf->ncomp < 1 || (mf->dtype != MG_F64 && mf->dtype != MG_F32)) {
-    set_error("fill_boundary: bad ngrow, ncomp or dtype");
+    set_error(std::string(who) + ": bad ngrow, ncomp or dtype");
     return MG_ERR_ARG;
   }
-  if (mf->ngrow == 0) return MG_OK;
+  if (mf->ngrow == 0) {
+    *skip = true;
+    return MG_OK;
+  }
   if (!mf->data) {
-    set_error("fill_boundary: data is null");
+    set_error(std::string(who) + ": data is null");
     return MG_ERR_ARG;
   }
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) {
-    set_error("fill_boundary: no HIP device");
-    return MG_ERR_HIP;
-  }
+  return MG_OK;
+}
+
+// The cached plan of this layout on device dev, built on first use (host
+// tables only; the device copy is made by the caller that needs one).
+int find_plan(const mg_multifab_t* mf, const mg_geom_t* geom, int dev, FbPlan** out) {
   std::string key;
   put(key, dev);
   put(key, mf->ngrow);
@@ -113,56 +123,125 @@ int fill_boundary(mg_multifab_t* mf, const mg_geom_t* geom, void* hip_stream) {
   put(key, mf->nbox);
   key.append(reinterpret_cast<const char*>(mf->boxes), sizeof(mg_box_t) * mf->nbox);
   key.append(reinterpret_cast<const char*>(mf->offsets), sizeof(int64_t) * mf->nbox);
+  auto it = g_cache.find(key);
+  if (it != g_cache.end()) {
+    *out = it->second.get();
+    return MG_OK;
+  }
+  std::vector<IBox> bx(mf->nbox);
+  for (int i = 0; i < mf->nbox; ++i) bx[i] = to_ibox(mf->boxes[i]);
+  const IBox dom = to_ibox(geom->domain);
+  std::string err;
+  if (!validate_boxes(bx, dom, false, &err)) {
+    set_error(err);
+    return MG_ERR_INVALID_BOXARRAY;
+  }
+  const int per[3] = {geom->is_periodic[0] != 0, geom->is_periodic[1] != 0,
+                      geom->is_periodic[2] != 0};
+  std::vector<int64_t> offs(mf->offsets, mf->offsets + mf->nbox);
+  std::unique_ptr<FbPlan> p(new FbPlan());
+  make_fb_tables(bx, dom, per, mf->ngrow, offs, mf->ncomp, p->tags, p->chunks);
+  p->device = dev;
+  *out = p.get();
+  g_cache[key] = std::move(p);
+  return MG_OK;
+}
 
+hipError_t launch_plan(const mg_multifab_t* mf, hipStream_t st, const FbTag* tags,
+                       const FbChunk* chunks, int nchunks) {
+  if (mf->dtype == MG_F64)
+    return launch_fill_boundary<double>(st, tags, chunks, nchunks, static_cast<double*>(mf->data),
+                                        mf->ncomp);
+  return launch_fill_boundary<float>(st, tags, chunks, nchunks, static_cast<float*>(mf->data),
+                                     mf->ncomp);
+}
+
+// Byte offset of the chunk table behind the tag table in the static scratch.
+size_t chunk_offset(size_t ntags) { return (sizeof(FbTag) * ntags + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" {
+
+int fill_boundary(mg_multifab_t* mf, const mg_geom_t* geom, void* hip_stream) {
+  bool skip = false;
+  int rc = check_fb_args(mf, geom, "fill_boundary", &skip);
+  if (rc != MG_OK || skip) return rc;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    set_error("fill_boundary: no HIP device");
+    return MG_ERR_HIP;
+  }
   FbPlan* plan = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mtx);
-    auto it = g_cache.find(key);
-    if (it != g_cache.end()) {
-      plan = it->second.get();
-    } else {
-      std::vector<IBox> bx(mf->nbox);
-      for (int i = 0; i < mf->nbox; ++i) bx[i] = to_ibox(mf->boxes[i]);
-      const IBox dom = to_ibox(geom->domain);
-      std::string err;
-      if (!validate_boxes(bx, dom, false, &err)) {
-        set_error(err);
-        return MG_ERR_INVALID_BOXARRAY;
+    rc = find_plan(mf, geom, dev, &plan);
+    if (rc != MG_OK) return rc;
+    if (!plan->tags.empty() && !plan->d_tags) {
+      FbTag* dt = nullptr;
+      FbChunk* dc = nullptr;
+      if (hipMalloc((void**)&dt, sizeof(FbTag) * plan->tags.size()) != hipSuccess ||
+          hipMalloc((void**)&dc, sizeof(FbChunk) * plan->chunks.size()) != hipSuccess ||
+          hipMemcpy(dt, plan->tags.data(), sizeof(FbTag) * plan->tags.size(),
+                    hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(dc, plan->chunks.data(), sizeof(FbChunk) * plan->chunks.size(),
+                    hipMemcpyHostToDevice) != hipSuccess) {
+        if (dt) hipFree(dt);
+        if (dc) hipFree(dc);
+        set_error("fill_boundary: could not upload the exchange plan");
+        return MG_ERR_HIP;
       }
-      const int per[3] = {geom->is_periodic[0] != 0, geom->is_periodic[1] != 0,
-                          geom->is_periodic[2] != 0};
-      std::vector<int64_t> offs(mf->offsets, mf->offsets + mf->nbox);
-      std::unique_ptr<FbPlan> p(new FbPlan());
-      make_fb_tables(bx, dom, per, mf->ngrow, offs, mf->ncomp, p->tags, p->chunks);
-      p->device = dev;
-      if (!p->tags.empty()) {
-        if (hipMalloc((void**)&p->d_tags, sizeof(FbTag) * p->tags.size()) != hipSuccess ||
-            hipMalloc((void**)&p->d_chunks, sizeof(FbChunk) * p->chunks.size()) != hipSuccess ||
-            hipMemcpy(p->d_tags, p->tags.data(), sizeof(FbTag) * p->tags.size(),
-                      hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(p->d_chunks, p->chunks.data(), sizeof(FbChunk) * p->chunks.size(),
-                      hipMemcpyHostToDevice) != hipSuccess) {
-          if (p->d_tags) hipFree(p->d_tags);
-          if (p->d_chunks) hipFree(p->d_chunks);
-          set_error("fill_boundary: could not upload the exchange plan");
-          return MG_ERR_HIP;
-        }
-      }
-      plan = p.get();
-      g_cache[key] = std::move(p);
+      plan->d_tags = dt;
+      plan->d_chunks = dc;
     }
   }
   if (plan->chunks.empty()) return MG_OK;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  hipError_t e;
-  if (mf->dtype == MG_F64)
-    e = launch_fill_boundary<double>(st, plan->d_tags, plan->d_chunks, (int)plan->chunks.size(),
-                                     static_cast<double*>(mf->data), mf->ncomp);
-  else
-    e = launch_fill_boundary<float>(st, plan->d_tags, plan->d_chunks, (int)plan->chunks.size(),
-                                    static_cast<float*>(mf->data), mf->ncomp);
+  const hipError_t e = launch_plan(mf, static_cast<hipStream_t>(hip_stream), plan->d_tags,
+                                   plan->d_chunks, (int)plan->chunks.size());
   if (e != hipSuccess) {
     set_error(std::string("fill_boundary: ") + hipGetErrorString(e));
+    return MG_ERR_HIP;
+  }
+  return MG_OK;
+}
+
+int mg_fill_boundary_noalloc(mg_multifab_t* mf, const mg_geom_t* geom, void* hip_stream) {
+  bool skip = false;
+  int rc = check_fb_args(mf, geom, "mg_fill_boundary_noalloc", &skip);
+  if (rc != MG_OK || skip) return rc;
+  int dev = 0;
+  void* scr = nullptr;
+  if (hipGetDevice(&dev) != hipSuccess || fb_scratch_address(&scr) != hipSuccess) {
+    set_error("mg_fill_boundary_noalloc: no HIP device or no scratch address");
+    return MG_ERR_HIP;
+  }
+  FbPlan* plan = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mtx);
+    rc = find_plan(mf, geom, dev, &plan);
+    if (rc != MG_OK) return rc;
+  }
+  if (plan->chunks.empty()) return MG_OK;
+  const size_t coff = chunk_offset(plan->tags.size());
+  const size_t need = coff + sizeof(FbChunk) * plan->chunks.size();
+  if (need > kFbScratchBytes) {
+    set_error("mg_fill_boundary_noalloc: the exchange plan needs " + std::to_string(need) +
+              " bytes, more than the " + std::to_string(kFbScratchBytes) +
+              " bytes of static scratch; use fill_boundary");
+    return MG_ERR_WORKSPACE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  unsigned char* base = static_cast<unsigned char*>(scr);
+  hipError_t e = hipMemcpyAsync(base, plan->tags.data(), sizeof(FbTag) * plan->tags.size(),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + coff, plan->chunks.data(), sizeof(FbChunk) * plan->chunks.size(),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = launch_plan(mf, st, reinterpret_cast<const FbTag*>(base),
+                    reinterpret_cast<const FbChunk*>(base + coff), (int)plan->chunks.size());
+  if (e != hipSuccess) {
+    set_error(std::string("mg_fill_boundary_noalloc: ") + hipGetErrorString(e));
     return MG_ERR_HIP;
   }
   return MG_OK;

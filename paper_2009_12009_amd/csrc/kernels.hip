@@ -14,6 +14,7 @@
 // access is x-contiguous across the lanes of a wavefront.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -2176,6 +2177,32 @@ hipError_t launch_fill_boundary(hipStream_t st, const FbTag* tags, const FbChunk
   hipLaunchKernelGGL(k_fill_boundary<T>, dim3(nchunks), dim3(FB_CHUNK), 0, st, tags, chunks, data,
                      ncomp);
   return hipGetLastError();
+}
+
+// Fixed device scratch of the allocation-free ghost exchange: the copy plan
+// (tags, then chunks) of the last such call on this device.  In host code the
+// array's name is not a device address; fb_scratch_address() returns the
+// address the runtime resolved for the current device.
+static __device__ __align__(256) unsigned char scratch[kFbScratchBytes];
+
+hipError_t fb_scratch_address(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mtx;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mtx);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_fill_u64(hipStream_t st, unsigned long long* p, int n, unsigned long long v) {

@@ -193,6 +193,11 @@ hipError_t launch_fill_boundary(hipStream_t st, const FbTag* tags, const FbChunk
 
 // Plain element-wise helpers over n elements.
 hipError_t launch_fill_u64(hipStream_t st, unsigned long long* p, int n, unsigned long long v);
+
+// Size of the static device scratch of the allocation-free ghost exchange,
+// and its address on the current device (looked up once per device).
+constexpr size_t kFbScratchBytes = size_t(4) << 20;
+hipError_t fb_scratch_address(void** ptr);
 template <typename TI, typename TO>
 hipError_t launch_convert(hipStream_t st, const TI* in, TO* out, long long n);
 // out = in over n16 16-byte elements (both 16-byte aligned), one per lane.

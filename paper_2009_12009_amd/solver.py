@@ -63,6 +63,15 @@ def fill_boundary(mf, domain, periodic, stream=None):
     L.check(L.lib.fill_boundary(C.byref(m), C.byref(g), _stream_handle(stream)), "fill_boundary")
 
 
+def fill_boundary_noalloc(mf, domain, periodic, stream=None):
+    """fill_boundary without device allocation (plan staged in the library's
+    static device scratch; overlapping calls on one device race)."""
+    g = L.geom_struct(domain, periodic)
+    m = mf.c_struct()
+    L.check(L.lib.mg_fill_boundary_noalloc(C.byref(m), C.byref(g), _stream_handle(stream)),
+            "mg_fill_boundary_noalloc")
+
+
 def stream_copy(dst, src, stream=None):
     """dst.copy_(src) with the library's streaming kernel (contiguous device
     tensors of equal byte size, 16-byte aligned)."""

@@ -390,6 +390,65 @@ int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, in
  * lx = 0 when it has no fused sweep at all).  shape: host int32_t[5]. */
 int mg_get_tile_shape(mg_solver_t* s, int32_t kernel, int32_t* shape);
 
+/* ---------------------------------------------------------------------------
+ * Nodal solver ("Linear Solvers": the nodal solver is built on finite
+ * elements, its stencil from moment integrals over the cells, its coarse
+ * operators from an algebraic coarsening).
+ *
+ * Solves -div(sigma grad phi) = f for phi at the nodes of the cell grid:
+ * phi is the continuous piecewise-trilinear function of its nodal values, the
+ * equation is tested with every nodal hat function, f is lumped to the nodes
+ * and every row divided by the cell volume:
+ *   (A phi)_p = (1/V) sum_{cells c at p} sigma_c sum_{corners q of c} K_pq phi_q,
+ * K the trilinear cell stiffness assembled from the 1D moment integrals
+ * int l_a l_b = h/3 or h/6 and int l_a' l_b' = +-1/h.  Walls are homogeneous
+ * Dirichlet (phi = 0 on every wall node: bc MG_BC_DIRICHLET0 on both sides
+ * of a non-periodic direction), periodic directions wrap (MG_BC_PERIODIC on
+ * both sides).  All periodic: the problem is singular; the bottom removes
+ * the mean of its right-hand side and the returned phi has zero mean.
+ *
+ * Multigrid: levels halve the cell count while every count stays even and
+ * half of it is >= opts.min_bottom_edge (at least two levels are required);
+ * interpolation trilinear, restriction its transpose / 8; coarse operators
+ * R A P (Galerkin, 27 couplings per node, exactly symmetric); Jacobi
+ * smoothing with weight 1 (nu1 >= 1 and nu2 sweeps); unpreconditioned CG at
+ * the bottom to opts.bottom_rel_tol; stop at max|f - A phi| over the unknown
+ * nodes <= max(rel_tol * max|f|, abs_tol).  FP64 only (precision 0, krylov
+ * 0); opts.use_graph replays the coarse levels as a HIP graph.
+ *
+ * Data: boxes must cover the domain.  sigma is a cell MultiFab (ixtype 0,
+ * ngrow 0) over the boxes, or NULL for sigma = 1; phi and rhs are nodal
+ * MultiFabs (ixtype 1,1,1: box lo..hi holds nodes lo..hi+1 grown by ngrow,
+ * ngrow 0 or 1), FP64, one component, canonical packing (boxes one after
+ * another, x fastest), else MG_ERR_MISMATCH.  A node that several boxes hold
+ * is read from the box whose cell range contains the node's index; on
+ * return every node of every box array inside the domain (ghosts included,
+ * walls 0, periodic images wrapped) holds the solution.  Ghost nodes beyond a
+ * wall are not written.
+ *
+ * Workspace: caller-owned device memory of mg_nodal_query_workspace bytes
+ * (per level: iterate, rhs and residual arrays over the unknown nodes plus
+ * one ghost layer; coarse levels 14 coupling arrays), which must outlive
+ * the handle.  The solver copies sigma; sigma may be freed after create.
+ * Streams and errors as for mg_create / mg_solve.  mg_nodal_solve returns
+ * after its result is complete; mg_nodal_apply is asynchronous. */
+typedef struct mg_nodal mg_nodal_t;
+
+int mg_nodal_query_workspace(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
+                             const mg_opts_t* opts, size_t* bytes);
+int mg_nodal_create(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
+                    const int32_t bc_lo[3], const int32_t bc_hi[3], const mg_multifab_t* sigma,
+                    const mg_opts_t* opts, void* workspace, size_t ws_bytes, void* hip_stream,
+                    mg_nodal_t** out);
+/* phi: in the initial guess, out the solution; info and resid_history (host,
+ * max_iter + 1 entries, max-norm residual before each cycle) nullable. */
+int mg_nodal_solve(mg_nodal_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, double rel_tol,
+                   double abs_tol, mg_info_t* info, double* resid_history);
+/* out = A phi on every node of out's arrays inside the domain (walls 0). */
+int mg_nodal_apply(mg_nodal_t* s, const mg_multifab_t* phi, mg_multifab_t* out);
+int mg_nodal_num_levels(const mg_nodal_t* s, int32_t* nlevels);
+void mg_nodal_destroy(mg_nodal_t* s);
+
 /* Free the device tables of fill_boundary's plan cache. */
 void mg_release_caches(void);
 

@@ -20,3 +20,4 @@ from .solver import (  # noqa: F401
     workspace_bytes,
 )
 from .autograd import MGSolve, mg_solve  # noqa: F401
+from .nodal import NodalMLMG, nodal_workspace_bytes  # noqa: F401

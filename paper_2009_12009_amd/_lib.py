@@ -112,6 +112,16 @@ SIGNATURES = {
                                 C.c_void_p, C.c_size_t, C.c_void_p, P(C.c_void_p)]),
     "mg_solve_amr": (C.c_int, [C.c_void_p, P(MgMultiFab), P(MgMultiFab), P(MgMultiFab),
                                P(MgMultiFab), C.c_double, C.c_double, P(MgInfo), P(C.c_double)]),
+    "mg_nodal_query_workspace": (C.c_int, [P(MgBox), C.c_int32, P(MgGeom), P(MgOpts),
+                                           P(C.c_size_t)]),
+    "mg_nodal_create": (C.c_int, [P(MgBox), C.c_int32, P(MgGeom), P(C.c_int32), P(C.c_int32),
+                                  P(MgMultiFab), P(MgOpts), C.c_void_p, C.c_size_t, C.c_void_p,
+                                  P(C.c_void_p)]),
+    "mg_nodal_solve": (C.c_int, [C.c_void_p, P(MgMultiFab), P(MgMultiFab), C.c_double,
+                                 C.c_double, P(MgInfo), P(C.c_double)]),
+    "mg_nodal_apply": (C.c_int, [C.c_void_p, P(MgMultiFab), P(MgMultiFab)]),
+    "mg_nodal_num_levels": (C.c_int, [C.c_void_p, P(C.c_int32)]),
+    "mg_nodal_destroy": (None, [C.c_void_p]),
     "mg_release_caches": (None, []),
     "mg_last_error": (C.c_char_p, []),
 }

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libamrmg.so")
 
-SOURCES = ["host.cpp", "fb.cpp", "solver.cpp", "kernels.hip"]
+SOURCES = ["host.cpp", "fb.cpp", "solver.cpp", "kernels.hip", "nodal.cpp", "nodal_kernels.hip"]
 
 ARCH = os.environ.get("AMRMG_ARCH", "gfx950")
 

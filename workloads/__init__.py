@@ -211,3 +211,64 @@ def config_c3():
     c["faces_target"] = harmonic_faces(bt, c["periodic"])
     c["name"] = "adjoint128"
     return c
+
+
+# ---------------------------------------------------------------------------
+# Nodal workload: node-centred unknowns on the same cell grid.
+
+def nodal_unknown_shape(n, periodic):
+    """Unknown nodes per direction: interior nodes along a wall direction,
+    nodes 0 .. n-1 along a periodic one."""
+    n = (n,) * 3 if np.isscalar(n) else tuple(n)
+    return tuple(n[d] if periodic[d] else n[d] - 1 for d in range(3))
+
+
+def nodes_from_unknowns(U, n, periodic):
+    """All nodes 0 .. n_d (shape n + 1) from the unknowns: 0 on wall nodes,
+    node n_d = node 0 along a periodic direction."""
+    n = (n,) * 3 if np.isscalar(n) else tuple(n)
+    G = np.zeros(tuple(x + 1 for x in n), dtype=U.dtype)
+    sl = tuple(slice(0, n[d]) if periodic[d] else slice(1, n[d]) for d in range(3))
+    G[sl] = U
+    for d in range(3):
+        if periodic[d]:
+            a = [slice(None)] * 3
+            b = [slice(None)] * 3
+            a[d] = slice(n[d], n[d] + 1)
+            b[d] = slice(0, 1)
+            G[tuple(a)] = G[tuple(b)]
+    return G
+
+
+def unknowns_from_nodes(G, periodic):
+    n = tuple(x - 1 for x in G.shape)
+    sl = tuple(slice(0, n[d]) if periodic[d] else slice(1, n[d]) for d in range(3))
+    return np.array(G[sl])
+
+
+def scatter_nodes(G, boxes, ng=0, fill=0.0, dlo=(0, 0, 0)):
+    """Per-box nodal arrays (nodes lo .. hi+1, ghost nodes set to ``fill``)
+    from an array of all nodes (shape n + 1)."""
+    out = []
+    for lo, hi in boxes:
+        shp = tuple(hi[d] - lo[d] + 2 + 2 * ng for d in range(3))
+        a = np.full(shp, fill, dtype=G.dtype)
+        v = G[lo[0] - dlo[0]:hi[0] - dlo[0] + 2, lo[1] - dlo[1]:hi[1] - dlo[1] + 2,
+              lo[2] - dlo[2]:hi[2] - dlo[2] + 2]
+        if ng > 0:
+            a[ng:-ng, ng:-ng, ng:-ng] = v
+        else:
+            a[...] = v
+        out.append(a)
+    return out
+
+
+def config_nodal(n, max_grid_size, sigma=1.0, periodic=(False, False, False), seed_b=SEED_B,
+                 seed_rhs=SEED_RHS):
+    """Nodal -div(sigma grad phi) = f: cell sigma = exp(sigma Z) (seed 1), f ~
+    U[-1, 1] on the unknown nodes (seed 2, one draw of the unknown shape)."""
+    per = tuple(bool(p) for p in periodic)
+    rng = np.random.default_rng(seed_rhs)
+    f = rng.uniform(-1.0, 1.0, nodal_unknown_shape(n, per))
+    return dict(name=f"nodal{n}", n=n, boxes=uniform_boxes(n, max_grid_size), periodic=per,
+                sigma_cells=lognormal_cells(n, sigma, seed_b), rhs_unknowns=f)

@@ -447,6 +447,11 @@ int mg_nodal_solve(mg_nodal_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, 
 /* out = A phi on every node of out's arrays inside the domain (walls 0). */
 int mg_nodal_apply(mg_nodal_t* s, const mg_multifab_t* phi, mg_multifab_t* out);
 int mg_nodal_num_levels(const mg_nodal_t* s, int32_t* nlevels);
+/* Mean duration of one finest-level Jacobi sweep launched alone reps times
+ * (between two of the solver's level-0 buffers, on the values the last solve
+ * left there), timed with HIP events on the solver's stream.  For roofline
+ * measurements; the solver's iterate buffers are overwritten. */
+int mg_nodal_time_smoother(mg_nodal_t* s, int32_t reps, double* mean_ms);
 void mg_nodal_destroy(mg_nodal_t* s);
 
 /* Free the device tables of fill_boundary's plan cache. */

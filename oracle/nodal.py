@@ -149,11 +149,12 @@ def _cells_at(sigma, s, periodic, m):
     return out
 
 
-def make_nodal_level(sigma, periodic):
-    """Finest level from the cell coefficient (n_x, n_y, n_z) on the unit cube."""
+def make_nodal_level(sigma, periodic, h=None):
+    """Finest level from the cell coefficient (n_x, n_y, n_z); cell widths h
+    (default: the unit cube, h_d = 1 / n_d)."""
     sigma = np.asarray(sigma, dtype=np.float64)
     n = sigma.shape
-    h = tuple(1.0 / n[d] for d in range(3))
+    h = tuple(1.0 / n[d] for d in range(3)) if h is None else tuple(float(x) for x in h)
     lev = NodalLevel(tuple(n), tuple(bool(p) for p in periodic), h, sigma)
     lev.w = fine_weights(lev)
     return lev
@@ -422,6 +423,85 @@ def nodal_solve(sigma, periodic, f, rel_tol=1e-10, abs_tol=0.0, opts=None, phi0=
         phi = nodal_vcycle(levs, 0, phi, f, opts)
         it += 1
     if is_singular_nodal(lev):
+        phi = phi - phi.mean()
+    info["iters"] = it
+    return phi, info
+
+
+def nodal_precond(levs, r, opts):
+    """One V-cycle from a zero guess on the finest level: z = M r.  With
+    nu1 = nu2 the cycle is a symmetric operator (a Jacobi sweep is
+    self-adjoint in the energy inner product, the coarse correction
+    P (R A P)^-1 R with R = P^T / 8 is symmetric)."""
+    return nodal_vcycle(levs, 0, None, r, opts, zero_guess=True)
+
+
+def nodal_pcg_solve(sigma, periodic, f, rel_tol=1e-10, abs_tol=0.0, opts=None, phi0=None,
+                    levs=None, precond=None):
+    """Conjugate gradients on A phi = f preconditioned by one V-cycle per
+    iteration (the paper's Krylov CG with its multigrid as preconditioner).
+
+    From r = f - A phi: z = M r, rho = r.z, p = z (then p = z + (rho/rho_old)
+    p), q = A p, alpha = rho / p.q, phi += alpha p, r -= alpha q.  Stop when
+    max|r| <= max(rel_tol max|f|, abs_tol), confirmed on the true residual f -
+    A phi; if that is above the tolerance, r is replaced by it and the
+    recurrence restarts from p = M r.  Dots are float64 sums.  All periodic:
+    the mean is taken out of r at the start and after a restart, out of every
+    z, and out of phi at the end.  ``precond(r) -> z`` replaces the V-cycle
+    (the identity gives plain CG).  Returns (phi, info) with info["history"][k]
+    = max|r| after k iterations."""
+    opts = opts or NodalOpts()
+    levs = levs or build_nodal_levels(sigma, periodic, opts)
+    lev = levs[0]
+    singular = is_singular_nodal(lev)
+    if precond is None:
+        def precond(r):
+            return nodal_precond(levs, r, opts)
+    f = np.asarray(f, dtype=np.float64)
+    phi = np.zeros(lev.m) if phi0 is None else np.array(phi0, dtype=np.float64)
+    normf = float(np.max(np.abs(f)))
+    info = {"iters": 0, "history": [], "converged": False, "normf": normf,
+            "nlevels": len(levs), "restarts": 0}
+    if normf == 0.0:
+        info["converged"] = True
+        return np.zeros(lev.m), info
+    tol = max(rel_tol * normf, abs_tol)
+
+    def true_residual():
+        r = nodal_residual(lev, phi, f)
+        return r - r.mean() if singular else r
+
+    r = true_residual()
+    p = None
+    rho = None
+    it = 0
+    while True:
+        rn = float(np.max(np.abs(r)))
+        info["history"].append(rn)
+        if not np.isfinite(rn):
+            break
+        if rn <= tol:
+            rt = true_residual()
+            if float(np.max(np.abs(rt))) <= tol:
+                info["converged"] = True
+                break
+            r = rt
+            p = None
+            info["restarts"] += 1
+        if it == opts.max_iter:
+            break
+        z = precond(r)
+        if singular:
+            z = z - z.mean()
+        rho_new = float(np.sum(r * z))
+        p = z.copy() if p is None else z + (rho_new / rho) * p
+        rho = rho_new
+        q = apply_nodal(lev, p)
+        alpha = rho / float(np.sum(p * q))
+        phi = phi + alpha * p
+        r = r - alpha * q
+        it += 1
+    if singular:
         phi = phi - phi.mean()
     info["iters"] = it
     return phi, info

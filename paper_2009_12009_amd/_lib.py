@@ -121,6 +121,7 @@ SIGNATURES = {
                                  C.c_double, P(MgInfo), P(C.c_double)]),
     "mg_nodal_apply": (C.c_int, [C.c_void_p, P(MgMultiFab), P(MgMultiFab)]),
     "mg_nodal_num_levels": (C.c_int, [C.c_void_p, P(C.c_int32)]),
+    "mg_nodal_time_smoother": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double)]),
     "mg_nodal_destroy": (None, [C.c_void_p]),
     "mg_release_caches": (None, []),
     "mg_last_error": (C.c_char_p, []),

@@ -648,6 +648,32 @@ int mg_nodal_apply(mg_nodal_t* s, const mg_multifab_t* phi, mg_multifab_t* out) 
   return call.finish();
 }
 
+int mg_nodal_time_smoother(mg_nodal_t* s, int32_t reps, double* mean_ms) {
+  if (!s || reps < 1 || !mean_ms) return fail(MG_ERR_ARG, "bad argument");
+  NdCall call(s);
+  int rc;
+  if ((rc = call.rc())) return rc;
+  NdLevel& l0 = s->L[0];
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPTRY(hipEventCreate(&a));
+  HIPTRY(hipEventCreate(&b));
+  auto one = [&](int k) {
+    return sweep(s, 0, l0.x[k & 1], l0.f, l0.x[1 - (k & 1)], ND_JACOBI, nullptr);
+  };
+  for (int k = 0; k < 2 && !rc; ++k) rc = one(k);
+  if (!rc && hipEventRecord(a, s->st) != hipSuccess) rc = fail(MG_ERR_HIP, "event record");
+  for (int k = 0; k < reps && !rc; ++k) rc = one(k);
+  if (!rc && hipEventRecord(b, s->st) != hipSuccess) rc = fail(MG_ERR_HIP, "event record");
+  float ms = 0.f;
+  if (!rc && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
+    rc = fail(MG_ERR_HIP, "event timing");
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  if (rc) return rc;
+  *mean_ms = ms / reps;
+  return call.finish();
+}
+
 int mg_nodal_num_levels(const mg_nodal_t* s, int32_t* nlevels) {
   if (!s || !nlevels) return fail(MG_ERR_ARG, "bad argument");
   *nlevels = (int32_t)s->L.size();

@@ -83,6 +83,13 @@ class NodalMLMG:
             out["history"] = list(hist[:info.iters + 1])
         return out
 
+    def time_smoother(self, reps=20):
+        """Mean ms of one finest-level Jacobi sweep (HIP events, solver stream)."""
+        ms = C.c_double()
+        L.check(L.lib.mg_nodal_time_smoother(self.handle, int(reps), C.byref(ms)),
+                "mg_nodal_time_smoother")
+        return ms.value
+
     def apply(self, phi, out):
         pm, om = phi.c_struct(), out.c_struct()
         L.check(L.lib.mg_nodal_apply(self.handle, C.byref(pm), C.byref(om)), "mg_nodal_apply")

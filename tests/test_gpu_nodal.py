@@ -180,3 +180,64 @@ def test_nodal_errors():
     assert info["status"] == P._lib.MG_ERR_NOT_CONVERGED and info["iters"] == 2
     s.close()
     s2.close()
+
+
+def _window_residual(sigma, per, G_phi, G_f, a, w):
+    """max |f - A phi| over the nodes a+2 .. a+w-2 of the cell window a .. a+w-1,
+    with the oracle's operator on that window (its boundary nodes read as 0,
+    so only nodes whose 27 neighbours lie inside the window are kept)."""
+    sl_c = tuple(slice(a[d], a[d] + w) for d in range(3))
+    lev = ON.make_nodal_level(sigma[sl_c], (False,) * 3, h=(1.0 / sigma.shape[0],) * 3)
+    sl_u = tuple(slice(a[d] + 1, a[d] + w) for d in range(3))
+    Aphi = ON.apply_nodal(lev, G_phi[sl_u])
+    r = G_f[sl_u] - Aphi
+    return np.abs(r[1:-1, 1:-1, 1:-1]).max()
+
+
+@pytest.mark.gpu
+def test_nodal_full_size_256():
+    """256^3 cells in 64 boxes of 64^3 (the benchmark's configuration): the GPU
+    operator against the oracle's on windows of the random field, and the
+    converged solution's residual recomputed by the oracle's operator on
+    windows (interior, at walls and corners)."""
+    print("[nodal] 256^3 full size", flush=True)
+    P = lib()
+    n = 256
+    cfg = W.config_nodal(n, 64)
+    boxes, per = cfg["boxes"], cfg["periodic"]
+    sigma, f = cfg["sigma_cells"], cfg["rhs_unknowns"]
+    s = _gpu(n, boxes, per, sigma, dict(min_bottom_edge=4))
+    rng = np.random.default_rng(21)
+    wins = [(0, 0, 0), (n - 20, n - 20, n - 20), (0, 100, n - 20)] + \
+        [tuple(int(x) for x in rng.integers(0, n - 20, 3)) for _ in range(5)]
+    # operator
+    x = rng.standard_normal(W.nodal_unknown_shape(n, per))
+    Gx = W.nodes_from_unknowns(x, n, per)
+    out = s.node_mf(0)
+    s.apply(P.MultiFab.from_numpy(boxes, W.scatter_nodes(Gx, boxes, 0), 0, ixtype=(1, 1, 1)), out)
+    torch.cuda.synchronize()
+    got, Gy = _unknowns(out, boxes, n, per)
+    del got
+    for a in wins:
+        sl_c = tuple(slice(a[d], a[d] + 20) for d in range(3))
+        lev = ON.make_nodal_level(sigma[sl_c], (False,) * 3, h=(1.0 / n,) * 3)
+        sl_u = tuple(slice(a[d] + 1, a[d] + 20) for d in range(3))
+        ref = ON.apply_nodal(lev, Gx[sl_u])[1:-1, 1:-1, 1:-1]
+        g = Gy[sl_u][1:-1, 1:-1, 1:-1]
+        assert np.abs(g - ref).max() <= 1e-13 * np.abs(ref).max(), a
+    # solve
+    rhs = _nodal_mf(P, boxes, f, n, per, 0)
+    phi = s.node_mf(0, fill=0.0)
+    info = s.solve(phi, rhs, 1e-10, history=True)
+    torch.cuda.synchronize()
+    assert info["converged"]
+    h = info["history"]
+    print(f"  {info['iters']} cycles, rel resid {info['rel_resid']:.2e}")
+    _, Gp = _unknowns(phi, boxes, n, per)
+    Gf = W.nodes_from_unknowns(f, n, per)
+    normf = np.abs(f).max()
+    for a in wins:
+        r = _window_residual(sigma, per, Gp, Gf, a, 20)
+        assert r <= 1e-10 * normf * 1.001 + 1e-13, (a, r / normf)
+    assert h[-1] <= 1e-10 * normf and h[0] == pytest.approx(normf)
+    s.close()

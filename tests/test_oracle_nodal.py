@@ -282,3 +282,78 @@ def test_vcycle_contraction_grid_independent():
         h = info["history"]
         rho.append((h[-1] / h[0]) ** (1.0 / info["iters"]))
     assert max(rho) < 0.35 and abs(rho[0] - rho[1]) < 0.05, rho
+
+
+def _matrix(fn, m):
+    M = np.zeros((int(np.prod(m)),) * 2)
+    for c in range(M.shape[0]):
+        e = np.zeros(M.shape[0])
+        e[c] = 1
+        M[:, c] = to_vec(fn(from_vec(e, m)))
+    return M
+
+
+@pytest.mark.parametrize("nu", [(2, 2), (2, 1)])
+def test_vcycle_preconditioner_symmetric_positive(nu):
+    """nu1 = nu2: M is symmetric positive definite; nu1 != nu2 breaks the
+    symmetry (so the pin fails if pre and post smoothing differ)."""
+    n, per = (8, 8, 8), (False, True, False)
+    sig = _sigma(n, 15)
+    opts = N.NodalOpts(nu1=nu[0], nu2=nu[1], bottom_tol=1e-15, min_bottom_cells=2)
+    levs = N.build_nodal_levels(sig, per, opts)
+    M = _matrix(lambda r: N.nodal_precond(levs, r, opts), levs[0].m)
+    asym = np.abs(M - M.T).max() / np.abs(M).max()
+    if nu[0] == nu[1]:
+        assert asym < 1e-10
+        assert np.linalg.eigvalsh(0.5 * (M + M.T))[0] > 0
+    else:
+        assert asym > 1e-6
+
+
+def test_pcg_identity_equals_scipy_cg_iterates():
+    """With the identity as preconditioner the k-th iterate is SciPy's CG
+    iterate on the independently assembled matrix."""
+    n, per = (8, 8, 8), (False, False, False)
+    sig = _sigma(n, 16)
+    A, m = assemble(sig, per)
+    f = np.random.default_rng(17).uniform(-1, 1, m)
+    for k in (1, 3, 6):
+        phi, info = N.nodal_pcg_solve(sig, per, f, 0.0, opts=N.NodalOpts(max_iter=k),
+                                      precond=lambda r: r.copy())
+        assert info["iters"] == k
+        ref, _ = sla.cg(A, to_vec(f), x0=np.zeros(A.shape[0]), maxiter=k, rtol=0.0, atol=0.0)
+        assert np.linalg.norm(to_vec(phi) - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("n,per", [((16, 16, 16), (False,) * 3), ((16, 16, 16), (True, False, True)),
+                                   ((8, 8, 8), (True, True, True))])
+def test_pcg_solve_equals_direct(n, per):
+    sig = _sigma(n, 18)
+    A, m = assemble(sig, per)
+    f = np.random.default_rng(19).uniform(-1, 1, m)
+    if all(per):
+        f = f - f.mean()
+    phi, info = N.nodal_pcg_solve(sig, per, f, 1e-12,
+                                  opts=N.NodalOpts(bottom_tol=1e-13, min_bottom_cells=2))
+    assert info["converged"]
+    if all(per):
+        # singular: the solution with zero mean of A x = f
+        Ad = A.toarray() + np.ones((A.shape[0],) * 2) / A.shape[0]
+        ref = from_vec(np.linalg.solve(Ad, to_vec(f)), m)
+        ref = ref - ref.mean()
+    else:
+        ref = from_vec(sla.spsolve(A.tocsc(), to_vec(f)), m)
+    assert np.linalg.norm(phi - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_pcg_needs_fewer_iterations_than_vcycles():
+    n, per = (32, 32, 32), (False,) * 3
+    sig = _sigma(n, 20)
+    f = np.random.default_rng(21).uniform(-1, 1, N.unknown_shape(n, per))
+    o = N.NodalOpts(min_bottom_cells=4)
+    levs = N.build_nodal_levels(sig, per, o)
+    _, iv = N.nodal_solve(sig, per, f, 1e-10, opts=o, levs=levs)
+    phi, ip = N.nodal_pcg_solve(sig, per, f, 1e-10, opts=o, levs=levs)
+    assert ip["converged"] and ip["iters"] < 0.7 * iv["iters"], (ip["iters"], iv["iters"])
+    phv, _ = N.nodal_solve(sig, per, f, 1e-12, opts=o, levs=levs)
+    assert np.linalg.norm(phi - phv) <= 1e-8 * np.linalg.norm(phv)

@@ -92,6 +92,10 @@ struct mg_nodal {
   int max_elems[3] = {0, 0, 0};
   double* bwork = nullptr;
   double* partials = nullptr;
+  // Krylov outer solve (opts.krylov = 1): finest-level x, r, p, q and the
+  // CG scalars rho (two, alternating), p.q
+  double *kx = nullptr, *kr = nullptr, *kp = nullptr, *kq = nullptr;
+  double* d_cg = nullptr;
   int* d_iters = nullptr;
   unsigned long long* d_norm = nullptr;  // 3 slots
   size_t ws_need = 0;
@@ -212,6 +216,13 @@ int plan(mg_nodal* s, Bump& bump) {
   s->partials = bump.take<double>((size_t)nd_sum_partials_count(g0));
   s->d_norm = bump.take<unsigned long long>(3 * (size_t)kNdNormSlot);
   s->d_iters = bump.take<int>(4);
+  if (s->opts.krylov) {
+    s->kx = bump.take<double>(s->L[0].size);
+    s->kr = bump.take<double>(s->L[0].size);
+    s->kp = bump.take<double>(s->L[0].size);
+    s->kq = bump.take<double>(s->L[0].size);
+    s->d_cg = bump.take<double>(4);
+  }
   // box tables: nodal ngrow 0 and 1, cells ngrow 0
   for (int t = 0; t < 3; ++t) {
     s->h_box[t].clear();
@@ -330,6 +341,114 @@ int coarse_part(mg_nodal* s, double* out) {
   return fill_ghosts(s, l0, out);
 }
 
+int read_slot(mg_nodal* s, int slot, double* out) {
+  HIPTRY(hipMemcpyAsync(s->h_norm + (size_t)slot * kNdNormSlot, nslot(s, slot),
+                        sizeof(unsigned long long) * kNdNormSlot, hipMemcpyDeviceToHost, s->st));
+  HIPTRY(hipStreamSynchronize(s->st));
+  unsigned long long m = 0;
+  for (int w = 0; w < kNdNormWays; ++w)
+    m = std::max(m, s->h_norm[(size_t)slot * kNdNormSlot + (size_t)w * kNdNormStride]);
+  std::memcpy(out, &m, sizeof(double));
+  return MG_OK;
+}
+
+// z = M r: one finest-level V-cycle from zero on right-hand side r (the
+// Krylov preconditioner).  Returns the level-0 buffer holding z.
+int precond(mg_nodal* s, const double* r, int* zi) {
+  NdLevel& l0 = s->L[0];
+  int rc;
+  int cur = 0;
+  if ((rc = sweep(s, 0, nullptr, r, l0.x[0], ND_ZERO, nullptr))) return rc;
+  for (int k = 1; k < s->opts.nu1; ++k) {
+    if ((rc = sweep(s, 0, l0.x[cur], r, l0.x[1 - cur], ND_JACOBI, nullptr))) return rc;
+    cur = 1 - cur;
+  }
+  if ((rc = sweep(s, 0, l0.x[cur], r, l0.r, ND_RESID, nullptr))) return rc;
+  if (s->graph[cur]) {
+    HIPTRY(hipGraphLaunch(s->graph[cur], s->st));
+  } else if ((rc = coarse_part(s, l0.x[cur]))) {
+    return rc;
+  }
+  for (int k = 0; k < s->opts.nu2; ++k) {
+    if ((rc = sweep(s, 0, l0.x[cur], r, l0.x[1 - cur], ND_JACOBI, nullptr))) return rc;
+    cur = 1 - cur;
+  }
+  *zi = cur;
+  return MG_OK;
+}
+
+// Conjugate gradients on the finest level preconditioned by one V-cycle per
+// iteration, from the gathered initial guess in kx: standard recurrences
+// with the scalars on the device; stop on the max norm of the recurrence
+// residual, confirmed on the true residual (if that is still above tol, r is
+// replaced by it and the recurrence restarts from p = M r).  All periodic:
+// the mean is taken out of r at the start and after a restart and out of
+// every z.
+int solve_pcg(mg_nodal* s, double tol, mg_info_t* inf, double* hist, int* status) {
+  NdLevel& l0 = s->L[0];
+  const NdGeo& g = l0.g;
+  double *x = s->kx, *r = s->kr, *p = s->kp, *q = s->kq;
+  int rc;
+  auto true_residual = [&](double* buf, double* norm) -> int {
+    int rc2;
+    if ((rc2 = fill_ghosts(s, l0, x))) return rc2;
+    HIPTRY(nd_launch_fill_u64(s->st, nslot(s, 2), kNdNormSlot, 0ull));
+    if ((rc2 = sweep(s, 0, x, l0.f, buf, ND_RESID, s->singular ? nullptr : nslot(s, 2))))
+      return rc2;
+    if (s->singular) {
+      HIPTRY(nd_launch_remove_mean(s->st, g, buf, s->partials));
+      HIPTRY(nd_launch_maxabs(s->st, g, buf, nslot(s, 2)));
+    }
+    return read_slot(s, 2, norm);
+  };
+  double rn;
+  if ((rc = true_residual(r, &rn))) return rc;
+  int it = 0;
+  bool restart = true;
+  *status = MG_OK;
+  while (true) {
+    if (hist) hist[it] = rn;
+    if (s->opts.verbose) fprintf(stderr, "amrmg nodal pcg %d  max|r| = %.6e\n", it, rn);
+    if (!std::isfinite(rn)) {
+      *status = fail(MG_ERR_NAN, "residual norm is not finite");
+      break;
+    }
+    if (rn <= tol) {
+      double rt;
+      if ((rc = true_residual(q, &rt))) return rc;
+      if (rt <= tol) {
+        inf->converged = 1;
+        break;
+      }
+      HIPTRY(hipMemcpyAsync(r, q, sizeof(double) * l0.size, hipMemcpyDeviceToDevice, s->st));
+      restart = true;
+    }
+    if (it == s->opts.max_iter) {
+      *status = fail(MG_ERR_NOT_CONVERGED, "max_iter reached");
+      break;
+    }
+    int zi = 0;
+    if ((rc = precond(s, r, &zi))) return rc;
+    double* z = l0.x[zi];
+    if (s->singular) HIPTRY(nd_launch_remove_mean(s->st, g, z, s->partials));
+    double* rho_new = s->d_cg + (it & 1);
+    double* rho_old = s->d_cg + ((it + 1) & 1);
+    HIPTRY(nd_launch_dot(s->st, g, r, z, s->partials, rho_new));
+    HIPTRY(nd_launch_cg_p(s->st, g, p, z, rho_new, rho_old, restart ? 1 : 0));
+    if ((rc = fill_ghosts(s, l0, p))) return rc;
+    restart = false;
+    if ((rc = sweep(s, 0, p, l0.f, q, ND_APPLY, nullptr))) return rc;
+    HIPTRY(nd_launch_dot(s->st, g, p, q, s->partials, s->d_cg + 2));
+    HIPTRY(nd_launch_fill_u64(s->st, nslot(s, 2), kNdNormSlot, 0ull));
+    HIPTRY(nd_launch_cg_xr(s->st, g, x, p, r, q, rho_new, s->d_cg + 2, nslot(s, 2)));
+    ++it;
+    if ((rc = read_slot(s, 2, &rn))) return rc;
+  }
+  inf->iters = it;
+  inf->abs_resid = rn;
+  return MG_OK;
+}
+
 // The rest of a finest-level V-cycle after its first sweep (from a to b):
 // the iterate never returns to buffer a.  Returns the buffer index holding
 // the new iterate.
@@ -356,16 +475,6 @@ int cycle_rest(mg_nodal* s, int a, int b, const double* F, int* out_idx) {
   return MG_OK;
 }
 
-int read_slot(mg_nodal* s, int slot, double* out) {
-  HIPTRY(hipMemcpyAsync(s->h_norm + (size_t)slot * kNdNormSlot, nslot(s, slot),
-                        sizeof(unsigned long long) * kNdNormSlot, hipMemcpyDeviceToHost, s->st));
-  HIPTRY(hipStreamSynchronize(s->st));
-  unsigned long long m = 0;
-  for (int w = 0; w < kNdNormWays; ++w)
-    m = std::max(m, s->h_norm[(size_t)slot * kNdNormSlot + (size_t)w * kNdNormStride]);
-  std::memcpy(out, &m, sizeof(double));
-  return MG_OK;
-}
 
 }  // namespace
 
@@ -416,8 +525,10 @@ int mg_nodal_create(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
     s->opts = *opts;
   else
     mg_default_opts(&s->opts);
-  if (s->opts.precision != MG_PREC_F64 || s->opts.krylov != 0)
-    return fail(MG_ERR_ARG, "the nodal solve runs FP64 V-cycles (precision 0, krylov 0)");
+  if (s->opts.precision != MG_PREC_F64 || (s->opts.krylov != 0 && s->opts.krylov != 1))
+    return fail(MG_ERR_ARG, "the nodal solve runs in FP64 (precision 0, krylov 0 or 1)");
+  if (s->opts.krylov && s->opts.nu1 != s->opts.nu2)
+    return fail(MG_ERR_ARG, "the nodal Krylov solve needs a symmetric V-cycle (nu1 == nu2)");
   if (s->opts.nu1 < 1 || s->opts.nu2 < 0 || s->opts.max_iter < 0 ||
       !(s->opts.bottom_rel_tol >= 0))
     return fail(MG_ERR_ARG, "the nodal solve needs nu1 >= 1, nu2 >= 0, max_iter >= 0");
@@ -524,9 +635,10 @@ int mg_nodal_solve(mg_nodal_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, 
   // over the three level-0 buffers
   HIPTRY(nd_launch_gather(s->st, l0.g, s->d_box[tr], nbox, s->max_elems[tr], tr, dlo,
                           static_cast<const double*>(rhs->data), l0.f));
+  double* x0 = s->opts.krylov ? s->kx : l0.x[0];
   HIPTRY(nd_launch_gather(s->st, l0.g, s->d_box[tp], nbox, s->max_elems[tp], tp, dlo,
-                          static_cast<const double*>(phi->data), l0.x[0]));
-  if ((rc = fill_ghosts(s, l0, l0.x[0]))) return rc;
+                          static_cast<const double*>(phi->data), x0));
+  if ((rc = fill_ghosts(s, l0, x0))) return rc;
   HIPTRY(nd_launch_fill_u64(s->st, s->d_norm, 3 * kNdNormSlot, 0ull));
   HIPTRY(nd_launch_maxabs(s->st, l0.g, l0.f, nslot(s, 0)));
   double normf;
@@ -534,10 +646,17 @@ int mg_nodal_solve(mg_nodal_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, 
   if (!std::isfinite(normf)) return fail(MG_ERR_NAN, "rhs holds a non-finite value");
   int status = MG_OK;
   int cur = 0;
+  double* result = nullptr;
   if (normf == 0.0) {
-    HIPTRY(nd_launch_fill(s->st, l0.x[0], l0.size, 0.0));
+    HIPTRY(nd_launch_fill(s->st, x0, l0.size, 0.0));
+    result = x0;
     inf.converged = 1;
     if (resid_history) resid_history[0] = 0.0;
+  } else if (s->opts.krylov) {
+    if ((rc = solve_pcg(s, std::max(rel_tol * normf, abs_tol), &inf, resid_history, &status)))
+      return rc;
+    inf.rel_resid = inf.abs_resid / normf;
+    result = s->kx;
   } else {
     const double tol = std::max(rel_tol * normf, abs_tol);
     int it = 0, rising = 0;
@@ -614,10 +733,11 @@ int mg_nodal_solve(mg_nodal_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, 
     inf.iters = it;
     inf.abs_resid = rn;
     inf.rel_resid = rn / normf;
+    result = l0.x[cur];
   }
-  if (s->singular) HIPTRY(nd_launch_remove_mean(s->st, l0.g, l0.x[cur], s->partials));
+  if (s->singular) HIPTRY(nd_launch_remove_mean(s->st, l0.g, result, s->partials));
   HIPTRY(nd_launch_scatter(s->st, l0.g, s->d_box[tp], nbox, s->max_elems[tp], tp, dlo, s->n,
-                           l0.x[cur], static_cast<double*>(phi->data)));
+                           result, static_cast<double*>(phi->data)));
   HIPTRY(hipMemcpyAsync(s->h_norm + 3 * kNdNormSlot, s->d_iters, sizeof(int),
                         hipMemcpyDeviceToHost, s->st));
   HIPTRY(hipStreamSynchronize(s->st));

@@ -99,6 +99,17 @@ hipError_t nd_launch_sigma(hipStream_t st, const NdGeo& g, const NdBox* boxes, i
 // doubles of scratch).
 int nd_sum_partials_count(const NdGeo& g);
 hipError_t nd_launch_remove_mean(hipStream_t st, const NdGeo& g, double* v, double* part);
+// Krylov vector work on the valid nodes (scalars stay on the device):
+// out = a.b (part: nd_sum_partials_count doubles of scratch); p = z or
+// z + (rho / rho_old) p; x += alpha p, r -= alpha q with alpha = rho / pq and
+// max |r| folded into norm.
+hipError_t nd_launch_dot(hipStream_t st, const NdGeo& g, const double* a, const double* b,
+                         double* part, double* out);
+hipError_t nd_launch_cg_p(hipStream_t st, const NdGeo& g, double* p, const double* z,
+                          const double* rho, const double* rho_old, int restart);
+hipError_t nd_launch_cg_xr(hipStream_t st, const NdGeo& g, double* x, const double* p, double* r,
+                           const double* q, const double* rho, const double* pq,
+                           unsigned long long* norm);
 hipError_t nd_launch_fill(hipStream_t st, double* a, long long n, double v);
 hipError_t nd_launch_fill_u64(hipStream_t st, unsigned long long* a, int n,
                               unsigned long long v);

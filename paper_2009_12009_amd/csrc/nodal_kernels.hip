@@ -680,6 +680,83 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Partial sums of a.b over the valid nodes, one per work-group.
+__global__ void __launch_bounds__(256)
+    k_nd_dot_partials(NdGeo g, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ part) {
+  __shared__ double red[4];
+  const int ux = blockIdx.x * 64 + threadIdx.x;
+  const int uy = blockIdx.y * 4 + threadIdx.y;
+  const int z0 = blockIdx.z * kTz;
+  double sm = 0.0;
+  if (ux < g.mx && uy < g.my) {
+    const int z1 = min(z0 + kTz, g.mz);
+    for (int uz = z0; uz < z1; ++uz) {
+      const int c = pidx(g, ux, uy, uz);
+      sm += a[c] * b[c];
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) sm += __shfl_xor(sm, o);
+  if (threadIdx.x == 0) red[threadIdx.y] = sm;
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0)
+    part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] =
+        (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out = sum of n partials (one work-group, fixed order).
+__global__ void __launch_bounds__(256)
+    k_nd_sum_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double red[4];
+  double sm = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) sm += part[i];
+  for (int o = 32; o > 0; o >>= 1) sm += __shfl_xor(sm, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sm;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// p = z (restart) or z + (rho / rho_old) p.
+__global__ void __launch_bounds__(256)
+    k_nd_cg_p(NdGeo g, double* __restrict__ p, const double* __restrict__ z,
+              const double* __restrict__ rho, const double* __restrict__ rho_old, int restart) {
+  const int ux = blockIdx.x * 64 + threadIdx.x;
+  const int uy = blockIdx.y * 4 + threadIdx.y;
+  const int z0 = blockIdx.z * kTz;
+  if (ux >= g.mx || uy >= g.my) return;
+  const double beta = restart ? 0.0 : *rho / *rho_old;
+  const int z1 = min(z0 + kTz, g.mz);
+  for (int uz = z0; uz < z1; ++uz) {
+    const int c = pidx(g, ux, uy, uz);
+    p[c] = restart ? z[c] : z[c] + beta * p[c];
+  }
+}
+
+// alpha = rho / pq; x += alpha p; r -= alpha q; max |r| into norm.
+__global__ void __launch_bounds__(256)
+    k_nd_cg_xr(NdGeo g, double* __restrict__ x, const double* __restrict__ p,
+               double* __restrict__ r, const double* __restrict__ q,
+               const double* __restrict__ rho, const double* __restrict__ pq,
+               unsigned long long* norm) {
+  const int ux = blockIdx.x * 64 + threadIdx.x;
+  const int uy = blockIdx.y * 4 + threadIdx.y;
+  const int z0 = blockIdx.z * kTz;
+  unsigned long long mx = 0;
+  if (ux < g.mx && uy < g.my) {
+    const double alpha = *rho / *pq;
+    const int z1 = min(z0 + kTz, g.mz);
+    for (int uz = z0; uz < z1; ++uz) {
+      const int c = pidx(g, ux, uy, uz);
+      x[c] += alpha * p[c];
+      const double rv = r[c] - alpha * q[c];
+      r[c] = rv;
+      const unsigned long long b = absbits(rv);
+      mx = b > mx ? b : mx;
+    }
+  }
+  nd_block_max(mx, norm);
+}
+
 __global__ void k_nd_fill(double* a, long long n, double v) {
   const long long i = blockIdx.x * 256ll + threadIdx.x;
   if (i < n) a[i] = v;
@@ -826,6 +903,30 @@ hipError_t nd_launch_remove_mean(hipStream_t st, const NdGeo& g, double* v, doub
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_nd_shift, sweep_grid(g), dim3(64, 4), 0, st, g, v, part,
                      nd_sum_partials_count(g));
+  return hipGetLastError();
+}
+
+hipError_t nd_launch_dot(hipStream_t st, const NdGeo& g, const double* a, const double* b,
+                         double* part, double* out) {
+  hipLaunchKernelGGL(k_nd_dot_partials, sweep_grid(g), dim3(64, 4), 0, st, g, a, b, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_nd_sum_final, dim3(1), dim3(256), 0, st, part, nd_sum_partials_count(g),
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t nd_launch_cg_p(hipStream_t st, const NdGeo& g, double* p, const double* z,
+                          const double* rho, const double* rho_old, int restart) {
+  hipLaunchKernelGGL(k_nd_cg_p, sweep_grid(g), dim3(64, 4), 0, st, g, p, z, rho, rho_old,
+                     restart);
+  return hipGetLastError();
+}
+
+hipError_t nd_launch_cg_xr(hipStream_t st, const NdGeo& g, double* x, const double* p, double* r,
+                           const double* q, const double* rho, const double* pq,
+                           unsigned long long* norm) {
+  hipLaunchKernelGGL(k_nd_cg_xr, sweep_grid(g), dim3(64, 4), 0, st, g, x, p, r, q, rho, pq, norm);
   return hipGetLastError();
 }
 

@@ -241,3 +241,64 @@ def test_nodal_full_size_256():
         assert r <= 1e-10 * normf * 1.001 + 1e-13, (a, r / normf)
     assert h[-1] <= 1e-10 * normf and h[0] == pytest.approx(normf)
     s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,n,boxes,per,mbe", CASES, ids=[c[0] for c in CASES])
+def test_nodal_pcg_vs_oracle(name, n, boxes, per, mbe):
+    """CG preconditioned by one V-cycle per iteration: same iteration count,
+    the recurrence residual's max norm equal to 1e-6 (plus the floor) at every
+    iteration, solutions within 1e-9 rel-L2 of the oracle's."""
+    print(f"[nodal] pcg {name}", flush=True)
+    P = lib()
+    sigma, f = _inputs(n, boxes, per)
+    s = _gpu(n, boxes, per, sigma, dict(bottom_rel_tol=TIGHT, min_bottom_edge=mbe, krylov=1))
+    rhs = _nodal_mf(P, boxes, f, n, per, 0)
+    phi = s.node_mf(1, fill=0.0)
+    g = s.solve(phi, rhs, 1e-10, history=True)
+    torch.cuda.synchronize()
+    got, _ = _unknowns(phi, boxes, n, per)
+    ophi, o = ON.nodal_pcg_solve(sigma, per, f, 1e-10, opts=ON.NodalOpts(
+        bottom_tol=TIGHT, min_bottom_cells=mbe))
+    s.close()
+    assert g["converged"] and o["converged"]
+    assert g["iters"] == o["iters"], (g["history"], o["history"])
+    nf = o["normf"]
+    for k, (a, b) in enumerate(zip(g["history"], o["history"])):
+        assert abs(a - b) <= 1e-6 * b + 1e-12 * nf, (k, a, b)
+    e = rel_l2(got, ophi)
+    print(f"  {g['iters']} iterations, rel-L2 vs oracle {e:.2e}")
+    assert e <= 1e-9
+    # the same solution as the V-cycle solve
+    vphi, _ = ON.nodal_solve(sigma, per, f, 1e-12, opts=ON.NodalOpts(bottom_tol=TIGHT,
+                                                                      min_bottom_cells=mbe))
+    assert rel_l2(got, vphi) <= 1e-8
+
+
+@pytest.mark.gpu
+def test_nodal_pcg_full_size_256():
+    """256^3 in the benchmark's configuration with the Krylov solve: the
+    converged solution's residual recomputed by the oracle's operator on
+    windows."""
+    print("[nodal] pcg 256^3 full size", flush=True)
+    P = lib()
+    n = 256
+    cfg = W.config_nodal(n, 64)
+    boxes, per = cfg["boxes"], cfg["periodic"]
+    sigma, f = cfg["sigma_cells"], cfg["rhs_unknowns"]
+    s = _gpu(n, boxes, per, sigma, dict(min_bottom_edge=4, krylov=1))
+    phi = s.node_mf(0, fill=0.0)
+    info = s.solve(phi, _nodal_mf(P, boxes, f, n, per, 0), 1e-10)
+    torch.cuda.synchronize()
+    assert info["converged"]
+    print(f"  {info['iters']} iterations, rel resid {info['rel_resid']:.2e}")
+    _, Gp = _unknowns(phi, boxes, n, per)
+    Gf = W.nodes_from_unknowns(f, n, per)
+    normf = np.abs(f).max()
+    rng = np.random.default_rng(22)
+    wins = [(0, 0, 0), (n - 20, n - 20, n - 20)] + \
+        [tuple(int(x) for x in rng.integers(0, n - 20, 3)) for _ in range(4)]
+    for a in wins:
+        r = _window_residual(sigma, per, Gp, Gf, a, 20)
+        assert r <= 1e-10 * normf * 1.001 + 1e-13, (a, r / normf)
+    s.close()

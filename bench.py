@@ -333,11 +333,14 @@ def bench_c2(args):
            "config": {"workload": "abec512_guillotine", "boxes": len(boxes), "edge_histogram": edges,
                       "aggregate": args.aggregate}, "variants": {}}
     phi = P.MultiFab(boxes, 1, fill=0.0)
+    # graph replay and tuning measured apart: tuned tiles (per box class where
+    # that wins) and default tiles at equal graph setting, then plain launches
     for prec in (0, 1):
-        for fast in (1, 0):
-            name = f"{'f64' if prec == 0 else 'f32_refine'}_{'graph_tuned' if fast else 'plain'}"
+        for graph, tune, tag in ((1, 2, "graph_tuned"), (1, 0, "graph_default"),
+                                 (0, 0, "plain_default")):
+            name = f"{'f64' if prec == 0 else 'f32_refine'}_{tag}"
             s = P.MLMG(boxes, W.domain_box(n), cfg["periodic"], 1.0, 1.0, b=bmf,
-                       opts=dict(precision=prec, use_graph=fast, tune=2 if fast else 0,
+                       opts=dict(precision=prec, use_graph=graph, tune=tune,
                                  aggregate=args.aggregate))
             times = []
             for k in range(args.warmup + args.steps):
@@ -348,7 +351,10 @@ def bench_c2(args):
                     times.append(info["solve_ms"])
             out["variants"][name] = {"time_to_tol_ms": float(np.median(times)),
                                      "cycles": info["iters"], "levels": info["nlevels"],
-                                     "rel_resid": info["rel_resid"], "setup_ms": info["setup_ms"]}
+                                     "rel_resid": info["rel_resid"], "setup_ms": info["setup_ms"],
+                                     "smoother_shape": s.tile_shape(0),
+                                     "smoother_class_shapes": {str(k): list(v) for k, v in
+                                                               s.class_tile_shapes().items()}}
             log(f"{name}: {np.median(times):.1f} ms, {info['iters']} cycles", args.quiet)
             s.close()
             torch.cuda.synchronize()

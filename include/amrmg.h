@@ -390,6 +390,22 @@ int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, in
  * lx = 0 when it has no fused sweep at all).  shape: host int32_t[5]. */
 int mg_get_tile_shape(mg_solver_t* s, int32_t kernel, int32_t* shape);
 
+/* Level-0 smoother tiles per box class ("tile size adjustable at run time",
+ * chosen per box class): the boxes whose x extent is x_extent get lx x ly
+ * lanes (lx in {16, 32, 64}) over tz planes per work-group, inside the one
+ * launch of the level's half-sweep; lx * ly must equal the launch's thread
+ * count and tz >= its unroll (the tuner with tune = 2 picks these shapes by
+ * timing each class and keeps them only when the whole table is faster).
+ * Other classes keep their shapes; mg_set_tile_shape (kernel 0 or 2) returns
+ * to one shape for all boxes.  Every choice gives bitwise-identical solves.
+ * MG_ERR_ARG when no box has that x extent, the shape is not such a
+ * candidate, or level 0 uses fused sweeps. */
+int mg_set_class_tile_shape(mg_solver_t* s, int32_t x_extent, int32_t lx, int32_t ly, int32_t tz);
+/* The level-0 smoother's per-class shapes in use: *n classes (0 = one shape
+ * for every box); out (host, nullable when cap = 0) receives cap >= *n
+ * quadruples (x extent, lx, ly, tz), else MG_ERR_ARG. */
+int mg_get_class_tile_shapes(mg_solver_t* s, int32_t* out, int32_t cap, int32_t* n);
+
 /* ---------------------------------------------------------------------------
  * Nodal solver ("Linear Solvers": the nodal solver is built on finite
  * elements, its stencil from moment integrals over the cells, its coarse

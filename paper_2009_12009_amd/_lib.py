@@ -103,6 +103,9 @@ SIGNATURES = {
                                    P(C.c_double)]),
     "mg_stream_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "mg_get_tile_shape": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32)]),
+    "mg_set_class_tile_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                          C.c_int32]),
+    "mg_get_class_tile_shapes": (C.c_int, [C.c_void_p, P(C.c_int32), C.c_int32, P(C.c_int32)]),
     "mg_set_tile_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                     C.c_int32]),
     "mg_query_workspace_amr": (C.c_int, [P(MgBox), C.c_int32, P(MgBox), C.c_int32, P(MgGeom),

@@ -309,7 +309,7 @@ __device__ __forceinline__ void write_through(const WtBox& wb, const WtEntry* ex
 template <typename T, int U, bool ZG, bool WP, bool WT, bool PE, bool BUF, bool RS>
 __global__ void __launch_bounds__(256)
     k_gsrb(const Tile* __restrict__ tiles, StencilArgs<T> op, T* __restrict__ phi,
-           const T* __restrict__ rhs, int rhs_ng, int colour, int tz,
+           const T* __restrict__ rhs, int rhs_ng, int colour, int tz_launch,
            const WtBox* __restrict__ wtb, const WtEntry* __restrict__ wte,
            const BoxInfo* __restrict__ cinfo, const T* __restrict__ ec,
            const BoxInfo* __restrict__ finfo, const T* __restrict__ rf, T* __restrict__ rout) {
@@ -317,16 +317,29 @@ __global__ void __launch_bounds__(256)
   static_assert(!(RS && (!ZG || WP || PE || BUF)), "folded restriction: zero-guess half-sweeps only");
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = op.boxes[t.box];
-  const int j = t.y0 + threadIdx.y;
-  if (!WT && j > B.hi[1]) return;  // with WT every lane reaches the barrier below
-  const bool row_ok = j <= B.hi[1];
+  // the tile's lane layout (its box class's shape): lx x ly lanes over the
+  // work-group's threads (lx a power of two), tz planes
+  int lxl, ly, tz;
+  if (t.shape) {
+    lxl = t.shape & 15;
+    ly = (t.shape >> 4) & 255;
+    tz = t.shape >> 16;
+  } else {
+    lxl = __builtin_ctz(blockDim.x);
+    ly = blockDim.y;
+    tz = tz_launch;
+  }
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const int tx = tid & ((1 << lxl) - 1), ty = tid >> lxl;
+  const int j = t.y0 + ty;
+  if (!WT && (ty >= ly || j > B.hi[1])) return;  // with WT every lane reaches the barrier below
+  const bool row_ok = ty < ly && j <= B.hi[1];
   const Strides s = strides_of(B, rhs_ng);
   const int jl = j - B.lo[1];
   const int kend = min(t.z0 + tz - 1, B.hi[2]);
   T* P = phi + B.off_g1;
   extern __shared__ double lds_gsrb[];
   T* XS = reinterpret_cast<T*>(lds_gsrb);  // [2][ly][tz] x-face values (WT)
-  const int ly = blockDim.y;
   const T* R = rhs + (rhs_ng ? B.off_g1 : B.off_g0);
   const T* BX = op.b0 + B.off_f[0];
   const T* BY = op.b1 + B.off_f[1];
@@ -377,7 +390,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = k0 + u;
-      const int i = t.x0 + 2 * (int)threadIdx.x + ((colour + t.x0 + j + k) & 1);
+      const int i = t.x0 + 2 * tx + ((colour + t.x0 + j + k) & 1);
       ok[u] = row_ok && k <= kend && i <= B.hi[0];
       il[u] = i - B.lo[0];
       pc[u] = (il[u] + 1) + s.sy * (jl + 1) + s.sz * (k - B.lo[2] + 1);
@@ -389,7 +402,7 @@ __global__ void __launch_bounds__(256)
         using V2 = T __attribute__((ext_vector_type(2)));
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          const int ic = t.x0 + 2 * (int)threadIdx.x + c;
+          const int ic = t.x0 + 2 * tx + c;
           if (ic > B.hi[0]) continue;
           const long long b =
               (2 * ic - F.lo[0]) + fsy * (2 * j - F.lo[1]) + fsz * (2 * k - F.lo[2]);
@@ -449,8 +462,8 @@ __global__ void __launch_bounds__(256)
       P[pc[u]] = nv;
       if (WT) {
         const int kk = k0 + u - t.z0;
-        if (il[u] == 0) XS[(0 * ly + threadIdx.y) * tz + kk] = nv;
-        if (il[u] == s.nx - 1) XS[(1 * ly + threadIdx.y) * tz + kk] = nv;
+        if (il[u] == 0) XS[(0 * ly + ty) * tz + kk] = nv;
+        if (il[u] == s.nx - 1) XS[(1 * ly + ty) * tz + kk] = nv;
         write_through_yz<T>(wb, wte, phi, s, il[u], jl, k0 + u - B.lo[2], nv);
       }
       if (WP && !ZG) {
@@ -465,12 +478,11 @@ __global__ void __launch_bounds__(256)
     // x faces of this tile: cells of the active colour in column 0 (tile
     // starts at the box's low x) and column nx-1 (tile reaches its high x)
     const bool has_lo = t.x0 == B.lo[0] && wb.count[0] > 0;
-    const bool has_hi = B.hi[0] <= t.x0 + 2 * (int)blockDim.x - 1 && wb.count[1] > 0;
+    const bool has_hi = B.hi[0] <= t.x0 + 2 * (1 << lxl) - 1 && wb.count[1] > 0;
     if (has_lo || has_hi) {
       __syncthreads();
       const int nz_t = kend - t.z0 + 1;
       const int n = ly * nz_t;
-      const int tid = threadIdx.x + blockDim.x * threadIdx.y;
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
         if (!(f ? has_hi : has_lo)) continue;

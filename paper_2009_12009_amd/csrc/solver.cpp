@@ -20,6 +20,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <sstream>
@@ -108,6 +109,10 @@ struct Level {
   Shape s_vec{64, 4, 16};
   Tile* d_vec = nullptr;
   size_t cap_gsrb = 0, cap_cell = 0;  // tile slots reserved in the workspace
+  // level 0: smoother tile shapes per box class (a box's x extent); empty =
+  // one shape for every box (s_gsrb)
+  std::map<int, Shape> cls;
+  Shape cls_base{32, 8, 16};  // the shape of boxes of other classes (with cls)
   // fused sweeps (both colours in one pass, out of place, rim pass after)
   bool fused = false;
   Shape s_sweep{64, 8, 16};
@@ -391,6 +396,64 @@ Shape fit_tz(const std::vector<BoxInfo>& info, Shape sh, int xmul, bool coarse) 
   return sh;
 }
 
+// ---------------------------------------------------------------------------
+// Smoother tile shapes per box class.  A class is a box's x extent (the
+// direction a wavefront's lanes run along, where a tile wider than the box
+// leaves lanes idle); all classes of a launch share its thread count, unroll
+// and whole-pair choice, and each tile carries its class's lane layout and
+// depth (Tile::shape).
+
+int pack_shape(Shape sh) { return __builtin_ctz((unsigned)sh.lx) | (sh.ly << 4) | (sh.tz << 16); }
+
+// Candidate class shapes for a launch of `threads` threads and unroll u.
+std::vector<Shape> class_candidates(int threads, int u, int wp) {
+  std::vector<Shape> c;
+  for (int lx : {16, 32, 64}) {
+    const int ly = threads / lx;
+    if (ly < 1 || lx * ly != threads || ly > 255) continue;
+    for (int tz : {1, 2, 4, 8, 16})
+      if (u <= tz) c.push_back({lx, ly, tz, u, wp});
+  }
+  return c;
+}
+
+// Tiles of the boxes in `only` (all boxes when empty) with each box's class
+// shape (dflt for classes not in cls), in the XCD-grouped order of
+// make_tiles.
+void make_class_tiles(const std::vector<BoxInfo>& info, const std::map<int, Shape>& cls, Shape dflt,
+                      const std::vector<int>& only, std::vector<Tile>& out) {
+  out.clear();
+  std::vector<int> boxes = only;
+  if (boxes.empty())
+    for (int b = 0; b < (int)info.size(); ++b) boxes.push_back(b);
+  for (int b : boxes) {
+    const int nx = info[b].hi[0] - info[b].lo[0] + 1;
+    auto it = cls.find(nx);
+    const Shape sh = it == cls.end() ? dflt : it->second;
+    const int code = pack_shape(sh);
+    for (int z = info[b].lo[2]; z <= info[b].hi[2]; z += sh.tz)
+      for (int y = info[b].lo[1]; y <= info[b].hi[1]; y += sh.ly)
+        for (int x = info[b].lo[0]; x <= info[b].hi[0]; x += 2 * sh.lx)
+          out.push_back({b, x, y, z, code});
+  }
+  const size_t n = out.size(), q = n / 8;
+  if (q > 0) {
+    std::vector<Tile> perm(out);
+    for (size_t p = 0; p < 8 * q; ++p) perm[p] = out[(p % 8) * q + p / 8];
+    out.swap(perm);
+  }
+}
+
+// The launch shape of a class table: dflt's lanes, unroll and whole pairs,
+// tz raised so that the write-through's LDS (2 ly tz values) fits every class.
+Shape class_launch_shape(const std::map<int, Shape>& cls, Shape dflt) {
+  int need = dflt.ly * dflt.tz;
+  for (const auto& kv : cls) need = std::max(need, kv.second.ly * kv.second.tz);
+  Shape l = dflt;
+  l.tz = (need + dflt.ly - 1) / dflt.ly;
+  return l;
+}
+
 // Write-through tables of a level: for every copy tag of the one-layer
 // exchange, the part of its destination region on one of the destination
 // box's six face-ghost slabs (edges and corners are never read by the
@@ -493,6 +556,24 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     if (l <= 1) {
       for (Shape c : gsrb_candidates())
         lv.cap_gsrb = std::max(lv.cap_gsrb, tile_count(lv.info, c, 2 * c.lx));
+      if (l == 0) {
+        // class tables: every box may take any class candidate of any thread count
+        size_t per_box = 0;
+        for (const BoxInfo& b : lv.info) {
+          size_t m = 0;
+          for (int th : {64, 128, 256})
+            for (Shape c : class_candidates(th, 1, 0)) {
+              std::vector<BoxInfo> one{b};
+              m = std::max(m, tile_count(one, c, 2 * c.lx));
+            }
+          for (Shape c : gsrb_candidates()) {
+            std::vector<BoxInfo> one{b};
+            m = std::max(m, tile_count(one, c, 2 * c.lx));
+          }
+          per_box += m;
+        }
+        lv.cap_gsrb = std::max(lv.cap_gsrb, per_box);
+      }
       for (Shape c : cell_candidates())
         lv.cap_cell = std::max(lv.cap_cell, tile_count(lv.info, c, c.lx));
     }
@@ -1240,6 +1321,7 @@ int apply_shape(mg_solver* s, Shape sh, bool gsrb, size_t lev = 0) {
     if (t.size() > l0.cap_gsrb) return fail(MG_ERR_ARG, "tile table larger than its reservation");
     l0.t_gsrb = t;
     l0.s_gsrb = sh;
+    l0.cls.clear();
     HIPTRY(hipMemcpyAsync(l0.d_gsrb, l0.t_gsrb.data(), sizeof(Tile) * l0.t_gsrb.size(),
                           hipMemcpyHostToDevice, s->st));
   } else {
@@ -1251,6 +1333,22 @@ int apply_shape(mg_solver* s, Shape sh, bool gsrb, size_t lev = 0) {
     HIPTRY(hipMemcpyAsync(l0.d_cell, l0.t_cell.data(), sizeof(Tile) * l0.t_cell.size(),
                           hipMemcpyHostToDevice, s->st));
   }
+  HIPTRY(hipStreamSynchronize(s->st));
+  return MG_OK;
+}
+
+// Level-0 smoother tiles with class shapes cls (dflt for other classes).
+int apply_class_tiles(mg_solver* s, const std::map<int, Shape>& cls, Shape dflt) {
+  Level& l0 = s->L[0];
+  std::vector<Tile> t;
+  make_class_tiles(l0.info, cls, dflt, {}, t);
+  if (t.size() > l0.cap_gsrb) return fail(MG_ERR_ARG, "tile table larger than its reservation");
+  l0.t_gsrb = t;
+  l0.s_gsrb = class_launch_shape(cls, dflt);
+  l0.cls = cls;
+  l0.cls_base = dflt;
+  HIPTRY(hipMemcpyAsync(l0.d_gsrb, l0.t_gsrb.data(), sizeof(Tile) * l0.t_gsrb.size(),
+                        hipMemcpyHostToDevice, s->st));
   HIPTRY(hipStreamSynchronize(s->st));
   return MG_OK;
 }
@@ -1463,6 +1561,100 @@ int time_rfold(mg_solver* s, bool f32, bool fold, T* phi, float* ms) {
   return MG_OK;
 }
 
+// Time a level-0 smoother tile table (as the solve launches it, with the
+// level's write-through tables), colours alternating.  Leaves the table on
+// the device; the caller re-applies the one it keeps.
+template <typename T>
+int time_table(mg_solver* s, const std::vector<Tile>& t, Shape launch, T* phi, const T* rhs,
+               const StencilArgs<T>& op, float* ms) {
+  Level& l0 = s->L[0];
+  if (t.size() > l0.cap_gsrb) return fail(MG_ERR_ARG, "tile table larger than its reservation");
+  HIPTRY(hipMemcpyAsync(l0.d_gsrb, t.data(), sizeof(Tile) * t.size(), hipMemcpyHostToDevice, s->st));
+  const WtBox* wtb = l0.wt ? l0.d_wtbox : nullptr;
+  const WtEntry* wte = l0.wt ? l0.d_wt : nullptr;
+  hipEvent_t a = take_event(s), b = take_event(s);
+  for (int w = 0; w < 2; ++w)
+    HIPTRY(launch_gsrb<T>(s->st, l0.d_gsrb, (int)t.size(), launch, op, phi, rhs, 0, w & 1, 0, wtb,
+                          wte));
+  HIPTRY(hipEventRecord(a, s->st));
+  const int reps = 6;
+  for (int w = 0; w < reps; ++w)
+    HIPTRY(launch_gsrb<T>(s->st, l0.d_gsrb, (int)t.size(), launch, op, phi, rhs, 0, w & 1, 0, wtb,
+                          wte));
+  HIPTRY(hipEventRecord(b, s->st));
+  HIPTRY(hipEventSynchronize(b));
+  float tm;
+  HIPTRY(hipEventElapsedTime(&tm, a, b));
+  *ms = tm / reps;
+  s->ev_used -= 2;
+  return MG_OK;
+}
+
+// Per-class smoother shapes for level 0 (boxes of at least two x extents):
+// each class's candidates (best_g's thread count, unroll and whole-pair
+// choice) are timed on that class's boxes alone, the best few again; the
+// table with every class at its winner is then timed against best_g's
+// uniform table, three times each, interleaved, and kept only if faster.
+// On return the kept table is applied; *cls is empty when the uniform one
+// won.
+template <typename T>
+int tune_classes(mg_solver* s, Shape best_g, T* phi, const T* rhs, const StencilArgs<T>& op,
+                 std::map<int, Shape>* cls, float* t_uni, float* t_cls) {
+  Level& l0 = s->L[0];
+  cls->clear();
+  std::map<int, std::vector<int>> members;
+  for (int b = 0; b < (int)l0.info.size(); ++b)
+    members[l0.info[b].hi[0] - l0.info[b].lo[0] + 1].push_back(b);
+  int rc;
+  *t_uni = *t_cls = 0;
+  if (members.size() < 2 || l0.fused) return MG_OK;
+  const int threads = best_g.lx * best_g.ly;
+  std::map<int, Shape> pick;
+  for (const auto& kv : members) {
+    std::vector<std::pair<float, Shape>> first;
+    for (Shape c : class_candidates(threads, best_g.u, best_g.wp)) {
+      std::map<int, Shape> one{{kv.first, c}};
+      std::vector<Tile> t;
+      make_class_tiles(l0.info, one, best_g, kv.second, t);
+      float ms;
+      if ((rc = time_table<T>(s, t, class_launch_shape(one, best_g), phi, rhs, op, &ms))) return rc;
+      first.push_back({ms, c});
+    }
+    Shape best = best_g;
+    float bt;
+    if ((rc = pick_finalist(first, [&](Shape c, float* ms) {
+           std::map<int, Shape> one{{kv.first, c}};
+           std::vector<Tile> t;
+           make_class_tiles(l0.info, one, best_g, kv.second, t);
+           return time_table<T>(s, t, class_launch_shape(one, best_g), phi, rhs, op, ms);
+         }, &best, &bt)))
+      return rc;
+    pick[kv.first] = best;
+  }
+  std::vector<Tile> tu, tc;
+  make_tiles(l0.info, best_g, 2 * best_g.lx, false, tu);
+  make_class_tiles(l0.info, pick, best_g, {}, tc);
+  const Shape lc = class_launch_shape(pick, best_g);
+  float bu = 1e30f, bc = 1e30f, ms;
+  for (int rep = 0; rep < 3; ++rep) {
+    if ((rc = time_table<T>(s, tu, best_g, phi, rhs, op, &ms))) return rc;
+    bu = std::min(bu, ms);
+    if ((rc = time_table<T>(s, tc, lc, phi, rhs, op, &ms))) return rc;
+    bc = std::min(bc, ms);
+  }
+  *t_uni = bu;
+  *t_cls = bc;
+  if (bc < bu) {
+    *cls = pick;
+    return apply_class_tiles(s, pick, best_g);
+  }
+  return apply_shape(s, best_g, true);
+}
+
+std::string class_key(const mg_solver* s, bool f32, int x_extent) {
+  return tune_key(s, "gsrbclass", f32) + "|x" + std::to_string(x_extent);
+}
+
 int autotune(mg_solver* s) {
   const bool f32 = s->opts.precision == MG_PREC_F32_REFINE;
   Level& l0 = s->L[0];
@@ -1503,6 +1695,29 @@ int autotune(mg_solver* s) {
       std::vector<Tile> t;
       make_tiles(l0.info, it->second, 2 * it->second.lx, false, t);
       if (t.size() <= l0.cap_gsrb && (rc = apply_shape(s, it->second, true))) return rc;
+      // class shapes, where the tuner found them faster than the uniform one
+      std::map<int, Shape> cls;
+      bool all = !l0.fused;
+      std::set<int> xs;
+      for (const BoxInfo& b : l0.info) xs.insert(b.hi[0] - b.lo[0] + 1);
+      for (int x : xs) {
+        auto ic = cache.find(class_key(s, f32, x));
+        if (ic == cache.end()) {
+          all = false;
+          break;
+        }
+        cls[x] = ic->second;
+      }
+      if (all && xs.size() >= 2) {
+        bool fits = true;
+        for (const auto& kv : cls)
+          fits = fits && kv.second.lx * kv.second.ly == it->second.lx * it->second.ly &&
+                 kv.second.u == it->second.u && kv.second.wp == it->second.wp;
+        std::vector<Tile> tc;
+        make_class_tiles(l0.info, cls, it->second, {}, tc);
+        if (fits && tc.size() <= l0.cap_gsrb && (rc = apply_class_tiles(s, cls, it->second)))
+          return rc;
+      }
     }
     it = cache.find(kr);
     if (it != cache.end() && shape_ok(it->second)) {
@@ -1572,6 +1787,33 @@ int autotune(mg_solver* s) {
   }
   if ((rc = apply_shape(s, best_g, true))) return rc;
   if ((rc = apply_shape(s, best_c, false))) return rc;
+  std::map<int, Shape> cls;
+  float tu = 0, tcl = 0;
+  rc = f32 ? tune_classes<float>(s, best_g, (float*)s->tune_scratch, l0.rhs32,
+                                 stencil_of<float>(s, l0, true), &cls, &tu, &tcl)
+           : tune_classes<double>(s, best_g, s->tune_scratch, l0.r64,
+                                  stencil_of<double>(s, l0, false), &cls, &tu, &tcl);
+  if (rc) return rc;
+  {
+    // a class entry per x extent; a class that keeps best_g is stored as
+    // best_g, so loading the cache rebuilds the same table (or none)
+    std::set<int> xs;
+    for (const BoxInfo& b : l0.info) xs.insert(b.hi[0] - b.lo[0] + 1);
+    for (int x : xs) {
+      auto it = cls.find(x);
+      if (it != cls.end())
+        cache[class_key(s, f32, x)] = it->second;
+      else
+        cache.erase(class_key(s, f32, x));
+    }
+    if (s->opts.verbose && xs.size() >= 2) {
+      fprintf(stderr, "amrmg tune classes: uniform %.4f ms, per class %.4f ms (%s)\n", tu, tcl,
+              cls.empty() ? "uniform kept" : "classes kept");
+      for (const auto& kv : cls)
+        fprintf(stderr, "  x extent %d: %dx%dx%d\n", kv.first, kv.second.lx, kv.second.ly,
+                kv.second.tz);
+    }
+  }
   Shape g1 = t1 ? s->L[1].s_gsrb : Shape{}, c1 = t1 ? s->L[1].s_cell : Shape{};
   float tg1 = 0, tr1 = 0;
   if (t1) {
@@ -3155,6 +3397,27 @@ int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, in
   return apply_shape(s, sh, kernel == 0);
 }
 
+int mg_set_class_tile_shape(mg_solver_t* s, int32_t x_extent, int32_t lx, int32_t ly,
+                            int32_t tz) {
+  if (!s) return fail(MG_ERR_ARG, "null solver");
+  Level& l0 = s->L[0];
+  if (l0.fused) return fail(MG_ERR_ARG, "level 0 uses fused sweeps");
+  bool have = false;
+  for (const BoxInfo& b : l0.info) have = have || b.hi[0] - b.lo[0] + 1 == x_extent;
+  if (!have) return fail(MG_ERR_ARG, "no level-0 box has that x extent");
+  const Shape base = l0.cls.empty() ? l0.s_gsrb : l0.cls_base;
+  bool ok = false;
+  for (Shape c : class_candidates(base.lx * base.ly, base.u, base.wp))
+    if (c.lx == lx && c.ly == ly && c.tz == tz) ok = true;
+  if (!ok) return fail(MG_ERR_ARG, "shape is not a class candidate of the current launch");
+  std::map<int, Shape> cls = l0.cls;
+  cls[x_extent] = Shape{lx, ly, tz, base.u, base.wp};
+  std::vector<Tile> t;
+  make_class_tiles(l0.info, cls, base, {}, t);
+  if (t.size() > l0.cap_gsrb) return fail(MG_ERR_ARG, "tile table larger than its reservation");
+  return apply_class_tiles(s, cls, base);
+}
+
 int mg_get_tile_shape(mg_solver_t* s, int32_t kernel, int32_t* shape) {
   if (!s || !shape) return fail(MG_ERR_ARG, "null argument");
   const Level& l0 = s->L[0];
@@ -3173,6 +3436,23 @@ int mg_get_tile_shape(mg_solver_t* s, int32_t kernel, int32_t* shape) {
     std::memcpy(shape, v, sizeof(v));
   } else {
     return fail(MG_ERR_ARG, "kernel must be 0, 1 or 3");
+  }
+  return MG_OK;
+}
+
+int mg_get_class_tile_shapes(mg_solver_t* s, int32_t* out, int32_t cap, int32_t* n) {
+  if (!s || !n) return fail(MG_ERR_ARG, "null argument");
+  const Level& l0 = s->L[0];
+  *n = (int32_t)l0.cls.size();
+  if (!out) return MG_OK;
+  if (cap < *n) return fail(MG_ERR_ARG, "capacity too small");
+  int i = 0;
+  for (const auto& kv : l0.cls) {
+    out[4 * i] = kv.first;
+    out[4 * i + 1] = kv.second.lx;
+    out[4 * i + 2] = kv.second.ly;
+    out[4 * i + 3] = kv.second.tz;
+    ++i;
   }
   return MG_OK;
 }

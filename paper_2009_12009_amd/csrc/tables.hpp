@@ -20,11 +20,14 @@ struct BoxInfo {
   long long off_f[3];  // ... in face data of direction d (ghost-free, +1 along d)
 };
 
-// One work-group's share: a tile of one box starting at cell (x0, y0, z0); the
-// tile extent is set by the launch (see the kernels).
+// One work-group's share: a tile of one box starting at cell (x0, y0, z0).
+// The tile extent is set by the launch, except for the smoother half-sweep,
+// which reads its lane layout from shape when non-zero: log2(lx) in bits
+// 0-3, ly in bits 4-11, planes in bits 16-31 (the tile's box class shape).
 struct Tile {
   int box;
   int x0, y0, z0;
+  int shape;
 };
 
 // One ghost-copy item, resolved to element offsets: region cell (i, j, k)

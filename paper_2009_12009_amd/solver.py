@@ -232,6 +232,20 @@ class MLMG:
         L.check(L.lib.mg_set_tile_shape(self.handle, kernel, lx, ly, tz, unroll),
                 "mg_set_tile_shape")
 
+    def set_class_tile_shape(self, x_extent, lx, ly, tz):
+        L.check(L.lib.mg_set_class_tile_shape(self.handle, x_extent, lx, ly, tz),
+                "mg_set_class_tile_shape")
+
+    def class_tile_shapes(self):
+        """{x extent: (lx, ly, tz)} of the level-0 smoother's per-class tiles ({} = uniform)."""
+        n = C.c_int32()
+        L.check(L.lib.mg_get_class_tile_shapes(self.handle, None, 0, C.byref(n)),
+                "mg_get_class_tile_shapes")
+        buf = (C.c_int32 * max(1, 4 * n.value))()
+        L.check(L.lib.mg_get_class_tile_shapes(self.handle, buf, n.value, C.byref(n)),
+                "mg_get_class_tile_shapes")
+        return {buf[4 * i]: (buf[4 * i + 1], buf[4 * i + 2], buf[4 * i + 3]) for i in range(n.value)}
+
     def time_smoother(self, phi, rhs, reps=20):
         pm, rm = phi.c_struct(), rhs.c_struct()
         ms = C.c_double(0)

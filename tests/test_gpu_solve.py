@@ -262,6 +262,47 @@ def test_tuned_shapes_bitwise_identical(precision, tmp_path, monkeypatch):
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_class_tile_shapes_bitwise_identical(precision, tmp_path, monkeypatch):
+    """Level-0 smoother tiles chosen per box class (x extent) inside one launch
+    -- forced shapes, including one-plane tiles and tiles wider than their
+    boxes, and the tuner's own per-class choice -- give the bits of the
+    uniform default tiling on uneven boxes (192^3: x extents 32, 48, 64, 96)."""
+    print(f"[solve] class tile shapes 192^3 guillotine precision={precision}", flush=True)
+    P = lib()
+    cfg = W.config_lognormal(192, None, boxes=W.guillotine_boxes(192))
+    boxes = cfg["boxes"]
+    rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(cfg["rhs"], boxes), 0)
+    monkeypatch.setenv("AMRMG_TUNE_CACHE", str(tmp_path / "tiles.txt"))
+    forced = [{96: (16, 16, 4), 48: (64, 4, 2), 64: (32, 8, 8), 32: (16, 16, 16)},
+              {96: (32, 8, 2), 48: (16, 16, 2)},
+              {32: (64, 4, 4), 64: (16, 16, 2), 96: (64, 4, 16), 48: (32, 8, 4)}]
+    outs = []
+    for k in range(len(forced) + 2):
+        tune = 2 if k == len(forced) + 1 else 0
+        s = gpu_solver(cfg, opts=dict(max_iter=3, tune=tune, precision=precision))
+        if 1 <= k <= len(forced):
+            for x, (lx, ly, tz) in forced[k - 1].items():
+                s.set_class_tile_shape(x, lx, ly, tz)
+            assert s.class_tile_shapes() == forced[k - 1]
+        phi = s.cell_mf(1, fill=0.0)
+        s.solve(phi, rhs, 1e-10, raise_on_fail=False)
+        torch.cuda.synchronize()
+        outs.append(to_global(phi, boxes, 192))
+        s.close()
+    assert np.all(np.isfinite(outs[0]))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    # a shape that is not a candidate of the launch is refused
+    s = gpu_solver(cfg, opts=dict(tune=0, precision=precision))
+    with pytest.raises(P.MGError):
+        s.set_class_tile_shape(96, 16, 4, 4)
+    with pytest.raises(P.MGError):
+        s.set_class_tile_shape(80, 32, 8, 4)
+    s.close()
+
+
 FUSED_CASES = [
     # (name, cfg, boxes or None, fused_min_edge, precision)
     ("lognormal64_32boxes_f64", lambda: W.config_lognormal(64, 32), None, 32, 0),

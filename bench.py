@@ -500,7 +500,7 @@ def bench_nodal(args):
     variants = {}
     for name, kry in (("vcycle", 0), ("mgpcg", 1)):
         sv = P.NodalMLMG(boxes, W.domain_box(n), per, sigma=sig,
-                         opts=dict(min_bottom_edge=4, krylov=kry))
+                         opts=dict(min_bottom_edge=4, krylov=kry, tune=2))
         phi = sv.node_mf(0, fill=0.0)
         tv = []
         for k in range(args.warmup + args.steps):

@@ -152,10 +152,21 @@ NdGeo geo_of(const int n[3], const int per[3]) {
   g.px = g.mx + 2;
   g.py = g.my + 2;
   g.per = (per[0] ? 1 : 0) | (per[1] ? 2 : 0) | (per[2] ? 4 : 0);
+  g.tz = 1;
   return g;
 }
 
 long long padded(const NdGeo& g) { return (long long)g.px * g.py * (g.mz + 2); }
+
+// Planes per work-group: as deep as 8 while the level still gets >= 2048
+// work-groups of 64 x 4 lanes (coarse levels: shallow, so that their
+// launches are not a few long serial marches).
+int default_tz(const NdGeo& g) {
+  const long long cols = (long long)((g.mx + 63) / 64) * ((g.my + 3) / 4);
+  int tz = 8;
+  while (tz > 1 && cols * ((g.mz + tz - 1) / tz) < 2048) tz /= 2;
+  return tz;
+}
 
 // K_ab / V of one cell for corners differing in the coordinates of `pat`,
 // from the 1D moment integrals (int l_a l_b = h/3 or h/6, int l_a' l_b' =
@@ -188,6 +199,7 @@ int plan(mg_nodal* s, Bump& bump) {
     NdLevel lv;
     for (int d = 0; d < 3; ++d) lv.n[d] = n[d];
     lv.g = geo_of(n, s->periodic);
+    lv.g.tz = default_tz(lv.g);
     if (lv.g.mx < 1 || lv.g.my < 1 || lv.g.mz < 1)
       return fail(MG_ERR_INVALID_BOXARRAY, "a level has no unknown nodes");
     lv.size = padded(lv.g);
@@ -213,7 +225,12 @@ int plan(mg_nodal* s, Bump& bump) {
   const NdGeo& g0 = s->L[0].g;
   s->sig = bump.take<double>((size_t)(g0.mx + 1) * (g0.my + 1) * (g0.mz + 1));
   s->bwork = bump.take<double>(3 * (size_t)s->L.back().size);
-  s->partials = bump.take<double>((size_t)nd_sum_partials_count(g0));
+  {
+    // room for the partial sums of the shallowest launch depth
+    NdGeo g1 = g0;
+    g1.tz = 1;
+    s->partials = bump.take<double>((size_t)nd_sum_partials_count(g1));
+  }
   s->d_norm = bump.take<unsigned long long>(3 * (size_t)kNdNormSlot);
   s->d_iters = bump.take<int>(4);
   if (s->opts.krylov) {
@@ -585,6 +602,38 @@ int mg_nodal_create(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
         HIPTRY(nd_launch_rap(s->st, f.g, c.g, cst(f.st), c.st));
       for (int q = 0; q < kNdStored; ++q)
         if ((rc = fill_ghosts(s.get(), c, c.st.w[q]))) return rc;
+    }
+    // tune = 2: the finest level's launch depth by timing its Jacobi sweep
+    // (on the zeroed buffers: the speed does not depend on the values)
+    if (s->opts.tune == 2) {
+      NdLevel& l0 = s->L[0];
+      hipEvent_t a = nullptr, b = nullptr;
+      HIPTRY(hipEventCreate(&a));
+      HIPTRY(hipEventCreate(&b));
+      float best = 1e30f;
+      int btz = l0.g.tz;
+      for (int tz : {2, 4, 8, 16}) {
+        l0.g.tz = tz;
+        for (int k = 0; k < 8 && !rc; ++k) {
+          if (k == 2 && hipEventRecord(a, s->st) != hipSuccess) rc = fail(MG_ERR_HIP, "event");
+          if (!rc) rc = sweep(s.get(), 0, l0.x[k & 1], l0.f, l0.x[1 - (k & 1)], ND_JACOBI, nullptr);
+        }
+        float ms = 0.f;
+        if (!rc && (hipEventRecord(b, s->st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                    hipEventElapsedTime(&ms, a, b) != hipSuccess))
+          rc = fail(MG_ERR_HIP, "event timing");
+        if (rc) break;
+        if (ms < best) {
+          best = ms;
+          btz = tz;
+        }
+      }
+      hipEventDestroy(a);
+      hipEventDestroy(b);
+      if (rc) return rc;
+      l0.g.tz = btz;
+      if (s->opts.verbose)
+        fprintf(stderr, "amrmg nodal tune: finest sweep %d planes, %.4f ms\n", btz, best / 6);
     }
     // the coarse part of the cycle as a graph, one per level-0 buffer it
     // interpolates into

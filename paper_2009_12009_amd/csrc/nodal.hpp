@@ -17,6 +17,7 @@ struct NdGeo {
   int mx, my, mz;  // unknowns per direction
   int px, py;      // padded pitches: mx + 2, my + 2
   int per;         // bit d: periodic along d
+  int tz;          // planes a work-group marches (level-wise launch depth)
 };
 
 // The 14 stored couplings of a coarse node (offsets >= 0 in (z, y, x)

@@ -20,8 +20,6 @@ namespace amrmg {
 
 namespace {
 
-constexpr int kTz = 8;
-
 __device__ __forceinline__ int pidx(const NdGeo& g, int x, int y, int z) {
   // padded element of unknown (x, y, z); x, y, z in [-1, m]
   return (x + 1) + g.px * ((y + 1) + g.py * (z + 1));
@@ -66,11 +64,11 @@ __global__ void __launch_bounds__(256)
                 double* __restrict__ out, double omega, unsigned long long* norm) {
   const int ux = blockIdx.x * 64 + threadIdx.x;
   const int uy = blockIdx.y * 4 + threadIdx.y;
-  const int z0 = blockIdx.z * kTz;
+  const int z0 = blockIdx.z * g.tz;
   const bool act = ux < g.mx && uy < g.my && z0 < g.mz;
   unsigned long long mx = 0;
   if (act) {
-    const int z1 = min(z0 + kTz, g.mz);
+    const int z1 = min(z0 + g.tz, g.mz);
     const int sx = g.mx + 1, sy = g.my + 1;  // sigma pitches
     double P[3][3][3];  // [z - uz + 1][y - uy + 1][x - ux + 1]
     double S[2][2][2];  // sigma of cells [z][y][x] = u + s
@@ -163,11 +161,11 @@ __global__ void __launch_bounds__(256)
                   unsigned long long* norm) {
   const int ux = blockIdx.x * 64 + threadIdx.x;
   const int uy = blockIdx.y * 4 + threadIdx.y;
-  const int z0 = blockIdx.z * kTz;
+  const int z0 = blockIdx.z * g.tz;
   const bool act = ux < g.mx && uy < g.my && z0 < g.mz;
   unsigned long long mx = 0;
   if (act) {
-    const int z1 = min(z0 + kTz, g.mz);
+    const int z1 = min(z0 + g.tz, g.mz);
     for (int uz = z0; uz < z1; ++uz) {
       const int c = pidx(g, ux, uy, uz);
       const double fv = f[c];
@@ -257,26 +255,32 @@ __device__ __forceinline__ void interp1(int q, bool per, int mc, int& ia, int& i
 
 __global__ void __launch_bounds__(256)
     k_nd_interp_add(NdGeo gf, NdGeo gc, const double* __restrict__ ec, double* __restrict__ pf) {
+  // lanes along x, gf.tz planes per work-group; every lane loads its 8
+  // coarse values (a term of weight 0 reads a valid node and adds 0 exactly,
+  // so neighbouring lanes of both parities take the same path)
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= gf.mx || y >= gf.my || z >= gf.mz) return;
-  int ix[2], iy[2], iz[2];
-  double wx[2], wy[2], wz[2];
+  const int z0 = blockIdx.z * gf.tz;
+  if (x >= gf.mx || y >= gf.my) return;
+  int ix[2], iy[2];
+  double wx[2], wy[2];
   interp1(x, gf.per & 1, gc.mx, ix[0], ix[1], wx[0], wx[1]);
   interp1(y, gf.per & 2, gc.my, iy[0], iy[1], wy[0], wy[1]);
-  interp1(z, gf.per & 4, gc.mz, iz[0], iz[1], wz[0], wz[1]);
-  double acc = 0.0;
+  const int z1 = min(z0 + gf.tz, gf.mz);
+  for (int z = z0; z < z1; ++z) {
+    int iz[2];
+    double wz[2];
+    interp1(z, gf.per & 4, gc.mz, iz[0], iz[1], wz[0], wz[1]);
+    double acc = 0.0;
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const double w = wx[a] * wy[b] * wz[c];
-        if (w != 0.0) acc += w * ec[pidx(gc, ix[a], iy[b], iz[c])];
-      }
-  pf[pidx(gf, x, y, z)] += acc;
+        for (int a = 0; a < 2; ++a)
+          acc += (wx[a] * wy[b] * wz[c]) * ec[pidx(gc, ix[a], iy[b], iz[c])];
+    pf[pidx(gf, x, y, z)] += acc;
+  }
 }
 
 // Ghosts of direction d from the opposite valid layer; grid covers the
@@ -532,10 +536,10 @@ __global__ void __launch_bounds__(256)
     k_nd_maxabs(NdGeo g, const double* __restrict__ v, unsigned long long* norm) {
   const int ux = blockIdx.x * 64 + threadIdx.x;
   const int uy = blockIdx.y * 4 + threadIdx.y;
-  const int z0 = blockIdx.z * kTz;
+  const int z0 = blockIdx.z * g.tz;
   unsigned long long mx = 0;
   if (ux < g.mx && uy < g.my) {
-    const int z1 = min(z0 + kTz, g.mz);
+    const int z1 = min(z0 + g.tz, g.mz);
     for (int uz = z0; uz < z1; ++uz) {
       const unsigned long long b = absbits(v[pidx(g, ux, uy, uz)]);
       mx = b > mx ? b : mx;
@@ -646,10 +650,10 @@ __global__ void __launch_bounds__(256)
   __shared__ double red[4];
   const int ux = blockIdx.x * 64 + threadIdx.x;
   const int uy = blockIdx.y * 4 + threadIdx.y;
-  const int z0 = blockIdx.z * kTz;
+  const int z0 = blockIdx.z * g.tz;
   double sm = 0.0;
   if (ux < g.mx && uy < g.my) {
-    const int z1 = min(z0 + kTz, g.mz);
+    const int z1 = min(z0 + g.tz, g.mz);
     for (int uz = z0; uz < z1; ++uz) sm += v[pidx(g, ux, uy, uz)];
   }
   for (int o = 32; o > 0; o >>= 1) sm += __shfl_xor(sm, o);
@@ -673,9 +677,9 @@ __global__ void __launch_bounds__(256)
   __syncthreads();
   const int ux = blockIdx.x * 64 + threadIdx.x;
   const int uy = blockIdx.y * 4 + threadIdx.y;
-  const int z0 = blockIdx.z * kTz;
+  const int z0 = blockIdx.z * g.tz;
   if (ux < g.mx && uy < g.my) {
-    const int z1 = min(z0 + kTz, g.mz);
+    const int z1 = min(z0 + g.tz, g.mz);
     for (int uz = z0; uz < z1; ++uz) v[pidx(g, ux, uy, uz)] -= mean;
   }
 }
@@ -687,10 +691,10 @@ __global__ void __launch_bounds__(256)
   __shared__ double red[4];
   const int ux = blockIdx.x * 64 + threadIdx.x;
   const int uy = blockIdx.y * 4 + threadIdx.y;
-  const int z0 = blockIdx.z * kTz;
+  const int z0 = blockIdx.z * g.tz;
   double sm = 0.0;
   if (ux < g.mx && uy < g.my) {
-    const int z1 = min(z0 + kTz, g.mz);
+    const int z1 = min(z0 + g.tz, g.mz);
     for (int uz = z0; uz < z1; ++uz) {
       const int c = pidx(g, ux, uy, uz);
       sm += a[c] * b[c];
@@ -722,10 +726,10 @@ __global__ void __launch_bounds__(256)
               const double* __restrict__ rho, const double* __restrict__ rho_old, int restart) {
   const int ux = blockIdx.x * 64 + threadIdx.x;
   const int uy = blockIdx.y * 4 + threadIdx.y;
-  const int z0 = blockIdx.z * kTz;
+  const int z0 = blockIdx.z * g.tz;
   if (ux >= g.mx || uy >= g.my) return;
   const double beta = restart ? 0.0 : *rho / *rho_old;
-  const int z1 = min(z0 + kTz, g.mz);
+  const int z1 = min(z0 + g.tz, g.mz);
   for (int uz = z0; uz < z1; ++uz) {
     const int c = pidx(g, ux, uy, uz);
     p[c] = restart ? z[c] : z[c] + beta * p[c];
@@ -740,11 +744,11 @@ __global__ void __launch_bounds__(256)
                unsigned long long* norm) {
   const int ux = blockIdx.x * 64 + threadIdx.x;
   const int uy = blockIdx.y * 4 + threadIdx.y;
-  const int z0 = blockIdx.z * kTz;
+  const int z0 = blockIdx.z * g.tz;
   unsigned long long mx = 0;
   if (ux < g.mx && uy < g.my) {
     const double alpha = *rho / *pq;
-    const int z1 = min(z0 + kTz, g.mz);
+    const int z1 = min(z0 + g.tz, g.mz);
     for (int uz = z0; uz < z1; ++uz) {
       const int c = pidx(g, ux, uy, uz);
       x[c] += alpha * p[c];
@@ -768,7 +772,7 @@ __global__ void k_nd_fill_u64(unsigned long long* a, int n, unsigned long long v
 }
 
 dim3 sweep_grid(const NdGeo& g) {
-  return dim3((g.mx + 63) / 64, (g.my + 3) / 4, (g.mz + kTz - 1) / kTz);
+  return dim3((g.mx + 63) / 64, (g.my + 3) / 4, (g.mz + g.tz - 1) / g.tz);
 }
 dim3 plane_grid(const NdGeo& g) { return dim3((g.mx + 63) / 64, (g.my + 3) / 4, g.mz); }
 
@@ -810,7 +814,7 @@ hipError_t nd_launch_restrict(hipStream_t st, const NdGeo& gf, const NdGeo& gc, 
 
 hipError_t nd_launch_interp_add(hipStream_t st, const NdGeo& gf, const NdGeo& gc,
                                 const double* ec, double* phif) {
-  hipLaunchKernelGGL(k_nd_interp_add, plane_grid(gf), dim3(64, 4), 0, st, gf, gc, ec, phif);
+  hipLaunchKernelGGL(k_nd_interp_add, sweep_grid(gf), dim3(64, 4), 0, st, gf, gc, ec, phif);
   return hipGetLastError();
 }
 

@@ -61,11 +61,18 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, shape):
+def _classes_key(classes):
+    """{x extent: (lx, ly, tz)} -> the canonical text of a block's `classes:` line."""
+    return "; ".join(f"{int(x)} {v[0]} {v[1]} {v[2]}"
+                     for x, v in sorted((int(x), v) for x, v in (classes or {}).items()))
+
+
+def measured_traffic(kernel, shape, classes=None):
     """HBM bytes per launch of the level-0 half-sweep from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
     None when the summary is missing, was taken on other kernel sources, or holds
-    no block for this kernel and tile shape."""
+    no block for this kernel, launch shape and per-class tile table (a block
+    without a `classes:` line is the uniform table)."""
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
@@ -79,7 +86,8 @@ def measured_traffic(kernel, shape):
                 kv[k.strip()] = v.strip()
         try:
             if (kv.get("source_sha256") != kernel_source_sha256() or kv.get("kernel") != kernel
-                    or tuple(int(x) for x in kv["shape"].split()) != tuple(shape)):
+                    or tuple(int(x) for x in kv["shape"].split()) != tuple(shape)
+                    or kv.get("classes", "") != _classes_key(classes)):
                 continue
             return (float(kv["fetch_kib_per_dispatch"]) * 1024 * float(kv["fetch_scale"])
                     + float(kv["write_kib_per_dispatch"]) * 1024 * float(kv["write_scale"]))
@@ -194,13 +202,15 @@ def main():
         for name, fid in (("smooth", 0), ("residual", 1), ("exchange", 2), ("restrict", 3),
                           ("prolong", 4), ("coarse_levels", 5), ("update", 6), ("rim", 7)):
             t, c = s.kernel_stats(fid)
-            fam[name] = dict(ms_per_solve=t / args.profile_steps,
-                             launches_per_solve=c / args.profile_steps)
+            fam[name] = dict(ms_per_solve=t / max(args.profile_steps, 1),
+                             launches_per_solve=c / max(args.profile_steps, 1))
         gs[k]["families"] = fam
         # rim launches only come with fused sweeps (the tuner may have kept half-sweeps)
         gs[k]["fused"] = fam["rim"]["launches_per_solve"] > 0
         gs[k]["tile_shapes"] = {"smoother": s.tile_shape(0), "cell": s.tile_shape(1),
-                                "fused_sweep": s.tile_shape(3)}
+                                "fused_sweep": s.tile_shape(3),
+                                "smoother_classes": {str(x): list(v) for x, v in
+                                                     sorted(s.class_tile_shapes().items())}}
         s.profile(False)
 
     # the level-0 FP64 half-sweep launched alone, without ghost write-through
@@ -270,8 +280,8 @@ def main():
              if g64["fused"] else
              "k_gsrb<double> level 0, one half-sweep with face-ghost write-through "
              "(64 boxes of 64^3)")
-    traffic = None if g64["fused"] else measured_traffic("k_gsrb<double>",
-                                                         g64["tile_shapes"]["smoother"])
+    traffic = None if g64["fused"] else measured_traffic(
+        "k_gsrb<double>", g64["tile_shapes"]["smoother"], g64["tile_shapes"]["smoother_classes"])
     result["roofline"] = {
         "bound": "hbm",
         "achieved": g64["gbps"],
@@ -406,12 +416,18 @@ def bench_c3(args):
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 20
+    # HIP events around the kernel itself on the solver's stream (profile family 8)
+    s.profile(True)
     e0.record()
     for _ in range(reps):
         s.face_grad_logb_global(ph, lm)
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    t_k, n_k = s.kernel_stats(8)
+    s.profile(False)
+    ms = t_k / max(n_k, 1)
+    # the whole call: ghost exchange of phi and lambda, output allocation, the kernel
+    ms_call = e0.elapsed_time(e1) / reps
     nf = 3 * (n + 1) * n * n
     # what the method must move: per face b in and the gradient out, per cell phi and lambda
     # once (one pass over all three directions)
@@ -422,7 +438,9 @@ def bench_c3(args):
            "value": float(np.median(fw) + np.median(bw)),
            "forward_ms": float(np.median(fw)), "backward_ms": float(np.median(bw)),
            "face_grad_ms": ms, "face_grad_gbps": alg / (ms * 1e-3) / 1e9,
-           "face_grad_alg_bytes": alg}
+           "face_grad_alg_bytes": alg, "face_grad_call_ms": ms_call,
+           "face_grad_timing": "kernel alone: HIP events on the solver's stream; call: "
+                               "exchange of phi and lambda, output allocation and the kernel"}
     print(json.dumps(out), flush=True)
     s.close()
 

@@ -348,7 +348,10 @@ int mg_num_levels(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
  * post-smoothing half-sweep that carries it when interp_fold applies),
  * 5 coarse levels (one graph or launch sequence per cycle, from the
  * restriction of the level-0 residual to level 1's corrections), 6 refinement
- * update and Krylov vector work, 7 the rim pass that ends a fused sweep. */
+ * update and Krylov vector work, 7 the rim pass that ends a fused sweep,
+ * 8 the face-gradient kernel of mg_face_grad_logb and
+ * mg_face_grad_logb_global (the pass alone, without the ghost exchange of
+ * phi and lambda before it). */
 int mg_profile(mg_solver_t* s, int32_t enable);
 int mg_kernel_stats(mg_solver_t* s, int32_t family, double* total_ms, int64_t* launches);
 

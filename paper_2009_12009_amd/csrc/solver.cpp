@@ -3061,6 +3061,7 @@ static int face_grad_run(mg_solver_t* s, mg_multifab_t* phi, mg_multifab_t* lam,
   const int perbits = (s->periodic[0] ? 1 : 0) | (s->periodic[1] ? 2 : 0) |
                       (s->periodic[2] ? 4 : 0);
   double* const o[3] = {(double*)out[0], (double*)out[1], (double*)out[2]};
+  ProfScope ps(s, 8, true);
   HIPTRY(launch_face_grad(s->st, l0.nbox, stencil_of<double>(s, l0, false),
                           (const double*)phi->data, (const double*)lam->data, o, mode, dlo, dn,
                           perbits, max_n));

@@ -40,6 +40,23 @@ def test_traffic_lookup_picks_the_matching_block(tmp_path, monkeypatch):
     assert bench.measured_traffic("k_sweep<double>", (32, 8, 2, 2, 0)) is None
 
 
+def test_traffic_lookup_keys_on_the_class_table(tmp_path, monkeypatch):
+    """A block with a `classes:` line matches only a run with that per-class table; a
+    block without one matches only the uniform table."""
+    sha = bench.kernel_source_sha256()
+    cls = dict(_block((32, 8, 2, 2, 0), sha, 400.0, 80.0), classes="64 64 4 2")
+    f = tmp_path / "traffic.md"
+    f.write_text(_summary([_block((32, 8, 2, 2, 0), sha, 100.0, 50.0), cls]))
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(f))
+    assert bench.measured_traffic("k_gsrb<double>", (32, 8, 2, 2, 0)) == (100 * 2 + 50) * 1024
+    assert bench.measured_traffic("k_gsrb<double>", (32, 8, 2, 2, 0), {}) == (100 * 2 + 50) * 1024
+    assert (bench.measured_traffic("k_gsrb<double>", (32, 8, 2, 2, 0), {"64": [64, 4, 2]})
+            == (400 * 2 + 80) * 1024)
+    assert bench.measured_traffic("k_gsrb<double>", (32, 8, 2, 2, 0), {"64": [32, 8, 4]}) is None
+    assert bench.measured_traffic("k_gsrb<double>", (32, 8, 2, 2, 0),
+                                  {"64": [64, 4, 2], "32": [32, 8, 2]}) is None
+
+
 def test_traffic_lookup_tolerates_missing_or_broken_summaries(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "absent.md"))
     assert bench.measured_traffic("k_gsrb<double>", (32, 8, 2, 2, 0)) is None

@@ -213,6 +213,10 @@ def main():
                                                      sorted(s.class_tile_shapes().items())}}
         s.profile(False)
 
+    # every variant's last solution, for its error against the oracle's (taken before
+    # the stand-alone smoother timing below sweeps the FP64 solver's phi in place)
+    sols = {k: W.gather_cells(phis[k].valid_numpy(), boxes, n) for k in solvers}
+
     # the level-0 FP64 half-sweep launched alone, without ghost write-through
     ms_alone = solvers["f64"].time_smoother(phis["f64"], rhs, reps=20)
     smoother_alone = {"mean_ms": ms_alone, "gbps": 6 * 8 * ncell / (ms_alone * 1e-3) / 1e9}
@@ -234,9 +238,6 @@ def main():
     copy_gbps = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     assert bool(torch.all(dst == 1.0))
     del src, dst
-
-    # every variant's last solution, for its error against the oracle's
-    sols = {k: W.gather_cells(phis[k].valid_numpy(), boxes, n) for k in solvers}
 
     t64 = [r["solve_ms"] for r in rec["f64"]]
     t32 = [r["solve_ms"] for r in rec["f32_refine"]]

@@ -25,6 +25,30 @@ __device__ __forceinline__ int pidx(const NdGeo& g, int x, int y, int z) {
   return (x + 1) + g.px * ((y + 1) + g.py * (z + 1));
 }
 
+// Work-groups go to the 8 XCDs round robin (block b to XCD b % 8), and each
+// XCD has its own L2.  The tiled kernels take their tile from a 1-D grid of
+// 8 * ceil(n / 8) blocks so that every XCD runs one contiguous run of the
+// tile order (x fastest, then y, then z): tiles that share halo rows and
+// planes then share an L2.  A block past the last tile has no work.
+constexpr int kNdXcds = 8;
+
+__device__ __forceinline__ bool nd_tile(int ntx, int nty, int ntz, int& tx, int& ty, int& tz) {
+  const int n = ntx * nty * ntz;
+  const int per = (n + kNdXcds - 1) / kNdXcds;
+  const int b = (int)blockIdx.x;
+  const int t = (b % kNdXcds) * per + b / kNdXcds;
+  if (t >= n) return false;
+  tx = t % ntx;
+  const int r = t / ntx;
+  ty = r % nty;
+  tz = r / nty;
+  return true;
+}
+
+__device__ __forceinline__ int nd_ntx(const NdGeo& g) { return (g.mx + 63) / 64; }
+__device__ __forceinline__ int nd_nty(const NdGeo& g) { return (g.my + 3) / 4; }
+__device__ __forceinline__ int nd_ntz(const NdGeo& g) { return (g.mz + g.tz - 1) / g.tz; }
+
 __device__ __forceinline__ unsigned long long absbits(double v) {
   return (unsigned long long)__double_as_longlong(fabs(v));
 }
@@ -62,9 +86,11 @@ __global__ void __launch_bounds__(256)
     k_nd_sweep0(NdGeo g, NdKappa kap, const double* __restrict__ sig,
                 const double* __restrict__ phi, const double* __restrict__ f,
                 double* __restrict__ out, double omega, unsigned long long* norm) {
-  const int ux = blockIdx.x * 64 + threadIdx.x;
-  const int uy = blockIdx.y * 4 + threadIdx.y;
-  const int z0 = blockIdx.z * g.tz;
+  int tx, ty, tz;
+  if (!nd_tile(nd_ntx(g), nd_nty(g), nd_ntz(g), tx, ty, tz)) return;  // whole block
+  const int ux = tx * 64 + threadIdx.x;
+  const int uy = ty * 4 + threadIdx.y;
+  const int z0 = tz * g.tz;
   const bool act = ux < g.mx && uy < g.my && z0 < g.mz;
   unsigned long long mx = 0;
   if (act) {
@@ -159,9 +185,11 @@ __global__ void __launch_bounds__(256)
     k_nd_sweep_st(NdGeo g, NdStencilC s, const double* __restrict__ phi,
                   const double* __restrict__ f, double* __restrict__ out, double omega,
                   unsigned long long* norm) {
-  const int ux = blockIdx.x * 64 + threadIdx.x;
-  const int uy = blockIdx.y * 4 + threadIdx.y;
-  const int z0 = blockIdx.z * g.tz;
+  int tx, ty, tz;
+  if (!nd_tile(nd_ntx(g), nd_nty(g), nd_ntz(g), tx, ty, tz)) return;  // whole block
+  const int ux = tx * 64 + threadIdx.x;
+  const int uy = ty * 4 + threadIdx.y;
+  const int z0 = tz * g.tz;
   const bool act = ux < g.mx && uy < g.my && z0 < g.mz;
   unsigned long long mx = 0;
   if (act) {
@@ -206,10 +234,11 @@ __device__ __forceinline__ double pw1(int t) { return t == 0 ? 1.0 : ((t == 1 ||
 
 __global__ void __launch_bounds__(256)
     k_nd_restrict(NdGeo gf, NdGeo gc, const double* __restrict__ rf, double* __restrict__ rc) {
-  const int I = blockIdx.x * 64 + threadIdx.x;
-  const int J = blockIdx.y * 4 + threadIdx.y;
-  const int K = blockIdx.z;
-  if (I >= gc.mx || J >= gc.my || K >= gc.mz) return;
+  int tx, ty, K;
+  if (!nd_tile(nd_ntx(gc), nd_nty(gc), gc.mz, tx, ty, K)) return;
+  const int I = tx * 64 + threadIdx.x;
+  const int J = ty * 4 + threadIdx.y;
+  if (I >= gc.mx || J >= gc.my) return;
   double acc = 0.0;
 #pragma unroll
   for (int uz = -1; uz <= 1; ++uz) {
@@ -258,9 +287,11 @@ __global__ void __launch_bounds__(256)
   // lanes along x, gf.tz planes per work-group; every lane loads its 8
   // coarse values (a term of weight 0 reads a valid node and adds 0 exactly,
   // so neighbouring lanes of both parities take the same path)
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  const int z0 = blockIdx.z * gf.tz;
+  int tx, ty, tz;
+  if (!nd_tile(nd_ntx(gf), nd_nty(gf), nd_ntz(gf), tx, ty, tz)) return;
+  const int x = tx * 64 + threadIdx.x;
+  const int y = ty * 4 + threadIdx.y;
+  const int z0 = tz * gf.tz;
   if (x >= gf.mx || y >= gf.my) return;
   int ix[2], iy[2];
   double wx[2], wy[2];
@@ -775,6 +806,18 @@ dim3 sweep_grid(const NdGeo& g) {
   return dim3((g.mx + 63) / 64, (g.my + 3) / 4, (g.mz + g.tz - 1) / g.tz);
 }
 dim3 plane_grid(const NdGeo& g) { return dim3((g.mx + 63) / 64, (g.my + 3) / 4, g.mz); }
+// 1-D grids of the XCD-grouped tile order (nd_tile)
+dim3 xcd_grid(long long ntiles) {
+  return dim3((unsigned)(kNdXcds * ((ntiles + kNdXcds - 1) / kNdXcds)));
+}
+dim3 sweep_grid_xcd(const NdGeo& g) {
+  const dim3 t = sweep_grid(g);
+  return xcd_grid((long long)t.x * t.y * t.z);
+}
+dim3 plane_grid_xcd(const NdGeo& g) {
+  const dim3 t = plane_grid(g);
+  return xcd_grid((long long)t.x * t.y * t.z);
+}
 
 }  // namespace
 
@@ -783,7 +826,7 @@ hipError_t nd_launch_sweep0(hipStream_t st, const NdGeo& g, const NdKappa& k, co
                             int mode, unsigned long long* norm) {
   const dim3 b(64, 4);
 #define L0(M, N) \
-  hipLaunchKernelGGL((k_nd_sweep0<M, N>), sweep_grid(g), b, 0, st, g, k, sig, phi, f, out, omega, norm)
+  hipLaunchKernelGGL((k_nd_sweep0<M, N>), sweep_grid_xcd(g), b, 0, st, g, k, sig, phi, f, out, omega, norm)
   if (mode == ND_ZERO) L0(ND_ZERO, false);
   else if (mode == ND_APPLY) L0(ND_APPLY, false);
   else if (mode == ND_RESID) { if (norm) L0(ND_RESID, true); else L0(ND_RESID, false); }
@@ -797,7 +840,7 @@ hipError_t nd_launch_sweep_st(hipStream_t st, const NdGeo& g, const NdStencilC& 
                               int mode, unsigned long long* norm) {
   const dim3 b(64, 4);
 #define LS(M, N) \
-  hipLaunchKernelGGL((k_nd_sweep_st<M, N>), sweep_grid(g), b, 0, st, g, s, phi, f, out, omega, norm)
+  hipLaunchKernelGGL((k_nd_sweep_st<M, N>), sweep_grid_xcd(g), b, 0, st, g, s, phi, f, out, omega, norm)
   if (mode == ND_ZERO) LS(ND_ZERO, false);
   else if (mode == ND_APPLY) LS(ND_APPLY, false);
   else if (mode == ND_RESID) { if (norm) LS(ND_RESID, true); else LS(ND_RESID, false); }
@@ -808,13 +851,13 @@ hipError_t nd_launch_sweep_st(hipStream_t st, const NdGeo& g, const NdStencilC& 
 
 hipError_t nd_launch_restrict(hipStream_t st, const NdGeo& gf, const NdGeo& gc, const double* rf,
                               double* rc) {
-  hipLaunchKernelGGL(k_nd_restrict, plane_grid(gc), dim3(64, 4), 0, st, gf, gc, rf, rc);
+  hipLaunchKernelGGL(k_nd_restrict, plane_grid_xcd(gc), dim3(64, 4), 0, st, gf, gc, rf, rc);
   return hipGetLastError();
 }
 
 hipError_t nd_launch_interp_add(hipStream_t st, const NdGeo& gf, const NdGeo& gc,
                                 const double* ec, double* phif) {
-  hipLaunchKernelGGL(k_nd_interp_add, sweep_grid(gf), dim3(64, 4), 0, st, gf, gc, ec, phif);
+  hipLaunchKernelGGL(k_nd_interp_add, sweep_grid_xcd(gf), dim3(64, 4), 0, st, gf, gc, ec, phif);
   return hipGetLastError();
 }
 

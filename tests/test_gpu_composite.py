@@ -219,8 +219,10 @@ def test_c4_full_size_composite_residual(krylov):
     normf = max(max(float(np.max(np.abs(x))) for x in f_f),
                 max(float(np.max(np.abs(x))) for x in fc_boxes))
     assert r <= 1e-10 * normf * (1 + 1e-3)
+    print(f"C4: reported residual {info['abs_resid']:.6e}, oracle's {r:.6e}, "
+          f"relative difference {abs(r - info['abs_resid']) / r:.2e}")
     # near 1e-10 the residual sits within ~1e3 ulps of the fine stencil's terms
     # (1/h_f^2 = 2.6e5, b up to e^4), so the two sides' summation orders differ
-    # by a few percent of r
-    assert abs(r - info["abs_resid"]) <= 0.05 * r
+    # in r's leading digits (measured 3.6e-4 relative stationary, 1.0e-5 FGMRES)
+    assert abs(r - info["abs_resid"]) <= 2e-3 * r
     s.close()

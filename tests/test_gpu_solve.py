@@ -47,6 +47,10 @@ def _check_history(g, o, rtol=1e-6):
     f - A phi (the two sides sum the stencil in different orders)."""
     assert g["iters"] == o["iters"], (g["history"], o["history"])
     nf = float(o["normf"])
+    worst_rel = max(abs(a - b) / b for a, b in zip(g["history"], o["history"]))
+    worst_abs = max(abs(a - b) for a, b in zip(g["history"], o["history"])) / nf
+    print(f"history: {g['iters']} cycles, worst |gpu - oracle| {worst_rel:.2e} relative, "
+          f"{worst_abs:.2e} max|f|")
     for k, (a, b) in enumerate(zip(g["history"], o["history"])):
         assert abs(a - b) <= rtol * b + 1e-12 * nf, (k, a, b)
 

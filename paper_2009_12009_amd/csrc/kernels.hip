@@ -715,12 +715,17 @@ __device__ double block_sum(double v, double* red, int& phase);
 // layout as phi, valid cells only): a red cell gets (f + off) / diag from
 // the same gathered values, the same expression as the half-sweep, and a
 // black cell its old value.  The residual is that of phi, before the update.
+// With wtb/wte (non-null) each new red value on the box's boundary layer is
+// also stored into the face ghosts of pnext that mirror it, as the
+// half-sweep's write-through does: the next half-sweep (black) reads only
+// red values, so pnext then needs no exchange.
 template <typename T, typename TO, int U, bool BUF, bool NX>
 __global__ void __launch_bounds__(256)
     k_residual(const Tile* __restrict__ tiles, StencilArgs<T> op, const T* __restrict__ phi,
                const T* __restrict__ rhs, int rhs_ng, TO* __restrict__ out,
                unsigned long long* normbits, int tz, int mode, double* __restrict__ dot_partials,
-               T* __restrict__ pnext) {
+               T* __restrict__ pnext, const WtBox* __restrict__ wtb,
+               const WtEntry* __restrict__ wte) {
   const Tile t = tiles[blockIdx.x];
   const BoxInfo B = op.boxes[t.box];
   const int i = t.x0 + threadIdx.x;
@@ -728,6 +733,13 @@ __global__ void __launch_bounds__(256)
   const bool act = i <= B.hi[0] && j <= B.hi[1];
   unsigned long long mx = 0;
   double dot = 0.0;
+  WtBox wb;
+  WtEntry ex[2];
+  if (NX && wtb) {
+    wb = wtb[t.box];
+    for (int f = 0; f < 2; ++f)
+      if (wb.count[f] == 1) ex[f] = wte[wb.first[f]];
+  }
   if (act) {
     const Strides s = strides_of(B, rhs_ng);
     const int kend = min(t.z0 + tz - 1, B.hi[2]);
@@ -765,8 +777,9 @@ __global__ void __launch_bounds__(256)
         if (O) O[il + s.nx * (jl + s.ny * kl)] = (TO)r;
         if (NX) {
           const bool red = ((i + j + k0 + u) & 1) == 0;
-          pnext[B.off_g1 + (il + 1) + s.sy * (jl + 1) + s.sz * (kl + 1)] =
-              red ? (v[u].f + c.off) / c.diag : v[u].pc;
+          const T nv = red ? (v[u].f + c.off) / c.diag : v[u].pc;
+          pnext[B.off_g1 + (il + 1) + s.sy * (jl + 1) + s.sz * (kl + 1)] = nv;
+          if (wtb && red) write_through<T>(wb, ex, wte, pnext, s, il, jl, kl, nv);
         }
         const unsigned long long bits = absbits(r);
         mx = bits > mx ? bits : mx;
@@ -1988,13 +2001,14 @@ template <typename T, typename TO>
 hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                            const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
                            TO* out, unsigned long long* normbits, int mode,
-                           double* dot_partials, T* pnext) {
+                           double* dot_partials, T* pnext, const WtBox* wtb, const WtEntry* wte) {
   if (ntiles <= 0) return hipSuccess;
   if (pnext && (mode != 0 || !rhs || pnext == phi)) return hipErrorInvalidValue;
+  if ((wtb || wte) && (!pnext || !wtb || !wte)) return hipErrorInvalidValue;
   const dim3 g(ntiles), b = block_of(sh);
 #define RS(U, F, N)                                                                           \
   hipLaunchKernelGGL((k_residual<T, TO, U, F, N>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng,    \
-                     out, normbits, sh.tz, mode, dot_partials, pnext)
+                     out, normbits, sh.tz, mode, dot_partials, pnext, wtb, wte)
 #define RSU(F, N) \
   if (sh.u >= 4) RS(4, F, N); else if (sh.u == 2) RS(2, F, N); else RS(1, F, N);
   // buffer loads where the level streams (op.buf)
@@ -2434,15 +2448,18 @@ INST(float)
 template hipError_t launch_residual<double, double>(hipStream_t, const Tile*, int, Shape,
                                                     const StencilArgs<double>&, const double*,
                                                     const double*, int, double*,
-                                                    unsigned long long*, int, double*, double*);
+                                                    unsigned long long*, int, double*, double*,
+                                                    const WtBox*, const WtEntry*);
 template hipError_t launch_residual<double, float>(hipStream_t, const Tile*, int, Shape,
                                                    const StencilArgs<double>&, const double*,
                                                    const double*, int, float*,
-                                                   unsigned long long*, int, double*, double*);
+                                                   unsigned long long*, int, double*, double*,
+                                                   const WtBox*, const WtEntry*);
 template hipError_t launch_residual<float, float>(hipStream_t, const Tile*, int, Shape,
                                                   const StencilArgs<float>&, const float*,
                                                   const float*, int, float*,
-                                                  unsigned long long*, int, double*, float*);
+                                                  unsigned long long*, int, double*, float*,
+                                                  const WtBox*, const WtEntry*);
 template hipError_t launch_convert<double, float>(hipStream_t, const double*, float*, long long);
 template hipError_t launch_convert<float, double>(hipStream_t, const float*, double*, long long);
 

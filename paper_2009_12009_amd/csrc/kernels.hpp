@@ -98,12 +98,16 @@ hipError_t launch_rim(hipStream_t st, const RimTile* tiles, int ntiles, const St
 // phi) the launch also writes phi after a red half-sweep into pnext's valid
 // cells (red cells updated with the half-sweep's expression, black cells
 // copied), so that a stop test's residual and the next cycle's first
-// half-sweep share one pass over the level; pnext's ghosts are not written.
+// half-sweep share one pass over the level.  pnext's ghosts are written only
+// with the level's write-through tables (wtb, wte; both or neither): then
+// each new red value reaches the face ghosts that mirror it (black ghosts
+// are left, the next half-sweep being black).
 template <typename T, typename TO>
 hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                            const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
                            TO* out, unsigned long long* normbits, int mode,
-                           double* dot_partials = nullptr, T* pnext = nullptr);
+                           double* dot_partials = nullptr, T* pnext = nullptr,
+                           const WtBox* wtb = nullptr, const WtEntry* wte = nullptr);
 
 // max |v| over valid cells folded into *normbits (v: ng 0 or 1 layout).
 template <typename T>

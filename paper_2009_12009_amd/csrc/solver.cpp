@@ -2870,9 +2870,12 @@ int solve_folded(mg_solver* s, double* P, const double* F, int rng, double tol, 
     HIPTRY(launch_fill_u64(s->st, norm_slot(s, slot), kNormSlot, 0ull));
     {
       ProfScope ps(s, 1, true);
+      // with write-through the pass also puts its red values into nxt's face
+      // ghosts, and the black half-sweep that follows reads nothing else
       HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell,
                                               op, cur, F, rng, nullptr, norm_slot(s, slot), 0,
-                                              nullptr, nxt)));
+                                              nullptr, nxt, l0.wt ? l0.d_wtbox : nullptr,
+                                              l0.wt ? l0.d_wt : nullptr)));
     }
     HIPTRY(hipMemcpyAsync(s->h_norm + (size_t)slot * kNormSlot, norm_slot(s, slot),
                           sizeof(unsigned long long) * kNormSlot, hipMemcpyDeviceToHost, s->st));
@@ -2887,7 +2890,7 @@ int solve_folded(mg_solver* s, double* P, const double* F, int rng, double tol, 
       if (d < 0) return fail(MG_ERR_HIP, "norm read-back failed");
       if (d) break;
     }
-    if ((rc = exchange<double>(s, l0, nxt, false))) return rc;
+    if (!l0.wt && (rc = exchange<double>(s, l0, nxt, false))) return rc;
     if ((rc = vcycle64(s, nxt, F, rng, true))) return rc;
     if (!wait) {
       const int d = decide();

@@ -1143,12 +1143,26 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-__global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ partials, int n,
-                                                  double* __restrict__ out) {
+// One work-group of kSumLanes lanes; lane l adds partials l, l + kSumLanes,
+// ... into four accumulators in turn (four independent loads in flight per
+// lane: tens of thousands of partials take a few round trips, not hundreds),
+// then the accumulators and the lanes in a fixed tree: the same order on
+// every call.
+constexpr int kSumLanes = 1024;
+__global__ void __launch_bounds__(kSumLanes) k_sum_final(const double* __restrict__ partials, int n,
+                                                        double* __restrict__ out) {
   __shared__ double red[32];
   int phase = 0;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += partials[i];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * kSumLanes < n; i += 4 * kSumLanes) {
+    a0 += partials[i];
+    a1 += partials[i + kSumLanes];
+    a2 += partials[i + 2 * kSumLanes];
+    a3 += partials[i + 3 * kSumLanes];
+  }
+  for (; i < n; i += kSumLanes) a0 += partials[i];
+  double s = (a0 + a1) + (a2 + a3);
   s = block_sum(s, red, phase);
   if (threadIdx.x == 0) *out = s;
 }
@@ -2084,7 +2098,7 @@ hipError_t launch_sum_valid(hipStream_t st, const Tile* tiles, int ntiles, Shape
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sum_partial, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, v, ng,
                      partials, sh.tz);
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partials, ntiles, sum);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kSumLanes), 0, st, partials, ntiles, sum);
   return hipGetLastError();
 }
 
@@ -2103,7 +2117,7 @@ hipError_t launch_dot(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_dot_partial, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, a, ang, b,
                      bng, partials, sh.tz);
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partials, ntiles, out);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kSumLanes), 0, st, partials, ntiles, out);
   return hipGetLastError();
 }
 
@@ -2119,7 +2133,7 @@ hipError_t launch_cg_xr(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
 
 hipError_t launch_sum_final(hipStream_t st, const double* partials, int n, double* out) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partials, n, out);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kSumLanes), 0, st, partials, n, out);
   return hipGetLastError();
 }
 
@@ -2183,7 +2197,7 @@ hipError_t launch_widen_dot(hipStream_t st, const Tile* tiles, int ntiles, Shape
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_widen_dot, dim3(ntiles), block_of(sh), 0, st, tiles, boxes, e, z, r,
                      partials, sh.tz);
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partials, ntiles, out);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kSumLanes), 0, st, partials, ntiles, out);
   return hipGetLastError();
 }
 

@@ -1952,7 +1952,10 @@ hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
     if (buf && sizeof(T) == 4) { GSU(false, false, true, true, true) }
     else { GSU(false, false, true, true, false) }
   } else if (wtb) {
-    if (zero_guess) { GSU(true, false, true, false, false) }
+    // a zero-guess half-sweep reads f and the faces once each: streaming
+    // levels take them through buffer descriptors with the non-temporal hint
+    if (zero_guess && buf) { GSU(true, false, true, false, true) }
+    else if (zero_guess) { GSU(true, false, true, false, false) }
     else if (sh.wp) { GSU(false, true, true, false, false) }
     else if (buf) { GSU(false, false, true, false, true) }
     else { GSU(false, false, true, false, false) }

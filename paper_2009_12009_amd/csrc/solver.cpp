@@ -311,7 +311,7 @@ std::vector<Shape> gsrb_candidates() {
   std::vector<Shape> c;
   for (int lx : {16, 32, 64})
     for (int ly : {1, 2, 4, 8, 16})
-      for (int tz : {2, 4, 8, 16, 32, 64})
+      for (int tz : {1, 2, 4, 8, 16, 32, 64})
         for (int u : {1, 2, 4})
           for (int wp : {0, 1})
             if (shape_ok({lx, ly, tz, u}) && u <= tz) c.push_back({lx, ly, tz, u, wp});
@@ -321,7 +321,7 @@ std::vector<Shape> cell_candidates() {
   std::vector<Shape> c;
   for (int lx : {32, 64, 128})
     for (int ly : {1, 2, 4, 8})
-      for (int tz : {2, 4, 8, 16, 32, 64})
+      for (int tz : {1, 2, 4, 8, 16, 32, 64})
         for (int u : {1, 2, 4})
           if (shape_ok({lx, ly, tz, u}) && u <= tz) c.push_back({lx, ly, tz, u});
   return c;

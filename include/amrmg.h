@@ -169,6 +169,21 @@ typedef struct {
                                       is read while it runs); same iterates,
                                       norms and result; 0 = a residual pass of
                                       its own before each cycle               */
+  int32_t coarse_tail;         /* [1024] the coarsest levels, from the first
+                                      level (>= 1) with at most this many cells
+                                      down to a CG bottom of at most 1024
+                                      cells, run as one launch of one 1024-lane
+                                      work-group per V-cycle (every level
+                                      between them half-swept with
+                                      write-through, nu1 >= 1): each pass of
+                                      those levels is a loop of its lanes with
+                                      a barrier after it, instead of a launch;
+                                      same arithmetic per cell, same result
+                                      (the paper's V-cycle, "Linear Solvers");
+                                      one compute unit then carries the
+                                      level, so this pays only where launches
+                                      cost more than its cells' loads;
+                                      0 = a launch per pass                   */
 } mg_opts_t;
 
 typedef struct {
@@ -180,6 +195,9 @@ typedef struct {
   double abs_resid;            /* max|f - A phi| at return                      */
   double setup_ms;             /* mg_create wall time                           */
   double solve_ms;             /* mg_solve wall time                            */
+  int32_t tail_level;          /* first level of the one-launch coarse tail
+                                      (opts coarse_tail), counted as nlevels
+                                      counts; 0 = none                         */
 } mg_info_t;
 
 /* One ghost-copy item: dst cells in dst_region take src cells at p - shift. */

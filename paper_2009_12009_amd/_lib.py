@@ -58,13 +58,13 @@ class MgOpts(C.Structure):
                 ("fused_min_edge", C.c_int32), ("krylov", C.c_int32),
                 ("ghost_write", C.c_int32), ("interp_fold", C.c_int32),
                 ("bottom_solver", C.c_int32), ("restrict_fold", C.c_int32),
-                ("stop_fold", C.c_int32)]
+                ("stop_fold", C.c_int32), ("coarse_tail", C.c_int32)]
 
 
 class MgInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("nlevels", C.c_int32), ("bottom_iters", C.c_int32),
                 ("converged", C.c_int32), ("rel_resid", C.c_double), ("abs_resid", C.c_double),
-                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("tail_level", C.c_int32)]
 
 
 class MgCopyTag(C.Structure):

@@ -910,11 +910,11 @@ __global__ void __launch_bounds__(256)
 }
 
 // Block sum in a fixed order: lanes by butterfly (every lane ends with the
-// same bits), then waves in index order.
-__device__ double block_sum(double v, double* red, int& phase) {
+// same bits), then the first nw waves in index order (every wave of the
+// work-group takes part in the barrier; later waves' sums are left out).
+__device__ double block_sum_w(double v, double* red, int& phase, int nw) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-  const int nw = (blockDim.x * blockDim.y + 63) / 64;
   double* buf = red + phase * 16;
   phase ^= 1;
   if ((tid & 63) == 0) buf[tid >> 6] = v;
@@ -922,6 +922,11 @@ __device__ double block_sum(double v, double* red, int& phase) {
   double s = buf[0];
   for (int w = 1; w < nw; ++w) s += buf[w];
   return s;
+}
+
+// ... over every wave of the work-group.
+__device__ double block_sum(double v, double* red, int& phase) {
+  return block_sum_w(v, red, phase, (blockDim.x * blockDim.y + 63) / 64);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1790,17 +1795,48 @@ __global__ void __launch_bounds__(256)
 // neighbours): an iteration then reads nothing but LDS.  The work-group is
 // sized to the bottom level (one wavefront for 64 cells), so its reductions
 // cross few wavefronts.  Same arithmetic per cell as k_bottom_cg.
-template <typename T, int CPT>
-__global__ void __launch_bounds__(1024)
-    k_bottom_cg_lds(BottomTables bt, const T* __restrict__ diag, const T* __restrict__ coef,
-                    const T* __restrict__ rhs, T* __restrict__ out, int accumulate, double tol,
-                    int maxiter, int singular, int* iters_out) {
-  extern __shared__ unsigned char lds_raw[];
-  T* p = reinterpret_cast<T*>(lds_raw);
-  __shared__ double red[32];
+// The body runs on any work-group: lanes stride the cells by nt (lane l owns
+// l, l+nt, ...), the dot products add the first nw waves' sums, and every
+// wave takes part in the barriers (lanes past the cells hold zeros).  p:
+// n values of LDS.
+// The CG's sums and barriers.  ONE_WAVE: the CG runs in wavefront 0 alone
+// (n <= 64, lanes 0..63): the butterfly leaves the sum in every lane (the
+// value the work-group form reads back for one wave) and LDS needs only
+// wave-level ordering.
+template <bool ONE_WAVE>
+__device__ __forceinline__ double cg_sum(double v, double* red, int& phase, int nw) {
+  if (ONE_WAVE) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+  }
+  return block_sum_w(v, red, phase, nw);
+}
+
+template <bool ONE_WAVE>
+__device__ __forceinline__ void cg_sync() {
+  if (ONE_WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <typename T, int CPT, bool ONE_WAVE = false>
+__device__ __forceinline__ void cg_lds_run(const BottomTables& bt, const T* __restrict__ diag,
+                                           const T* __restrict__ coef, const T* __restrict__ rhs,
+                                           T* __restrict__ out, int accumulate, double tol,
+                                           int maxiter, int singular, int* iters_out, T* p,
+                                           double* red, int nt, int nw) {
+  // no multiply-add fusion: whether the compiler fuses a product into an
+  // addition depends on the code around it, and the work-group and the
+  // one-wavefront forms (and every kernel that runs this body) must round
+  // the same way
+#pragma clang fp contract(off)
   int phase = 0;
   const int n = bt.n;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
   // stencil in registers up to two cells per lane (more would spill)
   constexpr bool REG = CPT <= 2;
   constexpr int RC = REG ? CPT : 1;
@@ -1825,7 +1861,7 @@ __global__ void __launch_bounds__(1024)
     }
   }
   if (singular) {
-    s = block_sum(s, red, phase);
+    s = cg_sum<ONE_WAVE>(s, red, phase, nw);
     const T mean = (T)(s / n);
 #pragma unroll
     for (int m = 0; m < CPT; ++m)
@@ -1834,7 +1870,7 @@ __global__ void __launch_bounds__(1024)
   s = 0.0;
 #pragma unroll
   for (int m = 0; m < CPT; ++m) s += (double)r[m] * (double)r[m];
-  double rho = block_sum(s, red, phase);
+  double rho = cg_sum<ONE_WAVE>(s, red, phase, nw);
   const double bnorm = sqrt(rho);
   int it = 0;
   if (bnorm > 0.0) {
@@ -1842,7 +1878,7 @@ __global__ void __launch_bounds__(1024)
     for (int m = 0; m < CPT; ++m)
       if (tid + m * nt < n) p[tid + m * nt] = r[m];
     while (it < maxiter) {
-      __syncthreads();
+      cg_sync<ONE_WAVE>();
       s = 0.0;
 #pragma unroll
       for (int m = 0; m < CPT; ++m) {
@@ -1865,7 +1901,7 @@ __global__ void __launch_bounds__(1024)
           s += (double)p[c] * (double)q[m];
         }
       }
-      const double pq = block_sum(s, red, phase);
+      const double pq = cg_sum<ONE_WAVE>(s, red, phase, nw);
       const T alT = (T)(rho / pq);
       s = 0.0;
 #pragma unroll
@@ -1878,7 +1914,7 @@ __global__ void __launch_bounds__(1024)
         }
       }
       ++it;
-      const double rho_new = block_sum(s, red, phase);
+      const double rho_new = cg_sum<ONE_WAVE>(s, red, phase, nw);
       if (!(sqrt(rho_new) > tol * bnorm)) break;
       const T btT = (T)(rho_new / rho);
 #pragma unroll
@@ -1894,7 +1930,7 @@ __global__ void __launch_bounds__(1024)
 #pragma unroll
     for (int m = 0; m < CPT; ++m)
       if (tid + m * nt < n) s += (double)x[m];
-    s = block_sum(s, red, phase);
+    s = cg_sum<ONE_WAVE>(s, red, phase, nw);
     const T mean = (T)(s / n);
 #pragma unroll
     for (int m = 0; m < CPT; ++m) x[m] = x[m] - mean;
@@ -1909,6 +1945,314 @@ __global__ void __launch_bounds__(1024)
   }
   if (tid == 0) *iters_out = it;
 }
+
+template <typename T, int CPT>
+__global__ void __launch_bounds__(1024)
+    k_bottom_cg_lds(BottomTables bt, const T* __restrict__ diag, const T* __restrict__ coef,
+                    const T* __restrict__ rhs, T* __restrict__ out, int accumulate, double tol,
+                    int maxiter, int singular, int* iters_out) {
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ double red[32];
+  cg_lds_run<T, CPT>(bt, diag, coef, rhs, out, accumulate, tol, maxiter, singular, iters_out,
+                     reinterpret_cast<T*>(lds_raw), red, blockDim.x, (blockDim.x + 63) / 64);
+}
+
+// ---------------------------------------------------------------------------
+// The coarse tail (launch_tail): one work-group, a barrier between passes.
+// Every pass evaluates the operator with eval and stores each result once,
+// with the update, residual, restriction and interpolation expressions of
+// the per-level kernels, so it stores the bits those launches store.
+// Box tables (BoxInfo, WtBox) are staged in LDS at the start; cell entries,
+// data and write-through entries stay in global memory (the L2 cache, at
+// these sizes).  Pointers read from the plan are cast to the global address
+// space so that their accesses compile to global loads and stores, which a
+// lane can have in flight while it reads LDS.
+
+#define TAIL_G __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ TAIL_G T* g1(T* p) {
+  return (TAIL_G T*)p;
+}
+
+__device__ __forceinline__ void tail_unpack(unsigned c, int& b, int& il, int& jl, int& kl) {
+  kl = (int)(c & 63u);
+  jl = (int)((c >> 6) & 63u);
+  il = (int)((c >> 12) & 63u);
+  b = (int)(c >> 18);
+}
+
+// The arrays of one tail level, global address space.
+template <typename T>
+struct TailPtrs {
+  TAIL_G T* e;
+  TAIL_G const T* rhs;
+  TAIL_G T* r;
+  TAIL_G const T* b0;
+  TAIL_G const T* b1;
+  TAIL_G const T* b2;
+  TAIL_G const T* a;
+  TAIL_G const WtEntry* wte;
+  TAIL_G const unsigned* cells;
+};
+
+template <typename T>
+__device__ __forceinline__ TailPtrs<T> tail_ptrs(const TailLevel<T>& L) {
+  TailPtrs<T> q;
+  q.e = g1(L.e);
+  q.rhs = g1((const T*)L.rhs);
+  q.r = g1(L.r);
+  q.b0 = g1(L.op.b0);
+  q.b1 = g1(L.op.b1);
+  q.b2 = g1(L.op.b2);
+  q.a = L.op.a ? g1(L.op.a) : nullptr;
+  q.wte = g1(L.wte);
+  q.cells = g1(L.cells);
+  return q;
+}
+
+// gather's loads (same indices, rhs without ghosts) through global pointers
+template <typename T, bool READ_PHI, bool READ_CENTRE>
+__device__ __forceinline__ void tail_gather(Nbr<T>& v, const Strides& s, const TailPtrs<T>& q,
+                                            const BoxInfo& B, bool read_f, int il, int jl,
+                                            int kl, int pc) {
+  TAIL_G const T* P = q.e + B.off_g1;
+  if (read_f) v.f = q.rhs[B.off_g0 + il + s.rsy * jl + s.rsz * kl];
+  const int fx = il + (s.nx + 1) * (jl + s.ny * kl);
+  const int fy = il + s.nx * (jl + (s.ny + 1) * kl);
+  const int fz = il + s.nx * (jl + s.ny * kl);
+  TAIL_G const T* BX = q.b0 + B.off_f[0];
+  TAIL_G const T* BY = q.b1 + B.off_f[1];
+  TAIL_G const T* BZ = q.b2 + B.off_f[2];
+  v.bxl = BX[fx];
+  v.bxh = BX[fx + 1];
+  v.byl = BY[fy];
+  v.byh = BY[fy + s.nx];
+  v.bzl = BZ[fz];
+  v.bzh = BZ[fz + s.nx * s.ny];
+  if (q.a) v.a = q.a[B.off_g0 + fz];
+  if (READ_CENTRE) v.pc = P[pc];
+  if (READ_PHI) {
+    v.pxl = P[pc - 1];
+    v.pxh = P[pc + 1];
+    v.pyl = P[pc - s.sy];
+    v.pyh = P[pc + s.sy];
+    v.pzl = P[pc - s.sz];
+    v.pzh = P[pc + s.sz];
+  }
+}
+
+// a new value of a cell on its box's boundary layer into the face ghosts
+// that mirror it (every entry of each face it lies on; wt_store's test)
+template <typename T>
+__device__ __forceinline__ void tail_wt(const WtBox& wb, TAIL_G const WtEntry* wte,
+                                        TAIL_G T* phi, const Strides& s, int il, int jl, int kl,
+                                        T v) {
+  const bool on[6] = {il == 0, il == s.nx - 1, jl == 0, jl == s.ny - 1, kl == 0, kl == s.nz - 1};
+  for (int f = 0; f < 6; ++f) {
+    if (!on[f]) continue;
+    for (int e = wb.first[f]; e < wb.first[f] + wb.count[f]; ++e) {
+      TAIL_G const WtEntry* w = wte + e;
+      if (il >= w->lo[0] && il <= w->hi[0] && jl >= w->lo[1] && jl <= w->hi[1] &&
+          kl >= w->lo[2] && kl <= w->hi[2])
+        phi[w->base + il + (long long)jl * w->sy + (long long)kl * w->sz] = v;
+    }
+  }
+}
+
+__device__ __forceinline__ bool on_rim(const Strides& s, int il, int jl, int kl) {
+  return il == 0 || il == s.nx - 1 || jl == 0 || jl == s.ny - 1 || kl == 0 || kl == s.nz - 1;
+}
+
+// Half-sweep of one colour (red = 0): two cells per lane and step; each
+// phase (cell entries, then the stencil's loads) is issued for both cells
+// before either waits.  ZG: from zero (only rhs is read).  bi, wb: the
+// level's box tables in LDS.
+template <typename T, bool ZG>
+__device__ __forceinline__ void tail_half(const TailLevel<T>& L, const TailPtrs<T>& q,
+                                          const BoxInfo* bi, const WtBox* wb, int colour) {
+  const int beg = colour ? L.nred : 0, end = colour ? L.ncell : L.nred;
+  const int nt = blockDim.x;
+  for (int q0 = beg + (int)threadIdx.x; q0 < end; q0 += 2 * nt) {
+    const bool ok1 = q0 + nt < end;
+    const unsigned c0 = q.cells[q0];
+    const unsigned c1 = ok1 ? q.cells[q0 + nt] : 0u;
+    Nbr<T> v[2];
+    int b[2], il[2], jl[2], kl[2], pc[2];
+    Strides s[2];
+    tail_unpack(c0, b[0], il[0], jl[0], kl[0]);
+    tail_unpack(c1, b[1], il[1], jl[1], kl[1]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !ok1) continue;
+      const BoxInfo& B = bi[b[u]];
+      s[u] = strides_of(B, 0);
+      pc[u] = (il[u] + 1) + s[u].sy * (jl[u] + 1) + s[u].sz * (kl[u] + 1);
+      tail_gather<T, !ZG, false>(v[u], s[u], q, B, true, il[u], jl[u], kl[u], pc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !ok1) continue;
+      const BoxInfo& B = bi[b[u]];
+      const Cell<T> c = eval<T, !ZG>(L.op, v[u], q.a != nullptr, B.bcmask, s[u], il[u], jl[u],
+                                     kl[u]);
+      const T nv = ZG ? v[u].f / c.diag : (v[u].f + c.off) / c.diag;
+      q.e[B.off_g1 + pc[u]] = nv;
+      if (on_rim(s[u], il[u], jl[u], kl[u]))
+        tail_wt<T>(wb[b[u]], q.wte, q.e, s[u], il[u], jl[u], kl[u], nv);
+    }
+  }
+}
+
+// r = rhs - A e on every cell (k_residual's expression)
+template <typename T>
+__device__ __forceinline__ void tail_resid(const TailLevel<T>& L, const TailPtrs<T>& q,
+                                           const BoxInfo* bi) {
+  const int nt = blockDim.x;
+  for (int q0 = (int)threadIdx.x; q0 < L.ncell; q0 += 2 * nt) {
+    const bool ok1 = q0 + nt < L.ncell;
+    const unsigned c0 = q.cells[q0];
+    const unsigned c1 = ok1 ? q.cells[q0 + nt] : 0u;
+    Nbr<T> v[2];
+    int b[2], il[2], jl[2], kl[2];
+    Strides s[2];
+    tail_unpack(c0, b[0], il[0], jl[0], kl[0]);
+    tail_unpack(c1, b[1], il[1], jl[1], kl[1]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !ok1) continue;
+      const BoxInfo& B = bi[b[u]];
+      s[u] = strides_of(B, 0);
+      const int pc = (il[u] + 1) + s[u].sy * (jl[u] + 1) + s[u].sz * (kl[u] + 1);
+      tail_gather<T, true, true>(v[u], s[u], q, B, true, il[u], jl[u], kl[u], pc);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !ok1) continue;
+      const BoxInfo& B = bi[b[u]];
+      const Cell<T> c = eval<T, true>(L.op, v[u], q.a != nullptr, B.bcmask, s[u], il[u], jl[u],
+                                      kl[u]);
+      const T Aphi = c.diag * v[u].pc - c.off;
+      q.r[B.off_g0 + il[u] + s[u].nx * (jl[u] + s[u].ny * kl[u])] = v[u].f - Aphi;
+    }
+  }
+}
+
+// rc (no ghosts, boxes ci) = mean of the 8 children in rf (no ghosts,
+// boxes fi), k_restrict's summation order
+template <typename T>
+__device__ __forceinline__ void tail_restrict(TAIL_G const T* rf, const BoxInfo* fi,
+                                              TAIL_G const unsigned* rcells, int n,
+                                              const BoxInfo* ci, TAIL_G T* rc) {
+  for (int q = (int)threadIdx.x; q < n; q += blockDim.x) {
+    int fb, oi, oj, ok;
+    tail_unpack(rcells[q], fb, oi, oj, ok);
+    const BoxInfo& F = fi[fb];
+    const BoxInfo& C = ci[F.parent];
+    const BoxDims df = dims(F), dc = dims(C);
+    const int I = fdiv2(F.lo[0]) + oi, J = fdiv2(F.lo[1]) + oj, K = fdiv2(F.lo[2]) + ok;
+    TAIL_G const T* R = rf + F.off_g0;
+    const long long sy = df.nx, sz = (long long)df.nx * df.ny;
+    const long long b = cidx(df, 0, 2 * I - F.lo[0], 2 * J - F.lo[1], 2 * K - F.lo[2]);
+    const T z0 = (R[b] + R[b + 1]) + (R[b + sy] + R[b + sy + 1]);
+    const T z1 = (R[b + sz] + R[b + sz + 1]) + (R[b + sz + sy] + R[b + sz + sy + 1]);
+    rc[C.off_g0 + cidx(dc, 0, I - C.lo[0], J - C.lo[1], K - C.lo[2])] = (z0 + z1) * T(0.125);
+  }
+}
+
+// e += parent value of ec (k_prolong_add's addition), written through to
+// the face ghosts, so the first post-smoothing half-sweep needs no exchange
+template <typename T>
+__device__ __forceinline__ void tail_prolong(const TailLevel<T>& L, const TailPtrs<T>& q,
+                                             const BoxInfo* bi, const WtBox* wb,
+                                             const BoxInfo* ci, TAIL_G const T* ec) {
+  for (int i0 = (int)threadIdx.x; i0 < L.ncell; i0 += blockDim.x) {
+    int b, il, jl, kl;
+    tail_unpack(q.cells[i0], b, il, jl, kl);
+    const BoxInfo& F = bi[b];
+    const BoxInfo& C = ci[F.parent];
+    const BoxDims df = dims(F), dc = dims(C);
+    const long long p = F.off_g1 + cidx(df, 1, il, jl, kl);
+    const int i = il + F.lo[0], j = jl + F.lo[1], k = kl + F.lo[2];
+    const T nv = q.e[p] + ec[C.off_g1 + cidx(dc, 1, fdiv2(i) - C.lo[0], fdiv2(j) - C.lo[1],
+                                              fdiv2(k) - C.lo[2])];
+    q.e[p] = nv;
+    const Strides s = strides_of(F, 0);
+    if (on_rim(s, il, jl, kl)) tail_wt<T>(wb[b], q.wte, q.e, s, il, jl, kl, nv);
+  }
+}
+
+__device__ __forceinline__ void lds_copy(void* dst, const void* src, int bytes) {
+  int* d = static_cast<int*>(dst);
+  TAIL_G const int* s = g1(static_cast<const int*>(src));
+  for (int i = (int)threadIdx.x; i < bytes / 4; i += blockDim.x) d[i] = s[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTailLanes) k_tail(const TailPlan<T>* __restrict__ tp) {
+  extern __shared__ __align__(16) unsigned char tail_lds[];
+  __shared__ double red[32];
+  const int nlev = tp->nlev, nu1 = tp->nu1, nu2 = tp->nu2;
+  // stage the box tables
+  lds_copy(tail_lds + tp->lds_fi, tp->finfo, (int)sizeof(BoxInfo) * tp->fnbox);
+  for (int l = 0; l < nlev; ++l) {
+    lds_copy(tail_lds + tp->lds_bi[l], tp->lev[l].op.boxes, (int)sizeof(BoxInfo) * tp->lev[l].nbox);
+    lds_copy(tail_lds + tp->lds_wb[l], tp->lev[l].wtb, (int)sizeof(WtBox) * tp->lev[l].nbox);
+  }
+  lds_copy(tail_lds + tp->lds_bi[nlev], tp->binfo, (int)sizeof(BoxInfo) * tp->bnbox);
+  __syncthreads();
+  auto BI = [&](int l) { return reinterpret_cast<const BoxInfo*>(tail_lds + tp->lds_bi[l]); };
+  auto WB = [&](int l) { return reinterpret_cast<const WtBox*>(tail_lds + tp->lds_wb[l]); };
+  tail_restrict<T>(g1(tp->rf), reinterpret_cast<const BoxInfo*>(tail_lds + tp->lds_fi),
+                   g1(tp->rcells), tp->nrc, BI(0), g1(tp->lev[0].rhs));
+  __syncthreads();
+  for (int l = 0; l < nlev; ++l) {
+    const TailLevel<T>& L = tp->lev[l];
+    const TailPtrs<T> q = tail_ptrs(L);
+    for (int k = 0; k < nu1; ++k) {
+      if (k == 0)
+        tail_half<T, true>(L, q, BI(l), WB(l), 0);
+      else
+        tail_half<T, false>(L, q, BI(l), WB(l), 0);
+      __syncthreads();
+      tail_half<T, false>(L, q, BI(l), WB(l), 1);
+      __syncthreads();
+    }
+    tail_resid<T>(L, q, BI(l));
+    __syncthreads();
+    tail_restrict<T>(q.r, BI(l), g1(L.rcells), L.nrc, BI(l + 1),
+                     g1(l + 1 < nlev ? tp->lev[l + 1].rhs : tp->brhs));
+    __syncthreads();
+  }
+  {
+    BottomTables bt = tp->bt;
+    T* p = reinterpret_cast<T*>(tail_lds);
+    if (bt.n <= 64) {
+      if (threadIdx.x < 64)
+        cg_lds_run<T, 1, true>(bt, tp->bdiag, tp->bcoef, tp->brhs, tp->be, 0, tp->tol,
+                               tp->maxiter, tp->singular, tp->iters, p, red, 64, 1);
+    } else {
+      cg_lds_run<T, 1>(bt, tp->bdiag, tp->bcoef, tp->brhs, tp->be, 0, tp->tol, tp->maxiter,
+                       tp->singular, tp->iters, p, red, blockDim.x, (bt.n + 63) / 64);
+    }
+  }
+  __syncthreads();
+  const int c0 = tp->reverse ? 1 : 0;
+  for (int l = nlev - 1; l >= 0; --l) {
+    const TailLevel<T>& L = tp->lev[l];
+    const TailPtrs<T> q = tail_ptrs(L);
+    tail_prolong<T>(L, q, BI(l), WB(l), BI(l + 1), g1(l + 1 < nlev ? tp->lev[l + 1].e : tp->be));
+    __syncthreads();
+    for (int k = 0; k < nu2; ++k) {
+      tail_half<T, false>(L, q, BI(l), WB(l), c0);
+      __syncthreads();
+      tail_half<T, false>(L, q, BI(l), WB(l), 1 - c0);
+      __syncthreads();
+    }
+  }
+}
+
+#undef TAIL_G
 
 inline dim3 block_of(Shape sh) { return dim3(sh.lx, sh.ly, 1); }
 
@@ -2411,6 +2755,14 @@ hipError_t launch_bottom_cg(hipStream_t st, const BottomTables& bt, const T* dia
 }
 
 template <typename T>
+hipError_t launch_tail(hipStream_t st, const TailPlan<T>* plan, int nbottom, size_t lds) {
+  if (!plan || nbottom <= 0 || nbottom > kTailMaxBottom || lds > kTailMaxLds)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(kTailLanes), lds, st, plan);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_bottom_bicgstab(hipStream_t st, const BottomTables& bt, const T* diag,
                                   const T* coef, const T* rhs, T* out, int accumulate, T* work,
                                   double tol, int maxiter, int singular, int* iters_out) {
@@ -2456,7 +2808,8 @@ hipError_t launch_bottom_bicgstab(hipStream_t st, const BottomTables& bt, const 
                                           const T*, T*, int, T*, double, int, int, int*);      \
   template hipError_t launch_bottom_bicgstab<T>(hipStream_t, const BottomTables&, const T*,      \
                                                 const T*, const T*, T*, int, T*, double, int,    \
-                                                int, int*);
+                                                int, int*);                                      \
+  template hipError_t launch_tail<T>(hipStream_t, const TailPlan<T>*, int, size_t);
 
 INST(double)
 INST(float)

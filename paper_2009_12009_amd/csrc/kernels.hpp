@@ -275,4 +275,81 @@ hipError_t launch_bottom_bicgstab(hipStream_t st, const BottomTables& bt, const 
                                   const T* coef, const T* rhs, T* out, int accumulate, T* work,
                                   double tol, int maxiter, int singular, int* iters_out);
 
+// The coarsest levels of a V-cycle in one launch of one work-group
+// (launch_tail): the levels from some level down to a CG bottom, every pass
+// a loop of the work-group's lanes over the level's cells with a barrier
+// after it, the arrays staying in the L2 cache between passes.  Each cell
+// gets the arithmetic of the per-level kernels (the same operator, update,
+// restriction and interpolation expressions, and the bottom's CG with the
+// same lane layout and summation order), so the result is the one of the
+// launches it replaces.
+// A cell entry packs box-local coordinates and the box:
+// kl | jl << 6 | il << 12 | box << 18 (box extents <= 64, < 2^14 boxes).
+// A restriction entry packs a coarse cell's offset from coarsen(fine box)'s
+// low corner the same way, with the fine box in the top bits.
+constexpr int kTailMaxLevels = 6;
+constexpr int kTailLanes = 1024;
+constexpr int kTailMaxBottom = 1024;  // bottom cells (one per lane)
+constexpr int kTailMaxExtent = 64;
+constexpr int kTailMaxBoxes = 1 << 14;
+// LDS of the tail kernel: the bottom CG's p, every box table it stages
+constexpr size_t kTailMaxLds = 60 * 1024;
+
+template <typename T>
+struct TailLevel {
+  StencilArgs<T> op;
+  T* e;    // correction, one ghost layer (face ghosts kept by write-through)
+  T* rhs;  // no ghosts
+  T* r;    // residual, no ghosts
+  const WtBox* wtb;
+  const WtEntry* wte;
+  const unsigned* cells;  // red cells [0, nred), black cells [nred, ncell)
+  int nred, ncell;
+  int nbox;
+  const unsigned* rcells;  // restriction of r into the next coarser level
+  int nrc;
+  const BoxInfo* cinfo;  // the next coarser level's boxes (parents)
+};
+
+template <typename T>
+struct TailPlan {
+  int nlev;  // smoothed levels; the bottom level follows the last of them
+  int nu1, nu2;
+  int reverse;  // post-smoothing black before red
+  // restriction of the residual of the level above the tail into the first
+  // tail level's right-hand side
+  const T* rf;
+  const BoxInfo* finfo;
+  int fnbox;
+  const unsigned* rcells;
+  int nrc;
+  TailLevel<T> lev[kTailMaxLevels];
+  const BoxInfo* binfo;  // the bottom level's boxes
+  int bnbox;
+  // LDS byte offsets of the staged box tables (the CG's p at 0): BoxInfo of
+  // the level above, of tail level l (l = nlev: the bottom), WtBox of tail
+  // level l; lds_bytes in all
+  int lds_fi;
+  int lds_bi[kTailMaxLevels + 1];
+  int lds_wb[kTailMaxLevels];
+  int lds_bytes;
+  // bottom: CG from zero on bt (bt.n <= kTailMaxBottom) into be (ng 1)
+  BottomTables bt;
+  const T* bdiag;
+  const T* bcoef;
+  T* be;
+  T* brhs;
+  double tol;
+  int maxiter, singular;
+  int* iters;
+};
+
+// One launch of kTailLanes lanes: restrict rf, then per level nu1 sweeps
+// (the first from zero), residual, restriction; the bottom CG; then per
+// level upward the interpolation of the coarser correction and nu2 sweeps.
+// plan: device copy (read only); nbottom = plan->bt.n; lds = plan->lds_bytes
+// (<= kTailMaxLds).
+template <typename T>
+hipError_t launch_tail(hipStream_t st, const TailPlan<T>* plan, int nbottom, size_t lds);
+
 }  // namespace amrmg

@@ -142,6 +142,12 @@ struct Level {
   double* next64 = nullptr;  // level 0, folded stop test: the other iterate (ng 1)
   float *b32[3] = {nullptr, nullptr, nullptr}, *a32 = nullptr;
   float *e32 = nullptr, *rhs32 = nullptr, *r32 = nullptr;
+  // coarse tail (launch_tail): packed cells of a tail level (red, then
+  // black) and the restriction entries of this level's residual into the
+  // next coarser one (the level above the tail and the tail levels)
+  std::vector<unsigned> h_tcells, h_trc;
+  int tail_nred = 0;
+  unsigned *d_tcells = nullptr, *d_trc = nullptr;
 };
 
 struct ProfRec {
@@ -182,6 +188,9 @@ struct mg_solver {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipEvent_t ev_norm[2] = {nullptr, nullptr};  // folded stop test: norm copies landed
   hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
+  // first level of the coarse tail (-1: none) and its device plan
+  int tail_lev = -1;
+  char* d_tail = nullptr;
   // pinned: [0, kNormSlot) read_norm; two more slots for the folded stop
   // test's copies in flight; then h_iters
   unsigned long long* h_norm = nullptr;
@@ -514,6 +523,108 @@ bool stop_fold_on(const mg_solver* s) {
          !s->composite && s->opts.nu1 >= 1 && s->L.size() > 1 && !s->L[0].fused;
 }
 
+// LDS bytes of the tail kernel starting at level t: the bottom CG's p (FP64
+// at most), BoxInfo of the level above, of every tail level and of the
+// bottom, WtBox of every tail level; offsets into *tp when given.
+template <typename T>
+size_t tail_lds_layout(const mg_solver* s, int t, TailPlan<T>* tp) {
+  const int nl = (int)s->L.size();
+  size_t off = (sizeof(double) * (size_t)s->L.back().ncell + 15) & ~size_t(15);
+  if (tp) tp->lds_fi = (int)off;
+  off += sizeof(BoxInfo) * s->L[t - 1].info.size();
+  for (int l = t; l <= nl - 1; ++l) {
+    if (tp) tp->lds_bi[l - t] = (int)off;
+    off += sizeof(BoxInfo) * s->L[l].info.size();
+  }
+  for (int l = t; l <= nl - 2; ++l) {
+    if (tp) tp->lds_wb[l - t] = (int)off;
+    off += sizeof(WtBox) * s->L[l].info.size();
+  }
+  if (tp) tp->lds_bytes = (int)off;
+  return off;
+}
+
+size_t tail_lds_need(const mg_solver* s, int t) {
+  return tail_lds_layout<double>(s, t, nullptr);
+}
+
+// The first level of the coarse tail: the levels from it down to the
+// bottom each hold at most opts.coarse_tail cells and are half-swept with
+// write-through (so are not the bottom), the bottom is a CG of at most
+// kTailMaxBottom cells, and the entries pack (box extents, box counts; the
+// level above the tail packs restriction entries, half its extents).
+// -1: no tail.
+int choose_tail(const mg_solver* s) {
+  const int nl = (int)s->L.size();
+  if (s->opts.coarse_tail <= 0 || nl < 3 || s->opts.bottom_solver != 0 || s->opts.nu1 < 1 ||
+      s->L.back().ncell > kTailMaxBottom)
+    return -1;
+  auto packs = [](const Level& lv, int max_extent) {
+    if (lv.nbox >= kTailMaxBoxes) return false;
+    for (const BoxInfo& b : lv.info)
+      for (int d = 0; d < 3; ++d)
+        if (b.hi[d] - b.lo[d] + 1 > max_extent) return false;
+    return true;
+  };
+  int start = nl - 1;
+  for (int l = nl - 2; l >= 1; --l) {
+    const Level& lv = s->L[l];
+    if (lv.ncell > s->opts.coarse_tail || !lv.wt || lv.fused || !packs(lv, kTailMaxExtent)) break;
+    start = l;
+  }
+  start = std::max(start, nl - 1 - kTailMaxLevels);
+  // the staged box tables must fit the kernel's LDS: start lower if not
+  while (start <= nl - 2 && tail_lds_need(s, start) > kTailMaxLds) ++start;
+  if (start > nl - 2) return -1;
+  if (!packs(s->L[start - 1], 2 * kTailMaxExtent)) return -1;
+  return start;
+}
+
+unsigned tail_pack(int b, int i, int j, int k) {
+  return (unsigned)k | ((unsigned)j << 6) | ((unsigned)i << 12) | ((unsigned)b << 18);
+}
+
+void build_tail_tables(mg_solver* s) {
+  for (Level& lv : s->L) {
+    lv.h_tcells.clear();
+    lv.h_trc.clear();
+    lv.tail_nred = 0;
+  }
+  const int t = s->tail_lev;
+  if (t < 1) return;
+  const int nl = (int)s->L.size();
+  for (int l = t; l <= nl - 2; ++l) {
+    Level& lv = s->L[l];
+    std::vector<unsigned> black;
+    for (int b = 0; b < lv.nbox; ++b) {
+      const BoxInfo& I = lv.info[b];
+      for (int k = I.lo[2]; k <= I.hi[2]; ++k)
+        for (int j = I.lo[1]; j <= I.hi[1]; ++j)
+          for (int i = I.lo[0]; i <= I.hi[0]; ++i) {
+            const unsigned e = tail_pack(b, i - I.lo[0], j - I.lo[1], k - I.lo[2]);
+            ((i + j + k) & 1 ? black : lv.h_tcells).push_back(e);
+          }
+    }
+    lv.tail_nred = (int)lv.h_tcells.size();
+    lv.h_tcells.insert(lv.h_tcells.end(), black.begin(), black.end());
+  }
+  for (int l = t - 1; l <= nl - 2; ++l) {
+    Level& lv = s->L[l];
+    for (int b = 0; b < lv.nbox; ++b) {
+      const BoxInfo& F = lv.info[b];
+      int clo[3], chi[3];
+      for (int d = 0; d < 3; ++d) {
+        clo[d] = floordiv(F.lo[d], 2);
+        chi[d] = floordiv(F.hi[d], 2);
+      }
+      for (int k = clo[2]; k <= chi[2]; ++k)
+        for (int j = clo[1]; j <= chi[1]; ++j)
+          for (int i = clo[0]; i <= chi[0]; ++i)
+            lv.h_trc.push_back(tail_pack(b, i - clo[0], j - clo[1], k - clo[2]));
+    }
+  }
+}
+
 int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
   std::string err;
   if (!validate_boxes(boxes, s->domain, true, &err)) return fail(MG_ERR_INVALID_BOXARRAY, err);
@@ -626,6 +737,9 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     c.fold_rs = l >= 2;
   }
 
+  s->tail_lev = choose_tail(s);
+  build_tail_tables(s);
+
   // bottom tables: cells of the bottom level enumerated box by box, x fastest
   Level& bl = s->L.back();
   s->nb = (int)bl.ncell;
@@ -717,6 +831,8 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
       lv.d_wt = bump.take<WtEntry>(std::max<size_t>(1, lv.h_wt.size()));
       lv.d_wtbox = bump.take<WtBox>(lv.h_wtbox.size());
     }
+    lv.d_tcells = lv.h_tcells.empty() ? nullptr : bump.take<unsigned>(lv.h_tcells.size());
+    lv.d_trc = lv.h_trc.empty() ? nullptr : bump.take<unsigned>(lv.h_trc.size());
     if (lv.fused) {
       lv.d_sweep = bump.take<Tile>(lv.cap_sweep);
       lv.d_rim = bump.take<RimTile>(lv.t_rim.size());
@@ -753,6 +869,7 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
   s->d_partials =
       bump.take<double>(std::max<size_t>({1, s->L[0].cap_cell, s->L[0].t_vec.size()}));
   if (s->opts.tune == 2) s->tune_scratch = bump.take<double>(s->L[0].n_g1);
+  s->d_tail = s->tail_lev > 0 ? bump.take<char>(sizeof(TailPlan<double>)) : nullptr;
   s->ws_need = bump.off + 256;
   return MG_OK;
 }
@@ -1065,6 +1182,14 @@ int coarse_cycle(mg_solver* s, size_t l, bool f32, const T* rf = nullptr) {
   const StencilArgs<T> op = stencil_of<T>(s, lv, f32);
   const bool prof = l == 0;
   int rc;
+  if ((int)l == s->tail_lev && rf) {
+    // the plan was built for the solver's precision (FP32 refinement: float)
+    if (f32 != (s->opts.precision == MG_PREC_F32_REFINE))
+      return fail(MG_ERR_ARG, "coarse tail in the other precision");
+    HIPTRY(launch_tail<T>(s->st, reinterpret_cast<const TailPlan<T>*>(s->d_tail), s->nb,
+                          tail_lds_need(s, s->tail_lev)));
+    return MG_OK;
+  }
   const bool rs = rf && fold_restrict(s, l);
   if (rf && !rs) {
     const Level& fl = s->L[l - 1];
@@ -1868,6 +1993,69 @@ int autotune(mg_solver* s) {
   return MG_OK;
 }
 
+template <typename T>
+TailPlan<T> tail_plan(mg_solver* s, bool f32) {
+  TailPlan<T> tp{};
+  const int nl = (int)s->L.size(), t = s->tail_lev;
+  tp.nlev = nl - 1 - t;
+  tp.nu1 = s->opts.nu1;
+  tp.nu2 = s->opts.nu2;
+  tp.reverse = s->opts.krylov != 0;
+  Level& up = s->L[t - 1];
+  tp.rf = ldata<T>(up, f32).r;
+  tp.finfo = up.d_info;
+  tp.fnbox = up.nbox;
+  tp.rcells = up.d_trc;
+  tp.nrc = (int)up.h_trc.size();
+  for (int i = 0; i < tp.nlev; ++i) {
+    Level& lv = s->L[t + i];
+    const LevelData<T> D = ldata<T>(lv, f32);
+    TailLevel<T>& L = tp.lev[i];
+    L.op = stencil_of<T>(s, lv, f32);
+    L.e = D.e;
+    L.rhs = D.rhs;
+    L.r = D.r;
+    L.wtb = lv.d_wtbox;
+    L.wte = lv.d_wt;
+    L.cells = lv.d_tcells;
+    L.nred = lv.tail_nred;
+    L.ncell = (int)lv.h_tcells.size();
+    L.nbox = lv.nbox;
+    L.rcells = lv.d_trc;
+    L.nrc = (int)lv.h_trc.size();
+    L.cinfo = s->L[t + i + 1].d_info;
+  }
+  const LevelData<T> B = ldata<T>(s->L.back(), f32);
+  tp.binfo = s->L.back().d_info;
+  tp.bnbox = s->L.back().nbox;
+  tail_lds_layout<T>(s, t, &tp);
+  tp.bt = bottom_tables(s);
+  tp.bdiag = f32 ? (const T*)s->bdiag32 : (const T*)s->bdiag64;
+  tp.bcoef = f32 ? (const T*)s->bcoef32 : (const T*)s->bcoef64;
+  tp.be = B.e;
+  tp.brhs = B.rhs;
+  tp.tol = s->opts.bottom_rel_tol;
+  tp.maxiter = s->opts.bottom_max_iter > 0 ? s->opts.bottom_max_iter : s->nb;
+  tp.singular = s->singular ? 1 : 0;
+  tp.iters = s->d_iters;
+  return tp;
+}
+
+// The tail's device plan (pinned staging, then a copy on the solver stream,
+// which the caller synchronises before the staging goes).
+template <typename T>
+int upload_tail_plan(mg_solver* s, bool f32) {
+  const TailPlan<T> tp = tail_plan<T>(s, f32);
+  TailPlan<T>* h = nullptr;
+  HIPTRY(hipHostMalloc((void**)&h, sizeof(TailPlan<T>), hipHostMallocDefault));
+  *h = tp;
+  hipError_t e = hipMemcpyAsync(s->d_tail, h, sizeof(TailPlan<T>), hipMemcpyHostToDevice, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  hipHostFree(h);
+  HIPTRY(e);
+  return MG_OK;
+}
+
 int upload_tables(mg_solver* s) {
   for (Level& lv : s->L) {
     HIPTRY(hipMemcpyAsync(lv.d_info, lv.info.data(), sizeof(BoxInfo) * lv.info.size(),
@@ -1911,6 +2099,19 @@ int upload_tables(mg_solver* s) {
   HIPTRY(hipMemcpyAsync(s->d_aidx, s->h_aidx.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s->st));
   HIPTRY(hipMemcpyAsync(s->d_map_rhs, s->h_map_rhs.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s->st));
   HIPTRY(hipMemcpyAsync(s->d_map_out, s->h_map_out.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s->st));
+  if (s->tail_lev > 0) {
+    for (Level& lv : s->L) {
+      if (!lv.h_tcells.empty())
+        HIPTRY(hipMemcpyAsync(lv.d_tcells, lv.h_tcells.data(), sizeof(unsigned) * lv.h_tcells.size(),
+                              hipMemcpyHostToDevice, s->st));
+      if (!lv.h_trc.empty())
+        HIPTRY(hipMemcpyAsync(lv.d_trc, lv.h_trc.data(), sizeof(unsigned) * lv.h_trc.size(),
+                              hipMemcpyHostToDevice, s->st));
+    }
+    const int rc = s->opts.precision == MG_PREC_F32_REFINE ? upload_tail_plan<float>(s, true)
+                                                           : upload_tail_plan<double>(s, false);
+    if (rc) return rc;
+  }
   return MG_OK;
 }
 
@@ -2515,6 +2716,7 @@ void mg_default_opts(mg_opts_t* o) {
   o->bottom_solver = 0;
   o->restrict_fold = 1;
   o->stop_fold = 1;
+  o->coarse_tail = 1024;
 }
 
 static int check_opts(const mg_opts_t* o) {
@@ -2532,6 +2734,7 @@ static int check_opts(const mg_opts_t* o) {
   if (o->bottom_solver != 0 && o->bottom_solver != 1) return fail(MG_ERR_ARG, "bad bottom_solver");
   if (o->restrict_fold < 0 || o->restrict_fold > 2) return fail(MG_ERR_ARG, "bad restrict_fold");
   if (o->stop_fold != 0 && o->stop_fold != 1) return fail(MG_ERR_ARG, "bad stop_fold");
+  if (o->coarse_tail < 0) return fail(MG_ERR_ARG, "coarse_tail < 0");
   return MG_OK;
 }
 
@@ -2926,6 +3129,7 @@ int mg_solve(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rhs, doubl
   mg_info_t inf;
   std::memset(&inf, 0, sizeof(inf));
   inf.nlevels = (int)s->L.size();
+  inf.tail_level = std::max(s->tail_lev, 0);
   inf.setup_ms = s->setup_ms;
 
   HIPTRY(launch_fill_u64(s->st, s->d_norm, 4 * kNormSlot, 0ull));
@@ -3315,6 +3519,7 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
   mg_info_t inf;
   std::memset(&inf, 0, sizeof(inf));
   inf.nlevels = (int)s->L.size() + 1;
+  inf.tail_level = s->tail_lev > 0 ? s->tail_lev + 1 : 0;
   inf.setup_ms = s->setup_ms;
   HIPTRY(launch_fill_u64(s->st, s->d_norm, 4 * kNormSlot, 0ull));
   HIPTRY(launch_copy_valid(s->st, L0.d_cell, (int)L0.t_cell.size(), L0.s_cell, L0.d_info, Fc,

@@ -152,7 +152,8 @@ class MLMG:
         out = {"status": code, "iters": info.iters, "nlevels": info.nlevels,
                "bottom_iters": info.bottom_iters, "converged": bool(info.converged),
                "rel_resid": info.rel_resid, "abs_resid": info.abs_resid,
-               "setup_ms": info.setup_ms, "solve_ms": info.solve_ms}
+               "setup_ms": info.setup_ms, "solve_ms": info.solve_ms,
+               "tail_level": info.tail_level}
         if history:
             out["history"] = list(hist[:info.iters + 1])
         return out
@@ -327,7 +328,8 @@ class CompositeMLMG:
             L.check(code, "mg_solve_amr")
         out = {"status": code, "iters": info.iters, "nlevels": info.nlevels,
                "converged": bool(info.converged), "rel_resid": info.rel_resid,
-               "abs_resid": info.abs_resid, "setup_ms": info.setup_ms, "solve_ms": info.solve_ms}
+               "abs_resid": info.abs_resid, "setup_ms": info.setup_ms, "solve_ms": info.solve_ms,
+               "tail_level": info.tail_level}
         if history:
             out["history"] = list(hist[:info.iters + 1])
         return out

@@ -458,6 +458,81 @@ def test_stop_fold_bitwise_equal_plain_loop(name, make, boxes, extra, tol):
         assert infos[0]["converged"]
 
 
+TAIL_CASES = [
+    # (name, cfg maker, boxes or None, opts (coarse_tail: the threshold), rel_tol, a != 1,
+    #  first tail level)
+    ("lognormal64_8boxes_aggregated_default", lambda: W.config_lognormal(64, 32), None,
+     dict(aggregate=1), 1e-10, False, 3),
+    ("lognormal64_8boxes_two_levels", lambda: W.config_lognormal(64, 32), None,
+     dict(coarse_tail=4096), 1e-10, False, 2),
+    ("lognormal64_8boxes_aggregated_three_levels", lambda: W.config_lognormal(64, 32), None,
+     dict(aggregate=1, coarse_tail=4096), 1e-10, False, 2),
+    ("lognormal64_tail_from_level1", lambda: W.config_lognormal(64, 32), None,
+     dict(coarse_tail=32768), 1e-10, False, 1),
+    ("poisson32_periodic_singular_from_level1", W.config_c0, None, dict(coarse_tail=4096),
+     1e-10, False, 1),
+    ("poisson32_periodic_singular_aggregated_default", W.config_c0, None, dict(aggregate=1),
+     1e-10, False, 2),
+    ("uneven_periodic_y", lambda: dict(W.config_c0(), periodic=(False, True, False)),
+     [((0, 0, 0), (15, 31, 31)), ((16, 0, 0), (31, 15, 31)), ((16, 16, 0), (31, 31, 15)),
+      ((16, 16, 16), (31, 31, 31))], dict(coarse_tail=4096), 1e-10, False, 1),
+    ("lognormal64_f32_refine", lambda: W.config_lognormal(64, 32), None,
+     dict(precision=1, aggregate=1, coarse_tail=4096), 1e-10, False, 2),
+    ("lognormal64_mgpcg", lambda: W.config_lognormal(64, 32), None,
+     dict(krylov=1, aggregate=1), 1e-10, False, 3),
+    ("lognormal64_mgpcg_f32", lambda: W.config_lognormal(64, 32), None,
+     dict(krylov=1, precision=1, coarse_tail=4096), 1e-10, False, 2),
+    ("lognormal64_nu1_nu2_1", lambda: W.config_lognormal(64, 32), None,
+     dict(nu1=1, nu2=1, coarse_tail=4096), 1e-9, False, 2),
+    ("lognormal64_nu2_0", lambda: W.config_lognormal(64, 32), None,
+     dict(nu1=3, nu2=0, coarse_tail=4096), 1e-8, False, 2),
+    ("lognormal64_no_graph_max_iter_3", lambda: W.config_lognormal(64, 32), None,
+     dict(use_graph=0, max_iter=3, coarse_tail=4096), 1e-10, False, 2),
+    ("lognormal32_periodic_x_cell_coefficient",
+     lambda: dict(W.config_lognormal(32, 16), periodic=(True, False, False), alpha=0.5), None,
+     dict(coarse_tail=4096), 1e-10, True, 1),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,make,boxes,extra,tol,with_a,level", TAIL_CASES,
+                         ids=[c[0] for c in TAIL_CASES])
+def test_coarse_tail_bitwise_equal_launches(name, make, boxes, extra, tol, with_a, level):
+    """The coarsest levels run as one single-work-group launch per cycle
+    (default) give the same norms, cycle count and solution bits as a launch
+    per pass (coarse_tail = 0)."""
+    print(f"[solve] coarse tail vs a launch per pass {name}", flush=True)
+    P = lib()
+    cfg = make()
+    boxes = boxes or cfg["boxes"]
+    f = cfg["rhs"] - (cfg["rhs"].mean() if all(cfg["periodic"]) else 0.0)
+    rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(f, boxes), 0)
+    a_cells = None
+    if with_a:
+        a_cells = np.random.default_rng(5).uniform(0.5, 2.0, size=(cfg["n"],) * 3)
+    outs, infos = [], []
+    for tail in (extra.get("coarse_tail", 1024), 0):
+        opts = dict(extra, tune=0, bottom_rel_tol=TIGHT, coarse_tail=tail)
+        s = gpu_solver(cfg, boxes=boxes, opts=opts, a_cells=a_cells)
+        phi = s.cell_mf(1, fill=0.0)
+        info = s.solve(phi, rhs, tol, raise_on_fail=False, history=True)
+        torch.cuda.synchronize()
+        outs.append(to_global(phi, boxes, cfg["n"]))
+        infos.append(info)
+        s.close()
+    assert infos[0]["tail_level"] == level and infos[1]["tail_level"] == 0
+    assert np.all(np.isfinite(outs[0]))
+    assert np.array_equal(outs[0], outs[1])
+    assert infos[0]["iters"] == infos[1]["iters"]
+    assert infos[0]["bottom_iters"] == infos[1]["bottom_iters"]
+    assert infos[0]["converged"] == infos[1]["converged"]
+    assert list(infos[0]["history"]) == list(infos[1]["history"])
+    if "max_iter" in extra:
+        assert infos[0]["iters"] == extra["max_iter"]
+    else:
+        assert infos[0]["converged"]
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("variant", ["f64", "f32_refine", "f64_mgpcg"])
 def test_c1_bench_configuration(variant, monkeypatch):

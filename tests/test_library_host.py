@@ -36,13 +36,13 @@ def test_struct_sizes_match_header_layout():
     L = P._lib
     assert C.sizeof(L.MgBox) == 24
     assert C.sizeof(L.MgGeom) == 24 + 48 + 12 + 4  # trailing padding to 8
-    # fused_min_edge, krylov, ghost_write, interp_fold, bottom_solver, restrict_fold, stop_fold
-    # (+4 bytes of trailing padding to 8)
-    assert C.sizeof(L.MgOpts) == 10 * 4 + 8 + 7 * 4 + 4
+    # fused_min_edge, krylov, ghost_write, interp_fold, bottom_solver, restrict_fold, stop_fold,
+    # coarse_tail
+    assert C.sizeof(L.MgOpts) == 10 * 4 + 8 + 8 * 4
     o = L.default_opts()
     assert (o.nu1, o.nu2, o.fused_min_edge, o.krylov, o.ghost_write, o.interp_fold,
-            o.bottom_solver, o.restrict_fold, o.stop_fold,
-            o.bottom_rel_tol) == (2, 2, 0, 0, 1, 1, 0, 1, 1, 1e-4)
+            o.bottom_solver, o.restrict_fold, o.stop_fold, o.coarse_tail,
+            o.bottom_rel_tol) == (2, 2, 0, 0, 1, 1, 0, 1, 1, 1024, 1e-4)
     assert C.sizeof(L.MgCopyTag) == 8 + 24 + 12
 
 

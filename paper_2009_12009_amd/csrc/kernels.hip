@@ -796,6 +796,80 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// rc = R (rhs - A phi): the residual of each cell, computed as k_residual
+// computes it (mode 0), summed over 2x2x2 blocks in k_restrict's order and
+// scaled, so the coarse right-hand side gets the bits that a residual pass
+// and a restriction pass store, without the fine residual reaching memory.
+// Tiles (lx x ly lanes, tz planes) start at even cells with lx, ly, tz
+// even, box extents even: a lane gathers its cell on two planes, x-pairs
+// are adjacent lanes, y-pairs go through LDS.  cinfo: the coarse level's
+// boxes (box b's parent); rc without ghosts.
+template <typename T, bool BUF>
+__global__ void __launch_bounds__(256)
+    k_resid_restrict(const Tile* __restrict__ tiles, StencilArgs<T> op, const T* __restrict__ phi,
+                     const T* __restrict__ rhs, int rhs_ng, int tz,
+                     const BoxInfo* __restrict__ cinfo, T* __restrict__ rc) {
+  __shared__ T ypair[2][128];
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = op.boxes[t.box];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i = t.x0 + tx, j = t.y0 + ty;
+  // x-pairs and y-pairs lie wholly inside or outside the box (even extents)
+  const bool act = i <= B.hi[0] && j <= B.hi[1];
+  const Strides s = strides_of(B, rhs_ng);
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  const T* P = phi + B.off_g1;
+  const T* R = rhs + (rhs_ng ? B.off_g1 : B.off_g0);
+  const T* BX = op.b0 + B.off_f[0];
+  const T* BY = op.b1 + B.off_f[1];
+  const T* BZ = op.b2 + B.off_f[2];
+  const T* A = op.a ? op.a + B.off_g0 : nullptr;
+  const int il = i - B.lo[0], jl = j - B.lo[1];
+  BoxBufs bb;
+  if (BUF) bb = bufs_of<T>(op, B, s, P, R, rhs_ng, BX, BY, BZ, A);
+  const BoxInfo C = cinfo[B.parent];
+  const BoxDims dc = dims(C);
+  const int slot = (ty >> 1) * (blockDim.x >> 1) + (tx >> 1);
+  for (int k0 = t.z0; k0 <= kend; k0 += 2) {
+    T r[2] = {T(0), T(0)};
+    if (act) {
+      Nbr<T> v[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int kl = k0 + u - B.lo[2];
+        const int pc = (il + 1) + s.sy * (jl + 1) + s.sz * (kl + 1);
+        if (BUF)
+          gather_buf<T, true, true, 2>(v[u], s, bb, rhs_ng, true, A != nullptr, il, jl, kl, pc);
+        else
+          gather<T, true, true>(v[u], s, P, R, rhs_ng, BX, BY, BZ, A, il, jl, kl, pc);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int kl = k0 + u - B.lo[2];
+        const Cell<T> c = eval<T, true>(op, v[u], A != nullptr, B.bcmask, s, il, jl, kl);
+        const T Aphi = c.diag * v[u].pc - c.off;
+        r[u] = v[u].f - Aphi;
+      }
+    }
+    // x-pair sums (both lanes of a pair get the same bits)
+    T sx[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) sx[u] = r[u] + __shfl_xor(r[u], 1);
+    if ((tx & 1) == 0 && (ty & 1) == 1) {
+      ypair[0][slot] = sx[0];
+      ypair[1][slot] = sx[1];
+    }
+    __syncthreads();
+    if ((tx & 1) == 0 && (ty & 1) == 0 && act) {
+      const T z0 = sx[0] + ypair[0][slot];
+      const T z1 = sx[1] + ypair[1][slot];
+      const int I = fdiv2(i), J = fdiv2(j), K = fdiv2(k0);
+      rc[C.off_g0 + cidx(dc, 0, I - C.lo[0], J - C.lo[1], K - C.lo[2])] = (z0 + z1) * T(0.125);
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_maxabs(const Tile* __restrict__ tiles, const BoxInfo* __restrict__ boxes,
@@ -2388,6 +2462,23 @@ hipError_t launch_residual(hipStream_t st, const Tile* tiles, int ntiles, Shape 
 }
 
 template <typename T>
+hipError_t launch_resid_restrict(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                                 const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
+                                 const BoxInfo* cinfo, T* rc) {
+  if (ntiles <= 0) return hipSuccess;
+  if (sh.lx < 2 || (sh.lx & 1) || (sh.ly & 1) || (sh.tz & 1) || sh.lx * sh.ly > 256)
+    return hipErrorInvalidValue;
+  const dim3 g(ntiles), b = block_of(sh);
+  if (op.buf)
+    hipLaunchKernelGGL((k_resid_restrict<T, true>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng,
+                       sh.tz, cinfo, rc);
+  else
+    hipLaunchKernelGGL((k_resid_restrict<T, false>), g, b, 0, st, tiles, op, phi, rhs, rhs_ng,
+                       sh.tz, cinfo, rc);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_maxabs(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                          const BoxInfo* boxes, const T* v, int ng, unsigned long long* normbits) {
   if (ntiles <= 0) return hipSuccess;
@@ -2794,6 +2885,9 @@ hipError_t launch_bottom_bicgstab(hipStream_t st, const BottomTables& bt, const 
                                        const T*, int, unsigned long long*);                      \
   template hipError_t launch_restrict<T>(hipStream_t, const Tile*, int, Shape, const BoxInfo*,   \
                                          const BoxInfo*, const T*, T*);                          \
+  template hipError_t launch_resid_restrict<T>(hipStream_t, const Tile*, int, Shape,             \
+                                               const StencilArgs<T>&, const T*, const T*, int,   \
+                                               const BoxInfo*, T*);                              \
   template hipError_t launch_prolong_add<T>(hipStream_t, const Tile*, int, Shape,                \
                                             const BoxInfo*, const BoxInfo*, T*, const T*);       \
   template hipError_t launch_zero_valid<T>(hipStream_t, const Tile*, int, Shape, const BoxInfo*, \

@@ -120,6 +120,16 @@ template <typename T>
 hipError_t launch_restrict(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
                            const BoxInfo* fine, const BoxInfo* coarse, const T* rf, T* rc);
 
+// rc = R (rhs - A phi): the residual pass and the restriction in one pass
+// (the fine residual is not stored; same bits in rc).  Tiles of lx x ly
+// lanes (lx, ly even, lx*ly <= 256) and tz planes (even), starting at even
+// cells of boxes with even extents; cinfo: the coarse boxes (each fine box's
+// parent), rc without ghosts.
+template <typename T>
+hipError_t launch_resid_restrict(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
+                                 const StencilArgs<T>& op, const T* phi, const T* rhs, int rhs_ng,
+                                 const BoxInfo* cinfo, T* rc);
+
 // Fine valid cell += parent coarse value; both with one ghost layer.
 template <typename T>
 hipError_t launch_prolong_add(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,

@@ -108,6 +108,11 @@ struct Level {
   std::vector<Tile> t_vec;
   Shape s_vec{64, 4, 16};
   Tile* d_vec = nullptr;
+  // level 0: tiles of the residual pass that writes the restriction into
+  // level 1's right-hand side (lx, ly, tz even)
+  std::vector<Tile> t_rr;
+  Shape s_rr{64, 4, 2, 2};
+  Tile* d_rr = nullptr;
   size_t cap_gsrb = 0, cap_cell = 0;  // tile slots reserved in the workspace
   // level 0: smoother tile shapes per box class (a box's x extent); empty =
   // one shape for every box (s_gsrb)
@@ -188,6 +193,8 @@ struct mg_solver {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipEvent_t ev_norm[2] = {nullptr, nullptr};  // folded stop test: norm copies landed
   hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
+  // the level-0 residual pass writes its restriction into level 1's rhs
+  bool rr_fold = false;
   // first level of the coarse tail (-1: none) and its device plan
   int tail_lev = -1;
   char* d_tail = nullptr;
@@ -660,6 +667,10 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     if (l == 0) {
       lv.s_vec = fit_tz(lv.info, shape_cell(mx[0], mx[1], mx[2]), 1, false);
       make_tiles(lv.info, lv.s_vec, lv.s_vec.lx, false, lv.t_vec);
+      const int rlx = std::max(2, std::min(64, pow2ceil(mx[0])));
+      lv.s_rr = Shape{rlx, std::max(2, std::min(256 / rlx, 4)), 2, 2};
+      lv.t_rr.clear();
+      if (hb.size() >= 2) make_tiles(lv.info, lv.s_rr, lv.s_rr.lx, false, lv.t_rr);
     }
     build_fb(lv, s->periodic, 1);
     lv.cap_gsrb = lv.t_gsrb.size();
@@ -737,6 +748,12 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     c.fold_rs = l >= 2;
   }
 
+  // the level-0 residual restricts as it goes: every level-0 box splits
+  // into whole 2x2x2 blocks (true whenever there is a level 1)
+  s->rr_fold = s->L.size() >= 2 && s->opts.restrict_fold >= 1 && !s->composite;
+  for (const BoxInfo& b : s->L[0].info)
+    for (int d = 0; d < 3; ++d)
+      if (((b.lo[d] % 2) + 2) % 2 != 0 || (b.hi[d] - b.lo[d] + 1) % 2 != 0) s->rr_fold = false;
   s->tail_lev = choose_tail(s);
   build_tail_tables(s);
 
@@ -826,7 +843,10 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
       lv.rhs64 = bump.take<double>(lv.n_g0);
       if (!bottom) lv.r64 = bump.take<double>(lv.n_g0);
     }
-    if (l == 0) lv.d_vec = bump.take<Tile>(lv.t_vec.size());
+    if (l == 0) {
+      lv.d_vec = bump.take<Tile>(lv.t_vec.size());
+      lv.d_rr = lv.t_rr.empty() ? nullptr : bump.take<Tile>(lv.t_rr.size());
+    }
     if (lv.wt) {
       lv.d_wt = bump.take<WtEntry>(std::max<size_t>(1, lv.h_wt.size()));
       lv.d_wtbox = bump.take<WtBox>(lv.h_wtbox.size());
@@ -1182,7 +1202,7 @@ int coarse_cycle(mg_solver* s, size_t l, bool f32, const T* rf = nullptr) {
   const StencilArgs<T> op = stencil_of<T>(s, lv, f32);
   const bool prof = l == 0;
   int rc;
-  if ((int)l == s->tail_lev && rf) {
+  if ((int)l == s->tail_lev) {
     // the plan was built for the solver's precision (FP32 refinement: float)
     if (f32 != (s->opts.precision == MG_PREC_F32_REFINE))
       return fail(MG_ERR_ARG, "coarse tail in the other precision");
@@ -1220,13 +1240,19 @@ int coarse_cycle(mg_solver* s, size_t l, bool f32, const T* rf = nullptr) {
     return rc;
   // write-through smoothing leaves the face ghosts current
   if (!(lv.wt && s->opts.nu1 > 0) && (rc = exchange<T>(s, lv, D.e, prof))) return rc;
-  {
-    ProfScope ps(s, 1, prof);
-    HIPTRY((launch_residual<T, T>(s->st, lv.d_cell, (int)lv.t_cell.size(), lv.s_cell, op, D.e,
-                                  D.rhs, 0, D.r, nullptr, 0)));
-  }
   Level& cl = s->L[l + 1];
   LevelData<T> C = ldata<T>(cl, f32);
+  // level 0 may restrict inside its residual pass (then level 1 gets no rf)
+  const bool rr = l == 0 && s->rr_fold;
+  {
+    ProfScope ps(s, 1, prof);
+    if (rr)
+      HIPTRY(launch_resid_restrict<T>(s->st, lv.d_rr, (int)lv.t_rr.size(), lv.s_rr, op, D.e,
+                                      D.rhs, 0, cl.d_info, C.rhs));
+    else
+      HIPTRY((launch_residual<T, T>(s->st, lv.d_cell, (int)lv.t_cell.size(), lv.s_cell, op, D.e,
+                                    D.rhs, 0, D.r, nullptr, 0)));
+  }
   // the coarser levels, starting with the restriction of D.r
   if (l == 0 && s->opts.use_graph) {
     hipGraphExec_t g = f32 ? s->graph32 : s->graph64;
@@ -1234,7 +1260,7 @@ int coarse_cycle(mg_solver* s, size_t l, bool f32, const T* rf = nullptr) {
     HIPTRY(hipGraphLaunch(g, s->st));
   } else {
     ProfScope ps(s, 5, l == 0);
-    if ((rc = coarse_cycle<T>(s, l + 1, f32, D.r))) return rc;
+    if ((rc = coarse_cycle<T>(s, l + 1, f32, rr ? nullptr : D.r))) return rc;
   }
   if (fold_interp(s, l))
     return smooth<T>(s, lv, op, D.e, D.rhs, 0, s->opts.nu2, false, prof, s->opts.krylov != 0,
@@ -1257,8 +1283,9 @@ int capture_graphs(mg_solver* s) {
   HIPTRY(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
   const bool saved = s->profile;
   s->profile = false;
-  int rc = f32 ? coarse_cycle<float>(s, 1, true, s->L[0].r32)
-               : coarse_cycle<double>(s, 1, false, s->L[0].r64);
+  // the level-0 residual pass restricts into level 1 itself with rr_fold
+  int rc = f32 ? coarse_cycle<float>(s, 1, true, s->rr_fold ? nullptr : s->L[0].r32)
+               : coarse_cycle<double>(s, 1, false, s->rr_fold ? nullptr : s->L[0].r64);
   s->profile = saved;
   hipError_t e = hipStreamEndCapture(s->st, &g);
   if (rc) return rc;
@@ -1314,19 +1341,24 @@ int vcycle64(mg_solver* s, double* phi, const double* rhs, int rhs_ng, bool red_
     return rc;
   }
   if (!(l0.wt && s->opts.nu1 > 0) && (rc = exchange<double>(s, l0, phi, true))) return rc;
+  Level& l1 = s->L[1];
   {
     ProfScope ps(s, 1, true);
-    HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell, op,
-                                            phi, rhs, rhs_ng, l0.r64, nullptr, 0)));
+    if (s->rr_fold)
+      HIPTRY(launch_resid_restrict<double>(s->st, l0.d_rr, (int)l0.t_rr.size(), l0.s_rr, op, phi,
+                                           rhs, rhs_ng, l1.d_info, l1.rhs64));
+    else
+      HIPTRY((launch_residual<double, double>(s->st, l0.d_cell, (int)l0.t_cell.size(), l0.s_cell,
+                                              op, phi, rhs, rhs_ng, l0.r64, nullptr, 0)));
   }
-  Level& l1 = s->L[1];
   // the coarser levels, starting with the restriction of the residual
+  // (already in level 1's rhs with rr_fold)
   if (s->opts.use_graph) {
     ProfScope ps(s, 5, true);
     HIPTRY(hipGraphLaunch(s->graph64, s->st));
   } else {
     ProfScope ps(s, 5, true);
-    if ((rc = coarse_cycle<double>(s, 1, false, l0.r64))) return rc;
+    if ((rc = coarse_cycle<double>(s, 1, false, s->rr_fold ? nullptr : l0.r64))) return rc;
   }
   if (fold_interp(s, 0))
     return smooth<double>(s, l0, op, phi, rhs, rhs_ng, s->opts.nu2, false, true, false, true,
@@ -1789,7 +1821,8 @@ int autotune(mg_solver* s) {
   const bool t1 = tune_level1_ok(s);
   const std::string kg1 = t1 ? tune_key(s, "gsrb", f32, 1) : "", kr1 = t1 ? tune_key(s, "resid", f32, 1) : "";
   // whether the restriction into level 1 folds (entry u = 1)
-  const bool tf = t1 && s->L[1].coarsened_1to1 && s->opts.restrict_fold == 1 && s->opts.nu1 >= 1;
+  const bool tf = t1 && s->L[1].coarsened_1to1 && s->opts.restrict_fold == 1 &&
+                  s->opts.nu1 >= 1 && !s->rr_fold;
   const std::string kf = tf ? tune_key(s, "rfold", f32, 1) : "";
   int rc;
   if (s->opts.tune == 1) {
@@ -2006,7 +2039,8 @@ TailPlan<T> tail_plan(mg_solver* s, bool f32) {
   tp.finfo = up.d_info;
   tp.fnbox = up.nbox;
   tp.rcells = up.d_trc;
-  tp.nrc = (int)up.h_trc.size();
+  // level 0's residual pass already restricted into the first tail level
+  tp.nrc = t == 1 && s->rr_fold ? 0 : (int)up.h_trc.size();
   for (int i = 0; i < tp.nlev; ++i) {
     Level& lv = s->L[t + i];
     const LevelData<T> D = ldata<T>(lv, f32);
@@ -2071,6 +2105,9 @@ int upload_tables(mg_solver* s) {
                             hipMemcpyHostToDevice, s->st));
     if (!lv.t_vec.empty())
       HIPTRY(hipMemcpyAsync(lv.d_vec, lv.t_vec.data(), sizeof(Tile) * lv.t_vec.size(),
+                            hipMemcpyHostToDevice, s->st));
+    if (!lv.t_rr.empty())
+      HIPTRY(hipMemcpyAsync(lv.d_rr, lv.t_rr.data(), sizeof(Tile) * lv.t_rr.size(),
                             hipMemcpyHostToDevice, s->st));
     if (lv.wt) {
       if (!lv.h_wt.empty())

@@ -209,6 +209,7 @@ def main():
         gs[k]["fused"] = fam["rim"]["launches_per_solve"] > 0
         gs[k]["tile_shapes"] = {"smoother": s.tile_shape(0), "cell": s.tile_shape(1),
                                 "fused_sweep": s.tile_shape(3),
+                                "resid_restrict": s.tile_shape(4),
                                 "smoother_classes": {str(x): list(v) for x, v in
                                                      sorted(s.class_tile_shapes().items())}}
         s.profile(False)

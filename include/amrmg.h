@@ -397,7 +397,10 @@ int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rh
  * up to 16 (kernel 0) or 8 (kernel 1); tz in {2,...,64}).  kernel 3: the
  * fused sweep of level 0 (lx x ly x tz cells per work-group of lx/2*ly lanes;
  * (lx, ly) in {(64,4), (64,8), (32,8), (32,16)}, tz in {4,8,16,32}; unroll
- * ignored; MG_ERR_ARG when level 0 does not use fused sweeps).  Every
+ * ignored; MG_ERR_ARG when level 0 does not use fused sweeps).  kernel 4:
+ * the level-0 residual pass that writes its restriction into level 1
+ * (lx x ly cells, lx, ly and tz even, a kernel 1 candidate with unroll 2;
+ * unroll ignored).  tz in {1,...,64} (kernels 0, 1, 2).  Every
  * shape gives bitwise-identical V-cycle solves; with krylov = 1 the dot
  * p.q is summed per tile of kernel 1, whose shape then changes the last
  * bits of the result. */
@@ -408,7 +411,9 @@ int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, in
  * half-sweep smoother -> {lx, ly, tz, unroll, whole_pairs}; kernel 1 the
  * one-lane-per-cell kernels -> {lx, ly, tz, unroll, 0}; kernel 3 the fused
  * sweep -> {lx, ly, tz, in_use, 0} (in_use 0 when level 0 runs half-sweeps;
- * lx = 0 when it has no fused sweep at all).  shape: host int32_t[5]. */
+ * lx = 0 when it has no fused sweep at all); kernel 4 the residual pass
+ * that restricts into level 1 -> {lx, ly, tz, in_use, 0}.  shape: host
+ * int32_t[5]. */
 int mg_get_tile_shape(mg_solver_t* s, int32_t kernel, int32_t* shape);
 
 /* Level-0 smoother tiles per box class ("tile size adjustable at run time",

@@ -113,6 +113,7 @@ struct Level {
   std::vector<Tile> t_rr;
   Shape s_rr{64, 4, 2, 2};
   Tile* d_rr = nullptr;
+  size_t cap_rr = 0;
   size_t cap_gsrb = 0, cap_cell = 0;  // tile slots reserved in the workspace
   // level 0: smoother tile shapes per box class (a box's x extent); empty =
   // one shape for every box (s_gsrb)
@@ -340,6 +341,15 @@ std::vector<Shape> cell_candidates() {
       for (int tz : {1, 2, 4, 8, 16, 32, 64})
         for (int u : {1, 2, 4})
           if (shape_ok({lx, ly, tz, u}) && u <= tz) c.push_back({lx, ly, tz, u});
+  return c;
+}
+
+// tiles of the fused residual-restriction pass: lx, ly, tz even
+std::vector<Shape> rr_candidates() {
+  std::vector<Shape> c;
+  for (Shape sh : cell_candidates())
+    if (sh.lx >= 2 && sh.lx % 2 == 0 && sh.ly % 2 == 0 && sh.tz % 2 == 0 && sh.u == 2)
+      c.push_back(sh);
   return c;
 }
 
@@ -671,6 +681,10 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
       lv.s_rr = Shape{rlx, std::max(2, std::min(256 / rlx, 4)), 2, 2};
       lv.t_rr.clear();
       if (hb.size() >= 2) make_tiles(lv.info, lv.s_rr, lv.s_rr.lx, false, lv.t_rr);
+      lv.cap_rr = lv.t_rr.size();
+      if (hb.size() >= 2)
+        for (Shape c : rr_candidates())
+          lv.cap_rr = std::max(lv.cap_rr, tile_count(lv.info, c, c.lx));
     }
     build_fb(lv, s->periodic, 1);
     lv.cap_gsrb = lv.t_gsrb.size();
@@ -845,7 +859,7 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     }
     if (l == 0) {
       lv.d_vec = bump.take<Tile>(lv.t_vec.size());
-      lv.d_rr = lv.t_rr.empty() ? nullptr : bump.take<Tile>(lv.t_rr.size());
+      lv.d_rr = lv.t_rr.empty() ? nullptr : bump.take<Tile>(lv.cap_rr);
     }
     if (lv.wt) {
       lv.d_wt = bump.take<WtEntry>(std::max<size_t>(1, lv.h_wt.size()));
@@ -1494,6 +1508,20 @@ int apply_shape(mg_solver* s, Shape sh, bool gsrb, size_t lev = 0) {
   return MG_OK;
 }
 
+// Level-0 tiles of the fused residual-restriction pass.
+int apply_rr_shape(mg_solver* s, Shape sh) {
+  Level& l0 = s->L[0];
+  std::vector<Tile> t;
+  make_tiles(l0.info, sh, sh.lx, false, t);
+  if (t.size() > l0.cap_rr) return fail(MG_ERR_ARG, "tile table larger than its reservation");
+  l0.t_rr = t;
+  l0.s_rr = sh;
+  HIPTRY(hipMemcpyAsync(l0.d_rr, l0.t_rr.data(), sizeof(Tile) * l0.t_rr.size(),
+                        hipMemcpyHostToDevice, s->st));
+  HIPTRY(hipStreamSynchronize(s->st));
+  return MG_OK;
+}
+
 // Level-0 smoother tiles with class shapes cls (dflt for other classes).
 int apply_class_tiles(mg_solver* s, const std::map<int, Shape>& cls, Shape dflt) {
   Level& l0 = s->L[0];
@@ -1593,10 +1621,15 @@ int time_resid(mg_solver* s, Shape sh, const T* phi, const T* rhs, const Stencil
   hipEvent_t a = take_event(s), b = take_event(s);
   Level& l0 = s->L[lev];
   unsigned long long* nb = norm_slot(s, 3);
+  // with rr_fold the level-0 V-cycle residual is the fused pass (tiles of
+  // its own): these tiles then serve the stop test alone
+  const bool stop_only = with_norm && lev == 0 && s->rr_fold;
   auto pair = [&]() -> hipError_t {
-    hipError_t e = launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi,
-                                         rhs, 0, out, nullptr, 0);
-    if (e != hipSuccess || !with_norm) return e;
+    if (!stop_only) {
+      hipError_t e = launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi,
+                                           rhs, 0, out, nullptr, 0);
+      if (e != hipSuccess || !with_norm) return e;
+    }
     T* nx = nullptr;
     if constexpr (std::is_same<T, double>::value) nx = lev == 0 ? l0.next64 : nullptr;
     return launch_residual<T, T>(s->st, l0.d_cell, (int)l0.t_cell.size(), sh, op, phi, rhs, 0,
@@ -1607,6 +1640,32 @@ int time_resid(mg_solver* s, Shape sh, const T* phi, const T* rhs, const Stencil
   HIPTRY(hipEventRecord(a, s->st));
   const int reps = lev ? 24 : with_norm ? 3 : 6;
   for (int w = 0; w < reps; ++w) HIPTRY(pair());
+  HIPTRY(hipEventRecord(b, s->st));
+  HIPTRY(hipEventSynchronize(b));
+  float t;
+  HIPTRY(hipEventElapsedTime(&t, a, b));
+  *ms = t / reps;
+  s->ev_used -= 2;
+  return MG_OK;
+}
+
+// Mean time of the fused residual-restriction pass (level 0 into level 1's
+// rhs, which the solve overwrites before use) with tiles sh.
+template <typename T>
+int time_rr(mg_solver* s, Shape sh, const T* phi, const T* rhs, const StencilArgs<T>& op,
+            T* rc, float* ms) {
+  int rc_;
+  if ((rc_ = apply_rr_shape(s, sh))) return rc_;
+  Level& l0 = s->L[0];
+  hipEvent_t a = take_event(s), b = take_event(s);
+  auto one = [&]() {
+    return launch_resid_restrict<T>(s->st, l0.d_rr, (int)l0.t_rr.size(), sh, op, phi, rhs, 0,
+                                    s->L[1].d_info, rc);
+  };
+  for (int w = 0; w < 2; ++w) HIPTRY(one());
+  HIPTRY(hipEventRecord(a, s->st));
+  const int reps = 6;
+  for (int w = 0; w < reps; ++w) HIPTRY(one());
   HIPTRY(hipEventRecord(b, s->st));
   HIPTRY(hipEventSynchronize(b));
   float t;
@@ -1818,6 +1877,7 @@ int autotune(mg_solver* s) {
   auto cache = read_cache();
   const std::string kg = tune_key(s, "gsrb", f32), kr = tune_key(s, "resid", f32);
   const std::string ks = tune_key(s, "sweep", f32);
+  const std::string krr = tune_key(s, "rr", f32);
   const bool t1 = tune_level1_ok(s);
   const std::string kg1 = t1 ? tune_key(s, "gsrb", f32, 1) : "", kr1 = t1 ? tune_key(s, "resid", f32, 1) : "";
   // whether the restriction into level 1 folds (entry u = 1)
@@ -1883,6 +1943,14 @@ int autotune(mg_solver* s) {
       make_tiles(l0.info, it->second, it->second.lx, false, t);
       if (t.size() <= l0.cap_cell && (rc = apply_shape(s, it->second, false))) return rc;
     }
+    it = s->rr_fold ? cache.find(krr) : cache.end();
+    if (it != cache.end()) {
+      bool cand = false;
+      for (Shape c : rr_candidates())
+        cand = cand || (c.lx == it->second.lx && c.ly == it->second.ly && c.tz == it->second.tz);
+      if (cand && (rc = apply_rr_shape(s, Shape{it->second.lx, it->second.ly, it->second.tz, 2})))
+        return rc;
+    }
     return MG_OK;
   }
   if (s->opts.tune != 2) return MG_OK;
@@ -1945,6 +2013,25 @@ int autotune(mg_solver* s) {
   }
   if ((rc = apply_shape(s, best_g, true))) return rc;
   if ((rc = apply_shape(s, best_c, false))) return rc;
+  if (s->rr_fold) {
+    std::vector<std::pair<float, Shape>> fq;
+    Shape best_q = l0.s_rr;
+    float tq = 1e30f;
+    Level& l1 = s->L[1];
+    auto time_q = [&](Shape sh, float* ms) {
+      return f32 ? time_rr<float>(s, sh, (const float*)s->tune_scratch, l0.rhs32,
+                                  stencil_of<float>(s, l0, true), l1.rhs32, ms)
+                 : time_rr<double>(s, sh, s->tune_scratch, l0.r64,
+                                   stencil_of<double>(s, l0, false), l1.rhs64, ms);
+    };
+    for (Shape sh : rr_candidates()) {
+      if ((rc = time_q(sh, &t))) return rc;
+      fq.push_back({t, sh});
+    }
+    if ((rc = pick_finalist(fq, time_q, &best_q, &tq))) return rc;
+    if ((rc = apply_rr_shape(s, best_q))) return rc;
+    cache[krr] = best_q;
+  }
   std::map<int, Shape> cls;
   float tu = 0, tcl = 0;
   rc = f32 ? tune_classes<float>(s, best_g, (float*)s->tune_scratch, l0.rhs32,
@@ -3632,6 +3719,13 @@ int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, in
     if (!ok) return fail(MG_ERR_ARG, "shape is not a candidate");
     return apply_sweep_shape(s, Shape{lx, ly, tz});
   }
+  if (kernel == 4) {
+    bool ok = false;
+    for (Shape c : rr_candidates())
+      if (c.lx == lx && c.ly == ly && c.tz == tz) ok = true;
+    if (!ok || !s->rr_fold) return fail(MG_ERR_ARG, "shape is not a candidate");
+    return apply_rr_shape(s, Shape{lx, ly, tz, 2});
+  }
   // kernel 2: the smoother storing whole x-pairs
   const int wp = kernel == 2 ? 1 : 0;
   if (kernel == 2) kernel = 0;
@@ -3680,8 +3774,12 @@ int mg_get_tile_shape(mg_solver_t* s, int32_t kernel, int32_t* shape) {
     const bool has = !l0.t_sweep.empty();
     const int32_t v[5] = {has ? w.lx : 0, has ? w.ly : 0, has ? w.tz : 0, l0.fused ? 1 : 0, 0};
     std::memcpy(shape, v, sizeof(v));
+  } else if (kernel == 4) {
+    const Shape& q = l0.s_rr;
+    const int32_t v[5] = {q.lx, q.ly, q.tz, s->rr_fold ? 1 : 0, 0};
+    std::memcpy(shape, v, sizeof(v));
   } else {
-    return fail(MG_ERR_ARG, "kernel must be 0, 1 or 3");
+    return fail(MG_ERR_ARG, "kernel must be 0, 1, 3 or 4");
   }
   return MG_OK;
 }

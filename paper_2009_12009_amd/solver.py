@@ -224,7 +224,8 @@ class MLMG:
 
     def tile_shape(self, kernel):
         """Level-0 tile shape in use: kernel 0 smoother (lx, ly, tz, unroll, whole_pairs),
-        1 cell kernels (lx, ly, tz, unroll, 0), 3 fused sweep (lx, ly, tz, in_use, 0)."""
+        1 cell kernels (lx, ly, tz, unroll, 0), 3 fused sweep (lx, ly, tz, in_use, 0),
+        4 residual pass restricting into level 1 (lx, ly, tz, in_use, 0)."""
         out = (C.c_int32 * 5)()
         L.check(L.lib.mg_get_tile_shape(self.handle, kernel, out), "mg_get_tile_shape")
         return tuple(out)

@@ -209,11 +209,13 @@ def test_tile_shapes_and_graph_bitwise_identical():
     boxes = cfg["boxes"]
     rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(cfg["rhs"], boxes), 0)
     outs = []
-    # kernels 0-2 on half-sweep levels (fused sweeps off), kernel 3 = fused sweep
+    # kernels 0-2 on half-sweep levels (fused sweeps off), kernel 3 = fused sweep,
+    # kernel 4 = the residual pass restricting into level 1
     shapes = [None, (0, 16, 4, 4, 1), (0, 32, 8, 32, 2), (0, 64, 4, 64, 4), (0, 32, 2, 2, 2),
-              (2, 32, 4, 4, 2), (2, 16, 4, 8, 1), (1, 32, 2, 8, 1), (1, 128, 2, 64, 4),
-              (1, 64, 4, 4, 2), (3, 64, 8, 16, 1), (3, 32, 8, 4, 1), (3, 64, 4, 32, 1),
-              (3, 32, 16, 8, 1)]
+              (0, 32, 8, 1, 1), (2, 32, 4, 4, 2), (2, 16, 4, 8, 1), (1, 32, 2, 8, 1),
+              (1, 128, 2, 64, 4), (1, 64, 4, 4, 2), (3, 64, 8, 16, 1), (3, 32, 8, 4, 1),
+              (3, 64, 4, 32, 1), (3, 32, 16, 8, 1), (4, 32, 2, 2, 2), (4, 64, 2, 8, 2),
+              (4, 128, 2, 4, 2), (4, 32, 8, 2, 2)]
     for graph in (1, 0):
         for sh in shapes:
             fused = 32 if sh is not None and sh[0] == 3 else 0

@@ -2365,9 +2365,10 @@ hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
   } else if (ec) {
     // never whole pairs: the other cell of a pair would be stored with its
     // correction while other lanes still read it and add the correction.
-    // Buffer loads (the correction's included) measured faster in FP32 and
-    // slower in FP64 (C1 level 0: 92.6 against 96.4 us; 181.5 against 175.8)
-    if (buf && sizeof(T) == 4) { GSU(false, false, true, true, true) }
+    // Buffer loads (the correction's included) where the level streams: at
+    // 256^3 with single-plane tiles 164 against 171 us (FP64), and faster in
+    // FP32 as well
+    if (buf) { GSU(false, false, true, true, true) }
     else { GSU(false, false, true, true, false) }
   } else if (wtb) {
     // a zero-guess half-sweep reads f and the faces once each: streaming

@@ -153,6 +153,25 @@ __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int idx) {
   }
 }
 
+// Elements idx and idx + 1 in one load (8 bytes FP32, 16 bytes FP64).  The
+// load's vector is cast whole to an integer and split by shifts: taking its
+// 32-bit elements one by one lets the compiler shrink the load to its first
+// element while still reading the second.
+template <typename T, int AUX>
+__device__ __forceinline__ void bload_pair(__amdgpu_buffer_rsrc_t r, int idx, T& lo, T& hi) {
+  if constexpr (sizeof(T) == 8) {
+    const unsigned __int128 u = __builtin_bit_cast(
+        unsigned __int128, __builtin_amdgcn_raw_buffer_load_b128(r, (int)((unsigned)idx * 8u), 0, AUX));
+    lo = __builtin_bit_cast(T, (unsigned long long)u);
+    hi = __builtin_bit_cast(T, (unsigned long long)(u >> 64));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(
+        unsigned long long, __builtin_amdgcn_raw_buffer_load_b64(r, (int)((unsigned)idx * 4u), 0, AUX));
+    lo = __builtin_bit_cast(T, (unsigned)u);
+    hi = __builtin_bit_cast(T, (unsigned)(u >> 32));
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ BoxBufs bufs_of(const StencilArgs<T>& op, const BoxInfo& B,
                                            const Strides& s, const T* P, const T* R, int rhs_ng,
@@ -182,17 +201,26 @@ __device__ __forceinline__ void gather_buf(Nbr<T>& v, const Strides& s, const Bo
   const int fx = il + (s.nx + 1) * (jl + s.ny * kl);
   const int fy = il + s.nx * (jl + (s.ny + 1) * kl);
   const int fz = il + s.nx * (jl + s.ny * kl);
-  v.bxl = bload<T, 2>(b.x, fx);
-  v.bxh = bload<T, 2>(b.x, fx + 1);
+  // the cell's two x faces are adjacent: one load of both (only 4-byte
+  // alignment is needed)
+  bload_pair<T, 2>(b.x, fx, v.bxl, v.bxh);
   v.byl = bload<T, 2>(b.y, fy);
   v.byh = bload<T, HI>(b.y, fy + s.nx);
   v.bzl = bload<T, 2>(b.z, fz);
   v.bzh = bload<T, HI>(b.z, fz + s.nx * s.ny);
   if (has_a) v.a = bload<T, 2>(b.a, fz);
-  if (READ_CENTRE) v.pc = bload<T, 0>(b.p, pc);
-  if (READ_PHI) {
-    v.pxl = bload<T, 0>(b.p, pc - 1);
+  if constexpr (READ_PHI && READ_CENTRE) {
+    // the low x neighbour and the cell in one load
+    bload_pair<T, 0>(b.p, pc - 1, v.pxl, v.pc);
     v.pxh = bload<T, 0>(b.p, pc + 1);
+  } else {
+    if (READ_CENTRE) v.pc = bload<T, 0>(b.p, pc);
+    if (READ_PHI) {
+      v.pxl = bload<T, 0>(b.p, pc - 1);
+      v.pxh = bload<T, 0>(b.p, pc + 1);
+    }
+  }
+  if (READ_PHI) {
     v.pyl = bload<T, 0>(b.p, pc - s.sy);
     v.pyh = bload<T, 0>(b.p, pc + s.sy);
     v.pzl = bload<T, 0>(b.p, pc - s.sz);

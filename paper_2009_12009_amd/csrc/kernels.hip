@@ -533,6 +533,216 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// FP32 half-sweep with two cells of the active colour per lane: lane tx of
+// a tile row covers the x-quad t.x0 + 4 tx .. + 3 and updates its cells i0
+// and i0 + 2 of that colour, each with the pair kernel's arithmetic (eval,
+// the same update).  The quad's values come in 16-byte buffer loads (dword
+// alignment; loads past a row read other cells and are not used, past the
+// array they read 0), so a lane issues about half the loads per cell of the
+// pair mapping.  Streaming levels (buffer descriptors) with write-through
+// only; ZG and PE as in k_gsrb.
+// A quad stays a 128-bit integer value; an element is a constant shift of
+// it.  (Kept as an array or a struct, a choice between two elements by the
+// lane's colour parity became an indexed access to a copy in scratch.)
+typedef unsigned __int128 Quad;
+
+__device__ __forceinline__ Quad qload(__amdgpu_buffer_rsrc_t r, int idx, int aux_nt) {
+  // the vector is cast whole (element-wise extraction let the compiler
+  // shrink wide buffer loads)
+  return aux_nt ? __builtin_bit_cast(Quad, __builtin_amdgcn_raw_buffer_load_b128(
+                                               r, (int)((unsigned)idx * 4u), 0, 2))
+                : __builtin_bit_cast(Quad, __builtin_amdgcn_raw_buffer_load_b128(
+                                               r, (int)((unsigned)idx * 4u), 0, 0));
+}
+
+template <int E>
+__device__ __forceinline__ float qel(Quad q) {
+  return __builtin_bit_cast(float, (unsigned)(q >> (32 * E)));
+}
+
+// element 2c + p (p = 0 or 1): the select is on values, not on addresses
+__device__ __forceinline__ float qpick(Quad q, int c, int p) {
+  const unsigned lo = (unsigned)(q >> (c ? 64 : 0)), hi = (unsigned)(q >> (c ? 96 : 32));
+  return __builtin_bit_cast(float, p ? hi : lo);
+}
+
+template <int U, bool ZG, bool PE>
+__global__ void __launch_bounds__(256)
+    k_gsrb_quad(const Tile* __restrict__ tiles, StencilArgs<float> op, float* __restrict__ phi,
+                const float* __restrict__ rhs, int rhs_ng, int colour, int tz_launch,
+                const WtBox* __restrict__ wtb, const WtEntry* __restrict__ wte,
+                const BoxInfo* __restrict__ cinfo, const float* __restrict__ ec) {
+  static_assert(!(PE && ZG), "folded interpolation: not from zero");
+  using T = float;
+  const Tile t = tiles[blockIdx.x];
+  const BoxInfo B = op.boxes[t.box];
+  const int lxl = __builtin_ctz(blockDim.x);
+  const int ly = blockDim.y;
+  const int tz = tz_launch;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int j = t.y0 + ty;
+  const bool row_ok = j <= B.hi[1];
+  const Strides s = strides_of(B, rhs_ng);
+  const int jl = j - B.lo[1];
+  const int kend = min(t.z0 + tz - 1, B.hi[2]);
+  T* P = phi + B.off_g1;
+  extern __shared__ double lds_gsrb[];
+  T* XS = reinterpret_cast<T*>(lds_gsrb);  // [2][ly][tz] x-face values
+  const T* R = rhs + (rhs_ng ? B.off_g1 : B.off_g0);
+  const T* BX = op.b0 + B.off_f[0];
+  const T* BY = op.b1 + B.off_f[1];
+  const T* BZ = op.b2 + B.off_f[2];
+  const T* A = op.a ? op.a + B.off_g0 : nullptr;
+  const int m = B.bcmask;
+  const BoxBufs bb = bufs_of<T>(op, B, s, P, R, rhs_ng, BX, BY, BZ, A);
+  WtBox wb = wtb[t.box];
+  WtEntry ex[2];
+  for (int f = 0; f < 2; ++f)
+    if (wb.count[f] == 1) ex[f] = wte[wb.first[f]];
+  const T* EC = nullptr;
+  int csy = 0, csz = 0, cbase = 0;
+  __amdgpu_buffer_rsrc_t ecr;
+  if (PE) {
+    const BoxInfo C = cinfo[B.parent];
+    csy = C.hi[0] - C.lo[0] + 3;
+    csz = csy * (C.hi[1] - C.lo[1] + 3);
+    EC = ec + C.off_g1;
+    cbase = (1 - C.lo[0]) + csy * (fdiv2(j) - C.lo[1] + 1) + csz * (1 - C.lo[2]);
+    ecr = rsrc_of(EC, (long long)csz * (C.hi[2] - C.lo[2] + 3), sizeof(T));
+  }
+  const int xq = t.x0 + 4 * tx;
+  const int ilq = xq - B.lo[0];
+  for (int k0 = t.z0; k0 <= kend; k0 += U) {
+    Nbr<T> v[U][2];
+    T ev[U][2][PE ? 4 : 1];
+    int pc[U], par[U];
+    bool ok[U][2];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u;
+      const int p = (colour + t.x0 + j + k) & 1;
+      par[u] = p;
+      ok[u][0] = row_ok && k <= kend && ilq + p <= s.nx - 1;
+      ok[u][1] = row_ok && k <= kend && ilq + p + 2 <= s.nx - 1;
+      const int kl = k - B.lo[2];
+      pc[u] = (ilq + 1) + s.sy * (jl + 1) + s.sz * (kl + 1);
+      if (!ok[u][0]) continue;
+      const int fxq = ilq + (s.nx + 1) * (jl + s.ny * kl);
+      const int fyq = ilq + s.nx * (jl + (s.ny + 1) * kl);
+      const int fzq = ilq + s.nx * (jl + s.ny * kl);
+      const Quad qf = qload(bb.r, (ilq + rhs_ng) + s.rsy * (jl + rhs_ng) + s.rsz * (kl + rhs_ng), 1);
+      const Quad qx = qload(bb.x, fxq + p, 1);
+      const Quad qyl = qload(bb.y, fyq, 1);
+      const Quad qyh = qload(bb.y, fyq + s.nx, 0);
+      const Quad qzl = qload(bb.z, fzq, 1);
+      const Quad qzh = qload(bb.z, fzq + s.nx * s.ny, 0);
+      Quad qa = 0;
+      if (A) qa = qload(bb.a, fzq, 1);
+      // element p + 2c of a quad, picked with constant indices (an index
+      // that depends on the lane's parity would put the quad in scratch)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        v[u][c].f = qpick(qf, c, p);
+        v[u][c].bxl = c ? qel<2>(qx) : qel<0>(qx);
+        v[u][c].bxh = c ? qel<3>(qx) : qel<1>(qx);
+        v[u][c].byl = qpick(qyl, c, p);
+        v[u][c].byh = qpick(qyh, c, p);
+        v[u][c].bzl = qpick(qzl, c, p);
+        v[u][c].bzh = qpick(qzh, c, p);
+        if (A) v[u][c].a = qpick(qa, c, p);
+      }
+      if (!ZG) {
+        // x neighbours: pc-1 .. pc+2 and pc+3 .. pc+6 of the quad's row
+        const Quad qp0 = qload(bb.p, pc[u] - 1, 0);
+        const Quad qp1 = qload(bb.p, pc[u] + 3, 0);
+        const Quad qyl_ = qload(bb.p, pc[u] - s.sy, 0);
+        const Quad qyh_ = qload(bb.p, pc[u] + s.sy, 0);
+        const Quad qzl_ = qload(bb.p, pc[u] - s.sz, 0);
+        const Quad qzh_ = qload(bb.p, pc[u] + s.sz, 0);
+        // the row from the quad's low neighbour on: x0..x5 = qp0's four
+        // values and qp1's first two; quad cell e has x_e below, x_(e+2) above
+        const T x0 = qel<0>(qp0), x1 = qel<1>(qp0), x2 = qel<2>(qp0), x3 = qel<3>(qp0);
+        const T x4 = qel<0>(qp1), x5 = qel<1>(qp1);
+        v[u][0].pxl = p ? x1 : x0;
+        v[u][0].pxh = p ? x3 : x2;
+        v[u][1].pxl = p ? x3 : x2;
+        v[u][1].pxh = p ? x5 : x4;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          v[u][c].pyl = qpick(qyl_, c, p);
+          v[u][c].pyh = qpick(qyh_, c, p);
+          v[u][c].pzl = qpick(qzl_, c, p);
+          v[u][c].pzh = qpick(qzh_, c, p);
+        }
+      }
+      if (PE) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          if (!ok[u][c]) continue;
+          const int i = xq + p + 2 * c;
+          const int cc = cbase + fdiv2(i) + csz * fdiv2(k);
+          ev[u][c][0] = bload<T, 0>(ecr, cc);
+          ev[u][c][1] = bload<T, 0>(ecr, cc + ((i & 1) ? 1 : -1));
+          ev[u][c][2] = bload<T, 0>(ecr, cc + ((j & 1) ? csy : -csy));
+          ev[u][c][3] = bload<T, 0>(ecr, cc + ((k & 1) ? csz : -csz));
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (!ok[u][c]) continue;
+        const int il = ilq + par[u] + 2 * c;
+        const int kl = k0 + u - B.lo[2];
+        Nbr<T>& w = v[u][c];
+        if (PE) {
+          const bool ox = (il + B.lo[0]) & 1, oy = j & 1, oz = (k0 + u) & 1;
+          w.pxl = w.pxl + (ox ? ev[u][c][0] : ev[u][c][1]);
+          w.pxh = w.pxh + (ox ? ev[u][c][1] : ev[u][c][0]);
+          w.pyl = w.pyl + (oy ? ev[u][c][0] : ev[u][c][2]);
+          w.pyh = w.pyh + (oy ? ev[u][c][2] : ev[u][c][0]);
+          w.pzl = w.pzl + (oz ? ev[u][c][0] : ev[u][c][3]);
+          w.pzh = w.pzh + (oz ? ev[u][c][3] : ev[u][c][0]);
+        }
+        const Cell<T> cl = eval<T, !ZG>(op, w, A != nullptr, m, s, il, jl, kl);
+        const T nv = ZG ? w.f / cl.diag : (w.f + cl.off) / cl.diag;
+        P[pc[u] + par[u] + 2 * c] = nv;
+        const int kk = k0 + u - t.z0;
+        if (il == 0) XS[(0 * ly + ty) * tz + kk] = nv;
+        if (il == s.nx - 1) XS[(1 * ly + ty) * tz + kk] = nv;
+        write_through_yz<T>(wb, wte, phi, s, il, jl, kl, nv);
+      }
+    }
+  }
+  // x faces of this tile, as in k_gsrb
+  const bool has_lo = t.x0 == B.lo[0] && wb.count[0] > 0;
+  const bool has_hi = B.hi[0] <= t.x0 + 4 * (1 << lxl) - 1 && wb.count[1] > 0;
+  if (has_lo || has_hi) {
+    __syncthreads();
+    const int nz_t = kend - t.z0 + 1;
+    const int n = ly * nz_t;
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      if (!(f ? has_hi : has_lo)) continue;
+      const int ilf = f ? s.nx - 1 : 0;
+      for (int q = tx + blockDim.x * ty; q < n; q += blockDim.x * blockDim.y) {
+        const int tyq = q / nz_t, kk = q - tyq * nz_t;
+        const int jj = t.y0 + tyq, k = t.z0 + kk;
+        if (jj > B.hi[1] || ((B.lo[0] + ilf + jj + k) & 1) != colour) continue;
+        const T xv = XS[(f * ly + tyq) * tz + kk];
+        const int jlf = jj - B.lo[1], klf = k - B.lo[2];
+        if (wb.count[f] == 1) {
+          wt_store<T>(ex[f], phi, ilf, jlf, klf, xv);
+        } else {
+          for (int e = wb.first[f]; e < wb.first[f] + wb.count[f]; ++e)
+            wt_store<T>(wte[e], phi, ilf, jlf, klf, xv);
+        }
+      }
+    }
+  }
+}
+
 // One full red/black sweep, out of place (see launch_sweep).  Box-local
 // coordinates throughout; colour of local cell (i, j, k) = (i+j+k+par) & 1,
 // red = 0.  LDS holds a ring of 5 old planes over the tile grown by 2 in x
@@ -2385,6 +2595,26 @@ hipError_t launch_gsrb(hipStream_t st, const Tile* tiles, int ntiles, Shape sh,
   // buffer loads on the write-through paths the solve runs most, where the
   // level streams (op.buf)
   const bool buf = op.buf != 0;
+  if (sh.wp == 2) {
+    // two cells of the colour per lane (FP32, buffer loads, write-through)
+    if constexpr (!std::is_same<T, float>::value) {
+      return hipErrorInvalidValue;
+    } else {
+      if (!buf || !wtb || rf || sh.u > 2) return hipErrorInvalidValue;
+#define GQ(Z, E)                                                                              \
+  if (sh.u == 2)                                                                              \
+    hipLaunchKernelGGL((k_gsrb_quad<2, Z, E>), g, b, lds, st, tiles, op, phi, rhs, rhs_ng,    \
+                       colour, sh.tz, wtb, wte, cinfo, ec);                                   \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_gsrb_quad<1, Z, E>), g, b, lds, st, tiles, op, phi, rhs, rhs_ng,    \
+                       colour, sh.tz, wtb, wte, cinfo, ec);
+      if (ec) { GQ(false, true) }
+      else if (zero_guess) { GQ(true, false) }
+      else { GQ(false, false) }
+#undef GQ
+      return hipGetLastError();
+    }
+  }
   if (rf) {
     // the restriction into this level's rhs folded into its zero-guess
     // first half-sweep (global loads, as on every cached level)

@@ -37,8 +37,14 @@ constexpr int kNormSlot = kNormWays * kNormStride;
 struct Shape {
   int lx, ly, tz;
   int u = 1;
-  int wp = 0;  // smoother: store whole x-pairs (see k_gsrb)
+  // smoother lane mapping: 0 = one x-pair per lane, 1 = the same storing
+  // whole x-pairs (see k_gsrb), 2 = one x-quad per lane, two cells of the
+  // colour (FP32 streaming levels, see k_gsrb_quad)
+  int wp = 0;
 };
+
+// x cells a smoother tile row covers (2 or 4 per lane)
+inline int gsrb_tx(Shape sh) { return (sh.wp == 2 ? 4 : 2) * sh.lx; }
 
 // Red/black Gauss-Seidel half-sweep over every box: lane (x, y) of a block
 // updates the cell of colour `colour` among tile cells x0+2x, x0+2x+1 on row

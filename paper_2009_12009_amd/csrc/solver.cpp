@@ -334,6 +334,16 @@ std::vector<Shape> gsrb_candidates() {
             if (shape_ok({lx, ly, tz, u}) && u <= tz) c.push_back({lx, ly, tz, u, wp});
   return c;
 }
+// FP32 smoother tiles with one x-quad per lane (streaming levels only).
+std::vector<Shape> quad_candidates() {
+  std::vector<Shape> c;
+  for (int lx : {8, 16, 32})
+    for (int ly : {2, 4, 8, 16, 32})
+      for (int tz : {1, 2, 4, 8})
+        for (int u : {1, 2})
+          if (shape_ok({lx, ly, tz, u}) && u <= tz) c.push_back({lx, ly, tz, u, 2});
+  return c;
+}
 std::vector<Shape> cell_candidates() {
   std::vector<Shape> c;
   for (int lx : {32, 64, 128})
@@ -671,7 +681,7 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     lv.s_rst = fit_tz(lv.info,
                       shape_cell(std::max(1, mx[0] / 2), std::max(1, mx[1] / 2), std::max(1, mx[2] / 2)),
                       1, true);
-    make_tiles(lv.info, lv.s_gsrb, 2 * lv.s_gsrb.lx, false, lv.t_gsrb);
+    make_tiles(lv.info, lv.s_gsrb, gsrb_tx(lv.s_gsrb), false, lv.t_gsrb);
     make_tiles(lv.info, lv.s_cell, lv.s_cell.lx, false, lv.t_cell);
     if (l + 1 < hb.size()) make_tiles(lv.info, lv.s_rst, lv.s_rst.lx, true, lv.t_rst);
     if (l == 0) {
@@ -691,7 +701,10 @@ int build_plan(mg_solver* s, const std::vector<IBox>& boxes, Bump& bump) {
     lv.cap_cell = lv.t_cell.size();
     if (l <= 1) {
       for (Shape c : gsrb_candidates())
-        lv.cap_gsrb = std::max(lv.cap_gsrb, tile_count(lv.info, c, 2 * c.lx));
+        lv.cap_gsrb = std::max(lv.cap_gsrb, tile_count(lv.info, c, gsrb_tx(c)));
+      if (l == 0)
+        for (Shape c : quad_candidates())
+          lv.cap_gsrb = std::max(lv.cap_gsrb, tile_count(lv.info, c, gsrb_tx(c)));
       if (l == 0) {
         // class tables: every box may take any class candidate of any thread count
         size_t per_box = 0;
@@ -1488,7 +1501,7 @@ int apply_shape(mg_solver* s, Shape sh, bool gsrb, size_t lev = 0) {
   Level& l0 = s->L[lev];
   if (gsrb) {
     std::vector<Tile> t;
-    make_tiles(l0.info, sh, 2 * sh.lx, false, t);
+    make_tiles(l0.info, sh, gsrb_tx(sh), false, t);
     if (t.size() > l0.cap_gsrb) return fail(MG_ERR_ARG, "tile table larger than its reservation");
     l0.t_gsrb = t;
     l0.s_gsrb = sh;
@@ -1823,7 +1836,8 @@ int tune_classes(mg_solver* s, Shape best_g, T* phi, const T* rhs, const Stencil
     members[l0.info[b].hi[0] - l0.info[b].lo[0] + 1].push_back(b);
   int rc;
   *t_uni = *t_cls = 0;
-  if (members.size() < 2 || l0.fused) return MG_OK;
+  // class tables keep the pair mapping
+  if (members.size() < 2 || l0.fused || best_g.wp == 2) return MG_OK;
   const int threads = best_g.lx * best_g.ly;
   std::map<int, Shape> pick;
   for (const auto& kv : members) {
@@ -1848,7 +1862,7 @@ int tune_classes(mg_solver* s, Shape best_g, T* phi, const T* rhs, const Stencil
     pick[kv.first] = best;
   }
   std::vector<Tile> tu, tc;
-  make_tiles(l0.info, best_g, 2 * best_g.lx, false, tu);
+  make_tiles(l0.info, best_g, gsrb_tx(best_g), false, tu);
   make_class_tiles(l0.info, pick, best_g, {}, tc);
   const Shape lc = class_launch_shape(pick, best_g);
   float bu = 1e30f, bc = 1e30f, ms;
@@ -1869,6 +1883,14 @@ int tune_classes(mg_solver* s, Shape best_g, T* phi, const T* rhs, const Stencil
 
 std::string class_key(const mg_solver* s, bool f32, int x_extent) {
   return tune_key(s, "gsrbclass", f32) + "|x" + std::to_string(x_extent);
+}
+
+// The quad smoother mapping runs on FP32 level-0 half-sweeps that stream
+// through buffer loads with write-through, one tile shape for every box.
+bool quad_ok(const mg_solver* s) {
+  const Level& l0 = s->L[0];
+  return s->opts.precision == MG_PREC_F32_REFINE && l0.wt && !l0.fused &&
+         stencil_of<float>(s, l0, true).buf != 0;
 }
 
 int autotune(mg_solver* s) {
@@ -1893,7 +1915,7 @@ int autotune(mg_solver* s) {
       auto it = cache.find(g ? kg1 : kr1);
       if (it == cache.end() || !shape_ok(it->second)) continue;
       std::vector<Tile> t;
-      make_tiles(s->L[1].info, it->second, g ? 2 * it->second.lx : it->second.lx, false, t);
+      make_tiles(s->L[1].info, it->second, g ? gsrb_tx(it->second) : it->second.lx, false, t);
       if (t.size() <= (g ? s->L[1].cap_gsrb : s->L[1].cap_cell) &&
           (rc = apply_shape(s, it->second, g == 1, 1)))
         return rc;
@@ -1909,9 +1931,9 @@ int autotune(mg_solver* s) {
       if (is->second.u == 0) l0.fused = false;
     }
     auto it = cache.find(kg);
-    if (it != cache.end() && shape_ok(it->second)) {
+    if (it != cache.end() && shape_ok(it->second) && (it->second.wp != 2 || quad_ok(s))) {
       std::vector<Tile> t;
-      make_tiles(l0.info, it->second, 2 * it->second.lx, false, t);
+      make_tiles(l0.info, it->second, gsrb_tx(it->second), false, t);
       if (t.size() <= l0.cap_gsrb && (rc = apply_shape(s, it->second, true))) return rc;
       // class shapes, where the tuner found them faster than the uniform one
       std::map<int, Shape> cls;
@@ -1972,6 +1994,12 @@ int autotune(mg_solver* s) {
       if ((rc = time_gsrb<float>(s, sh, phi, l0.rhs32, op, &t))) return rc;
       fg.push_back({t, sh});
     }
+    // one x-quad per lane where the level streams through buffer loads
+    if (quad_ok(s))
+      for (Shape sh : quad_candidates()) {
+        if ((rc = time_gsrb<float>(s, sh, phi, l0.rhs32, op, &t))) return rc;
+        fg.push_back({t, sh});
+      }
     if ((rc = pick_finalist(fg, [&](Shape sh, float* ms) {
            return time_gsrb<float>(s, sh, phi, l0.rhs32, op, ms);
          }, &best_g, &tg)))
@@ -3719,6 +3747,13 @@ int mg_set_tile_shape(mg_solver_t* s, int32_t kernel, int32_t lx, int32_t ly, in
     if (!ok) return fail(MG_ERR_ARG, "shape is not a candidate");
     return apply_sweep_shape(s, Shape{lx, ly, tz});
   }
+  if (kernel == 5) {
+    bool ok = false;
+    for (Shape c : quad_candidates())
+      if (c.lx == lx && c.ly == ly && c.tz == tz && c.u == unroll) ok = true;
+    if (!ok || !quad_ok(s)) return fail(MG_ERR_ARG, "shape is not a candidate");
+    return apply_shape(s, Shape{lx, ly, tz, unroll, 2}, true);
+  }
   if (kernel == 4) {
     bool ok = false;
     for (Shape c : rr_candidates())
@@ -3742,6 +3777,8 @@ int mg_set_class_tile_shape(mg_solver_t* s, int32_t x_extent, int32_t lx, int32_
   if (!s) return fail(MG_ERR_ARG, "null solver");
   Level& l0 = s->L[0];
   if (l0.fused) return fail(MG_ERR_ARG, "level 0 uses fused sweeps");
+  if (l0.cls.empty() && l0.s_gsrb.wp == 2)
+    return fail(MG_ERR_ARG, "level 0 uses the quad smoother mapping (no class tables)");
   bool have = false;
   for (const BoxInfo& b : l0.info) have = have || b.hi[0] - b.lo[0] + 1 == x_extent;
   if (!have) return fail(MG_ERR_ARG, "no level-0 box has that x extent");

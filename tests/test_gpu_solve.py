@@ -460,6 +460,41 @@ def test_stop_fold_bitwise_equal_plain_loop(name, make, boxes, extra, tol):
         assert infos[0]["converged"]
 
 
+@pytest.mark.gpu
+def test_quad_smoother_bitwise_fp32_256():
+    """The FP32 smoother with one x-quad per lane (two cells of the colour,
+    16-byte loads; level-0 FP32 arrays that stream through buffer loads, so
+    256^3) gives the bits of the x-pair mapping: the same FP32+refine
+    history and solution for every quad shape, with one and two planes in
+    flight, including the zero-guess and folded-interpolation half-sweeps."""
+    print("[solve] quad smoother mapping FP32 256^3", flush=True)
+    P = lib()
+    cfg = W.config_c1()
+    boxes = cfg["boxes"]
+    rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(cfg["rhs"], boxes), 0)
+    outs, hists = [], []
+    for sh in (None, (5, 16, 16, 1, 1), (5, 16, 8, 2, 2), (5, 8, 16, 4, 1), (5, 32, 8, 1, 1)):
+        s_ = gpu_solver(cfg, opts=dict(max_iter=3, tune=0, precision=1, aggregate=1))
+        if sh is not None:
+            s_.set_tile_shape(*sh)
+            assert s_.tile_shape(0)[4] == 2
+        phi = s_.cell_mf(1, fill=0.0)
+        info = s_.solve(phi, rhs, 1e-10, raise_on_fail=False, history=True)
+        torch.cuda.synchronize()
+        outs.append(to_global(phi, boxes, cfg["n"]))
+        hists.append(list(info["history"]))
+        s_.close()
+    assert np.all(np.isfinite(outs[0]))
+    for o, h in zip(outs[1:], hists[1:]):
+        assert h == hists[0]
+        assert np.array_equal(o, outs[0])
+    # not on an FP64 solver
+    s_ = gpu_solver(cfg, opts=dict(max_iter=1, tune=0, aggregate=1))
+    with pytest.raises(Exception):
+        s_.set_tile_shape(5, 16, 16, 1, 1)
+    s_.close()
+
+
 TAIL_CASES = [
     # (name, cfg maker, boxes or None, opts (coarse_tail: the threshold), rel_tol, a != 1,
     #  first tail level)

@@ -43,6 +43,12 @@ def parse():
     p.add_argument("--f32-smoother-shape", default=None,
                    help="lx,ly,tz,unroll[,mapping]: the same for the FP32 V-cycle solvers only "
                         "(after --smoother-shape); mapping 1 = whole x-pairs, 2 = one x-quad per lane")
+    p.add_argument("--cell-shape", default=None,
+                   help="lx,ly,tz,unroll: level-0 tiles of the residual kernels (the stop test, "
+                        "the FP64 residual of the FP32 cycle), applied after tuning (counter runs)")
+    p.add_argument("--rr-shape", default=None,
+                   help="lx,ly,tz: level-0 tiles of the residual pass restricting into level 1, "
+                        "applied after tuning (counter runs)")
     p.add_argument("--quiet", action="store_true")
     p.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "nodal"],
                    help="c1: the headline 256^3 line; c2: 512^3 uneven boxes, four variants; "
@@ -162,6 +168,14 @@ def main():
         kern = {0: 0, 1: 2, 2: 5}[v[4] if len(v) == 5 else 0]
         for k in ("f32_refine", "f32_mgpcg"):
             solvers[k].set_tile_shape(kern, *v[:4])
+    if args.cell_shape:
+        v = [int(x) for x in args.cell_shape.split(",")]
+        for s in solvers.values():
+            s.set_tile_shape(1, *v[:4])
+    if args.rr_shape:
+        v = [int(x) for x in args.rr_shape.split(",")]
+        for s in solvers.values():
+            s.set_tile_shape(4, *v[:3])
     phis = {k: s.cell_mf(1, fill=0.0) for k, s in solvers.items()}
     setup_ms = {k: s.solve(phis[k], rhs, 1e-10)["setup_ms"] for k, s in solvers.items()}
 

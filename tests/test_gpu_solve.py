@@ -495,6 +495,38 @@ def test_quad_smoother_bitwise_fp32_256():
     s_.close()
 
 
+@pytest.mark.gpu
+def test_quad_smoother_bitwise_fp32_uneven_boxes():
+    """The same on 256^3 cut into 62 guillotine boxes with x extents 32, 48,
+    64, 96 and 128: quad tiles of 32, 64 and 128 cells per row leave ragged
+    last tiles (a quad partly or wholly past its box, a row's last quad with
+    one cell of the colour) and boxes whose x faces meet several
+    neighbours."""
+    print("[solve] quad smoother mapping FP32 256^3 guillotine boxes", flush=True)
+    P = lib()
+    cfg = W.config_c2(256)
+    boxes = cfg["boxes"]
+    assert sorted({h[0] - l[0] + 1 for l, h in boxes}) == [32, 48, 64, 96, 128]
+    rhs = P.MultiFab.from_numpy(boxes, W.scatter_cells(cfg["rhs"], boxes), 0)
+    outs, hists = [], []
+    for sh in (None, (5, 8, 16, 1, 1), (5, 16, 8, 2, 2), (5, 32, 8, 1, 1)):
+        s_ = gpu_solver(cfg, opts=dict(max_iter=3, tune=0, precision=1, aggregate=1))
+        if sh is not None:
+            s_.set_tile_shape(*sh)
+            assert s_.tile_shape(0)[4] == 2
+        phi = s_.cell_mf(1, fill=0.0)
+        info = s_.solve(phi, rhs, 1e-10, raise_on_fail=False, history=True)
+        torch.cuda.synchronize()
+        outs.append(to_global(phi, boxes, cfg["n"]))
+        hists.append(list(info["history"]))
+        s_.close()
+    assert np.all(np.isfinite(outs[0]))
+    assert hists[0][-1] < hists[0][0]
+    for o, h in zip(outs[1:], hists[1:]):
+        assert h == hists[0]
+        assert np.array_equal(o, outs[0])
+
+
 TAIL_CASES = [
     # (name, cfg maker, boxes or None, opts (coarse_tail: the threshold), rel_tol, a != 1,
     #  first tail level)

@@ -403,8 +403,10 @@ int mg_time_smoother(mg_solver_t* s, mg_multifab_t* phi, const mg_multifab_t* rh
  * unroll ignored).  kernel 5: the FP32 smoother with one x-quad per lane
  * (block lx x ly lanes covering 4*lx x ly cells, lx in {8,16,32}, tz in
  * {1,2,4,8}, unroll 1 or 2; only for MG_PREC_F32_REFINE solvers whose
- * level 0 streams through buffer loads with write-through, else
- * MG_ERR_ARG); mg_get_tile_shape reports it as kernel 0 with whole_pairs = 2.  tz in {1,...,64} (kernels 0, 1, 2).  Every
+ * level 0 streams through buffer loads with write-through and whose level-0
+ * boxes all have x extents that are multiples of 4, else MG_ERR_ARG);
+ * mg_get_tile_shape reports it as kernel 0 with whole_pairs = 2.  tz in
+ * {1,...,64} (kernels 0, 1, 2).  Every
  * shape gives bitwise-identical V-cycle solves; with krylov = 1 the dot
  * p.q is summed per tile of kernel 1, whose shape then changes the last
  * bits of the result. */

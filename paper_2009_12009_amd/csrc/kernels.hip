@@ -540,7 +540,8 @@ __global__ void __launch_bounds__(256)
 // alignment; loads past a row read other cells and are not used, past the
 // array they read 0), so a lane issues about half the loads per cell of the
 // pair mapping.  Streaming levels (buffer descriptors) with write-through
-// only; ZG and PE as in k_gsrb.
+// only, every box's x extent a multiple of 4 (no quad reaches past the end of
+// an array); ZG and PE as in k_gsrb.
 // A quad stays a 128-bit integer value; an element is a constant shift of
 // it.  (Kept as an array or a struct, a choice between two elements by the
 // lane's colour parity became an indexed access to a copy in scratch.)

@@ -1889,6 +1889,12 @@ std::string class_key(const mg_solver* s, bool f32, int x_extent) {
 // through buffer loads with write-through, one tile shape for every box.
 bool quad_ok(const mg_solver* s) {
   const Level& l0 = s->L[0];
+  // with every box's x extent a multiple of 4 no quad load reaches past the
+  // end of an array (its cells past a row's end are the next row's); a
+  // partly out-of-range load would leave its in-range cells to the
+  // hardware's range check
+  for (const BoxInfo& b : l0.info)
+    if ((b.hi[0] - b.lo[0] + 1) % 4) return false;
   return s->opts.precision == MG_PREC_F32_REFINE && l0.wt && !l0.fused &&
          stencil_of<float>(s, l0, true).buf != 0;
 }

@@ -525,6 +525,16 @@ def test_quad_smoother_bitwise_fp32_uneven_boxes():
     for o, h in zip(outs[1:], hists[1:]):
         assert h == hists[0]
         assert np.array_equal(o, outs[0])
+    # x extents 126 and 130 (2 mod 4): a row's last quad would reach past
+    # the end of the last row's arrays, so the mapping is refused
+    c1 = W.config_c1()
+    odd = [((x0, y0, z0), (x1, y0 + 63, z0 + 63)) for x0, x1 in ((0, 125), (126, 255))
+           for y0 in range(0, 256, 64) for z0 in range(0, 256, 64)]
+    s_ = gpu_solver(c1, boxes=odd, opts=dict(max_iter=1, tune=0, precision=1, aggregate=1))
+    with pytest.raises(Exception):
+        s_.set_tile_shape(5, 16, 16, 1, 1)
+    assert s_.tile_shape(0)[4] != 2
+    s_.close()
 
 
 TAIL_CASES = [

@@ -249,7 +249,8 @@ int mg_solve_amr(mg_solver_t* s, mg_multifab_t* phi_c, mg_multifab_t* phi_f,
 
 /* Bytes of device workspace mg_create needs for these boxes and options
  * (has_acoef: whether a cell coefficient a will be given).  Host only; may be
- * called without a GPU.  Validates the box array like mg_create. */
+ * called without a GPU.  Validates the box array like mg_create (nbox < 1 or
+ * a null boxes or bytes pointer: MG_ERR_ARG). */
 int mg_query_workspace(const mg_box_t* boxes, int32_t nbox, const mg_geom_t* geom,
                        const mg_opts_t* opts, int32_t has_acoef, size_t* bytes);
 

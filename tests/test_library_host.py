@@ -90,6 +90,14 @@ def test_validation_errors():
             P.workspace_bytes(boxes, dom, (False,) * 3)
         assert e.value.code == P._lib.MG_ERR_INVALID_BOXARRAY
     assert P.workspace_bytes(W.uniform_boxes(8, 4), dom, (False,) * 3) > 0
+    # an empty box list is an argument error (no level to solve on), for the
+    # solver and for the exchange's tag builder alike
+    with pytest.raises(P.MGError) as e:
+        P.workspace_bytes([], dom, (False,) * 3)
+    assert e.value.code == P._lib.MG_ERR_ARG
+    with pytest.raises(P.MGError) as e:
+        P.copy_tags([], dom, (False,) * 3, 1)
+    assert e.value.code == P._lib.MG_ERR_ARG
 
 
 def test_workspace_too_small_rejected_before_any_device_call():

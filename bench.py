@@ -49,6 +49,10 @@ def parse():
     p.add_argument("--rr-shape", default=None,
                    help="lx,ly,tz: level-0 tiles of the residual pass restricting into level 1, "
                         "applied after tuning (counter runs)")
+    p.add_argument("--trace-solve", action="store_true",
+                   help="only the FP64 V-cycle solver of the 256^3 workload: set-up (tuned), three "
+                        "warm-up solves and one more, no JSON line (a kernel trace of one tuned "
+                        "solve, the last one in the trace)")
     p.add_argument("--quiet", action="store_true")
     p.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "nodal"],
                    help="c1: the headline 256^3 line; c2: 512^3 uneven boxes, four variants; "
@@ -147,6 +151,16 @@ def main():
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s", q)
 
     common = dict(tune=args.tune, aggregate=args.aggregate, fused_min_edge=args.fused_min_edge)
+    if args.trace_solve:
+        s = P.MLMG(boxes, dom, cfg["periodic"], 1.0, 1.0, b=bmf, opts=dict(precision=0, **common))
+        phi = s.cell_mf(1, fill=0.0)
+        for k in range(5):
+            phi.data.zero_()
+            info = s.solve(phi, rhs, 1e-10)
+            log(f"solve {k}: {info['iters']} cycles, {info['solve_ms']:.2f} ms", q)
+        torch.cuda.synchronize()
+        s.close()
+        return
     solvers = {
         "f64": P.MLMG(boxes, dom, cfg["periodic"], 1.0, 1.0, b=bmf, opts=dict(precision=0, **common)),
         "f32_refine": P.MLMG(boxes, dom, cfg["periodic"], 1.0, 1.0, b=bmf,
